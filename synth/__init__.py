@@ -1,0 +1,329 @@
+"""Seeded synthetic workloads for the batched atmospheric forward model.
+
+This module only *generates inputs*: spectral grids, line-list cross-section
+tables, collision-induced-absorption (CIA) tables, Rayleigh coefficients,
+bins, observational errors and parameter draws.  It holds none of the forward
+model's arithmetic (no profiles, hydrostatics, interpolation, radiative
+transfer or likelihood); both the FP64 oracle and the HIP library consume
+exactly the arrays produced here.
+
+The workloads stand in for the paper's opacity-sampled HELIOS-k tables and
+HST/JWST spectra (Section "Gas phase opacities" and Table 2), which are not
+available; their shapes follow those workloads: 100 layers, tens of thousands
+of wavenumbers, 4-8 absorbers, 10-13 parameters.
+
+Configurations (ids 0-4) and the spec batch:
+
+* 0 -- plain transmission, one sample, isothermal, one absorber, 2000 nu.
+* 1 -- JWST-like transmission, 6 absorbers x 20 T x 20 log p x 30000 nu,
+       reduced Guillot profile, CIA, Rayleigh, grey cloud, 400 ln-lambda bins.
+* 2 -- emission, 8 absorbers, 20000 nu (1-12 um), 5 PCHIP knot temperatures.
+* 3 -- transmission setup of 1, used for gradients (B=128).
+* 4 -- high-resolution transmission, 4 absorbers x 8 x 8 x 400000 nu,
+       per-sample layer counts 60-150.
+
+Every random stream is ``numpy.random.default_rng([19687, cid, stream])``.
+"""
+from __future__ import annotations
+
+import functools
+import os
+
+import numpy as np
+
+# ----------------------------------------------------------------------------
+# physical constants the generators need (cgs); the model's own constants live
+# separately in the oracle and in the C library
+BAR = 1.0e6            # dyn cm^-2
+R_JUP = 7.1492e9       # cm
+R_SUN = 6.957e10       # cm
+
+# species order of the paper's opacity list (Section "Gas phase opacities")
+# with molecular masses in atomic mass units
+SPECIES = ("H2O", "CO2", "CO", "CH4", "NH3", "H2S", "SO2", "Na")
+SPECIES_MASS = (18.015, 44.009, 28.010, 16.043, 17.031, 34.081, 64.066, 22.990)
+
+TP_ISOTHERMAL = 0
+TP_GUILLOT3 = 1
+TP_PCHIP = 2
+
+MODE_TRANSMISSION = 0
+MODE_EMISSION = 1
+
+STREAM_LINES = 1
+STREAM_CIA = 2
+STREAM_PARAMS = 3
+STREAM_NOISE = 4
+STREAM_TRUTH = 5
+STREAM_LAYERS = 6
+
+_DATA_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
+
+
+def _rng(cid: int, stream: int, sub: int = 0) -> np.random.Generator:
+    return np.random.default_rng([19687, int(cid), int(stream), int(sub)])
+
+
+# ----------------------------------------------------------------------------
+# line-list cross sections
+def line_list(cid: int, species: int, n_lines: int, nu_min: float, nu_max: float):
+    """Seeded line list: uniform centres, log-normal strengths.
+
+    log10 S ~ N(-21, 1.5) [cm^-1 / (molecule cm^-2)]; centres ~ U(nu_min, nu_max).
+    """
+    g = _rng(cid, STREAM_LINES, species)
+    centres = g.uniform(nu_min, nu_max, n_lines)
+    log_s = g.normal(-21.0, 1.5, n_lines)
+    return centres, 10.0 ** log_s
+
+
+def lorentz_log10_xsec(nu, t_grid, logp_grid, centres, strengths, gamma0=0.07,
+                       cutoff=25.0, continuum=1.0e-24):
+    """log10 cross section [cm^2] on a (T, log10 p[bar], nu) grid.
+
+    sigma(nu; T, p) = continuum + sum_j S_j (g/pi) / ((nu - c_j)^2 + g^2), with
+    the Lorentz half width g = gamma0 (p / 1 bar) (T / 296 K)^-0.5 shared by all
+    lines and each line truncated at ``cutoff`` cm^-1 from its centre.  The
+    strengths do not depend on T.
+    """
+    nu = np.asarray(nu, dtype=np.float64)
+    n = nu.size
+    dnu = (nu[-1] - nu[0]) / (n - 1)
+    width = int(np.ceil(2.0 * cutoff / dnu)) + 2
+    i0 = np.ceil((centres - cutoff - nu[0]) / dnu).astype(np.int64)
+    idx = i0[:, None] + np.arange(width)[None, :]
+    inside = (idx >= 0) & (idx < n)
+    idxc = np.clip(idx, 0, n - 1)
+    d2 = (nu[idxc] - centres[:, None]) ** 2
+    inside &= d2 <= cutoff * cutoff
+    flat_idx = idxc[inside]
+    d2_in = d2[inside]
+    s_in = np.broadcast_to(strengths[:, None], idx.shape)[inside]
+    out = np.empty((len(t_grid), len(logp_grid), n), dtype=np.float64)
+    for it, t in enumerate(t_grid):
+        for ip, lp in enumerate(logp_grid):
+            g = gamma0 * (10.0 ** lp) * (t / 296.0) ** -0.5
+            prof = s_in * (g / np.pi) / (d2_in + g * g)
+            sig = continuum + np.bincount(flat_idx, weights=prof, minlength=n)
+            out[it, ip] = np.log10(sig)
+    return out
+
+
+def cia_log10(cid: int, pair: int, nu, tc_grid, n_bands=4):
+    """Smooth seeded CIA band model log10 k(T, nu) [cm^5].
+
+    k = sum_g A_g exp(-(nu - c_g)^2 / (2 w_g^2)) (T / 1000 K)^beta_g + 1e-50,
+    log10 A ~ U[-46, -44], w ~ U[200, 1500] cm^-1, beta ~ U[-1, 1],
+    c ~ U(nu range).
+    """
+    g = _rng(cid, STREAM_CIA, pair)
+    log_a = g.uniform(-46.0, -44.0, n_bands)
+    w = g.uniform(200.0, 1500.0, n_bands)
+    beta = g.uniform(-1.0, 1.0, n_bands)
+    c = g.uniform(nu[0], nu[-1], n_bands)
+    out = np.empty((len(tc_grid), len(nu)), dtype=np.float64)
+    for it, t in enumerate(tc_grid):
+        k = np.full(len(nu), 1.0e-50)
+        for b in range(n_bands):
+            k += 10.0 ** log_a[b] * np.exp(-0.5 * ((nu - c[b]) / w[b]) ** 2) * (t / 1000.0) ** beta[b]
+        out[it] = np.log10(k)
+    return out
+
+
+def ln_lambda_bins(nu, n_bins):
+    """Contiguous native-index bins [lo_k, hi_k) uniform in ln(nu) (= ln lambda).
+
+    Bins are ordered by ascending nu and together cover every native point.
+    """
+    nu = np.asarray(nu)
+    edges = np.exp(np.linspace(np.log(nu[0]), np.log(nu[-1]), n_bins + 1))
+    lo = np.searchsorted(nu, edges[:-1], side="left")
+    hi = np.searchsorted(nu, edges[1:], side="left")
+    hi[-1] = len(nu)
+    lo[0] = 0
+    if np.any(hi <= lo):
+        raise ValueError("empty bin; use fewer bins")
+    return lo.astype(np.int32), hi.astype(np.int32)
+
+
+# ----------------------------------------------------------------------------
+# configuration descriptions
+_BASE = dict(
+    p_ref_bar=10.0,          # reference pressure of the altitude grid
+    r_p=R_JUP,               # planet reference radius [cm]
+    r_s=R_SUN,               # stellar radius [cm]
+    g_ref=1000.0,            # gravity at the reference radius [cm s^-2]
+    kappa_ir=1.0e-2,         # Guillot infrared opacity [cm^2 g^-1]
+    f_hem=0.25,              # hemispheric redistribution factor
+    kappa_cloud=60.0,        # grey deck opacity [cm^2 g^-1]: 3 q Q/(4 rho_d r) with q=1e-2, Q=2, rho_d=2.5, r=1 um
+    t_star=5500.0,           # stellar blackbody temperature [K] (emission)
+    dilution=1.0,            # emission dilution factor s
+    err_c=-99.0,             # error inflation exponent c (off)
+    ray_h2=8.0e-29,          # H2 Rayleigh cross section at 1e4 cm^-1 [cm^2], scales as nu^4
+    ray_he=6.0e-30,          # He Rayleigh cross section at 1e4 cm^-1 [cm^2]
+    n_mu=4,                  # Gauss-Legendre angles (emission)
+    sigma_ppm=50.0,          # observational error per bin [ppm]
+)
+
+CONFIGS = {
+    0: dict(mode=MODE_TRANSMISSION, tp=TP_ISOTHERMAL, n_layers=50, p_bot=100.0, p_top=1.0e-6,
+            n_species=1, n_nu=2000, nu_min=2000.0, nu_max=10000.0,
+            t_grid=np.linspace(500.0, 2500.0, 8), logp_grid=np.linspace(-6.0, 2.0, 8),
+            n_lines=300, cia=False, rayleigh=True, cloud=False, scale=False, offset=False,
+            mu_fixed=2.3, n_bins=100, batch=1),
+    1: dict(mode=MODE_TRANSMISSION, tp=TP_GUILLOT3, n_layers=100, p_bot=100.0, p_top=1.0e-7,
+            n_species=6, n_nu=30000, nu_min=1.0e4 / 5.3, nu_max=1.0e4 / 0.6,
+            t_grid=np.linspace(300.0, 3500.0, 20), logp_grid=np.linspace(-7.0, 2.0, 20),
+            n_lines=2000, cia=True, rayleigh=True, cloud=True, scale=True, offset=True,
+            mu_fixed=0.0, n_bins=400, batch=256),
+    2: dict(mode=MODE_EMISSION, tp=TP_PCHIP, n_layers=100, p_bot=100.0, p_top=1.0e-7,
+            n_species=8, n_nu=20000, nu_min=1.0e4 / 12.0, nu_max=1.0e4 / 1.0,
+            t_grid=np.linspace(300.0, 3500.0, 20), logp_grid=np.linspace(-7.0, 2.0, 20),
+            n_lines=2000, cia=True, rayleigh=False, cloud=False, scale=False, offset=False,
+            mu_fixed=0.0, n_bins=400, batch=1024, n_knots=5),
+    3: dict(mode=MODE_TRANSMISSION, tp=TP_GUILLOT3, n_layers=100, p_bot=100.0, p_top=1.0e-7,
+            n_species=6, n_nu=30000, nu_min=1.0e4 / 5.3, nu_max=1.0e4 / 0.6,
+            t_grid=np.linspace(300.0, 3500.0, 20), logp_grid=np.linspace(-7.0, 2.0, 20),
+            n_lines=2000, cia=True, rayleigh=True, cloud=True, scale=True, offset=True,
+            mu_fixed=0.0, n_bins=400, batch=128),
+    4: dict(mode=MODE_TRANSMISSION, tp=TP_GUILLOT3, n_layers=150, p_bot=100.0, p_top=1.0e-7,
+            n_species=4, n_nu=400000, nu_min=1.0e4 / 2.5, nu_max=1.0e4 / 0.95,
+            t_grid=np.linspace(300.0, 3500.0, 8), logp_grid=np.linspace(-7.0, 2.0, 8),
+            n_lines=2000, cia=True, rayleigh=True, cloud=True, scale=True, offset=True,
+            mu_fixed=0.0, n_bins=400, batch=64, ragged=(60, 150)),
+}
+
+# configs 1 and 3 share tables (same seeds) so the spec batch reuses them
+_TABLE_CID = {0: 0, 1: 1, 2: 2, 3: 1, 4: 4}
+
+
+def param_names(cfg) -> list:
+    s = cfg["n_species"]
+    if cfg["tp"] == TP_ISOTHERMAL:
+        names = ["T_iso"]
+    elif cfg["tp"] == TP_GUILLOT3:
+        names = ["T_int", "T_eq", "log10_gamma_v"]
+    else:
+        names = [f"T_knot{k}" for k in range(cfg["n_knots"])]
+    names += [f"log10_X_{SPECIES[i]}" for i in range(s)]
+    if cfg["cloud"]:
+        names.append("log10_P_cloud_bar")
+    if cfg["scale"]:
+        names.append("R_p_scale")
+    if cfg["offset"]:
+        names.append("offset_ppm")
+    return names
+
+
+def param_bounds(cfg):
+    """Uniform prior bounds, one (lo, hi) pair per parameter."""
+    s = cfg["n_species"]
+    if cfg["tp"] == TP_ISOTHERMAL:
+        b = [(1200.0, 1200.0)]
+    elif cfg["tp"] == TP_GUILLOT3:
+        b = [(100.0, 1500.0), (500.0, 2000.0), (-3.0, 2.0)]
+    else:
+        b = [(800.0, 2500.0)] * cfg["n_knots"]
+    b += [(-8.0, -2.0)] * s if cfg["tp"] != TP_ISOTHERMAL else [(-3.0, -3.0)] * s
+    if cfg["cloud"]:
+        b.append((-6.0, 2.0))
+    if cfg["scale"]:
+        b.append((0.95, 1.05))
+    if cfg["offset"]:
+        b.append((-100.0, 100.0))
+    return np.array(b, dtype=np.float64)
+
+
+def draw_params(cid: int, batch: int, stream: int = STREAM_PARAMS) -> np.ndarray:
+    """[batch, P] uniform draws; row b does not depend on ``batch``."""
+    cfg = CONFIGS[cid]
+    bounds = param_bounds(cfg)
+    u = _rng(cid, stream).uniform(0.0, 1.0, size=(batch, len(bounds)))
+    return bounds[:, 0] + u * (bounds[:, 1] - bounds[:, 0])
+
+
+def draw_layers(cid: int, batch: int) -> np.ndarray | None:
+    cfg = CONFIGS[cid]
+    if "ragged" not in cfg:
+        return None
+    lo, hi = cfg["ragged"]
+    return _rng(cid, STREAM_LAYERS).integers(lo, hi + 1, size=batch).astype(np.int32)
+
+
+@functools.lru_cache(maxsize=4)
+def _tables(tcid: int):
+    cfg = CONFIGS[tcid]
+    nu = np.linspace(cfg["nu_min"], cfg["nu_max"], cfg["n_nu"])
+    xs = np.empty((cfg["n_species"], len(cfg["t_grid"]), len(cfg["logp_grid"]), len(nu)))
+    for s in range(cfg["n_species"]):
+        c, st = line_list(tcid, s, cfg["n_lines"], cfg["nu_min"], cfg["nu_max"])
+        xs[s] = lorentz_log10_xsec(nu, cfg["t_grid"], cfg["logp_grid"], c, st)
+    tc = np.linspace(300.0, 3500.0, 20)
+    if cfg["cia"]:
+        cia = np.stack([cia_log10(tcid, p, nu, tc) for p in range(2)])
+    else:
+        cia = None
+    for a in (nu, xs, tc) + ((cia,) if cia is not None else ()):
+        a.setflags(write=False)
+    return nu, xs, tc, cia
+
+
+def obs_path(cid: int) -> str:
+    return os.path.join(_DATA_DIR, f"obs_c{cid}.txt")
+
+
+def load_obs(cid: int, n_bins: int):
+    """Observed binned spectrum y_k (written beforehand from the FP64 oracle at a
+    seeded truth parameter vector, plus seeded Gaussian noise)."""
+    path = obs_path(cid)
+    if not os.path.exists(path):
+        return None
+    y = np.loadtxt(path, dtype=np.float64)
+    if y.shape != (n_bins,):
+        raise ValueError(f"{path}: expected {n_bins} values, got {y.shape}")
+    return y
+
+
+def truth_params(cid: int) -> np.ndarray:
+    return draw_params(cid, 1, stream=STREAM_TRUTH)[0]
+
+
+def noise(cid: int, n_bins: int, sigma_ppm: float) -> np.ndarray:
+    return _rng(cid, STREAM_NOISE).normal(0.0, sigma_ppm * 1.0e-6, n_bins)
+
+
+def workload(cid: int, batch: int | None = None, require_obs: bool = True) -> dict:
+    """Everything one configuration needs, as plain numpy arrays and scalars.
+
+    Units are cgs except where a key says otherwise (pressures in bar).
+    """
+    cfg = CONFIGS[cid]
+    nu, xs, tc, cia = _tables(_TABLE_CID[cid])
+    lo, hi = ln_lambda_bins(nu, cfg["n_bins"]) if cid != 0 else _uniform_bins(len(nu), cfg["n_bins"])
+    b = cfg["batch"] if batch is None else int(batch)
+    wl = dict(_BASE)
+    wl.update({k: v for k, v in cfg.items() if k not in ("t_grid", "logp_grid")})
+    wl.update(
+        cid=cid, batch=b, nu=nu, t_grid=np.asarray(cfg["t_grid"], dtype=np.float64),
+        logp_grid=np.asarray(cfg["logp_grid"], dtype=np.float64), log10_xsec=xs,
+        species=SPECIES[: cfg["n_species"]], species_mass=np.array(SPECIES_MASS[: cfg["n_species"]]),
+        tc_grid=tc, log10_cia=cia, bin_lo=lo, bin_hi=hi,
+        y_err=np.full(cfg["n_bins"], _BASE["sigma_ppm"] * 1.0e-6),
+        offset_mask=(0.5 * (nu[lo] + nu[hi - 1]) <= 1.0e4 / 3.0).astype(np.uint8) if cfg["offset"]
+        else np.zeros(cfg["n_bins"], np.uint8),
+        params=draw_params(cid, b), n_layers_per_sample=draw_layers(cid, b),
+        param_names=param_names(cfg), param_bounds=param_bounds(cfg),
+        n_knots=cfg.get("n_knots", 0),
+    )
+    y = load_obs(cid, cfg["n_bins"])
+    if y is None:
+        if require_obs:
+            raise FileNotFoundError(f"{obs_path(cid)} missing; regenerate it with tests/golden/make_obs.py")
+        y = np.zeros(cfg["n_bins"])
+    wl["y_obs"] = y
+    return wl
+
+
+def _uniform_bins(n, k):
+    edges = np.linspace(0, n, k + 1).round().astype(np.int32)
+    return edges[:-1].copy(), edges[1:].copy()
