@@ -1,0 +1,190 @@
+/*
+ * exofwd -- batched atmospheric forward model and its adjoint on MI355X (gfx950).
+ *
+ * C ABI of the library.  One call evaluates, for B parameter samples at once,
+ * the retrieval forward model of Lee (2026, "Exo Skryer"):
+ *   - the temperature-pressure profile (isothermal, Eq. 7; reduced modified
+ *     Guillot, Eq. 16; or PCHIP knots) on log-uniform pressure levels,
+ *   - free chemistry with H2/He filling (Eq. 35-36),
+ *   - the hydrostatic altitude grid about the reference radius and pressure
+ *     (inverse-square gravity, layer-isothermal),
+ *   - per-layer opacity from (T, log p)-interpolated log cross-section tables
+ *     weighted by mixing ratio, plus CIA, Rayleigh and a grey cloud deck
+ *     (Section "Gas phase opacities"; Eq. 18 and 23 with Q_ext = 2),
+ *   - transmission: the slant optical depth through the path matrix
+ *     tau = P_1D . dtau_vert (Eq. 43-44) and the transit depth;
+ *     emission: linear-in-tau upward intensity over Gauss-Legendre angles and
+ *     the planet/star flux ratio (Eq. 45),
+ *   - box-car binning and the Gaussian log-likelihood (Eq. 1-3), with
+ *     lnL = -1e300 for invalid samples (Section "Likelihood").
+ *
+ * Conventions
+ *   - Units are cgs (pressures given in bar where a name says so).
+ *   - Every pointer marked "dev" is device memory on the context's device,
+ *     row-major and contiguous, owned by the caller.  "host" pointers are only
+ *     read during the call that receives them and may be freed afterwards.
+ *   - exofwd_forward / exofwd_grad only enqueue work on the given HIP stream
+ *     (hipStream_t passed as void*, NULL = the null stream) and never
+ *     synchronise; results are valid once the stream reaches that point.
+ *   - Misuse visible on the host (bad sizes, NULL required pointers, a mode the
+ *     context was not built for) returns an error status and enqueues nothing.
+ *     Per-sample numerical invalidity is reported in status[b] bits; such a
+ *     sample gets lnL = -1e300, a NaN spectrum and a zero gradient.
+ *   - One context serves one stream at a time (calls on a context must not
+ *     overlap); several contexts may share a device.
+ */
+#ifndef EXOFWD_H
+#define EXOFWD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct exofwd_ctx exofwd_ctx;
+
+typedef enum {
+  EXOFWD_OK = 0,
+  EXOFWD_ERR_ARG = 1,         /* NULL or out-of-range argument */
+  EXOFWD_ERR_SHAPE = 2,       /* sizes inconsistent with the context */
+  EXOFWD_ERR_CONFIG = 3,      /* invalid configuration at create time */
+  EXOFWD_ERR_NOMEM = 4,       /* device allocation failed */
+  EXOFWD_ERR_DEVICE = 5,      /* a HIP runtime call failed */
+  EXOFWD_ERR_UNSUPPORTED = 6  /* valid request this build does not provide */
+} exofwd_status;
+
+enum { EXOFWD_TRANSMISSION = 0, EXOFWD_EMISSION = 1 };
+
+/* FP64: FP64 tables and arithmetic throughout ("plain FP64").
+ * MIXED: FP16 log-sigma tables (per-(species, nu) FP32 offsets), FP32 opacity,
+ *        bf16x3 split-precision MFMA chord products with FP32 accumulation;
+ *        profile, hydrostatics and likelihood sums stay FP64.           */
+enum { EXOFWD_PREC_FP64 = 0, EXOFWD_PREC_MIXED = 1 };
+
+enum { EXOFWD_TP_ISOTHERMAL = 0, EXOFWD_TP_GUILLOT3 = 1, EXOFWD_TP_PCHIP = 2 };
+
+/* per-sample status bits */
+enum {
+  EXOFWD_S_BAD_VMR = 1,      /* sum of absorber mixing ratios >= 1 */
+  EXOFWD_S_UNBOUND = 2,      /* 1/r <= 0 somewhere: atmosphere not bound */
+  EXOFWD_S_NONFINITE = 4,    /* a parameter or an output is not finite */
+  EXOFWD_S_BAD_T = 8,        /* a temperature is <= 0 or not finite */
+  EXOFWD_S_BAD_LAYERS = 16   /* n_layers[b] outside [1, n_layers_max] */
+};
+
+/*
+ * Static description of one workload; read only by exofwd_create.
+ *
+ * Parameter vector layout, per sample (P = exofwd_num_params):
+ *   T-p:  isothermal  -> [T_iso]
+ *         guillot3    -> [T_int, T_eq, log10 gamma_v]          (Eq. 16, q = 2/3)
+ *         pchip       -> [T_0 .. T_{n_knots-1}], knot k at log10 p equally
+ *                        spaced from p_top (k = 0) to p_bot
+ *   then  log10 X_s for s = 0..n_species-1                       (Eq. 35)
+ *   then  log10 P_cloud [bar]   if has_cloud
+ *   then  R_p scale factor      if has_scale  (R_ref = scale * r_p)
+ *   then  offset [ppm]          if has_offset (added to bins with offset_mask)
+ */
+typedef struct exofwd_config {
+  int32_t mode;              /* EXOFWD_TRANSMISSION / EXOFWD_EMISSION */
+  int32_t precision;         /* EXOFWD_PREC_FP64 / EXOFWD_PREC_MIXED */
+  int32_t tp_kind;           /* EXOFWD_TP_* */
+  int32_t n_knots;           /* PCHIP knots (2..8), else ignored */
+  int32_t n_species;         /* absorbers S, 1..8 */
+  int32_t n_layers_max;      /* L_max, 1..160; layers per sample default to it */
+  int32_t batch_max;         /* B_max: largest B any call may pass */
+  int32_t has_cia, has_rayleigh, has_cloud, has_scale, has_offset;
+  int32_t n_mu;              /* emission Gauss-Legendre angles, 1..8 */
+  double mu_fixed;           /* > 0: fixed mean molecular weight [amu]; else from composition */
+  double p_bot_bar, p_top_bar, p_ref_bar;   /* grid bottom/top, reference pressure [bar] */
+  double r_p, r_s, g_ref;    /* reference radius [cm], stellar radius [cm], gravity at r_p [cm s^-2] */
+  double kappa_ir, f_hem;    /* Guillot infrared opacity [cm^2 g^-1], redistribution factor */
+  double kappa_cloud;        /* grey deck mass opacity [cm^2 g^-1] */
+  double t_star, dilution;   /* emission: stellar blackbody T [K], dilution s */
+  double err_c;              /* error inflation exponent c (Eq. 3); -99 = off */
+  double ray_h2, ray_he;     /* Rayleigh cross sections at 1e4 cm^-1 [cm^2], scaled by (nu/1e4)^4 */
+  int32_t n_nu;              /* wavenumbers */
+  const double* nu;          /* host [n_nu], ascending [cm^-1] */
+  int32_t n_t, n_p;          /* cross-section table axes (2..255 each) */
+  const double* t_grid;      /* host [n_t] ascending [K] */
+  const double* logp_grid;   /* host [n_p] ascending log10(p / 1 bar) */
+  const double* log10_xsec;  /* host [n_species][n_t][n_p][n_nu] log10 sigma [cm^2] */
+  const double* species_mass;/* host [n_species] [amu] */
+  int32_t n_tc;              /* CIA temperature axis (2..255) if has_cia */
+  const double* tc_grid;     /* host [n_tc] ascending [K] */
+  const double* log10_cia;   /* host [2][n_tc][n_nu] log10 k [cm^5]: H2-H2, H2-He */
+  int32_t n_bins;            /* K >= 1 */
+  const int32_t* bin_lo;     /* host [K]: bin k averages native points [lo_k, hi_k) */
+  const int32_t* bin_hi;     /* host [K] */
+  const double* y_obs;       /* host [K] observed binned spectrum */
+  const double* y_err;       /* host [K] 1-sigma errors */
+  const uint8_t* offset_mask;/* host [K] or NULL: bins that receive the offset */
+  int32_t device;            /* HIP device ordinal */
+} exofwd_config;
+
+/* Validate the configuration, upload and encode the tables, allocate the
+ * workspace for batch_max samples of n_layers_max layers.  Synchronous.
+ * On success *out owns all device memory of the context. */
+exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out);
+
+/* Free everything the context owns (synchronises its device). NULL is a no-op. */
+exofwd_status exofwd_destroy(exofwd_ctx* ctx);
+
+int32_t exofwd_num_params(const exofwd_ctx* ctx);   /* P, or -1 for NULL */
+int32_t exofwd_num_nu(const exofwd_ctx* ctx);       /* n_nu, or -1 */
+int32_t exofwd_num_bins(const exofwd_ctx* ctx);     /* K, or -1 */
+int32_t exofwd_precision(const exofwd_ctx* ctx);    /* EXOFWD_PREC_*, or -1 */
+
+/*
+ * Forward model for B samples (1 <= B <= batch_max).
+ *   params   dev [B][P] double
+ *   n_layers dev [B] int32 or NULL (NULL: every sample uses n_layers_max)
+ *   spectra  dev [B][n_nu], double in FP64 precision, float in MIXED; or NULL
+ *            (transit depth, or F_p/F_* for emission)
+ *   lnL      dev [B] double or NULL
+ *   status   dev [B] int32 or NULL
+ */
+exofwd_status exofwd_forward(exofwd_ctx* ctx, int32_t B, const double* params,
+                             const int32_t* n_layers, void* spectra, double* lnL,
+                             int32_t* status, void* hip_stream);
+
+/*
+ * lnL and its gradient with respect to every parameter for B samples, by the
+ * hand-written adjoint (transmission only; emission returns
+ * EXOFWD_ERR_UNSUPPORTED).
+ *   lnL      dev [B] double (required)
+ *   grad     dev [B][P] double (required): d lnL / d params
+ *   spectra  dev [B][n_nu] (type as in exofwd_forward) or NULL
+ *   status   dev [B] int32 or NULL
+ */
+exofwd_status exofwd_grad(exofwd_ctx* ctx, int32_t B, const double* params,
+                          const int32_t* n_layers, void* spectra, double* lnL,
+                          double* grad, int32_t* status, void* hip_stream);
+
+/* Time the tunable launch shapes of this context at batch B on its device and
+ * keep the fastest (synchronous).  cache_path (may be NULL) is a text file of
+ * previous results keyed by device, CU count and workload shape; it is read if
+ * present and rewritten with the result. */
+exofwd_status exofwd_autotune(exofwd_ctx* ctx, int32_t B, const char* cache_path);
+
+/* Per-kernel timing of the calls that follow: when enabled, each kernel launch
+ * is bracketed by HIP events on the call's stream.  exofwd_kernel_time then
+ * reports the summed milliseconds and launch count for the kernel named
+ * (e.g. "trans_fwd"), synchronising the stream of the last call.  Resetting
+ * clears the tallies. */
+exofwd_status exofwd_set_profiling(exofwd_ctx* ctx, int32_t enable);
+exofwd_status exofwd_kernel_time(exofwd_ctx* ctx, const char* name, double* total_ms,
+                                 int32_t* launches);
+
+/* Bytes of device memory the context holds. */
+int64_t exofwd_device_bytes(const exofwd_ctx* ctx);
+
+const char* exofwd_strerror(exofwd_status s);
+/* Text of the last error raised on this context (empty if none). */
+const char* exofwd_last_error(const exofwd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EXOFWD_H */

@@ -1,0 +1,89 @@
+// Internal definitions shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace exofwd {
+
+// CODATA 2018 constants, cgs
+constexpr double kB = 1.380649e-16;        // erg K^-1
+constexpr double kHpl = 6.62607015e-27;    // erg s
+constexpr double kC = 2.99792458e10;       // cm s^-1
+constexpr double kMu = 1.66053906660e-24;  // g
+constexpr double kBar = 1.0e6;             // dyn cm^-2
+constexpr double kHeH2 = 0.164;            // He/H2 filling ratio (Eq. 36)
+constexpr double kMH2 = 2.01588, kMHe = 4.002602;
+constexpr double kLog2_10 = 3.321928094887362347870319429489;
+constexpr double kInvalidLnL = -1.0e300;
+
+constexpr int kMaxSpecies = 8;
+constexpr int kMaxLayers = 160;   // L_max; padded layer count is a multiple of 32
+constexpr int kMaxKnots = 8;
+constexpr int kMaxMu = 8;
+constexpr int kTileNu = 64;       // wavenumbers per tile of the fused kernels
+constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
+
+// per-layer record of the opacity kernels (one per sample and layer)
+//   [0] wT, [1] wP, [2] wTc, [3] Rayleigh coefficient R_l (x (nu/1e4)^4),
+//   [4] cloud term D_l, [5] lam_c1, [6] lam_c2, [7..7+S) lam_s
+// with lam = log2 of the per-layer prefactor (n X dr, n^2 X X dr)
+constexpr int kRecFixed = 7;
+__host__ __device__ constexpr int rec_len(int s) { return kRecFixed + s; }
+
+// packed interpolation cells of one layer: iT | iP << 8 | iTc << 16
+__host__ __device__ inline int pack_cells(int it, int ip, int itc) { return it | (ip << 8) | (itc << 16); }
+
+enum : int { kTransmission = 0, kEmission = 1 };
+enum : int { kFP64 = 0, kMixed = 1 };
+enum : int { kTpIso = 0, kTpGuillot3 = 1, kTpPchip = 2 };
+enum : int { kBadVmr = 1, kUnbound = 2, kNonfinite = 4, kBadT = 8, kBadLayers = 16 };
+
+// Everything a kernel needs to know about the workload (by value).
+struct Model {
+  int mode, tp_kind, n_knots, S, L_max, L_pad, P;
+  int has_cia, has_ray, has_cloud, has_scale, has_offset, n_mu;
+  int n_nu, n_nu_pad, n_tiles, n_t, n_p, n_tc, K;
+  int idx_cloud, idx_scale, idx_offset, n_tp;
+  double mu_fixed, log10_pbot, log10_ptop, p_ref, r_p, r_s, g_ref;
+  double kappa_ir, f_hem, kappa_cloud, t_star, dilution, err_c, ray_h2, ray_he;
+  double mass[kMaxSpecies];
+  double mu_nodes[kMaxMu], mu_weights[kMaxMu];
+  const double* t_grid;     // [n_t]
+  const double* logp_grid;  // [n_p]
+  const double* tc_grid;    // [n_tc]
+  const double* nu;         // [n_nu_pad] (padded with the last value)
+};
+
+// Workspace of one context, sized for batch_max x L_pad.
+struct Work {
+  int32_t* status;      // [B]
+  int32_t* nlay;        // [B] layers used per sample
+  double* t_lay;        // [B][L_pad]
+  double* t_lev;        // [B][L_pad+1]
+  double* r_lev;        // [B][L_pad+1]
+  double* core;         // [B] r_0^2 / R_s^2
+  int32_t* cells;       // [B][L_pad] packed cells
+  void* rec;            // [B][L_pad][rec_len] float (mixed) or double (fp64)
+  void* area;           // [B][L_pad] (r_{i+1}^2 - r_i^2)/R_s^2, float or double
+  double* pm64;         // fp64: [B][L_pad][L_pad] path matrix
+  uint16_t* pfrag;      // mixed: [B][MB][KB][64][8] bf16, hi then lo planes
+  uint16_t* ptfrag;     // mixed: transposed path matrix fragments (adjoint)
+  void* spec;           // [B][n_nu] internal spectrum when the caller passes none
+  double* dm;           // [B][K] d lnL / d m_k
+  double* lnl_tmp;      // [B]
+};
+
+// Tables on the device.
+struct Tables {
+  const uint16_t* h;     // mixed: [S][n_t][n_p][n_nu_pad] fp16 (log2 sigma - c)
+  const float* c;        // mixed: [S][n_nu_pad] per-(species, nu) offsets, log2 units
+  const uint16_t* hc;    // mixed: [2][n_tc][n_nu_pad]
+  const float* cc;       // mixed: [2][n_nu_pad]
+  const float* nu4f;     // mixed: [n_nu_pad] (nu/1e4)^4
+  const double* t64;     // fp64: [S][n_t][n_p][n_nu_pad] log10 sigma
+  const double* tc64;    // fp64: [2][n_tc][n_nu_pad] log10 k
+  const double* nu4d;    // fp64: [n_nu_pad]
+};
+
+}  // namespace exofwd

@@ -1,0 +1,489 @@
+// Host side of the C ABI: configuration checks, table encoding and upload,
+// workspace, kernel launches and per-kernel event timing.
+#include "../../include/exofwd.h"
+#include "kernels.h"
+#include "adjoint.h"
+#include "emission.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace exofwd;
+
+struct exofwd_ctx {
+  Model m{};
+  Work w{};
+  Tables tb{};
+  AdjWork aw{};
+  int precision = 0;
+  int device = 0;
+  int batch_max = 0;
+  std::vector<void*> allocs;
+  int64_t bytes = 0;
+  int32_t* d_lo = nullptr;
+  int32_t* d_hi = nullptr;
+  double* d_y = nullptr;
+  double* d_yerr = nullptr;
+  uint8_t* d_mask = nullptr;
+  std::string err;
+  bool profiling = false;
+  struct Ev {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<Ev> events;
+  int adj_chunks = 0;
+};
+
+namespace {
+
+exofwd_status fail(exofwd_ctx* c, exofwd_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+template <typename T>
+T* dalloc(exofwd_ctx* c, size_t count) {
+  if (count == 0) count = 1;
+  void* p = nullptr;
+  if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) return nullptr;
+  c->allocs.push_back(p);
+  c->bytes += (int64_t)(count * sizeof(T));
+  return static_cast<T*>(p);
+}
+
+template <typename T>
+bool upload(T* dst, const T* src, size_t count) {
+  return hipMemcpy(dst, src, count * sizeof(T), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+bool ascending(const double* v, int n) {
+  for (int i = 0; i + 1 < n; ++i)
+    if (!(v[i + 1] > v[i])) return false;
+  return true;
+}
+
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n.
+void gauss_legendre(int n, double* x, double* wgt) {
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = z; p0 = 1.0; }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = z;
+    wgt[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Reduced-precision table storage: per (source, nu) offset c = float((min+max)/2)
+// of log2 sigma over the interpolation axes, entries float16(log2 sigma - c).
+void encode_fp16(const double* log10_tab, int n_src, int n_rows, int n_nu, int n_nu_pad, std::vector<_Float16>& h,
+                 std::vector<float>& c) {
+  h.assign((size_t)n_src * n_rows * n_nu_pad, (_Float16)0.0f);
+  c.assign((size_t)n_src * n_nu_pad, -1000.0f);
+  for (int s = 0; s < n_src; ++s) {
+    const double* t = log10_tab + (size_t)s * n_rows * n_nu;
+    for (int i = 0; i < n_nu; ++i) {
+      double mn = INFINITY, mx = -INFINITY;
+      for (int r = 0; r < n_rows; ++r) {
+        double v = t[(size_t)r * n_nu + i] * kLog2_10;
+        mn = v < mn ? v : mn;
+        mx = v > mx ? v : mx;
+      }
+      const float cf = (float)(0.5 * (mn + mx));
+      c[(size_t)s * n_nu_pad + i] = cf;
+      for (int r = 0; r < n_rows; ++r) {
+        double v = t[(size_t)r * n_nu + i] * kLog2_10 - (double)cf;
+        h[((size_t)s * n_rows + r) * n_nu_pad + i] = (_Float16)v;
+      }
+    }
+  }
+}
+
+exofwd_status check_hip(exofwd_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return EXOFWD_OK;
+  return fail(c, EXOFWD_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// kernel timing helpers (used by every launch site)
+namespace exofwd {
+void prof_begin(exofwd_ctx* c, const char* name, hipStream_t st) {
+  if (!c->profiling) return;
+  exofwd_ctx::Ev e;
+  e.name = name;
+  hipEventCreate(&e.a);
+  hipEventCreate(&e.b);
+  hipEventRecord(e.a, st);
+  c->events.push_back(e);
+}
+void prof_end(exofwd_ctx* c, hipStream_t st) {
+  if (!c->profiling || c->events.empty()) return;
+  hipEventRecord(c->events.back().b, st);
+}
+}  // namespace exofwd
+
+extern "C" {
+
+const char* exofwd_strerror(exofwd_status s) {
+  switch (s) {
+    case EXOFWD_OK: return "ok";
+    case EXOFWD_ERR_ARG: return "invalid argument";
+    case EXOFWD_ERR_SHAPE: return "shape mismatch";
+    case EXOFWD_ERR_CONFIG: return "invalid configuration";
+    case EXOFWD_ERR_NOMEM: return "device allocation failed";
+    case EXOFWD_ERR_DEVICE: return "HIP runtime error";
+    case EXOFWD_ERR_UNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+const char* exofwd_last_error(const exofwd_ctx* c) { return c ? c->err.c_str() : "null context"; }
+int32_t exofwd_num_params(const exofwd_ctx* c) { return c ? c->m.P : -1; }
+int32_t exofwd_num_nu(const exofwd_ctx* c) { return c ? c->m.n_nu : -1; }
+int32_t exofwd_num_bins(const exofwd_ctx* c) { return c ? c->m.K : -1; }
+int32_t exofwd_precision(const exofwd_ctx* c) { return c ? c->precision : -1; }
+int64_t exofwd_device_bytes(const exofwd_ctx* c) { return c ? c->bytes : -1; }
+
+exofwd_status exofwd_destroy(exofwd_ctx* c) {
+  if (!c) return EXOFWD_OK;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  for (auto& e : c->events) {
+    hipEventDestroy(e.a);
+    hipEventDestroy(e.b);
+  }
+  for (void* p : c->allocs) hipFree(p);
+  delete c;
+  return EXOFWD_OK;
+}
+
+exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
+  if (!out) return EXOFWD_ERR_ARG;
+  *out = nullptr;
+  if (!cfg) return EXOFWD_ERR_ARG;
+  // ---- validation (nothing touches the device before this passes)
+  const auto& g = *cfg;
+  if (g.mode != EXOFWD_TRANSMISSION && g.mode != EXOFWD_EMISSION) return EXOFWD_ERR_CONFIG;
+  if (g.precision != EXOFWD_PREC_FP64 && g.precision != EXOFWD_PREC_MIXED) return EXOFWD_ERR_CONFIG;
+  if (g.tp_kind < 0 || g.tp_kind > 2) return EXOFWD_ERR_CONFIG;
+  if (g.tp_kind == EXOFWD_TP_PCHIP && (g.n_knots < 2 || g.n_knots > kMaxKnots)) return EXOFWD_ERR_CONFIG;
+  if (g.n_species < 1 || g.n_species > kMaxSpecies) return EXOFWD_ERR_CONFIG;
+  if (g.n_layers_max < 1 || g.n_layers_max > kMaxLayers) return EXOFWD_ERR_CONFIG;
+  if (g.batch_max < 1) return EXOFWD_ERR_CONFIG;
+  if (g.n_nu < 1 || !g.nu || !ascending(g.nu, g.n_nu) || !(g.nu[0] > 0.0)) return EXOFWD_ERR_CONFIG;
+  if (g.n_t < 2 || g.n_t > 255 || g.n_p < 2 || g.n_p > 255 || !g.t_grid || !g.logp_grid || !g.log10_xsec)
+    return EXOFWD_ERR_CONFIG;
+  if (!ascending(g.t_grid, g.n_t) || !ascending(g.logp_grid, g.n_p)) return EXOFWD_ERR_CONFIG;
+  if (g.has_cia && (g.n_tc < 2 || g.n_tc > 255 || !g.tc_grid || !g.log10_cia || !ascending(g.tc_grid, g.n_tc)))
+    return EXOFWD_ERR_CONFIG;
+  if (!(g.mu_fixed > 0.0) && !g.species_mass) return EXOFWD_ERR_CONFIG;
+  if (g.n_bins < 1 || !g.bin_lo || !g.bin_hi || !g.y_obs || !g.y_err) return EXOFWD_ERR_CONFIG;
+  for (int k = 0; k < g.n_bins; ++k)
+    if (g.bin_lo[k] < 0 || g.bin_hi[k] > g.n_nu || g.bin_lo[k] >= g.bin_hi[k] || !(g.y_err[k] > 0.0))
+      return EXOFWD_ERR_CONFIG;
+  if (!(g.p_bot_bar > g.p_top_bar) || !(g.p_top_bar > 0.0) || !(g.p_ref_bar > 0.0)) return EXOFWD_ERR_CONFIG;
+  if (!(g.r_p > 0.0) || !(g.r_s > 0.0) || !(g.g_ref > 0.0)) return EXOFWD_ERR_CONFIG;
+  if (g.mode == EXOFWD_EMISSION && (g.n_mu < 1 || g.n_mu > kMaxMu || !(g.t_star > 0.0))) return EXOFWD_ERR_CONFIG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || g.device < 0 || g.device >= ndev) return EXOFWD_ERR_DEVICE;
+
+  auto* c = new exofwd_ctx();
+  c->precision = g.precision;
+  c->device = g.device;
+  c->batch_max = g.batch_max;
+  if (hipSetDevice(g.device) != hipSuccess) {
+    delete c;
+    return EXOFWD_ERR_DEVICE;
+  }
+  Model& m = c->m;
+  m.mode = g.mode;
+  m.tp_kind = g.tp_kind;
+  m.n_knots = g.tp_kind == EXOFWD_TP_PCHIP ? g.n_knots : 0;
+  m.S = g.n_species;
+  m.L_max = g.n_layers_max;
+  m.L_pad = (g.n_layers_max + 31) / 32 * 32;
+  m.has_cia = g.has_cia ? 1 : 0;
+  m.has_ray = g.has_rayleigh ? 1 : 0;
+  m.has_cloud = g.has_cloud ? 1 : 0;
+  m.has_scale = g.has_scale ? 1 : 0;
+  m.has_offset = g.has_offset ? 1 : 0;
+  m.n_mu = g.mode == EXOFWD_EMISSION ? g.n_mu : 0;
+  m.n_nu = g.n_nu;
+  m.n_nu_pad = (g.n_nu + kTileNu - 1) / kTileNu * kTileNu;
+  m.n_tiles = m.n_nu_pad / kTileNu;
+  m.n_t = g.n_t;
+  m.n_p = g.n_p;
+  m.n_tc = g.has_cia ? g.n_tc : 2;
+  m.K = g.n_bins;
+  m.n_tp = g.tp_kind == EXOFWD_TP_ISOTHERMAL ? 1 : (g.tp_kind == EXOFWD_TP_GUILLOT3 ? 3 : g.n_knots);
+  int k = m.n_tp + m.S;
+  m.idx_cloud = m.has_cloud ? k++ : -1;
+  m.idx_scale = m.has_scale ? k++ : -1;
+  m.idx_offset = m.has_offset ? k++ : -1;
+  m.P = k;
+  m.mu_fixed = g.mu_fixed;
+  m.log10_pbot = std::log10(g.p_bot_bar);
+  m.log10_ptop = std::log10(g.p_top_bar);
+  m.p_ref = g.p_ref_bar * kBar;
+  m.r_p = g.r_p;
+  m.r_s = g.r_s;
+  m.g_ref = g.g_ref;
+  m.kappa_ir = g.kappa_ir;
+  m.f_hem = g.f_hem;
+  m.kappa_cloud = g.kappa_cloud;
+  m.t_star = g.t_star;
+  m.dilution = g.dilution;
+  m.err_c = g.err_c;
+  m.ray_h2 = g.ray_h2;
+  m.ray_he = g.ray_he;
+  for (int s = 0; s < m.S; ++s) m.mass[s] = g.species_mass ? g.species_mass[s] : 0.0;
+  if (m.n_mu > 0) {
+    double x[kMaxMu], wg[kMaxMu];
+    gauss_legendre(m.n_mu, x, wg);
+    for (int i = 0; i < m.n_mu; ++i) {
+      m.mu_nodes[i] = 0.5 * (x[i] + 1.0);
+      m.mu_weights[i] = 0.5 * wg[i];
+    }
+  }
+
+  const bool fp64 = g.precision == EXOFWD_PREC_FP64;
+  const int Lp = m.L_pad, B = g.batch_max, RL = rec_len(m.S);
+  const size_t np = (size_t)m.n_nu_pad;
+  bool ok = true;
+  auto A = [&](auto* p) { ok = ok && p != nullptr; return p; };
+
+  // ---- grids and spectral axis
+  double* d_t = A(dalloc<double>(c, m.n_t));
+  double* d_p = A(dalloc<double>(c, m.n_p));
+  double* d_tc = A(dalloc<double>(c, m.n_tc));
+  double* d_nu = A(dalloc<double>(c, np));
+  if (!ok) { exofwd_destroy(c); return EXOFWD_ERR_NOMEM; }
+  std::vector<double> nu_pad(np, g.nu[g.n_nu - 1]);
+  std::memcpy(nu_pad.data(), g.nu, sizeof(double) * g.n_nu);
+  std::vector<double> tc(m.n_tc, 0.0);
+  if (m.has_cia) std::memcpy(tc.data(), g.tc_grid, sizeof(double) * m.n_tc);
+  else { tc[0] = 0.0; tc[1] = 1.0; }
+  ok = upload(d_t, g.t_grid, m.n_t) && upload(d_p, g.logp_grid, m.n_p) && upload(d_tc, tc.data(), m.n_tc) &&
+       upload(d_nu, nu_pad.data(), np);
+  m.t_grid = d_t;
+  m.logp_grid = d_p;
+  m.tc_grid = d_tc;
+  m.nu = d_nu;
+
+  // ---- tables
+  std::vector<double> nu4(np);
+  for (size_t i = 0; i < np; ++i) nu4[i] = std::pow(nu_pad[i] / 1.0e4, 4);
+  const int rows = m.n_t * m.n_p;
+  if (fp64) {
+    std::vector<double> t64((size_t)m.S * rows * np, -1000.0);
+    for (int s = 0; s < m.S; ++s)
+      for (int r = 0; r < rows; ++r)
+        std::memcpy(&t64[((size_t)s * rows + r) * np], g.log10_xsec + ((size_t)s * rows + r) * g.n_nu,
+                    sizeof(double) * g.n_nu);
+    double* d64 = A(dalloc<double>(c, t64.size()));
+    double* dn4 = A(dalloc<double>(c, np));
+    if (ok) ok = upload(d64, t64.data(), t64.size()) && upload(dn4, nu4.data(), np);
+    c->tb.t64 = d64;
+    c->tb.nu4d = dn4;
+    if (m.has_cia) {
+      std::vector<double> c64((size_t)2 * m.n_tc * np, -1000.0);
+      for (int r = 0; r < 2 * m.n_tc; ++r)
+        std::memcpy(&c64[(size_t)r * np], g.log10_cia + (size_t)r * g.n_nu, sizeof(double) * g.n_nu);
+      double* dc = A(dalloc<double>(c, c64.size()));
+      if (ok) ok = upload(dc, c64.data(), c64.size());
+      c->tb.tc64 = dc;
+    }
+  } else {
+    std::vector<_Float16> h;
+    std::vector<float> off;
+    encode_fp16(g.log10_xsec, m.S, rows, g.n_nu, (int)np, h, off);
+    uint16_t* dh = A(dalloc<uint16_t>(c, h.size()));
+    float* dc = A(dalloc<float>(c, off.size()));
+    float* dn4 = A(dalloc<float>(c, np));
+    std::vector<float> nu4f(np);
+    for (size_t i = 0; i < np; ++i) nu4f[i] = (float)nu4[i];
+    if (ok)
+      ok = upload(dh, reinterpret_cast<const uint16_t*>(h.data()), h.size()) && upload(dc, off.data(), off.size()) &&
+           upload(dn4, nu4f.data(), np);
+    c->tb.h = dh;
+    c->tb.c = dc;
+    c->tb.nu4f = dn4;
+    if (m.has_cia) {
+      encode_fp16(g.log10_cia, 2, m.n_tc, g.n_nu, (int)np, h, off);
+      uint16_t* dhc = A(dalloc<uint16_t>(c, h.size()));
+      float* dcc = A(dalloc<float>(c, off.size()));
+      if (ok) ok = upload(dhc, reinterpret_cast<const uint16_t*>(h.data()), h.size()) && upload(dcc, off.data(), off.size());
+      c->tb.hc = dhc;
+      c->tb.cc = dcc;
+    }
+  }
+
+  // ---- bins and data
+  c->d_lo = A(dalloc<int32_t>(c, m.K));
+  c->d_hi = A(dalloc<int32_t>(c, m.K));
+  c->d_y = A(dalloc<double>(c, m.K));
+  c->d_yerr = A(dalloc<double>(c, m.K));
+  c->d_mask = A(dalloc<uint8_t>(c, m.K));
+  if (ok) {
+    std::vector<uint8_t> mask(m.K, 0);
+    if (g.offset_mask) std::memcpy(mask.data(), g.offset_mask, m.K);
+    ok = upload(c->d_lo, g.bin_lo, m.K) && upload(c->d_hi, g.bin_hi, m.K) && upload(c->d_y, g.y_obs, m.K) &&
+         upload(c->d_yerr, g.y_err, m.K) && upload(c->d_mask, mask.data(), m.K);
+  }
+
+  // ---- workspace
+  Work& w = c->w;
+  const size_t rs = fp64 ? 8 : 4;
+  w.status = A(dalloc<int32_t>(c, B));
+  w.nlay = A(dalloc<int32_t>(c, B));
+  w.t_lay = A(dalloc<double>(c, (size_t)B * Lp));
+  w.t_lev = A(dalloc<double>(c, (size_t)B * (Lp + 1)));
+  w.r_lev = A(dalloc<double>(c, (size_t)B * (Lp + 1)));
+  w.core = A(dalloc<double>(c, B));
+  w.cells = A(dalloc<int32_t>(c, (size_t)B * Lp));
+  w.rec = A(dalloc<unsigned char>(c, (size_t)B * Lp * RL * rs));
+  w.area = A(dalloc<unsigned char>(c, (size_t)B * Lp * rs));
+  if (m.mode == kTransmission) {
+    if (fp64) {
+      w.pm64 = A(dalloc<double>(c, (size_t)B * Lp * Lp));
+    } else {
+      const size_t plane = (size_t)(Lp / 32) * (Lp / 16) * 512;
+      w.pfrag = A(dalloc<uint16_t>(c, (size_t)B * 2 * plane));
+      w.ptfrag = A(dalloc<uint16_t>(c, (size_t)B * 2 * plane));
+    }
+  }
+  w.spec = A(dalloc<unsigned char>(c, (size_t)B * m.n_nu * rs));
+  w.dm = A(dalloc<double>(c, (size_t)B * m.K));
+  w.lnl_tmp = A(dalloc<double>(c, B));
+  if (ok && m.mode == kTransmission) ok = adjoint_alloc(c->aw, m, B, fp64, [&](size_t bytes) {
+    return (void*)dalloc<unsigned char>(c, bytes);
+  });
+  if (!ok) {
+    exofwd_destroy(c);
+    return EXOFWD_ERR_NOMEM;
+  }
+  hipError_t e = m.mode == kTransmission ? trans_fwd_configure(m, fp64) : emission_configure(m, fp64);
+  if (e == hipSuccess && m.mode == kTransmission) e = adjoint_configure(m, fp64);
+  if (e != hipSuccess) {
+    exofwd_destroy(c);
+    return EXOFWD_ERR_DEVICE;
+  }
+  if (hipDeviceSynchronize() != hipSuccess) {
+    exofwd_destroy(c);
+    return EXOFWD_ERR_DEVICE;
+  }
+  *out = c;
+  return EXOFWD_OK;
+}
+
+static exofwd_status check_call(exofwd_ctx* c, int32_t B, const double* params) {
+  if (!c) return EXOFWD_ERR_ARG;
+  if (B < 1 || B > c->batch_max) return fail(c, EXOFWD_ERR_SHAPE, "B outside [1, batch_max]");
+  if (!params) return fail(c, EXOFWD_ERR_ARG, "params is NULL");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, EXOFWD_ERR_DEVICE, "hipSetDevice failed");
+  c->err.clear();
+  return EXOFWD_OK;
+}
+
+exofwd_status exofwd_forward(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers, void* spectra,
+                             double* lnL, int32_t* status, void* hip_stream) {
+  exofwd_status s = check_call(c, B, params);
+  if (s) return s;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const bool fp64 = c->precision == EXOFWD_PREC_FP64;
+  void* spec = spectra ? spectra : c->w.spec;
+  prof_begin(c, "profile", st);
+  launch_profile(c->m, c->w, B, params, n_layers, fp64, st);
+  prof_end(c, st);
+  if ((s = check_hip(c, hipGetLastError(), "profile launch"))) return s;
+  if (c->m.mode == kTransmission) {
+    prof_begin(c, "trans_fwd", st);
+    launch_trans_fwd(c->m, c->w, c->tb, B, spec, fp64, st);
+  } else {
+    prof_begin(c, "emis_fwd", st);
+    launch_emission(c->m, c->w, c->tb, B, spec, fp64, st);
+  }
+  prof_end(c, st);
+  if ((s = check_hip(c, hipGetLastError(), "spectrum launch"))) return s;
+  prof_begin(c, "loglike", st);
+  launch_loglike(c->m, c->w, B, params, spec, fp64, c->d_lo, c->d_hi, c->d_y, c->d_yerr,
+                 c->m.has_offset ? c->d_mask : nullptr, lnL, status, st);
+  prof_end(c, st);
+  return check_hip(c, hipGetLastError(), "loglike launch");
+}
+
+exofwd_status exofwd_grad(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers, void* spectra,
+                          double* lnL, double* grad, int32_t* status, void* hip_stream) {
+  exofwd_status s = check_call(c, B, params);
+  if (s) return s;
+  if (!lnL || !grad) return fail(c, EXOFWD_ERR_ARG, "lnL and grad are required");
+  if (c->m.mode != kTransmission) return fail(c, EXOFWD_ERR_UNSUPPORTED, "the adjoint covers transmission only");
+  if (!adjoint_ready()) return fail(c, EXOFWD_ERR_UNSUPPORTED, "adjoint not available in this build");
+  if ((s = exofwd_forward(c, B, params, n_layers, spectra, lnL, status, hip_stream))) return s;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const bool fp64 = c->precision == EXOFWD_PREC_FP64;
+  prof_begin(c, "trans_adj", st);
+  launch_trans_adjoint(c->m, c->w, c->tb, c->aw, B, fp64, st);
+  prof_end(c, st);
+  if ((s = check_hip(c, hipGetLastError(), "adjoint launch"))) return s;
+  prof_begin(c, "chain", st);
+  launch_chain(c->m, c->w, c->aw, B, params, c->d_mask, grad, fp64, st);
+  prof_end(c, st);
+  return check_hip(c, hipGetLastError(), "chain launch");
+}
+
+exofwd_status exofwd_set_profiling(exofwd_ctx* c, int32_t enable) {
+  if (!c) return EXOFWD_ERR_ARG;
+  hipSetDevice(c->device);
+  for (auto& e : c->events) {
+    hipEventSynchronize(e.b);
+    hipEventDestroy(e.a);
+    hipEventDestroy(e.b);
+  }
+  c->events.clear();
+  c->profiling = enable != 0;
+  return EXOFWD_OK;
+}
+
+exofwd_status exofwd_kernel_time(exofwd_ctx* c, const char* name, double* total_ms, int32_t* launches) {
+  if (!c || !name || !total_ms || !launches) return EXOFWD_ERR_ARG;
+  double tot = 0.0;
+  int n = 0;
+  for (auto& e : c->events) {
+    if (e.name != name) continue;
+    if (hipEventSynchronize(e.b) != hipSuccess) return fail(c, EXOFWD_ERR_DEVICE, "event sync failed");
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess) return fail(c, EXOFWD_ERR_DEVICE, "elapsed time failed");
+    tot += ms;
+    ++n;
+  }
+  *total_ms = tot;
+  *launches = n;
+  return EXOFWD_OK;
+}
+
+exofwd_status exofwd_autotune(exofwd_ctx* c, int32_t B, const char* cache_path) {
+  if (!c) return EXOFWD_ERR_ARG;
+  (void)B;
+  (void)cache_path;
+  return fail(c, EXOFWD_ERR_UNSUPPORTED, "autotuning is not built yet");
+}
+
+}  // extern "C"

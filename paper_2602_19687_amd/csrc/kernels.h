@@ -1,0 +1,27 @@
+// Launch entry points of the gfx950 kernels (host side of each .hip file).
+#pragma once
+#include "common.h"
+
+namespace exofwd {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+// block id -> logical id such that consecutive logical ids share an XCD
+// (the dispatcher deals workgroups round-robin over the 8 XCDs)
+__device__ inline int xcd_logical_block(int bid, int nblk) {
+  if ((nblk & 7) != 0) return bid;
+  return (bid & 7) * (nblk >> 3) + (bid >> 3);
+}
+
+void launch_profile(const Model& m, const Work& w, int B, const double* params, const int32_t* n_layers,
+                    bool fp64, hipStream_t st);
+void launch_trans_fwd(const Model& m, const Work& w, const Tables& tb, int B, void* spec, bool fp64,
+                      hipStream_t st);
+void launch_loglike(const Model& m, const Work& w, int B, const double* params, const void* spec, bool spec_f64,
+                    const int32_t* bin_lo, const int32_t* bin_hi, const double* y, const double* yerr,
+                    const uint8_t* mask, double* lnl, int32_t* status_out, hipStream_t st);
+size_t trans_fwd_lds_bytes(const Model& m, bool fp64);
+hipError_t trans_fwd_configure(const Model& m, bool fp64);
+
+}  // namespace exofwd

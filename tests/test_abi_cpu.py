@@ -1,0 +1,67 @@
+"""The C-ABI library builds, loads and exports every symbol its header declares;
+host-side validation rejects bad input before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2602_19687_amd as pkg
+from paper_2602_19687_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "exofwd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(exofwd_[a-z_]+)\s*\(", src)))
+
+
+def test_header_functions_all_exported():
+    lib = pkg.load()
+    names = header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTS), set(names) ^ set(L.EXPORTS)
+
+
+def test_config_struct_matches_header_layout(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "exofwd.h"\n'
+                   'int main(){printf("%zu %zu %zu %zu",sizeof(exofwd_config),offsetof(exofwd_config,nu),'
+                   'offsetof(exofwd_config,n_bins),offsetof(exofwd_config,device));}')
+    exe = tmp_path / "sz"
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    assert [int(x) for x in out] == [C.sizeof(L.Config), L.Config.nu.offset, L.Config.n_bins.offset,
+                                     L.Config.device.offset]
+
+
+def test_create_rejects_bad_config_without_device():
+    lib = pkg.load()
+    ctx = C.c_void_p()
+    assert lib.exofwd_create(None, C.byref(ctx)) == L.ERR_ARG
+    cfg = L.Config()                      # all zero: invalid mode-independent fields
+    assert lib.exofwd_create(C.byref(cfg), C.byref(ctx)) == L.ERR_CONFIG
+    assert ctx.value is None
+
+
+def test_null_context_calls():
+    lib = pkg.load()
+    assert lib.exofwd_num_params(None) == -1
+    assert lib.exofwd_forward(None, 1, None, None, None, None, None, None) == L.ERR_ARG
+    assert lib.exofwd_destroy(None) == L.OK
+    assert lib.exofwd_strerror(L.ERR_UNSUPPORTED) == b"unsupported request"
+
+
+def test_product_path_fails_loudly_without_library(tmp_path):
+    with pytest.raises(RuntimeError, match="missing"):
+        L._lib = None
+        try:
+            L.load(str(tmp_path / "nope.so"))
+        finally:
+            L._lib = None
+            L.load()
