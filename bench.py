@@ -1,0 +1,194 @@
+"""Benchmark: batched transmission forward model + adjoint on one MI355X.
+
+Workload: JWST-like transmission (6 absorbers x 20 T x 20 log p x 30000
+wavenumbers, 100 layers, reduced Guillot profile, CIA, Rayleigh, grey cloud,
+400 bins, 12 parameters) at B = 1024 parameter samples per step.  A step is
+one call of the whole hot path (profile, fused opacity + chord + transit depth,
+likelihood, and the adjoint to d lnL / d params) on inputs already resident in
+HBM.  The reduced-precision path (FP16 tables, FP32 opacity, bf16x3 MFMA chord,
+FP64 profile and likelihood) is the measured value; the plain FP64 path is
+timed beside it, and the FP64 oracle on the host cores gives the CPU baseline.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# vector FP32 peak without packed math: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz lane-ops/s
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def algorithmic_bytes_per_sample(L, S, n_nu, b_tab, b_out):
+    """Table entries the method must gather per sample (4 bilinear corners per
+    layer, species and wavenumber; 2 T corners for each of 2 CIA pairs), the
+    Rayleigh axis and the output spectrum."""
+    return (4 * L * S * n_nu + 4 * L * n_nu) * b_tab + 2 * n_nu * 4 + n_nu * b_out
+
+
+_WL = {}
+
+
+def _oracle_init(cid, batch):
+    os.environ["OMP_NUM_THREADS"] = "1"
+    import synth
+    _WL["wl"] = synth.workload(cid, batch=batch)
+
+
+def _oracle_worker(args):
+    idx, do_grad = args
+    import oracle
+    wl = _WL["wl"]
+    th = wl["params"][idx]
+    t0 = time.perf_counter()
+    out = oracle.forward(wl, th)
+    g = oracle.grad_complex_step(wl, th) if do_grad else None
+    return idx, out["spectrum"], out["lnL"], g, time.perf_counter() - t0
+
+
+def cpu_baseline(cid, batch, n_samples, do_grad):
+    """Time the FP64 oracle, as it stands, on a bounded sample of the workload on
+    the host cores: one sample per task, one BLAS thread per worker process;
+    throughput = samples / (summed per-sample seconds / workers)."""
+    cores = min(16, os.cpu_count() or 1)
+    idx = list(range(0, batch, max(1, batch // n_samples)))[:n_samples]
+    workers = min(cores, len(idx))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers, initializer=_oracle_init, initargs=(cid, batch)) as pool:
+        res = pool.map(_oracle_worker, [(i, do_grad) for i in idx], chunksize=1)
+    busy = sum(r[4] for r in res)
+    return [r[:4] for r in res], busy / workers, workers
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--cpu-samples", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the path shards by samples with no exchange, "
+              "and multi-GPU runs are not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2602_19687_amd import ForwardModel
+    from paper_2602_19687_amd import _lib as L
+
+    cid, B = 1, args.batch
+    t_setup = time.perf_counter()
+    wl = synth.workload(cid, batch=B)
+    L_, S, n_nu = wl["n_layers"], wl["n_species"], len(wl["nu"])
+    th = torch.tensor(wl["params"], dtype=torch.float64, device="cuda")
+    print(f"[bench] workload ready in {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
+
+    def run(prec, steps, warmup):
+        fm = ForwardModel(wl, precision=prec, batch_max=B)
+        try:
+            fm.grad(th[:1])
+            has_grad = True
+        except L.ExoError:
+            has_grad = False
+        step = (lambda: fm.grad(th)) if has_grad else (lambda: fm.forward(th, want_spectra=False))
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        fm.set_profiling(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kern = {k: fm.kernel_time(k) for k in ("profile", "trans_fwd", "loglike", "trans_adj", "chain")}
+        fm.set_profiling(False)
+        spec, lnl, status = fm.forward(th)
+        torch.cuda.synchronize()
+        res = dict(ms_per_step=dt / steps * 1e3, has_grad=has_grad, kernels=kern,
+                   spec=spec.double().cpu().numpy(), lnl=lnl.cpu().numpy(), status=status.cpu().numpy(),
+                   grad=out[1].cpu().numpy() if has_grad else None, bytes=fm.device_bytes())
+        fm.close()
+        return res
+
+    mixed = run("mixed", args.steps, args.warmup)
+    print(f"[bench] mixed {mixed['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+    fp64 = None
+    if not args.no_fp64:
+        fp64 = run("fp64", max(2, args.steps // 4), 1)
+        print(f"[bench] fp64 {fp64['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+
+    value = B / (mixed["ms_per_step"] / 1e3)
+    # dominant kernel: fused forward (plus the fused adjoint when present)
+    names = ["trans_fwd"] + (["trans_adj"] if mixed["has_grad"] else [])
+    ms = sum(mixed["kernels"][n][0] for n in names)
+    launches = mixed["kernels"]["trans_fwd"][1]
+    per_launch_ms = ms / max(1, launches)
+    alg_bytes = algorithmic_bytes_per_sample(L_, S, n_nu, 2, 4) * B
+    achieved_gbs = alg_bytes / (per_launch_ms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "+".join(names), "kernel_ms": round(per_launch_ms, 4),
+                "algorithmic_bytes_per_launch": alg_bytes}
+
+    out = {
+        "metric": "forward+grad spectra/sec at B=1024 (FP32/FP16 vs FP64 plain), max rel err"
+        if mixed["has_grad"] else "forward spectra/sec at B=1024 (FP32/FP16 vs FP64 plain), max rel err",
+        "value": round(value, 1), "unit": "spectra/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(mixed["ms_per_step"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "jwst-like transmission, 6 absorbers, 20x20x30000 FP16 tables, 100 layers, "
+                               "400 bins, 12 params", "batch": B, "n_nu": n_nu, "n_layers": L_, "n_species": S,
+                   "precision": "fp16 tables / fp32 opacity / bf16x3 mfma chord / fp64 profile+lnL"},
+        "roofline": roofline,
+        "kernel_ms_per_step": {k: round(v[0] / max(1, v[1]), 4) for k, v in mixed["kernels"].items() if v[1]},
+    }
+    if fp64 is not None:
+        out["fp64_plain"] = {"spectra_per_s": round(B / (fp64["ms_per_step"] / 1e3), 1),
+                             "ms_per_step": round(fp64["ms_per_step"], 3),
+                             "kernel_ms_per_step": {k: round(v[0] / max(1, v[1]), 4)
+                                                    for k, v in fp64["kernels"].items() if v[1]}}
+        out["speedup_vs_fp64"] = round(fp64["ms_per_step"] / mixed["ms_per_step"], 3)
+        ok = (mixed["status"] == 0) & (fp64["status"] == 0)
+        out["max_rel_err_vs_fp64_gpu"] = float(np.max(np.abs(mixed["spec"][ok] - fp64["spec"][ok])
+                                                      / np.abs(fp64["spec"][ok])))
+    if not args.no_cpu_baseline:
+        res, dt, cores = cpu_baseline(cid, B, args.cpu_samples, mixed["has_grad"])
+        n = len(res)
+        errs, lerrs, gerrs = [], [], []
+        for idx, spec, lnl, g in res:
+            if not np.all(np.isfinite(spec)):
+                continue
+            errs.append(float(np.max(np.abs(mixed["spec"][idx] - spec) / np.abs(spec))))
+            lerrs.append(abs(mixed["lnl"][idx] - lnl) / abs(lnl))
+            if g is not None and mixed["grad"] is not None:
+                gm = mixed["grad"][idx]
+                scale = np.maximum(np.abs(g), 1e-3 * np.max(np.abs(g)))
+                gerrs.append(float(np.max(np.abs(gm - g) / scale)))
+        out["cpu_baseline"] = {"value": round(n / dt, 4), "unit": "spectra/s", "cores": cores, "kind": "oracle",
+                               "sample": f"{n} of the {B} samples (every {B // n}th), FP64 oracle forward"
+                                         + (" + complex-step gradient" if mixed["has_grad"] else "")
+                                         + f", {cores} worker processes, {dt:.1f} s per worker"}
+        out["max_rel_err"] = {"spectrum": max(errs) if errs else None, "lnL": float(max(lerrs)) if lerrs else None,
+                              "grad": max(gerrs) if gerrs else None, "samples": len(errs)}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -21,8 +21,10 @@ constexpr int kMaxSpecies = 8;
 constexpr int kMaxLayers = 160;   // L_max; padded layer count is a multiple of 32
 constexpr int kMaxKnots = 8;
 constexpr int kMaxMu = 8;
-constexpr int kTileNu = 64;       // wavenumbers per tile of the fused kernels
+constexpr int kTileNu = 128;      // wavenumbers per tile of the reduced-precision transmission kernels
+constexpr int kTile64 = 64;       // wavenumbers per tile of the FP64 and emission kernels
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
+constexpr int kBlockT = 512;      // threads per workgroup of the reduced-precision transmission kernels
 
 // per-layer record of the opacity kernels (one per sample and layer)
 //   [0] wT, [1] wP, [2] wTc, [3] Rayleigh coefficient R_l (x (nu/1e4)^4),
@@ -43,7 +45,7 @@ enum : int { kBadVmr = 1, kUnbound = 2, kNonfinite = 4, kBadT = 8, kBadLayers = 
 struct Model {
   int mode, tp_kind, n_knots, S, L_max, L_pad, P;
   int has_cia, has_ray, has_cloud, has_scale, has_offset, n_mu;
-  int n_nu, n_nu_pad, n_tiles, n_t, n_p, n_tc, K;
+  int n_nu, n_nu_pad, n_tiles, n_tiles64, n_t, n_p, n_tc, K;
   int idx_cloud, idx_scale, idx_offset, n_tp;
   double mu_fixed, log10_pbot, log10_ptop, p_ref, r_p, r_s, g_ref;
   double kappa_ir, f_hem, kappa_cloud, t_star, dilution, err_c, ray_h2, ray_he;

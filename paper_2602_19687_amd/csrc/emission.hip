@@ -90,16 +90,16 @@ __global__ __launch_bounds__(kBlock) void k_emission(Model m, Work w, Tables tb,
   const int b = logical % B, tile = logical / B;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int Lp = m.L_pad;
-  const int nu0 = tile * kTileNu;
+  const int nu0 = tile * kTile64;
   Real* out = spec + (size_t)b * m.n_nu;
   if (w.status[b]) {
-    if (tid < kTileNu && nu0 + tid < m.n_nu) out[nu0 + tid] = Real(NAN);
+    if (tid < kTile64 && nu0 + tid < m.n_nu) out[nu0 + tid] = Real(NAN);
     return;
   }
   const int L = w.nlay[b];
   Real* s_dt = reinterpret_cast<Real*>(lds);          // [Lp][64]
-  Real* s_b = s_dt + (size_t)Lp * kTileNu;            // [Lp+1][64] Planck at levels
-  Real* s_f = s_b + (size_t)(Lp + 1) * kTileNu;       // [4][64] flux partials
+  Real* s_b = s_dt + (size_t)Lp * kTile64;            // [Lp+1][64] Planck at levels
+  Real* s_f = s_b + (size_t)(Lp + 1) * kTile64;       // [4][64] flux partials
   const int RL = rec_len(m.S);
   const Real* rec = reinterpret_cast<const Real*>(w.rec) + (size_t)b * Lp * RL;
   const int32_t* cells = w.cells + (size_t)b * Lp;
@@ -113,11 +113,11 @@ __global__ __launch_bounds__(kBlock) void k_emission(Model m, Work w, Tables tb,
       ccs[0] = tb.cc[nu];
       ccs[1] = tb.cc[(size_t)m.n_nu_pad + nu];
     }
-    for (int l = wv; l < L; l += 4) s_dt[l * kTileNu + lane] = opacity_mixed_e(m, tb, cells[l], rec + (size_t)l * RL, nu, cs, ccs);
+    for (int l = wv; l < L; l += 4) s_dt[l * kTile64 + lane] = opacity_mixed_e(m, tb, cells[l], rec + (size_t)l * RL, nu, cs, ccs);
   } else {
-    for (int l = wv; l < L; l += 4) s_dt[l * kTileNu + lane] = opacity_fp64_e(m, tb, cells[l], rec + (size_t)l * RL, nu);
+    for (int l = wv; l < L; l += 4) s_dt[l * kTile64 + lane] = opacity_fp64_e(m, tb, cells[l], rec + (size_t)l * RL, nu);
   }
-  for (int j = wv; j <= L; j += 4) s_b[j * kTileNu + lane] = planck<Real>(Real(t_lev[j]), nuv);
+  for (int j = wv; j <= L; j += 4) s_b[j * kTile64 + lane] = planck<Real>(Real(t_lev[j]), nuv);
   __syncthreads();
 
   // upward sweep, one (wavenumber, angle) per thread
@@ -127,18 +127,18 @@ __global__ __launch_bounds__(kBlock) void k_emission(Model m, Work w, Tables tb,
     const Real inv_mu = Real(1) / mu;
     Real inten = s_b[lane];
     for (int l = 0; l < L; ++l) {
-      const Real x = s_dt[l * kTileNu + lane] * inv_mu;
+      const Real x = s_dt[l * kTile64 + lane] * inv_mu;
       Real e;
       if constexpr (sizeof(Real) == 8) e = exp(-x); else e = __expf(-x);
-      const Real bb = s_b[l * kTileNu + lane], bt = s_b[(l + 1) * kTileNu + lane];
+      const Real bb = s_b[l * kTile64 + lane], bt = s_b[(l + 1) * kTile64 + lane];
       inten = inten * e + bt * (Real(1) - e) + (bb - bt) * lin_source<Real>(x, e);
     }
     flux += Real(2.0 * M_PI * m.mu_weights[k]) * mu * inten;
   }
-  s_f[wv * kTileNu + lane] = flux;
+  s_f[wv * kTile64 + lane] = flux;
   __syncthreads();
-  if (tid < kTileNu && nu0 + tid < m.n_nu) {
-    const Real f = (s_f[tid] + s_f[kTileNu + tid]) + (s_f[2 * kTileNu + tid] + s_f[3 * kTileNu + tid]);
+  if (tid < kTile64 && nu0 + tid < m.n_nu) {
+    const Real f = (s_f[tid] + s_f[kTile64 + tid]) + (s_f[2 * kTile64 + tid] + s_f[3 * kTile64 + tid]);
     const Real fstar = Real(M_PI) * planck<Real>(Real(m.t_star), Real(m.nu[nu0 + tid]));
     out[nu0 + tid] = Real(m.dilution) * f / fstar * Real(w.core[b]);
   }
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_emission(Model m, Work w, Tables tb,
 
 size_t emission_lds_bytes(const Model& m, bool fp64) {
   const size_t rs = fp64 ? 8 : 4;
-  return rs * ((size_t)m.L_pad * kTileNu + (size_t)(m.L_pad + 1) * kTileNu + 4 * kTileNu);
+  return rs * ((size_t)m.L_pad * kTile64 + (size_t)(m.L_pad + 1) * kTile64 + 4 * kTile64);
 }
 
 hipError_t emission_configure(const Model& m, bool fp64) {
@@ -157,7 +157,7 @@ hipError_t emission_configure(const Model& m, bool fp64) {
 }
 
 void launch_emission(const Model& m, const Work& w, const Tables& tb, int B, void* spec, bool fp64, hipStream_t st) {
-  const dim3 grid((unsigned)(m.n_tiles * B));
+  const dim3 grid((unsigned)(m.n_tiles64 * B));
   const size_t lds = emission_lds_bytes(m, fp64);
   if (fp64)
     hipLaunchKernelGGL(k_emission<double>, grid, dim3(kBlock), lds, st, m, w, tb, B, (double*)spec);

@@ -228,6 +228,7 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   m.n_nu = g.n_nu;
   m.n_nu_pad = (g.n_nu + kTileNu - 1) / kTileNu * kTileNu;
   m.n_tiles = m.n_nu_pad / kTileNu;
+  m.n_tiles64 = m.n_nu_pad / kTile64;
   m.n_t = g.n_t;
   m.n_p = g.n_p;
   m.n_tc = g.has_cia ? g.n_tc : 2;

@@ -1,90 +1,45 @@
-// Fused transmission forward kernel: per (sample, 64-wavenumber tile) it
-// builds every layer's vertical optical depth from the interpolated
-// cross-section tables, forms the slant optical depth through the path matrix
-// (Eq. 44) and reduces it to the transit depth of each wavenumber.
+// Fused transmission forward kernels: per (sample, wavenumber tile) they build
+// every layer's vertical optical depth from the interpolated cross-section
+// tables, form the slant optical depth through the path matrix (Eq. 44) and
+// reduce it to the transit depth of each wavenumber.
 //
-// MIXED instance: FP16 log2-sigma tables with FP32 per-(species, nu) offsets,
-// FP32 opacity (one exp2 per layer, species and wavenumber), chord product on
+// Reduced-precision instance (512 threads, 128 wavenumbers per tile, two per
+// lane): FP16 log2-sigma tables read with scalar-offset buffer loads, FP32
+// opacity with one exp2 per layer, source and wavenumber, chord product on
 // v_mfma_f32_32x32x16_bf16 with a bf16 hi/lo split of both operands
 // (hi*hi + hi*lo + lo*hi, FP32 accumulation).
-// FP64 instance: FP64 tables and arithmetic, chord product on the FP64 VALU.
+// FP64 instance (256 threads, 64 wavenumbers per tile): FP64 tables and
+// arithmetic, chord product on the FP64 VALU.
 #include "kernels.h"
+#include "opacity.h"
 
 namespace exofwd {
 
-__device__ inline uint16_t bf16_bits_rn(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ inline float bf16_bits_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-// Opacity of one (layer, wavenumber) element, reduced-precision form:
-//   dtau = D + R nu4 + sum_s 2^(c_s + bilinear(h_s) + lam_s) + sum_pairs 2^(c_c + lerp_T(h_c) + lam_c)
-__device__ inline float opacity_mixed(const Model& m, const Tables& tb, int cells, const float* __restrict__ rl,
-                                      int nu, float nu4, const float* cs, const float* ccs) {
-  const int it = cells & 255, ip = (cells >> 8) & 255, itc = cells >> 16;
-  const float wt = rl[0], wp = rl[1];
-  const float w11 = wt * wp, w10 = wt - w11, w01 = wp - w11, w00 = 1.0f - wt - wp + w11;
-  const size_t npad = (size_t)m.n_nu_pad;
-  float acc = fmaf(rl[3], nu4, rl[4]);
-  const _Float16* __restrict__ h = reinterpret_cast<const _Float16*>(tb.h);
-  for (int s = 0; s < m.S; ++s) {
-    const _Float16* p = h + (((size_t)s * m.n_t + it) * m.n_p + ip) * npad + nu;
-    const float h00 = (float)p[0];
-    const float h01 = (float)p[npad];
-    const float h10 = (float)p[(size_t)m.n_p * npad];
-    const float h11 = (float)p[(size_t)(m.n_p + 1) * npad];
-    float v = cs[s] + rl[kRecFixed + s];
-    v = fmaf(w00, h00, v);
-    v = fmaf(w10, h10, v);
-    v = fmaf(w01, h01, v);
-    v = fmaf(w11, h11, v);
-    acc += exp2f(v);
-  }
-  if (m.has_cia) {
-    const float wtc = rl[2];
-    const _Float16* __restrict__ hc = reinterpret_cast<const _Float16*>(tb.hc);
-    for (int c = 0; c < 2; ++c) {
-      const _Float16* p = hc + ((size_t)c * m.n_tc + itc) * npad + nu;
-      float v = ccs[c] + rl[5 + c];
-      v = fmaf(1.0f - wtc, (float)p[0], v);
-      v = fmaf(wtc, (float)p[npad], v);
-      acc += exp2f(v);
+// Path-matrix A fragments: cost-balanced split of the 32-row blocks between the
+// two waves that share a 32-column block.
+__device__ inline unsigned mblocks_for(int part, int MBe, int KBe) {
+  unsigned mine = 0;
+  int c0 = 0, c1 = 0;
+  for (int mi = 0; mi < MBe; ++mi) {
+    const int cost = KBe - 2 * mi;
+    if (c0 <= c1) {
+      if (part == 0) mine |= 1u << mi;
+      c0 += cost;
+    } else {
+      if (part == 1) mine |= 1u << mi;
+      c1 += cost;
     }
   }
-  return fminf(acc, 16384.0f);
+  return mine;
 }
 
-// The same element in FP64 from log10-sigma tables.
-__device__ inline double opacity_fp64(const Model& m, const Tables& tb, int cells, const double* __restrict__ rl,
-                                      int nu, double nu4) {
-  const int it = cells & 255, ip = (cells >> 8) & 255, itc = cells >> 16;
-  const double wt = rl[0], wp = rl[1];
-  const size_t npad = (size_t)m.n_nu_pad;
-  double acc = rl[3] * nu4 + rl[4];
-  for (int s = 0; s < m.S; ++s) {
-    const double* p = tb.t64 + (((size_t)s * m.n_t + it) * m.n_p + ip) * npad + nu;
-    const double v = (1.0 - wt) * (1.0 - wp) * p[0] + wt * (1.0 - wp) * p[(size_t)m.n_p * npad] +
-                     (1.0 - wt) * wp * p[npad] + wt * wp * p[(size_t)(m.n_p + 1) * npad];
-    acc += exp2(v * kLog2_10 + rl[kRecFixed + s]);
-  }
-  if (m.has_cia) {
-    const double wtc = rl[2];
-    for (int c = 0; c < 2; ++c) {
-      const double* p = tb.tc64 + ((size_t)c * m.n_tc + itc) * npad + nu;
-      const double v = (1.0 - wtc) * p[0] + wtc * p[npad];
-      acc += exp2(v * kLog2_10 + rl[5 + c]);
-    }
-  }
-  return acc;
-}
-
-__global__ __launch_bounds__(kBlock) void k_trans_fwd_mixed(Model m, Work w, Tables tb, int B, float* __restrict__ spec) {
+template <int S, bool CIA>
+__global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Tables tb, int B, float* __restrict__ spec) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = logical % B, tile = logical / B;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int Lp = m.L_pad;
   const int nu0 = tile * kTileNu;
   float* out = spec + (size_t)b * m.n_nu;
@@ -93,67 +48,72 @@ __global__ __launch_bounds__(kBlock) void k_trans_fwd_mixed(Model m, Work w, Tab
     return;
   }
   const int L = w.nlay[b];
-  const int stride = Lp + 8;   // bf16 per wavenumber row of the B operand
+  const int stride = Lp + 8;   // bf16 per wavenumber row of the B operand (keeps b128 reads conflict-free)
   uint16_t* s_bhi = reinterpret_cast<uint16_t*>(lds);
   uint16_t* s_blo = s_bhi + kTileNu * stride;
   float* s_area = reinterpret_cast<float*>(s_blo + kTileNu * stride);
-  float* s_red = s_area + Lp;   // [4][32]
+  float* s_red = s_area + Lp;   // [8][32]
 
   const float* area = reinterpret_cast<const float*>(w.area) + (size_t)b * Lp;
-  for (int i = tid; i < Lp; i += kBlock) s_area[i] = area[i];
+  for (int i = tid; i < Lp; i += kBlockT) s_area[i] = area[i];
 
-  // phase A: vertical optical depth of every layer, bf16 hi/lo into LDS
-  const int RL = rec_len(m.S);
-  const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * RL;
+  // phase A: vertical optical depth of every layer -> bf16 hi/lo B operand in LDS
+  const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * rec_len(S);
   const int32_t* cells = w.cells + (size_t)b * Lp;
-  const int nu = nu0 + lane;
-  const float nu4 = tb.nu4f[nu];
-  float cs[kMaxSpecies], ccs[2];
-  for (int s = 0; s < m.S; ++s) cs[s] = tb.c[(size_t)s * m.n_nu_pad + nu];
-  ccs[0] = ccs[1] = 0.0f;
-  if (m.has_cia) {
-    ccs[0] = tb.cc[nu];
-    ccs[1] = tb.cc[(size_t)m.n_nu_pad + nu];
-  }
-  const int KBe = (L + 15) >> 4;   // K blocks of 16 layers that hold real layers
-  for (int o = wv; o < 2 * KBe; o += 4) {
-    uint16_t hv[8], lv[8];
-#pragma unroll
+  TableGeom g;
+  g.row_bytes = (uint32_t)m.n_nu_pad * 2u;
+  g.tstep = (uint32_t)m.n_p * g.row_bytes;
+  g.pstep = g.row_bytes;
+  const size_t npad = (size_t)m.n_nu_pad;
+  const __amdgpu_buffer_rsrc_t rh = make_rsrc(tb.h, (size_t)S * m.n_t * m.n_p * npad * 2);
+  const __amdgpu_buffer_rsrc_t rhc = make_rsrc(CIA ? (const void*)tb.hc : (const void*)tb.h,
+                                               CIA ? (size_t)2 * m.n_tc * npad * 2 : 0);
+  const uint32_t voff = (uint32_t)lane * 4u;
+  const LaneConst<S> kc = load_lane<S, CIA>(m, tb, nu0 + 2 * lane);
+  const int KBe = (L + 15) >> 4;
+  for (int o = wv; o < 2 * KBe; o += kBlockT / 64) {
+    uint16_t h0[8], l0[8], h1[8], l1[8];
+#pragma unroll 2
     for (int j = 0; j < 8; ++j) {
       const int l = 8 * o + j;
-      float dt = 0.0f;
-      if (l < L) dt = opacity_mixed(m, tb, cells[l], rec + (size_t)l * RL, nu, nu4, cs, ccs);
-      hv[j] = bf16_bits_rn(dt);
-      lv[j] = bf16_bits_rn(dt - bf16_bits_to_f(hv[j]));
+      float d0 = 0.0f, d1 = 0.0f;
+      if (l < L) {
+        const LayerCoef<S> c = load_layer<S>(m, cells, rec, l, (uint32_t)nu0 * 2u, g);
+        layer_terms<S, CIA, false>(c, kc, g, rh, rhc, voff, d0, d1);
+        d0 = fminf(d0, 16384.0f);
+        d1 = fminf(d1, 16384.0f);
+      }
+      h0[j] = bf16_bits_rn(d0);
+      l0[j] = bf16_bits_rn(d0 - bf16_bits_to_f(h0[j]));
+      h1[j] = bf16_bits_rn(d1);
+      l1[j] = bf16_bits_rn(d1 - bf16_bits_to_f(h1[j]));
     }
-    uint4 ph, pl;
-    ph.x = hv[0] | ((uint32_t)hv[1] << 16); ph.y = hv[2] | ((uint32_t)hv[3] << 16);
-    ph.z = hv[4] | ((uint32_t)hv[5] << 16); ph.w = hv[6] | ((uint32_t)hv[7] << 16);
-    pl.x = lv[0] | ((uint32_t)lv[1] << 16); pl.y = lv[2] | ((uint32_t)lv[3] << 16);
-    pl.z = lv[4] | ((uint32_t)lv[5] << 16); pl.w = lv[6] | ((uint32_t)lv[7] << 16);
-    *reinterpret_cast<uint4*>(s_bhi + lane * stride + 8 * o) = ph;
-    *reinterpret_cast<uint4*>(s_blo + lane * stride + 8 * o) = pl;
+    auto pack = [](const uint16_t* v) {
+      uint4 p;
+      p.x = v[0] | ((uint32_t)v[1] << 16);
+      p.y = v[2] | ((uint32_t)v[3] << 16);
+      p.z = v[4] | ((uint32_t)v[5] << 16);
+      p.w = v[6] | ((uint32_t)v[7] << 16);
+      return p;
+    };
+    const int r0 = (2 * lane) * stride + 8 * o, r1 = r0 + stride;
+    *reinterpret_cast<uint4*>(s_bhi + r0) = pack(h0);
+    *reinterpret_cast<uint4*>(s_blo + r0) = pack(l0);
+    *reinterpret_cast<uint4*>(s_bhi + r1) = pack(h1);
+    *reinterpret_cast<uint4*>(s_blo + r1) = pack(l1);
   }
   __syncthreads();
 
-  // phase B: tau = P dtau on MFMA; wave pair (wv >> 1) takes a cost-balanced set of
-  // 32-row blocks, wave parity (wv & 1) picks the 32-column half of the tile
+  // phase B: tau = P dtau on MFMA; wave wv owns 32-column block (wv & 3) and a
+  // cost-balanced half (wv >> 2) of the 32-row blocks
   const int MBe = (L + 31) >> 5;
   const int KB = Lp >> 4;
-  const int ni = wv & 1, pair = wv >> 1;
-  unsigned mine = 0;
-  {
-    int c0 = 0, c1 = 0;
-    for (int mi = 0; mi < MBe; ++mi) {
-      const int cost = KBe - 2 * mi;
-      if (c0 <= c1) { if (pair == 0) mine |= 1u << mi; c0 += cost; }
-      else { if (pair == 1) mine |= 1u << mi; c1 += cost; }
-    }
-  }
+  const int nb = wv & 3;
+  const unsigned mine = mblocks_for(wv >> 2, MBe, KBe);
   const size_t plane = (size_t)(Lp >> 5) * KB * 512;
   const uint16_t* fh = w.pfrag + (size_t)b * 2 * plane;
   const uint16_t* fl = fh + plane;
-  const int col = 32 * ni + (lane & 31);
+  const int col = 32 * nb + (lane & 31);
   const int khalf = 8 * (lane >> 5);
   float dsum = 0.0f;
   for (int mi = 0; mi < MBe; ++mi) {
@@ -173,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void k_trans_fwd_mixed(Model m, Work w, Tab
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int row = 32 * mi + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
-      dsum = fmaf(s_area[row], 1.0f - __expf(-acc[j]), dsum);
+      dsum = fmaf(s_area[row], 1.0f - exp2_fast(-1.4426950408889634f * acc[j]), dsum);
     }
   }
   dsum += __shfl_xor(dsum, 32);
@@ -181,32 +141,60 @@ __global__ __launch_bounds__(kBlock) void k_trans_fwd_mixed(Model m, Work w, Tab
   __syncthreads();
   if (tid < kTileNu) {
     const int h = tid >> 5, c = tid & 31;
-    const float tot = s_red[h * 32 + c] + s_red[(h + 2) * 32 + c];
+    const float tot = s_red[h * 32 + c] + s_red[(h + 4) * 32 + c];
     if (nu0 + tid < m.n_nu) out[nu0 + tid] = (float)w.core[b] + tot;
   }
 }
 
+// FP64 element: bilinear log10 sigma, 2^(v log2 10 + lam)
+template <int S, bool CIA>
+__device__ inline double opacity_fp64(const Model& m, const Tables& tb, int cl, const double* __restrict__ rl, int nu,
+                                      double nu4) {
+  const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
+  const double wt = rl[0], wp = rl[1];
+  const size_t npad = (size_t)m.n_nu_pad;
+  double acc = rl[3] * nu4 + rl[4];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const double* p = tb.t64 + (((size_t)s * m.n_t + it) * m.n_p + ip) * npad + nu;
+    const double v = (1.0 - wt) * (1.0 - wp) * p[0] + wt * (1.0 - wp) * p[(size_t)m.n_p * npad] +
+                     (1.0 - wt) * wp * p[npad] + wt * wp * p[(size_t)(m.n_p + 1) * npad];
+    acc += exp2(v * kLog2_10 + rl[kRecFixed + s]);
+  }
+  if (CIA) {
+    const double wtc = rl[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const double* p = tb.tc64 + ((size_t)c * m.n_tc + itc) * npad + nu;
+      acc += exp2(((1.0 - wtc) * p[0] + wtc * p[npad]) * kLog2_10 + rl[5 + c]);
+    }
+  }
+  return acc;
+}
+
+template <int S, bool CIA>
 __global__ __launch_bounds__(kBlock) void k_trans_fwd_fp64(Model m, Work w, Tables tb, int B, double* __restrict__ spec) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = logical % B, tile = logical / B;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int Lp = m.L_pad;
-  const int nu0 = tile * kTileNu;
+  const int nu0 = tile * kTile64;
   double* out = spec + (size_t)b * m.n_nu;
   if (w.status[b]) {
-    if (tid < kTileNu && nu0 + tid < m.n_nu) out[nu0 + tid] = __builtin_nan("");
+    if (tid < kTile64 && nu0 + tid < m.n_nu) out[nu0 + tid] = __builtin_nan("");
     return;
   }
   const int L = w.nlay[b];
   double* s_dt = reinterpret_cast<double*>(lds);   // [Lp][64]
-  double* s_red = s_dt + (size_t)Lp * kTileNu;     // [4][64]
-  const int RL = rec_len(m.S);
-  const double* rec = reinterpret_cast<const double*>(w.rec) + (size_t)b * Lp * RL;
+  double* s_red = s_dt + (size_t)Lp * kTile64;     // [4][64]
+  const double* rec = reinterpret_cast<const double*>(w.rec) + (size_t)b * Lp * rec_len(S);
   const int32_t* cells = w.cells + (size_t)b * Lp;
   const int nu = nu0 + lane;
   const double nu4 = tb.nu4d[nu];
-  for (int l = wv; l < L; l += 4) s_dt[l * kTileNu + lane] = opacity_fp64(m, tb, cells[l], rec + (size_t)l * RL, nu, nu4);
+  for (int l = wv; l < L; l += 4)
+    s_dt[l * kTile64 + lane] = opacity_fp64<S, CIA>(m, tb, cells[l], rec + (size_t)l * rec_len(S), nu, nu4);
   __syncthreads();
   const double* pm = w.pm64 + (size_t)b * Lp * Lp;
   const double* area = reinterpret_cast<const double*>(w.area) + (size_t)b * Lp;
@@ -214,35 +202,55 @@ __global__ __launch_bounds__(kBlock) void k_trans_fwd_fp64(Model m, Work w, Tabl
   for (int i = wv; i < L; i += 4) {
     const double* prow = pm + (size_t)i * Lp;
     double tau = 0.0;
-    for (int l = i; l < L; ++l) tau = fma(prow[l], s_dt[l * kTileNu + lane], tau);
+    for (int l = i; l < L; ++l) tau = fma(prow[l], s_dt[l * kTile64 + lane], tau);
     dsum += area[i] * -expm1(-tau);
   }
-  s_red[wv * kTileNu + lane] = dsum;
+  s_red[wv * kTile64 + lane] = dsum;
   __syncthreads();
-  if (tid < kTileNu) {
-    const double tot = (s_red[tid] + s_red[kTileNu + tid]) + (s_red[2 * kTileNu + tid] + s_red[3 * kTileNu + tid]);
+  if (tid < kTile64) {
+    const double tot = (s_red[tid] + s_red[kTile64 + tid]) + (s_red[2 * kTile64 + tid] + s_red[3 * kTile64 + tid]);
     if (nu0 + tid < m.n_nu) out[nu0 + tid] = w.core[b] + tot;
   }
 }
 
+// ---------------------------------------------------------------------------
+// host side: one instance per (species count, CIA present)
+template <bool F64, int S, bool CIA>
+const void* fwd_kernel() {
+  if constexpr (F64) return (const void*)k_trans_fwd_fp64<S, CIA>;
+  else return (const void*)k_trans_fwd_mixed<S, CIA>;
+}
+
+template <bool F64>
+const void* fwd_kernel_for(int S, bool cia) {
+#define EXOFWD_CASE(n) \
+  case n: return cia ? fwd_kernel<F64, n, true>() : fwd_kernel<F64, n, false>();
+  switch (S) {
+    EXOFWD_CASE(1) EXOFWD_CASE(2) EXOFWD_CASE(3) EXOFWD_CASE(4)
+    EXOFWD_CASE(5) EXOFWD_CASE(6) EXOFWD_CASE(7) EXOFWD_CASE(8)
+  }
+#undef EXOFWD_CASE
+  return nullptr;
+}
+
 size_t trans_fwd_lds_bytes(const Model& m, bool fp64) {
-  if (fp64) return (size_t)m.L_pad * kTileNu * 8 + 4 * kTileNu * 8;
-  return (size_t)2 * kTileNu * (m.L_pad + 8) * 2 + (size_t)m.L_pad * 4 + 4 * 32 * 4;
+  if (fp64) return (size_t)m.L_pad * kTile64 * 8 + 4 * kTile64 * 8;
+  return (size_t)2 * kTileNu * (m.L_pad + 8) * 2 + (size_t)m.L_pad * 4 + 8 * 32 * 4;
 }
 
 hipError_t trans_fwd_configure(const Model& m, bool fp64) {
-  const int bytes = (int)trans_fwd_lds_bytes(m, fp64);
-  if (fp64) return hipFuncSetAttribute((const void*)k_trans_fwd_fp64, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  return hipFuncSetAttribute((const void*)k_trans_fwd_mixed, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  const void* k = fp64 ? fwd_kernel_for<true>(m.S, m.has_cia) : fwd_kernel_for<false>(m.S, m.has_cia);
+  if (!k) return hipErrorInvalidValue;
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)trans_fwd_lds_bytes(m, fp64));
 }
 
 void launch_trans_fwd(const Model& m, const Work& w, const Tables& tb, int B, void* spec, bool fp64, hipStream_t st) {
-  const dim3 grid((unsigned)(m.n_tiles * B));
   const size_t lds = trans_fwd_lds_bytes(m, fp64);
+  void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec};
   if (fp64)
-    hipLaunchKernelGGL(k_trans_fwd_fp64, grid, dim3(kBlock), lds, st, m, w, tb, B, (double*)spec);
+    hipLaunchKernel(fwd_kernel_for<true>(m.S, m.has_cia), dim3((unsigned)(m.n_tiles64 * B)), dim3(kBlock), args, lds, st);
   else
-    hipLaunchKernelGGL(k_trans_fwd_mixed, grid, dim3(kBlock), lds, st, m, w, tb, B, (float*)spec);
+    hipLaunchKernel(fwd_kernel_for<false>(m.S, m.has_cia), dim3((unsigned)(m.n_tiles * B)), dim3(kBlockT), args, lds, st);
 }
 
 }  // namespace exofwd
