@@ -1,5 +1,5 @@
-// Adjoint of the transmission path: per-sample partial sums from the fused
-// reverse kernel and the FP64 chain to d lnL / d params.
+// Adjoint of the transmission path: per-(sample, wavenumber chunk) partial
+// sums from the fused reverse kernels, and the FP64 chain to d lnL / d params.
 #pragma once
 #include "common.h"
 
@@ -7,19 +7,32 @@
 
 namespace exofwd {
 
+// Per-layer sums over wavenumber produced by the reverse kernels, in this order:
+//   [0, S)  G_s   = sum_nu dtau_bar_l t_ls           (t_ls: line term of source s)
+//   S       HT    = sum_nu dtau_bar_l sum_s t_ls dv_ls/dwT   (log2 units)
+//   S+1,2   Gc_p  = sum_nu dtau_bar_l t_lp           (CIA pairs H2-H2, H2-He)
+//   S+3     HTc   = sum_nu dtau_bar_l sum_p t_lp dv_lp/dwTc
+//   S+4     GR    = sum_nu dtau_bar_l (nu/1e4)^4
+//   S+5     GD    = sum_nu dtau_bar_l
+constexpr int kExtraSums = 6;
+__host__ __device__ constexpr int n_sums(int s) { return s + kExtraSums; }
+
 struct AdjWork {
-  int n_chunks;        // wavenumber chunks per sample in the reverse kernel
-  double* layer_sums;  // [B][n_chunks][L_pad][n_sums] per-layer sums over nu
-  double* pbar;        // [B][n_chunks][L_pad][L_pad] d lnL / d P_il partials
-  double* abar;        // [B][n_chunks][L_pad + 1] d lnL / d area_i, last = d lnL / d core
+  int max_pairs;       // allocated (sample, chunk) pairs
+  double* layer_sums;  // [pair][L_pad][n_sums]
+  void* pbar;          // [pair][L_pad][L_pad] d lnL / d P_il (row i, column l), float (mixed) or double (FP64)
+  double* abar;        // [pair][L_pad] d lnL / d area_i
 };
 
-bool adjoint_alloc(AdjWork& aw, const Model& m, int B, bool fp64, const std::function<void*(size_t)>& alloc);
+// wavenumber chunks per sample for a batch of B (pair index = b * chunks + chunk)
+int adjoint_chunks(const Model& m, int B, bool fp64);
+bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std::function<void*(size_t)>& alloc);
 hipError_t adjoint_configure(const Model& m, bool fp64);
 void launch_trans_adjoint(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, bool fp64,
                           hipStream_t st);
 void launch_chain(const Model& m, const Work& w, const AdjWork& aw, int B, const double* params, const uint8_t* mask,
                   double* grad, bool fp64, hipStream_t st);
-bool adjoint_ready();
+// whether the adjoint supports this workload (transmission, L_pad <= 128, no PCHIP profile)
+bool adjoint_supported(const Model& m);
 
 }  // namespace exofwd

@@ -1,13 +1,911 @@
+// Reverse pass of the transmission path.
+//
+// For every (sample, wavenumber chunk) a fused kernel recomputes the layer
+// optical depths and the slant optical depth, forms the seeds
+//   delta_bar(nu) = (d lnL / d m_k) / N_k          (nu in bin k)
+//   tau_bar_i(nu) = delta_bar(nu) a_i e^{-tau_i(nu)}
+// and accumulates, over its wavenumbers,
+//   abar_i   = sum_nu delta_bar (1 - e^{-tau_i})                      (annulus areas)
+//   Pbar_il  = sum_nu tau_bar_i dtau_l                                (path matrix)
+//   dtau_bar = P^T tau_bar  and the per-layer sums of adjoint.h        (opacity)
+// The FP64 chain kernel then walks back through the path-matrix geometry,
+// the hydrostatic recursion, n = p/kT, chemistry, the cloud deck and the T-p
+// profile to d lnL / d params.
 #include "adjoint.h"
+#include "kernels.h"
+#include "opacity.h"
 
 namespace exofwd {
-bool adjoint_alloc(AdjWork& aw, const Model&, int, bool, const std::function<void*(size_t)>&) {
-  aw = AdjWork{};
-  return true;
+
+typedef __attribute__((ext_vector_type(4))) double f64x4;
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
 }
-hipError_t adjoint_configure(const Model&, bool) { return hipSuccess; }
-void launch_trans_adjoint(const Model&, const Work&, const Tables&, const AdjWork&, int, bool, hipStream_t) {}
-void launch_chain(const Model&, const Work&, const AdjWork&, int, const double*, const uint8_t*, double*, bool,
-                  hipStream_t) {}
-bool adjoint_ready() { return false; }
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// cost-balanced split of 32-row blocks between two waves; `rev` costs rows by
+// their K extent in the transposed product (grows with the block index)
+__device__ inline unsigned split_blocks(int part, int MBe, int KBe, bool rev) {
+  unsigned mine = 0;
+  int c0 = 0, c1 = 0;
+  for (int q = 0; q < MBe; ++q) {
+    const int mi = rev ? MBe - 1 - q : q;
+    const int cost = rev ? min(2 * mi + 2, KBe) : KBe - 2 * mi;
+    if (c0 <= c1) {
+      if (part == 0) mine |= 1u << mi;
+      c0 += cost;
+    } else {
+      if (part == 1) mine |= 1u << mi;
+      c1 += cost;
+    }
+  }
+  return mine;
+}
+
+// index of the q-th set bit of mask (or -1)
+__device__ inline int nth_bit(unsigned mask, int q) {
+  for (int i = 0; i < 32; ++i)
+    if (mask & (1u << i)) {
+      if (q == 0) return i;
+      --q;
+    }
+  return -1;
+}
+
+__device__ inline uint32_t pack2(uint16_t a, uint16_t b) { return (uint32_t)a | ((uint32_t)b << 16); }
+
+// bf16x8 gathered from 8 wavenumber rows of a [nu][stride] bf16 array
+__device__ inline bf16x8 gather8(const uint16_t* base, int stride) {
+  uint4 p;
+  p.x = pack2(base[0], base[stride]);
+  p.y = pack2(base[2 * stride], base[3 * stride]);
+  p.z = pack2(base[4 * stride], base[5 * stride]);
+  p.w = pack2(base[6 * stride], base[7 * stride]);
+  return __builtin_bit_cast(bf16x8, p);
+}
+
+constexpr int kSlots = 2;    // 32-row blocks per wave (the greedy split gives at most 2 for L_pad <= 128)
+constexpr int kPSlots = 2;   // path-matrix adjoint tiles per wave
+
+// ============================================================================
+// reduced-precision reverse kernel: 512 threads, 128-wavenumber tiles
+template <int S, bool CIA>
+__global__ __launch_bounds__(kBlockT) void k_trans_adj_mixed(Model m, Work w, Tables tb, AdjWork aw, int B, int C) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int b = logical % B, chunk = logical / B;
+  if (w.status[b]) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int Lp = m.L_pad, L = w.nlay[b];
+  constexpr int NS = n_sums(S);
+  const int stride = Lp + 8;
+  uint16_t* s_dh = reinterpret_cast<uint16_t*>(lds);   // dtau hi  [nu][stride]
+  uint16_t* s_dl = s_dh + kTileNu * stride;            // dtau lo
+  uint16_t* s_th = s_dl + kTileNu * stride;            // tau_bar hi [nu][stride]
+  uint16_t* s_tl = s_th + kTileNu * stride;            // tau_bar lo
+  float* s_dtb = reinterpret_cast<float*>(s_th);       // dtau_bar [Lp][128] (after the products)
+  double* s_sums = reinterpret_cast<double*>(s_tl + kTileNu * stride);  // [Lp][NS]
+  float* s_area = reinterpret_cast<float*>(s_sums + (size_t)Lp * NS);   // [Lp]
+
+  const float* area = reinterpret_cast<const float*>(w.area) + (size_t)b * Lp;
+  for (int i = tid; i < Lp; i += kBlockT) s_area[i] = area[i];
+  for (int i = tid; i < Lp * NS; i += kBlockT) s_sums[i] = 0.0;
+
+  const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * rec_len(S);
+  const int32_t* cells = w.cells + (size_t)b * Lp;
+  TableGeom g;
+  g.row_bytes = (uint32_t)m.n_nu_pad * 2u;
+  g.tstep = (uint32_t)m.n_p * g.row_bytes;
+  g.pstep = g.row_bytes;
+  const size_t npad = (size_t)m.n_nu_pad;
+  const __amdgpu_buffer_rsrc_t rh = make_rsrc(tb.h, (size_t)S * m.n_t * m.n_p * npad * 2);
+  const __amdgpu_buffer_rsrc_t rhc = make_rsrc(CIA ? (const void*)tb.hc : (const void*)tb.h,
+                                               CIA ? (size_t)2 * m.n_tc * npad * 2 : 0);
+  const uint32_t voff = (uint32_t)lane * 4u;
+
+  const int KBe = (L + 15) >> 4, MBe = (L + 31) >> 5, KB = Lp >> 4;
+  const int nb = wv & 3, part = wv >> 2;
+  const unsigned mine_t = split_blocks(part, MBe, KBe, false);   // rows i of tau
+  const unsigned mine_d = split_blocks(part, MBe, KBe, true);    // rows l of dtau_bar
+  const size_t plane = (size_t)(Lp >> 5) * KB * 512;
+  const uint16_t* fh = w.pfrag + (size_t)b * 2 * plane;
+  const uint16_t* fl = fh + plane;
+  const uint16_t* th_ = w.ptfrag + (size_t)b * 2 * plane;
+  const uint16_t* tl_ = th_ + plane;
+  const int col = 32 * nb + (lane & 31);
+  const int h = lane >> 5;
+  const double* dm = w.dm + (size_t)b * m.K;
+
+  // path-matrix adjoint tiles (32x32 blocks with column block >= row block), round-robin over waves
+  int pt_mi[kPSlots], pt_nl[kPSlots];
+  {
+    int t = 0;
+    for (int q = 0; q < kPSlots; ++q) pt_mi[q] = pt_nl[q] = -1;
+    for (int mi = 0; mi < MBe; ++mi)
+      for (int nl = mi; nl < MBe; ++nl, ++t)
+        if (t % 8 == wv && t / 8 < kPSlots) {
+          pt_mi[t / 8] = mi;
+          pt_nl[t / 8] = nl;
+        }
+  }
+  f32x16 abar_acc[kSlots], pbar_acc[kPSlots];
+#pragma unroll
+  for (int q = 0; q < kSlots; ++q) abar_acc[q] = f32x16{};
+#pragma unroll
+  for (int q = 0; q < kPSlots; ++q) pbar_acc[q] = f32x16{};
+
+  const int t0 = chunk * m.n_tiles / C, t1 = (chunk + 1) * m.n_tiles / C;
+  for (int tile = t0; tile < t1; ++tile) {
+    const int nu0 = tile * kTileNu;
+    // ---- phase A: layer optical depths -> bf16 hi/lo [nu][l]
+    {
+      const LaneConst<S> kc = load_lane<S, CIA>(m, tb, nu0 + 2 * lane);
+      for (int o = wv; o < 4 * MBe; o += kBlockT / 64) {
+        uint16_t h0[8], l0[8], h1[8], l1[8];
+#pragma unroll 2
+        for (int j = 0; j < 8; ++j) {
+          const int l = 8 * o + j;
+          float d0 = 0.0f, d1 = 0.0f;
+          if (l < L) {
+            const LayerCoef<S> c = load_layer<S>(m, cells, rec, l, (uint32_t)nu0 * 2u, g);
+            layer_terms<S, CIA, false>(c, kc, g, rh, rhc, voff, d0, d1);
+            d0 = fminf(d0, 16384.0f);
+            d1 = fminf(d1, 16384.0f);
+          }
+          h0[j] = bf16_bits_rn(d0);
+          l0[j] = bf16_bits_rn(d0 - bf16_bits_to_f(h0[j]));
+          h1[j] = bf16_bits_rn(d1);
+          l1[j] = bf16_bits_rn(d1 - bf16_bits_to_f(h1[j]));
+        }
+        const int r0 = (2 * lane) * stride + 8 * o, r1 = r0 + stride;
+        *reinterpret_cast<uint4*>(s_dh + r0) = make_uint4(pack2(h0[0], h0[1]), pack2(h0[2], h0[3]), pack2(h0[4], h0[5]), pack2(h0[6], h0[7]));
+        *reinterpret_cast<uint4*>(s_dl + r0) = make_uint4(pack2(l0[0], l0[1]), pack2(l0[2], l0[3]), pack2(l0[4], l0[5]), pack2(l0[6], l0[7]));
+        *reinterpret_cast<uint4*>(s_dh + r1) = make_uint4(pack2(h1[0], h1[1]), pack2(h1[2], h1[3]), pack2(h1[4], h1[5]), pack2(h1[6], h1[7]));
+        *reinterpret_cast<uint4*>(s_dl + r1) = make_uint4(pack2(l1[0], l1[1]), pack2(l1[2], l1[3]), pack2(l1[4], l1[5]), pack2(l1[6], l1[7]));
+      }
+    }
+    __syncthreads();
+
+    // ---- phases B, C: tau = P dtau; seeds; tau_bar -> [nu][i]; abar accumulation
+    {
+      const int nu_g = nu0 + col;
+      const int bin = w.bin_of[nu_g];
+      const float dbar = bin >= 0 ? (float)(dm[bin] * w.inv_cnt[bin]) : 0.0f;
+#pragma unroll
+      for (int q = 0; q < kSlots; ++q) {
+        const int mi = nth_bit(mine_t, q);
+        if (mi < 0) continue;
+        f32x16 acc = {};
+#pragma unroll 1
+        for (int kb = 2 * mi; kb < KBe; ++kb) {
+          const size_t fo = ((size_t)(mi * KB + kb) * 64 + lane) * 8;
+          const bf16x8 ah = *reinterpret_cast<const bf16x8*>(fh + fo);
+          const bf16x8 al = *reinterpret_cast<const bf16x8*>(fl + fo);
+          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(s_dh + col * stride + 16 * kb + 8 * h);
+          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(s_dl + col * stride + 16 * kb + 8 * h);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int qd = 0; qd < 4; ++qd) {
+          uint16_t hv[4], lv[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int j = 4 * qd + r;
+            const int row = 32 * mi + 8 * qd + 4 * h + r;
+            const float e = exp2_fast(-1.4426950408889634f * acc[j]);
+            abar_acc[q][j] = fmaf(dbar, 1.0f - e, abar_acc[q][j]);
+            const float tb_ = dbar * s_area[row] * e;
+            hv[r] = bf16_bits_rn(tb_);
+            lv[r] = bf16_bits_rn(tb_ - bf16_bits_to_f(hv[r]));
+          }
+          const int off = col * stride + 32 * mi + 8 * qd + 4 * h;
+          *reinterpret_cast<uint2*>(s_th + off) = make_uint2(pack2(hv[0], hv[1]), pack2(hv[2], hv[3]));
+          *reinterpret_cast<uint2*>(s_tl + off) = make_uint2(pack2(lv[0], lv[1]), pack2(lv[2], lv[3]));
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- phase E: Pbar += tau_bar dtau^T over this tile's wavenumbers
+#pragma unroll
+    for (int q = 0; q < kPSlots; ++q) {
+      const int mi = pt_mi[q], nl = pt_nl[q];
+      if (mi < 0) continue;
+      const int ri = 32 * mi + (lane & 31), cl = 32 * nl + (lane & 31);
+#pragma unroll 1
+      for (int ks = 0; ks < kTileNu / 16; ++ks) {
+        const int nu_r = 16 * ks + 8 * h;
+        const bf16x8 ah = gather8(s_th + nu_r * stride + ri, stride);
+        const bf16x8 al = gather8(s_tl + nu_r * stride + ri, stride);
+        const bf16x8 bh = gather8(s_dh + nu_r * stride + cl, stride);
+        const bf16x8 bl = gather8(s_dl + nu_r * stride + cl, stride);
+        pbar_acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, pbar_acc[q], 0, 0, 0);
+        pbar_acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, pbar_acc[q], 0, 0, 0);
+        pbar_acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, pbar_acc[q], 0, 0, 0);
+      }
+    }
+    // ---- phase D: dtau_bar = P^T tau_bar (rows l, this wave's column block)
+    f32x16 dtb[kSlots];
+#pragma unroll
+    for (int q = 0; q < kSlots; ++q) {
+      dtb[q] = f32x16{};
+      const int ml = nth_bit(mine_d, q);
+      if (ml < 0) continue;
+      const int kend = min(2 * ml + 2, KBe);
+#pragma unroll 1
+      for (int ki = 0; ki < kend; ++ki) {
+        const size_t fo = ((size_t)(ml * KB + ki) * 64 + lane) * 8;
+        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(th_ + fo);
+        const bf16x8 al = *reinterpret_cast<const bf16x8*>(tl_ + fo);
+        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(s_th + col * stride + 16 * ki + 8 * h);
+        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(s_tl + col * stride + 16 * ki + 8 * h);
+        dtb[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, dtb[q], 0, 0, 0);
+        dtb[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, dtb[q], 0, 0, 0);
+        dtb[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, dtb[q], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    // dtau_bar -> LDS [l][nu] FP32
+#pragma unroll
+    for (int q = 0; q < kSlots; ++q) {
+      const int ml = nth_bit(mine_d, q);
+      if (ml < 0) continue;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int row = 32 * ml + 8 * (j >> 2) + 4 * h + (j & 3);
+        s_dtb[row * kTileNu + col] = dtb[q][j];
+      }
+    }
+    __syncthreads();
+
+    // ---- phase G: per-layer sums of dtau_bar times each opacity source
+    {
+      const LaneConst<S> kc = load_lane<S, CIA>(m, tb, nu0 + 2 * lane);
+      for (int l = wv; l < L; l += kBlockT / 64) {
+        const LayerCoef<S> c = load_layer<S>(m, cells, rec, l, (uint32_t)nu0 * 2u, g);
+        float d0, d1, t0[S + 2], t1[S + 2], dw0[S + 2], dw1[S + 2];
+        layer_terms<S, CIA, true>(c, kc, g, rh, rhc, voff, d0, d1, t0, t1, dw0, dw1);
+        const float2 db = *reinterpret_cast<const float2*>(s_dtb + l * kTileNu + 2 * lane);
+        float sums[NS];
+        float ht = 0.0f, htc = 0.0f;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const float a0 = db.x * t0[s], a1 = db.y * t1[s];
+          sums[s] = a0 + a1;
+          ht = fmaf(a0, dw0[s], fmaf(a1, dw1[s], ht));
+        }
+        sums[S] = ht;
+        if (CIA) {
+#pragma unroll
+          for (int p = 0; p < 2; ++p) {
+            const float a0 = db.x * t0[S + p], a1 = db.y * t1[S + p];
+            sums[S + 1 + p] = a0 + a1;
+            htc = fmaf(a0, dw0[S + p], fmaf(a1, dw1[S + p], htc));
+          }
+        } else {
+          sums[S + 1] = sums[S + 2] = 0.0f;
+        }
+        sums[S + 3] = htc;
+        sums[S + 4] = fmaf(db.x, kc.nu4_0, db.y * kc.nu4_1);
+        sums[S + 5] = db.x + db.y;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const float tot = wave_sum(sums[k]);
+          if (lane == 0) s_sums[l * NS + k] += (double)tot;
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- write this chunk's partials
+  const size_t pair = (size_t)b * C + chunk;
+  double* ls = aw.layer_sums + pair * Lp * NS;
+  for (int i = tid; i < Lp * NS; i += kBlockT) ls[i] = s_sums[i];
+  float* pb = reinterpret_cast<float*>(aw.pbar) + pair * Lp * Lp;
+#pragma unroll
+  for (int q = 0; q < kPSlots; ++q) {
+    const int mi = pt_mi[q], nl = pt_nl[q];
+    if (mi < 0) continue;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int row = 32 * mi + 8 * (j >> 2) + 4 * h + (j & 3);
+      pb[(size_t)row * Lp + 32 * nl + (lane & 31)] = pbar_acc[q][j];
+    }
+  }
+  double* ab = aw.abar + pair * Lp;
+#pragma unroll
+  for (int q = 0; q < kSlots; ++q) {
+    const int mi = nth_bit(mine_t, q);
+    if (mi < 0) continue;
+    // this wave holds rows of block mi for column block nb; the other wave pair
+    // member holds other rows, and the four column blocks are four waves:
+    // reduce over the 32 columns here, then over column blocks through LDS
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      float v = abar_acc[q][j];
+      for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      abar_acc[q][j] = v;
+    }
+  }
+  // column blocks 0..3 of the same rows live in waves nb = 0..3 with the same
+  // `part`; sum them in LDS (reuse s_sums region, all waves are past the loop)
+  double* s_ab = s_sums;   // [4][Lp]
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kSlots; ++q) {
+    const int mi = nth_bit(mine_t, q);
+    if (mi < 0) continue;
+    if ((lane & 31) == 0) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int row = 32 * mi + 8 * (j >> 2) + 4 * h + (j & 3);
+        s_ab[nb * Lp + row] = (double)abar_acc[q][j];
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < Lp; i += kBlockT)
+    ab[i] = i < 32 * MBe ? (s_ab[i] + s_ab[Lp + i]) + (s_ab[2 * Lp + i] + s_ab[3 * Lp + i]) : 0.0;
+}
+
+// ============================================================================
+// FP64 reverse kernel: 512 threads, 64-wavenumber tiles, VALU chord products,
+// FP64 MFMA (16x16x4) for Pbar
+template <int S, bool CIA>
+__device__ inline void opacity_fp64_terms(const Model& m, const Tables& tb, int cl, const double* __restrict__ rl,
+                                          int nu, double nu4, double& dtau, double* t, double* dw) {
+  const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
+  const double wt = rl[0], wp = rl[1];
+  const size_t npad = (size_t)m.n_nu_pad;
+  double acc = rl[3] * nu4 + rl[4];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const double* p = tb.t64 + (((size_t)s * m.n_t + it) * m.n_p + ip) * npad + nu;
+    const double t00 = p[0], t10 = p[(size_t)m.n_p * npad], t01 = p[npad], t11 = p[(size_t)(m.n_p + 1) * npad];
+    const double v = (1.0 - wt) * (1.0 - wp) * t00 + wt * (1.0 - wp) * t10 + (1.0 - wt) * wp * t01 + wt * wp * t11;
+    const double e = exp2(v * kLog2_10 + rl[kRecFixed + s]);
+    acc += e;
+    if (t) {
+      t[s] = e;
+      dw[s] = ((1.0 - wp) * (t10 - t00) + wp * (t11 - t01)) * kLog2_10;   // log2 units
+    }
+  }
+  if (CIA) {
+    const double wtc = rl[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const double* p = tb.tc64 + ((size_t)c * m.n_tc + itc) * npad + nu;
+      const double e = exp2(((1.0 - wtc) * p[0] + wtc * p[npad]) * kLog2_10 + rl[5 + c]);
+      acc += e;
+      if (t) {
+        t[S + c] = e;
+        dw[S + c] = (p[npad] - p[0]) * kLog2_10;
+      }
+    }
+  }
+  dtau = acc;
+}
+
+constexpr int kRows64 = 16;    // rows per wave (L_pad <= 128, 8 waves)
+constexpr int kPSlots64 = 5;   // 16x16 Pbar tiles per wave
+
+template <int S, bool CIA>
+__global__ __launch_bounds__(kBlockT) void k_trans_adj_fp64(Model m, Work w, Tables tb, AdjWork aw, int B, int C) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int b = logical % B, chunk = logical / B;
+  if (w.status[b]) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int Lp = m.L_pad, L = w.nlay[b];
+  constexpr int NS = n_sums(S);
+  const int ld = Lp + 1;                              // padded row length (doubles)
+  double* s_dt = reinterpret_cast<double*>(lds);      // dtau [nu][ld]
+  double* s_tb = s_dt + kTile64 * ld;                 // tau_bar [nu][ld], later dtau_bar
+  double* s_sums = s_tb + kTile64 * ld;               // [Lp][NS]
+  for (int i = tid; i < Lp * NS; i += kBlockT) s_sums[i] = 0.0;
+
+  const double* rec = reinterpret_cast<const double*>(w.rec) + (size_t)b * Lp * rec_len(S);
+  const int32_t* cells = w.cells + (size_t)b * Lp;
+  const double* pm = w.pm64 + (size_t)b * Lp * Lp;
+  const double* area = reinterpret_cast<const double*>(w.area) + (size_t)b * Lp;
+  const double* dm = w.dm + (size_t)b * m.K;
+
+  double abar_r[kRows64];
+#pragma unroll
+  for (int k = 0; k < kRows64; ++k) abar_r[k] = 0.0;
+  // 16x16 Pbar tiles with column block >= row block, round-robin over waves
+  const int MB16 = (L + 15) >> 4;
+  int pt_mi[kPSlots64], pt_nl[kPSlots64];
+  {
+    int t = 0;
+    for (int q = 0; q < kPSlots64; ++q) pt_mi[q] = pt_nl[q] = -1;
+    for (int mi = 0; mi < MB16; ++mi)
+      for (int nl = mi; nl < MB16; ++nl, ++t)
+        if (t % 8 == wv && t / 8 < kPSlots64) {
+          pt_mi[t / 8] = mi;
+          pt_nl[t / 8] = nl;
+        }
+  }
+  f64x4 pacc[kPSlots64];
+#pragma unroll
+  for (int q = 0; q < kPSlots64; ++q) pacc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  const int t0 = chunk * m.n_tiles64 / C, t1 = (chunk + 1) * m.n_tiles64 / C;
+  for (int tile = t0; tile < t1; ++tile) {
+    const int nu = tile * kTile64 + lane;
+    const double nu4 = tb.nu4d[nu];
+    for (int l = wv; l < Lp; l += 8) {
+      double d = 0.0;
+      if (l < L) opacity_fp64_terms<S, CIA>(m, tb, cells[l], rec + (size_t)l * rec_len(S), nu, nu4, d, nullptr, nullptr);
+      s_dt[lane * ld + l] = d;
+    }
+    const int bin = w.bin_of[nu];
+    const double dbar = bin >= 0 ? dm[bin] * w.inv_cnt[bin] : 0.0;
+    __syncthreads();
+    // tau_i, seeds, tau_bar
+#pragma unroll
+    for (int k = 0; k < kRows64; ++k) {
+      const int i = wv + 8 * k;
+      if (i < Lp) {
+        double tbv = 0.0;
+        if (i < L) {
+          double tau = 0.0;
+          for (int l = i; l < L; ++l) tau = fma(pm[(size_t)i * Lp + l], s_dt[lane * ld + l], tau);
+          const double one_m_e = -expm1(-tau);
+          abar_r[k] += dbar * one_m_e;
+          tbv = dbar * area[i] * (1.0 - one_m_e);
+        }
+        s_tb[lane * ld + i] = tbv;
+      }
+    }
+    __syncthreads();
+    // Pbar += tau_bar dtau^T (FP64 MFMA, k = wavenumber)
+#pragma unroll
+    for (int q = 0; q < kPSlots64; ++q) {
+      const int mi = pt_mi[q], nl = pt_nl[q];
+      if (mi < 0) continue;
+      const int ri = 16 * mi + (lane & 15), cl = 16 * nl + (lane & 15);
+#pragma unroll 1
+      for (int ks = 0; ks < kTile64 / 4; ++ks) {
+        const int nr = 4 * ks + (lane >> 4);
+        pacc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_tb[nr * ld + ri], s_dt[nr * ld + cl], pacc[q], 0, 0, 0);
+      }
+    }
+    // dtau_bar_l = sum_{i <= l} P_il tau_bar_i
+    double dtb[kRows64];
+#pragma unroll
+    for (int k = 0; k < kRows64; ++k) {
+      const int l = wv + 8 * k;
+      double acc = 0.0;
+      if (l < L)
+        for (int i = 0; i <= l; ++i) acc = fma(pm[(size_t)i * Lp + l], s_tb[lane * ld + i], acc);
+      dtb[k] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRows64; ++k) {
+      const int l = wv + 8 * k;
+      if (l < Lp) s_tb[lane * ld + l] = dtb[k];
+    }
+    __syncthreads();
+    // per-layer sums
+    for (int l = wv; l < L; l += 8) {
+      double d, t[S + 2], dw[S + 2];
+      opacity_fp64_terms<S, CIA>(m, tb, cells[l], rec + (size_t)l * rec_len(S), nu, nu4, d, t, dw);
+      const double db = s_tb[lane * ld + l];
+      double sums[NS];
+      double ht = 0.0, htc = 0.0;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        sums[s] = db * t[s];
+        ht += db * t[s] * dw[s];
+      }
+      sums[S] = ht;
+      if (CIA) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          sums[S + 1 + p] = db * t[S + p];
+          htc += db * t[S + p] * dw[S + p];
+        }
+      } else {
+        sums[S + 1] = sums[S + 2] = 0.0;
+      }
+      sums[S + 3] = htc;
+      sums[S + 4] = db * nu4;
+      sums[S + 5] = db;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const double tot = wave_sum(sums[k]);
+        if (lane == 0) s_sums[l * NS + k] += tot;
+      }
+    }
+    __syncthreads();
+  }
+
+  const size_t pair = (size_t)b * C + chunk;
+  double* ls = aw.layer_sums + pair * Lp * NS;
+  for (int i = tid; i < Lp * NS; i += kBlockT) ls[i] = s_sums[i];
+  double* pb = reinterpret_cast<double*>(aw.pbar) + pair * Lp * Lp;
+#pragma unroll
+  for (int q = 0; q < kPSlots64; ++q) {
+    const int mi = pt_mi[q], nl = pt_nl[q];
+    if (mi < 0) continue;
+#pragma unroll
+    // v_mfma_f64_16x16x4f64 result: D[i][j] at lane j + 16 (i % 4), element i / 4
+    for (int j = 0; j < 4; ++j) pb[(size_t)(16 * mi + (lane >> 4) + 4 * j) * Lp + 16 * nl + (lane & 15)] = pacc[q][j];
+  }
+  double* ab = aw.abar + pair * Lp;
+#pragma unroll
+  for (int k = 0; k < kRows64; ++k) {
+    const int i = wv + 8 * k;
+    const double v = wave_sum(abar_r[k]);
+    if (lane == 0 && i < Lp) ab[i] = v;
+  }
+}
+
+// ============================================================================
+// FP64 chain: one workgroup per sample
+__device__ inline void block_sum(double* s_red, int tid, int n) {
+  // s_red[n][kBlock]: tree over the second index, result in s_red[k][0]
+  for (int hh = kBlock / 2; hh > 0; hh >>= 1) {
+    __syncthreads();
+    if (tid < hh)
+      for (int k = 0; k < n; ++k) s_red[k * kBlock + tid] += s_red[k * kBlock + tid + hh];
+  }
+  __syncthreads();
+}
+
+// derivatives of P_il with respect to r_l, r_{l+1} and b_i (l > i), or the
+// full derivatives with respect to r_i, r_{i+1} on the diagonal
+__device__ inline void path_derivs(const double* r, int i, int l, double& d_lo, double& d_up, double& d_b) {
+  if (l == i) {
+    const double dr = r[i + 1] - r[i];
+    const double q = (3.0 * r[i + 1] + r[i]) / dr;
+    const double sq = sqrt(q);
+    d_up = (3.0 - q) / (2.0 * dr * sq);
+    d_lo = (1.0 + q) / (2.0 * dr * sq);
+    d_b = 0.0;
+    return;
+  }
+  const double bb = 0.5 * (r[i] + r[i + 1]);
+  const double rup = r[l + 1], rlo = r[l];
+  const double sup = sqrt((rup - bb) * (rup + bb)), slo = sqrt((rlo - bb) * (rlo + bb));
+  const double nn = 2.0 * (rup + rlo), den = sup + slo;
+  const double f = nn / (den * den);
+  d_up = 2.0 / den - f * rup / sup;
+  d_lo = 2.0 / den - f * rlo / slo;
+  d_b = f * bb * (1.0 / sup + 1.0 / slo);
+}
+
+template <typename PbarT>
+__global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, int C, const double* __restrict__ params,
+                                                  const uint8_t* __restrict__ mask, double* __restrict__ grad) {
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int Lp = m.L_pad;
+  const int NS = n_sums(m.S);
+  double* gout = grad + (size_t)b * m.P;
+  if (w.status[b]) {
+    for (int k = tid; k < m.P; k += kBlock) gout[k] = 0.0;
+    return;
+  }
+  const int L = w.nlay[b];
+  const double* th = params + (size_t)b * m.P;
+  __shared__ double s_r[kMaxLayers + 1], s_rb[kMaxLayers + 1], s_ub[kMaxLayers + 1];
+  __shared__ double s_t[kMaxLayers], s_tb[kMaxLayers], s_lndr[kMaxLayers];
+  __shared__ double s_clo[kMaxLayers], s_cup[kMaxLayers], s_bb[kMaxLayers];
+  __shared__ double s_red[16 * kBlock];
+  __shared__ double s_scal[8];
+
+  const double* rl = w.r_lev + (size_t)b * (Lp + 1);
+  const double* tl = w.t_lay + (size_t)b * Lp;
+  for (int j = tid; j <= L; j += kBlock) s_r[j] = rl[j];
+  for (int l = tid; l < L; l += kBlock) s_t[l] = tl[l];
+
+  // chemistry and constants (every thread)
+  double x[kMaxSpecies];
+  double sx = 0.0;
+  for (int s = 0; s < m.S; ++s) { x[s] = exp10(th[m.n_tp + s]); sx += x[s]; }
+  const double xh2 = (1.0 - sx) / (1.0 + kHeH2), xhe = kHeH2 * xh2;
+  const bool mu_free = !(m.mu_fixed > 0.0);
+  double mu = m.mu_fixed;
+  if (mu_free) {
+    mu = xh2 * kMH2 + xhe * kMHe;
+    for (int s = 0; s < m.S; ++s) mu += x[s] * m.mass[s];
+  }
+  const double scale = m.has_scale ? th[m.idx_scale] : 1.0;
+  const double r_ref = m.r_p * scale;
+  const double kk = kB / (mu * kMu * m.g_ref * r_ref * r_ref);
+  const double step = (m.log10_ptop - m.log10_pbot) / L;
+  const double ln10 = 2.302585092994045684017991454684;
+  const double dlnp = -step * ln10;
+  auto logp_lev = [&](int j) { return j == L ? m.log10_ptop : m.log10_pbot + j * step; };
+  const double rs2 = m.r_s * m.r_s;
+  const double log10_pc = m.has_cloud ? th[m.idx_cloud] : 0.0;
+  __syncthreads();
+
+  // per-layer sums reduced over chunks, and the per-layer chain through
+  // n = p/kT, dr, the Rayleigh and cloud prefactors; accumulators for chemistry
+  // go to s_red rows: [0,S) lnX_s, S lnXH2, S+1 lnXHe, S+2 XH2 direct,
+  // S+3 XHe direct, S+4 ln mu, S+5 theta_cloud
+  const int NR = m.S + 6;
+  for (int k = 0; k < NR; ++k) s_red[k * kBlock + tid] = 0.0;
+  for (int l = tid; l < L; l += kBlock) {
+    double sm[kMaxSpecies + kExtraSums];
+    for (int k = 0; k < NS; ++k) {
+      double v = 0.0;
+      for (int c = 0; c < C; ++c) v += aw.layer_sums[(((size_t)b * C + c) * Lp + l) * NS + k];
+      sm[k] = v;
+    }
+    const double t = s_t[l];
+    const double lp_bar = 0.5 * (logp_lev(l) + logp_lev(l + 1));
+    const double n = exp10(lp_bar) * kBar / (kB * t);
+    const double dr = s_r[l + 1] - s_r[l];
+    const double rr = (m.has_ray ? n * (xh2 * m.ray_h2 + xhe * m.ray_he) * dr : 0.0);
+    double f = 0.0, dd = 0.0;
+    if (m.has_cloud) {
+      f = (logp_lev(l) - log10_pc) * ln10 / dlnp;
+      f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+      dd = m.kappa_cloud * mu * kMu * n * f * dr;
+    }
+    double gline = 0.0;
+    for (int s = 0; s < m.S; ++s) gline += sm[s];
+    const double gc1 = sm[m.S + 1], gc2 = sm[m.S + 2], gr = sm[m.S + 4], gd = sm[m.S + 5];
+    const double lnn_bar = gline + 2.0 * gc1 + 2.0 * gc2 + gr * rr + gd * dd;
+    const double lndr_bar = gline + gc1 + gc2 + gr * rr + gd * dd;
+    s_lndr[l] = lndr_bar / dr;
+    // dT from n = p/kT and from the table weights (interior cells only)
+    double tbar = -lnn_bar / t;
+    const double ln2 = 0.69314718055994530941723212145818;
+    if (t > m.t_grid[0] && t < m.t_grid[m.n_t - 1]) {
+      int lo = 0, hi = m.n_t - 1;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (m.t_grid[mid] <= t) lo = mid; else hi = mid;
+      }
+      tbar += ln2 * sm[m.S] / (m.t_grid[lo + 1] - m.t_grid[lo]);
+    }
+    if (m.has_cia && t > m.tc_grid[0] && t < m.tc_grid[m.n_tc - 1]) {
+      int lo = 0, hi = m.n_tc - 1;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (m.tc_grid[mid] <= t) lo = mid; else hi = mid;
+      }
+      tbar += ln2 * sm[m.S + 3] / (m.tc_grid[lo + 1] - m.tc_grid[lo]);
+    }
+    s_tb[l] = tbar;
+    for (int s = 0; s < m.S; ++s) s_red[s * kBlock + tid] += sm[s];
+    s_red[(m.S) * kBlock + tid] += 2.0 * gc1 + gc2;
+    s_red[(m.S + 1) * kBlock + tid] += gc2;
+    s_red[(m.S + 2) * kBlock + tid] += gr * n * dr * m.ray_h2;
+    s_red[(m.S + 3) * kBlock + tid] += gr * n * dr * m.ray_he;
+    s_red[(m.S + 4) * kBlock + tid] += gd * dd;
+    if (m.has_cloud && f > 0.0 && f < 1.0)
+      s_red[(m.S + 5) * kBlock + tid] += gd * m.kappa_cloud * mu * kMu * n * dr * (-ln10 / dlnp);
+  }
+  block_sum(s_red, tid, NR);
+  double chem[kMaxSpecies + 6];
+  for (int k = 0; k < NR; ++k) chem[k] = s_red[k * kBlock];
+  __syncthreads();
+
+  // path-matrix adjoint: column pass (r_l, r_{l+1}) and row pass (b_i)
+  const PbarT* pbar = reinterpret_cast<const PbarT*>(aw.pbar);
+  auto pb = [&](int i, int l) {
+    double v = 0.0;
+    for (int c = 0; c < C; ++c) v += (double)pbar[(((size_t)b * C + c) * Lp + i) * Lp + l];
+    return v;
+  };
+  for (int l = tid; l < L; l += kBlock) {
+    double clo = 0.0, cup = 0.0;
+    for (int i = 0; i <= l; ++i) {
+      double dlo, dup, db;
+      path_derivs(s_r, i, l, dlo, dup, db);
+      const double p = pb(i, l);
+      clo += p * dlo;
+      cup += p * dup;
+    }
+    s_clo[l] = clo;
+    s_cup[l] = cup;
+  }
+  for (int i = tid; i < L; i += kBlock) {
+    double acc = 0.0;
+    for (int l = i + 1; l < L; ++l) {
+      double dlo, dup, db;
+      path_derivs(s_r, i, l, dlo, dup, db);
+      acc += pb(i, l) * db;
+    }
+    s_bb[i] = acc;
+  }
+  double core_bar = 0.0;
+  for (int k = 0; k < m.K; ++k) core_bar += w.dm[(size_t)b * m.K + k];
+  __syncthreads();
+  for (int j = tid; j <= L; j += kBlock) {
+    double rb = 0.0;
+    double ab_j = 0.0, ab_jm = 0.0;
+    for (int c = 0; c < C; ++c) {
+      if (j < L) ab_j += aw.abar[((size_t)b * C + c) * Lp + j];
+      if (j >= 1) ab_jm += aw.abar[((size_t)b * C + c) * Lp + j - 1];
+    }
+    if (j < L) rb += s_clo[j] + 0.5 * s_bb[j] - 2.0 * s_r[j] * ab_j / rs2 - s_lndr[j];
+    if (j >= 1) rb += s_cup[j - 1] + 0.5 * s_bb[j - 1] + 2.0 * s_r[j] * ab_jm / rs2 + s_lndr[j - 1];
+    if (j == 0) rb += 2.0 * s_r[0] * core_bar / rs2;
+    s_rb[j] = rb;
+    s_ub[j] = -rb * s_r[j] * s_r[j];
+  }
+  __syncthreads();
+
+  // hydrostatic recursion in reverse (sequential over levels)
+  if (tid == 0) {
+    const double lpref = log10(m.p_ref / kBar);
+    int cnt = 0;
+    for (int j = 0; j <= L; ++j) cnt += logp_lev(j) > lpref;
+    const int lref = min(max(cnt - 1, 0), L - 1);
+    const double a1 = (logp_lev(lref) - lpref) * ln10, a2 = (lpref - logp_lev(lref + 1)) * ln10;
+    double ub_ref = 0.0, kbar = 0.0;
+    // Q_j = (u_j - u_ref)/K from the same recursion
+    double q = s_t[lref] * a1;
+    double pre = 0.0;   // sum_{j <= l} ub_j, built from the bottom
+    for (int j = 0; j <= L; ++j) ub_ref += s_ub[j];
+    // levels at and below lref
+    double qj = q;
+    kbar += s_ub[lref] * qj;
+    for (int j = lref - 1; j >= 0; --j) {
+      qj += s_t[j] * dlnp;
+      kbar += s_ub[j] * qj;
+    }
+    qj = -s_t[lref] * a2;
+    kbar += s_ub[lref + 1] * qj;
+    for (int j = lref + 2; j <= L; ++j) {
+      qj -= s_t[j - 1] * dlnp;
+      kbar += s_ub[j] * qj;
+    }
+    // temperatures
+    double below = 0.0;
+    for (int j = 0; j <= lref; ++j) below += s_ub[j];
+    double above = ub_ref - below;
+    s_tb[lref] += kk * (a1 * below - a2 * above);
+    pre = 0.0;
+    for (int l = 0; l < lref; ++l) {
+      pre += s_ub[l];
+      s_tb[l] += kk * dlnp * pre;
+    }
+    double suf = 0.0;
+    for (int l = L - 1; l > lref; --l) {
+      suf += s_ub[l + 1];
+      s_tb[l] -= kk * dlnp * suf;
+    }
+    s_scal[0] = -ub_ref / (r_ref * r_ref) - 2.0 * kbar * kk / r_ref;   // d lnL / d R_ref
+    s_scal[1] = -kbar * kk;                                            // d lnL / d ln mu (hydrostatics)
+  }
+  __syncthreads();
+
+  // T-p profile
+  for (int k = 0; k < 4; ++k) s_red[k * kBlock + tid] = 0.0;
+  for (int l = tid; l < L; l += kBlock) {
+    const double tbar = s_tb[l];
+    if (m.tp_kind == kTpIso) {
+      s_red[tid] += tbar;
+    } else {
+      const double lp_bar = 0.5 * (logp_lev(l) + logp_lev(l + 1));
+      const double tau = m.kappa_ir * exp10(lp_bar) * kBar / m.g_ref;
+      const double t = s_t[l], t3 = t * t * t;
+      const double s3 = 1.7320508075688772935274463415059;
+      const double gam = exp10(th[2]);
+      const double e = exp(-gam * tau * s3);
+      const double bk = 2.0 / 3.0 + 1.0 / (gam * s3) + (gam / s3 - 1.0 / (gam * s3)) * e;
+      const double dbk = -1.0 / (gam * gam * s3) + (1.0 / s3 + 1.0 / (gam * gam * s3)) * e +
+                         (gam / s3 - 1.0 / (gam * s3)) * e * (-tau * s3);
+      const double ti = th[0], te = th[1];
+      s_red[tid] += tbar * 3.0 * ti * ti * ti * (2.0 / 3.0 + tau) / (4.0 * t3);
+      s_red[kBlock + tid] += tbar * 12.0 * m.f_hem * te * te * te * bk / (4.0 * t3);
+      s_red[2 * kBlock + tid] += tbar * 3.0 * m.f_hem * te * te * te * te * dbk * gam * ln10 / (4.0 * t3);
+    }
+  }
+  block_sum(s_red, tid, 3);
+  if (tid == 0) {
+    for (int k = 0; k < m.n_tp; ++k) gout[k] = s_red[k * kBlock];
+    // chemistry: X_H2 = (1 - sum X)/1.164, X_He = 0.164 X_H2, mu = sum X m
+    const double lnmu_bar = chem[m.S + 4] + s_scal[1];
+    const double mu_bar = mu_free ? lnmu_bar / mu : 0.0;
+    const double xhe_bar = chem[m.S + 1] / xhe + chem[m.S + 3] + mu_bar * kMHe;
+    const double xh2_bar = chem[m.S] / xh2 + chem[m.S + 2] + mu_bar * kMH2 + kHeH2 * xhe_bar;
+    for (int s = 0; s < m.S; ++s) {
+      const double xb = chem[s] / x[s] + mu_bar * m.mass[s] - xh2_bar / (1.0 + kHeH2);
+      gout[m.n_tp + s] = xb * x[s] * ln10;
+    }
+    if (m.has_cloud) gout[m.idx_cloud] = chem[m.S + 5];
+    if (m.has_scale) gout[m.idx_scale] = s_scal[0] * m.r_p;
+    if (m.has_offset) {
+      double o = 0.0;
+      for (int k = 0; k < m.K; ++k)
+        if (mask && mask[k]) o += w.dm[(size_t)b * m.K + k];
+      gout[m.idx_offset] = o * 1.0e-6;
+    }
+  }
+}
+
+// ============================================================================
+// host side
+int adjoint_chunks(const Model& m, int B, bool fp64) {
+  const int tiles = fp64 ? m.n_tiles64 : m.n_tiles;
+  int c = (1024 + B - 1) / B;
+  return c < 1 ? 1 : (c > tiles ? tiles : c);
+}
+
+bool adjoint_supported(const Model& m) { return m.mode == kTransmission && m.L_pad <= 128 && m.tp_kind != kTpPchip; }
+
+bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std::function<void*(size_t)>& alloc) {
+  aw = AdjWork{};
+  if (!adjoint_supported(m)) return true;
+  int pairs = 0;
+  for (int B = 1; B <= B_max; ++B) pairs = std::max(pairs, B * adjoint_chunks(m, B, fp64));
+  aw.max_pairs = pairs;
+  const size_t Lp = m.L_pad;
+  aw.layer_sums = (double*)alloc((size_t)pairs * Lp * n_sums(m.S) * sizeof(double));
+  aw.pbar = alloc((size_t)pairs * Lp * Lp * (fp64 ? sizeof(double) : sizeof(float)));
+  aw.abar = (double*)alloc((size_t)pairs * Lp * sizeof(double));
+  return aw.layer_sums && aw.pbar && aw.abar;
+}
+
+static size_t adj_lds_bytes(const Model& m, bool fp64) {
+  const size_t Lp = m.L_pad, ns = n_sums(m.S);
+  if (fp64) return (size_t)2 * kTile64 * (Lp + 1) * 8 + Lp * ns * 8;
+  return (size_t)4 * kTileNu * (Lp + 8) * 2 + Lp * ns * 8 + Lp * 4;
+}
+
+template <bool F64, int S, bool CIA>
+const void* adj_kernel() {
+  if constexpr (F64) return (const void*)k_trans_adj_fp64<S, CIA>;
+  else return (const void*)k_trans_adj_mixed<S, CIA>;
+}
+
+template <bool F64>
+const void* adj_kernel_for(int S, bool cia) {
+#define EXOFWD_CASE(n) \
+  case n: return cia ? adj_kernel<F64, n, true>() : adj_kernel<F64, n, false>();
+  switch (S) {
+    EXOFWD_CASE(1) EXOFWD_CASE(2) EXOFWD_CASE(3) EXOFWD_CASE(4)
+    EXOFWD_CASE(5) EXOFWD_CASE(6) EXOFWD_CASE(7) EXOFWD_CASE(8)
+  }
+#undef EXOFWD_CASE
+  return nullptr;
+}
+
+hipError_t adjoint_configure(const Model& m, bool fp64) {
+  if (!adjoint_supported(m)) return hipSuccess;
+  const void* k = fp64 ? adj_kernel_for<true>(m.S, m.has_cia) : adj_kernel_for<false>(m.S, m.has_cia);
+  if (!k) return hipErrorInvalidValue;
+  const size_t bytes = adj_lds_bytes(m, fp64);
+  if (bytes > 160 * 1024) return hipErrorInvalidValue;
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+void launch_trans_adjoint(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, bool fp64,
+                          hipStream_t st) {
+  int C = adjoint_chunks(m, B, fp64);
+  void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&aw, (void*)&B, (void*)&C};
+  const void* k = fp64 ? adj_kernel_for<true>(m.S, m.has_cia) : adj_kernel_for<false>(m.S, m.has_cia);
+  hipLaunchKernel(k, dim3((unsigned)(B * C)), dim3(kBlockT), args, adj_lds_bytes(m, fp64), st);
+}
+
+void launch_chain(const Model& m, const Work& w, const AdjWork& aw, int B, const double* params, const uint8_t* mask,
+                  double* grad, bool fp64, hipStream_t st) {
+  const int C = adjoint_chunks(m, B, fp64);
+  if (fp64)
+    hipLaunchKernelGGL(k_chain<double>, dim3(B), dim3(kBlock), 0, st, m, w, aw, C, params, mask, grad);
+  else
+    hipLaunchKernelGGL(k_chain<float>, dim3(B), dim3(kBlock), 0, st, m, w, aw, C, params, mask, grad);
+}
+
 }  // namespace exofwd

@@ -74,6 +74,8 @@ struct Work {
   void* spec;           // [B][n_nu] internal spectrum when the caller passes none
   double* dm;           // [B][K] d lnL / d m_k
   double* lnl_tmp;      // [B]
+  const int32_t* bin_of;  // [n_nu_pad] bin holding each wavenumber, -1 if none
+  const double* inv_cnt;  // [K] 1 / (hi_k - lo_k)
 };
 
 // Tables on the device.

@@ -195,9 +195,12 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
     return EXOFWD_ERR_CONFIG;
   if (!(g.mu_fixed > 0.0) && !g.species_mass) return EXOFWD_ERR_CONFIG;
   if (g.n_bins < 1 || !g.bin_lo || !g.bin_hi || !g.y_obs || !g.y_err) return EXOFWD_ERR_CONFIG;
-  for (int k = 0; k < g.n_bins; ++k)
+  for (int k = 0; k < g.n_bins; ++k) {
     if (g.bin_lo[k] < 0 || g.bin_hi[k] > g.n_nu || g.bin_lo[k] >= g.bin_hi[k] || !(g.y_err[k] > 0.0))
       return EXOFWD_ERR_CONFIG;
+    // bins are ordered and disjoint, so every wavenumber feeds at most one bin
+    if (k > 0 && g.bin_lo[k] < g.bin_hi[k - 1]) return EXOFWD_ERR_CONFIG;
+  }
   if (!(g.p_bot_bar > g.p_top_bar) || !(g.p_top_bar > 0.0) || !(g.p_ref_bar > 0.0)) return EXOFWD_ERR_CONFIG;
   if (!(g.r_p > 0.0) || !(g.r_s > 0.0) || !(g.g_ref > 0.0)) return EXOFWD_ERR_CONFIG;
   if (g.mode == EXOFWD_EMISSION && (g.n_mu < 1 || g.n_mu > kMaxMu || !(g.t_star > 0.0))) return EXOFWD_ERR_CONFIG;
@@ -373,6 +376,19 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   w.spec = A(dalloc<unsigned char>(c, (size_t)B * m.n_nu * rs));
   w.dm = A(dalloc<double>(c, (size_t)B * m.K));
   w.lnl_tmp = A(dalloc<double>(c, B));
+  {
+    int32_t* d_bin = A(dalloc<int32_t>(c, np));
+    double* d_inv = A(dalloc<double>(c, m.K));
+    std::vector<int32_t> bin_of(np, -1);
+    std::vector<double> inv(m.K);
+    for (int k2 = 0; k2 < m.K; ++k2) {
+      for (int i = g.bin_lo[k2]; i < g.bin_hi[k2]; ++i) bin_of[i] = k2;
+      inv[k2] = 1.0 / (double)(g.bin_hi[k2] - g.bin_lo[k2]);
+    }
+    if (ok) ok = upload(d_bin, bin_of.data(), np) && upload(d_inv, inv.data(), m.K);
+    w.bin_of = d_bin;
+    w.inv_cnt = d_inv;
+  }
   if (ok && m.mode == kTransmission) ok = adjoint_alloc(c->aw, m, B, fp64, [&](size_t bytes) {
     return (void*)dalloc<unsigned char>(c, bytes);
   });
@@ -436,7 +452,8 @@ exofwd_status exofwd_grad(exofwd_ctx* c, int32_t B, const double* params, const 
   if (s) return s;
   if (!lnL || !grad) return fail(c, EXOFWD_ERR_ARG, "lnL and grad are required");
   if (c->m.mode != kTransmission) return fail(c, EXOFWD_ERR_UNSUPPORTED, "the adjoint covers transmission only");
-  if (!adjoint_ready()) return fail(c, EXOFWD_ERR_UNSUPPORTED, "adjoint not available in this build");
+  if (!adjoint_supported(c->m))
+    return fail(c, EXOFWD_ERR_UNSUPPORTED, "the adjoint needs n_layers_max <= 128 and a non-PCHIP profile");
   if ((s = exofwd_forward(c, B, params, n_layers, spectra, lnL, status, hip_stream))) return s;
   hipStream_t st = (hipStream_t)hip_stream;
   const bool fp64 = c->precision == EXOFWD_PREC_FP64;

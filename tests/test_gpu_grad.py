@@ -1,0 +1,120 @@
+"""GPU adjoint (d lnL / d params) against the FP64 oracle's complex-step
+gradient and against central differences.
+
+Per-component error is |g - g*| / max(|g*_j|, 1e-3 max_j |g*_j|).
+Tolerances: FP64 path 1e-5; reduced-precision path 1e-3.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity_util import reduced
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL = {"fp64": 1e-5, "mixed": 1e-3}
+
+
+def grad_err(g, gref):
+    scale = np.maximum(np.abs(gref), 1e-3 * np.max(np.abs(gref)))
+    return np.max(np.abs(g - gref) / scale)
+
+
+def _grad(wl, prec, params, n_layers=None):
+    from paper_2602_19687_amd import ForwardModel
+    print(f"[gpu] grad cid={wl['cid']} prec={prec} B={len(params)} n_nu={len(wl['nu'])}", flush=True)
+    fm = ForwardModel(wl, precision=prec, batch_max=len(params))
+    th = torch.tensor(params, dtype=torch.float64, device="cuda")
+    lnl, g, st, _ = fm.grad(th, n_layers=n_layers)
+    _, lnl_f, _ = fm.forward(th, n_layers=n_layers, want_spectra=False)
+    torch.cuda.synchronize()
+    out = lnl.cpu().numpy(), g.cpu().numpy(), st.cpu().numpy(), lnl_f.cpu().numpy()
+    fm.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_reduced_grad_vs_complex_step(prec):
+    wl = reduced(3, n_nu=900, n_bins=30, batch=6)
+    lnl, g, st, lnl_f = _grad(wl, prec, wl["params"])
+    assert np.array_equal(lnl, lnl_f)
+    errs = []
+    for b in range(len(wl["params"])):
+        gref = oracle.grad_complex_step(wl, wl["params"][b])
+        assert st[b] == 0
+        e = grad_err(g[b], gref)
+        errs.append(e)
+        print(f"sample {b}: grad err {e:.3e}\n  gpu {g[b]}\n  ref {gref}")
+    print(f"reduced {prec}: max grad err {max(errs):.3e}")
+    assert max(errs) < TOL[prec]
+
+
+def test_isothermal_single_absorber_grad():
+    wl = synth.workload(0)
+    for prec in ("fp64", "mixed"):
+        lnl, g, st, _ = _grad(wl, prec, wl["params"])
+        gref = oracle.grad_complex_step(wl, wl["params"][0])
+        e = grad_err(g[0], gref)
+        print(f"c0 {prec}: {g[0]} vs {gref}: {e:.3e}")
+        assert e < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_full_c3_sampled(prec):
+    wl = synth.workload(3)
+    lnl, g, st, _ = _grad(wl, prec, wl["params"])
+    for b in (5, 77):
+        gref = oracle.grad_complex_step(wl, wl["params"][b])
+        e = grad_err(g[b], gref)
+        print(f"c3 {prec} sample {b}: grad err {e:.3e}")
+        assert e < TOL[prec]
+    assert np.all(np.isfinite(g[st == 0]))
+    assert np.all(g[st != 0] == 0)
+
+
+def test_fp64_grad_vs_central_differences_of_gpu_forward():
+    """Independent of the oracle: the FP64 adjoint against central differences of the
+    FP64 GPU forward model (h_j = 1e-6 max(1, |theta_j|))."""
+    from paper_2602_19687_amd import ForwardModel
+    wl = reduced(3, n_nu=640, n_bins=20, batch=2)
+    th0 = wl["params"][:2]
+    P = th0.shape[1]
+    fm = ForwardModel(wl, precision="fp64", batch_max=2 * P)
+    lnl, g, st, _ = fm.grad(torch.tensor(th0, device="cuda"))
+    g = g.cpu().numpy()
+    for b in range(2):
+        h = 1e-6 * np.maximum(1.0, np.abs(th0[b]))
+        plus = th0[b][None, :] + np.diag(h)
+        minus = th0[b][None, :] - np.diag(h)
+        _, lp, _ = fm.forward(torch.tensor(plus, device="cuda"), want_spectra=False)
+        _, lm, _ = fm.forward(torch.tensor(minus, device="cuda"), want_spectra=False)
+        fd = (lp.cpu().numpy() - lm.cpu().numpy()) / (2 * h)
+        e = grad_err(g[b], fd)
+        print(f"FD sample {b}: {e:.3e}")
+        assert e < 1e-5
+    fm.close()
+
+
+def test_autograd_function_backward():
+    from paper_2602_19687_amd import ExoLogLike, ForwardModel
+    wl = reduced(1, n_nu=512, n_bins=16, batch=3)
+    fm = ForwardModel(wl, precision="mixed", batch_max=3)
+    th = torch.tensor(wl["params"], device="cuda", requires_grad=True)
+    lnl = ExoLogLike.apply(th, fm, None)
+    w = torch.tensor([0.5, -1.0, 2.0], device="cuda", dtype=torch.float64)
+    (lnl * w).sum().backward()
+    _, g, _, _ = fm.grad(th.detach())
+    np.testing.assert_allclose(th.grad.cpu().numpy(), (w[:, None] * g).cpu().numpy(), rtol=1e-14)
+    fm.close()
+
+
+def test_invalid_samples_zero_gradient():
+    wl = reduced(1, n_nu=300, n_bins=5, batch=3)
+    th = wl["params"].copy()
+    th[1, 3] = -0.01
+    th[1, 4] = -0.3
+    lnl, g, st, _ = _grad(wl, "mixed", th)
+    assert st[1] != 0 and lnl[1] == -1e300 and np.all(g[1] == 0)
+    assert st[0] == 0 and np.all(np.isfinite(g[0])) and np.any(g[0] != 0)
