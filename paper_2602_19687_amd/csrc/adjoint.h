@@ -18,10 +18,15 @@ constexpr int kExtraSums = 6;
 __host__ __device__ constexpr int n_sums(int s) { return s + kExtraSums; }
 
 struct AdjWork {
-  int max_pairs;       // allocated (sample, chunk) pairs
-  double* layer_sums;  // [pair][L_pad][n_sums]
+  int max_pairs;       // allocated (sample, chunk) pairs of the fused reverse kernel
+  double* layer_sums;  // FP64 path: [pair][L_pad][n_sums]
   void* pbar;          // [pair][L_pad][L_pad] d lnL / d P_il (row i, column l), float (mixed) or double (FP64)
   double* abar;        // [pair][L_pad] d lnL / d area_i
+  // reduced-precision path: the fused kernel stores dtau_bar, a second kernel forms the layer sums
+  float* dtau;         // [B_max][L_max][n_nu_pad] layer optical depths stored by the forward kernel
+  float* dtb;          // [B_max][L_max][n_nu_pad] d lnL / d dtau_l(nu)
+  float* lsum;         // [B_max][lsum_chunks][L_pad][n_sums] partial layer sums
+  int lsum_chunks;     // wavenumber chunks of the layer-sum kernel
 };
 
 // wavenumber chunks per sample for a batch of B (pair index = b * chunks + chunk)
@@ -30,6 +35,8 @@ bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std:
 hipError_t adjoint_configure(const Model& m, bool fp64);
 void launch_trans_adjoint(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, bool fp64,
                           hipStream_t st);
+// reduced-precision path only: per-layer sums from the stored dtau_bar
+void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, hipStream_t st);
 void launch_chain(const Model& m, const Work& w, const AdjWork& aw, int B, const double* params, const uint8_t* mask,
                   double* grad, bool fp64, hipStream_t st);
 // whether the adjoint supports this workload (transmission, L_pad <= 128, no PCHIP profile)

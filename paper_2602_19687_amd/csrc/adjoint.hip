@@ -76,8 +76,11 @@ constexpr int kPSlots = 2;   // path-matrix adjoint tiles per wave
 
 // ============================================================================
 // reduced-precision reverse kernel: 512 threads, 128-wavenumber tiles
+constexpr int kTileA = 64;     // wavenumbers per tile of the reduced-precision reverse kernel
+constexpr int kPSlotsA = 3;    // 32x32 Pbar tiles per wave (10 tiles over 4 waves for L_pad <= 128)
+
 template <int S, bool CIA>
-__global__ __launch_bounds__(kBlockT) void k_trans_adj_mixed(Model m, Work w, Tables tb, AdjWork aw, int B, int C) {
+__global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tables tb, AdjWork aw, int B, int C) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = logical % B, chunk = logical / B;
@@ -85,19 +88,13 @@ __global__ __launch_bounds__(kBlockT) void k_trans_adj_mixed(Model m, Work w, Ta
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int Lp = m.L_pad, L = w.nlay[b];
-  constexpr int NS = n_sums(S);
-  const int stride = Lp + 8;
-  uint16_t* s_dh = reinterpret_cast<uint16_t*>(lds);   // dtau hi  [nu][stride]
-  uint16_t* s_dl = s_dh + kTileNu * stride;            // dtau lo
-  uint16_t* s_th = s_dl + kTileNu * stride;            // tau_bar hi [nu][stride]
-  uint16_t* s_tl = s_th + kTileNu * stride;            // tau_bar lo
-  float* s_dtb = reinterpret_cast<float*>(s_th);       // dtau_bar [Lp][128] (after the products)
-  double* s_sums = reinterpret_cast<double*>(s_tl + kTileNu * stride);  // [Lp][NS]
-  float* s_area = reinterpret_cast<float*>(s_sums + (size_t)Lp * NS);   // [Lp]
+  const int ld = Lp + 4;                               // floats per wavenumber row (b128-conflict-free)
+  float* s_dt = reinterpret_cast<float*>(lds);         // dtau      [nu][ld]
+  float* s_tt = s_dt + kTileA * ld;                    // tau_bar   [nu][ld]
+  float* s_area = s_tt + kTileA * ld;                  // [Lp]
 
   const float* area = reinterpret_cast<const float*>(w.area) + (size_t)b * Lp;
-  for (int i = tid; i < Lp; i += kBlockT) s_area[i] = area[i];
-  for (int i = tid; i < Lp * NS; i += kBlockT) s_sums[i] = 0.0;
+  for (int i = tid; i < Lp; i += kBlock) s_area[i] = area[i];
 
   const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * rec_len(S);
   const int32_t* cells = w.cells + (size_t)b * Lp;
@@ -109,10 +106,10 @@ __global__ __launch_bounds__(kBlockT) void k_trans_adj_mixed(Model m, Work w, Ta
   const __amdgpu_buffer_rsrc_t rh = make_rsrc(tb.h, (size_t)S * m.n_t * m.n_p * npad * 2);
   const __amdgpu_buffer_rsrc_t rhc = make_rsrc(CIA ? (const void*)tb.hc : (const void*)tb.h,
                                                CIA ? (size_t)2 * m.n_tc * npad * 2 : 0);
-  const uint32_t voff = (uint32_t)lane * 4u;
+  const uint32_t voff = (uint32_t)lane * 2u;
 
   const int KBe = (L + 15) >> 4, MBe = (L + 31) >> 5, KB = Lp >> 4;
-  const int nb = wv & 3, part = wv >> 2;
+  const int nb = wv & 1, part = wv >> 1;
   const unsigned mine_t = split_blocks(part, MBe, KBe, false);   // rows i of tau
   const unsigned mine_d = split_blocks(part, MBe, KBe, true);    // rows l of dtau_bar
   const size_t plane = (size_t)(Lp >> 5) * KB * 512;
@@ -124,57 +121,46 @@ __global__ __launch_bounds__(kBlockT) void k_trans_adj_mixed(Model m, Work w, Ta
   const int h = lane >> 5;
   const double* dm = w.dm + (size_t)b * m.K;
 
-  // path-matrix adjoint tiles (32x32 blocks with column block >= row block), round-robin over waves
-  int pt_mi[kPSlots], pt_nl[kPSlots];
+  // Pbar tiles (32x32, column block >= row block), round-robin over the 4 waves
+  int pt_mi[kPSlotsA], pt_nl[kPSlotsA];
   {
     int t = 0;
-    for (int q = 0; q < kPSlots; ++q) pt_mi[q] = pt_nl[q] = -1;
+    for (int q = 0; q < kPSlotsA; ++q) pt_mi[q] = pt_nl[q] = -1;
     for (int mi = 0; mi < MBe; ++mi)
       for (int nl = mi; nl < MBe; ++nl, ++t)
-        if (t % 8 == wv && t / 8 < kPSlots) {
-          pt_mi[t / 8] = mi;
-          pt_nl[t / 8] = nl;
+        if ((t & 3) == wv && (t >> 2) < kPSlotsA) {
+          pt_mi[t >> 2] = mi;
+          pt_nl[t >> 2] = nl;
         }
   }
-  f32x16 abar_acc[kSlots], pbar_acc[kPSlots];
+  f32x16 abar_acc[kSlots], pbar_acc[kPSlotsA];
 #pragma unroll
   for (int q = 0; q < kSlots; ++q) abar_acc[q] = f32x16{};
 #pragma unroll
-  for (int q = 0; q < kPSlots; ++q) pbar_acc[q] = f32x16{};
+  for (int q = 0; q < kPSlotsA; ++q) pbar_acc[q] = f32x16{};
 
-  const int t0 = chunk * m.n_tiles / C, t1 = (chunk + 1) * m.n_tiles / C;
+  const int ntiles = m.n_nu_pad / kTileA;
+  const int t0 = chunk * ntiles / C, t1 = (chunk + 1) * ntiles / C;
   for (int tile = t0; tile < t1; ++tile) {
-    const int nu0 = tile * kTileNu;
-    // ---- phase A: layer optical depths -> bf16 hi/lo [nu][l]
+    const int nu0 = tile * kTileA;
+    // ---- phase A: layer optical depths of the tile (stored by the forward kernel) -> LDS [nu][l]
     {
-      const LaneConst<S> kc = load_lane<S, CIA>(m, tb, nu0 + 2 * lane);
-      for (int o = wv; o < 4 * MBe; o += kBlockT / 64) {
-        uint16_t h0[8], l0[8], h1[8], l1[8];
-#pragma unroll 2
+      const float* src = aw.dtau + (size_t)b * m.L_max * npad + nu0 + lane;
+      for (int o = wv; o < 4 * MBe; o += kBlock / 64) {
+        float d[8];
+#pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int l = 8 * o + j;
-          float d0 = 0.0f, d1 = 0.0f;
-          if (l < L) {
-            const LayerCoef<S> c = load_layer<S>(m, cells, rec, l, (uint32_t)nu0 * 2u, g);
-            layer_terms<S, CIA, false>(c, kc, g, rh, rhc, voff, d0, d1);
-            d0 = fminf(d0, 16384.0f);
-            d1 = fminf(d1, 16384.0f);
-          }
-          h0[j] = bf16_bits_rn(d0);
-          l0[j] = bf16_bits_rn(d0 - bf16_bits_to_f(h0[j]));
-          h1[j] = bf16_bits_rn(d1);
-          l1[j] = bf16_bits_rn(d1 - bf16_bits_to_f(h1[j]));
+          d[j] = l < L ? src[(size_t)l * npad] : 0.0f;
         }
-        const int r0 = (2 * lane) * stride + 8 * o, r1 = r0 + stride;
-        *reinterpret_cast<uint4*>(s_dh + r0) = make_uint4(pack2(h0[0], h0[1]), pack2(h0[2], h0[3]), pack2(h0[4], h0[5]), pack2(h0[6], h0[7]));
-        *reinterpret_cast<uint4*>(s_dl + r0) = make_uint4(pack2(l0[0], l0[1]), pack2(l0[2], l0[3]), pack2(l0[4], l0[5]), pack2(l0[6], l0[7]));
-        *reinterpret_cast<uint4*>(s_dh + r1) = make_uint4(pack2(h1[0], h1[1]), pack2(h1[2], h1[3]), pack2(h1[4], h1[5]), pack2(h1[6], h1[7]));
-        *reinterpret_cast<uint4*>(s_dl + r1) = make_uint4(pack2(l1[0], l1[1]), pack2(l1[2], l1[3]), pack2(l1[4], l1[5]), pack2(l1[6], l1[7]));
+        float* dst = s_dt + lane * ld + 8 * o;
+        *reinterpret_cast<float4*>(dst) = make_float4(d[0], d[1], d[2], d[3]);
+        *reinterpret_cast<float4*>(dst + 4) = make_float4(d[4], d[5], d[6], d[7]);
       }
     }
     __syncthreads();
 
-    // ---- phases B, C: tau = P dtau; seeds; tau_bar -> [nu][i]; abar accumulation
+    // ---- phases B, C: tau = P dtau; seeds; tau_bar -> LDS [nu][i]; abar accumulation
     {
       const int nu_g = nu0 + col;
       const int bin = w.bin_of[nu_g];
@@ -189,132 +175,75 @@ __global__ __launch_bounds__(kBlockT) void k_trans_adj_mixed(Model m, Work w, Ta
           const size_t fo = ((size_t)(mi * KB + kb) * 64 + lane) * 8;
           const bf16x8 ah = *reinterpret_cast<const bf16x8*>(fh + fo);
           const bf16x8 al = *reinterpret_cast<const bf16x8*>(fl + fo);
-          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(s_dh + col * stride + 16 * kb + 8 * h);
-          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(s_dl + col * stride + 16 * kb + 8 * h);
+          bf16x8 bh, bl;
+          split8(s_dt + col * ld + 16 * kb + 8 * h, bh, bl);
           acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
           acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
           acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
         }
 #pragma unroll
         for (int qd = 0; qd < 4; ++qd) {
-          uint16_t hv[4], lv[4];
+          float tv[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int j = 4 * qd + r;
             const int row = 32 * mi + 8 * qd + 4 * h + r;
             const float e = exp2_fast(-1.4426950408889634f * acc[j]);
             abar_acc[q][j] = fmaf(dbar, 1.0f - e, abar_acc[q][j]);
-            const float tb_ = dbar * s_area[row] * e;
-            hv[r] = bf16_bits_rn(tb_);
-            lv[r] = bf16_bits_rn(tb_ - bf16_bits_to_f(hv[r]));
+            tv[r] = dbar * s_area[row] * e;
           }
-          const int off = col * stride + 32 * mi + 8 * qd + 4 * h;
-          *reinterpret_cast<uint2*>(s_th + off) = make_uint2(pack2(hv[0], hv[1]), pack2(hv[2], hv[3]));
-          *reinterpret_cast<uint2*>(s_tl + off) = make_uint2(pack2(lv[0], lv[1]), pack2(lv[2], lv[3]));
+          *reinterpret_cast<float4*>(s_tt + col * ld + 32 * mi + 8 * qd + 4 * h) = make_float4(tv[0], tv[1], tv[2], tv[3]);
         }
       }
     }
     __syncthreads();
 
-    // ---- phase E: Pbar += tau_bar dtau^T over this tile's wavenumbers
+    // ---- phase E: Pbar += tau_bar dtau^T over the tile's wavenumbers (FP32 MFMA, k = wavenumber)
 #pragma unroll
-    for (int q = 0; q < kPSlots; ++q) {
+    for (int q = 0; q < kPSlotsA; ++q) {
       const int mi = pt_mi[q], nl = pt_nl[q];
       if (mi < 0) continue;
-      const int ri = 32 * mi + (lane & 31), cl = 32 * nl + (lane & 31);
-#pragma unroll 1
-      for (int ks = 0; ks < kTileNu / 16; ++ks) {
-        const int nu_r = 16 * ks + 8 * h;
-        const bf16x8 ah = gather8(s_th + nu_r * stride + ri, stride);
-        const bf16x8 al = gather8(s_tl + nu_r * stride + ri, stride);
-        const bf16x8 bh = gather8(s_dh + nu_r * stride + cl, stride);
-        const bf16x8 bl = gather8(s_dl + nu_r * stride + cl, stride);
-        pbar_acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, pbar_acc[q], 0, 0, 0);
-        pbar_acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, pbar_acc[q], 0, 0, 0);
-        pbar_acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, pbar_acc[q], 0, 0, 0);
-      }
+      const float* pa = s_tt + h * ld + 32 * mi + (lane & 31);
+      const float* pbp = s_dt + h * ld + 32 * nl + (lane & 31);
+#pragma unroll 4
+      for (int ks = 0; ks < kTileA / 2; ++ks)
+        pbar_acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(pa[2 * ks * ld], pbp[2 * ks * ld], pbar_acc[q], 0, 0, 0);
     }
-    // ---- phase D: dtau_bar = P^T tau_bar (rows l, this wave's column block)
-    f32x16 dtb[kSlots];
-#pragma unroll
-    for (int q = 0; q < kSlots; ++q) {
-      dtb[q] = f32x16{};
-      const int ml = nth_bit(mine_d, q);
-      if (ml < 0) continue;
-      const int kend = min(2 * ml + 2, KBe);
-#pragma unroll 1
-      for (int ki = 0; ki < kend; ++ki) {
-        const size_t fo = ((size_t)(ml * KB + ki) * 64 + lane) * 8;
-        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(th_ + fo);
-        const bf16x8 al = *reinterpret_cast<const bf16x8*>(tl_ + fo);
-        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(s_th + col * stride + 16 * ki + 8 * h);
-        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(s_tl + col * stride + 16 * ki + 8 * h);
-        dtb[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, dtb[q], 0, 0, 0);
-        dtb[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, dtb[q], 0, 0, 0);
-        dtb[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, dtb[q], 0, 0, 0);
-      }
-    }
-    __syncthreads();
-    // dtau_bar -> LDS [l][nu] FP32
-#pragma unroll
-    for (int q = 0; q < kSlots; ++q) {
-      const int ml = nth_bit(mine_d, q);
-      if (ml < 0) continue;
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int row = 32 * ml + 8 * (j >> 2) + 4 * h + (j & 3);
-        s_dtb[row * kTileNu + col] = dtb[q][j];
-      }
-    }
-    __syncthreads();
-
-    // ---- phase G: per-layer sums of dtau_bar times each opacity source
+    // ---- phase D: dtau_bar = P^T tau_bar (rows l, this wave's column block) -> HBM
     {
-      const LaneConst<S> kc = load_lane<S, CIA>(m, tb, nu0 + 2 * lane);
-      for (int l = wv; l < L; l += kBlockT / 64) {
-        const LayerCoef<S> c = load_layer<S>(m, cells, rec, l, (uint32_t)nu0 * 2u, g);
-        float d0, d1, t0[S + 2], t1[S + 2], dw0[S + 2], dw1[S + 2];
-        layer_terms<S, CIA, true>(c, kc, g, rh, rhc, voff, d0, d1, t0, t1, dw0, dw1);
-        const float2 db = *reinterpret_cast<const float2*>(s_dtb + l * kTileNu + 2 * lane);
-        float sums[NS];
-        float ht = 0.0f, htc = 0.0f;
+      float* dst = aw.dtb + (size_t)b * m.L_max * npad + nu0 + col;
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-          const float a0 = db.x * t0[s], a1 = db.y * t1[s];
-          sums[s] = a0 + a1;
-          ht = fmaf(a0, dw0[s], fmaf(a1, dw1[s], ht));
+      for (int q = 0; q < kSlots; ++q) {
+        const int ml = nth_bit(mine_d, q);
+        if (ml < 0) continue;
+        f32x16 acc = {};
+        const int kend = min(2 * ml + 2, KBe);
+#pragma unroll 1
+        for (int ki = 0; ki < kend; ++ki) {
+          const size_t fo = ((size_t)(ml * KB + ki) * 64 + lane) * 8;
+          const bf16x8 ah = *reinterpret_cast<const bf16x8*>(th_ + fo);
+          const bf16x8 al = *reinterpret_cast<const bf16x8*>(tl_ + fo);
+          bf16x8 bh, bl;
+          split8(s_tt + col * ld + 16 * ki + 8 * h, bh, bl);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
         }
-        sums[S] = ht;
-        if (CIA) {
 #pragma unroll
-          for (int p = 0; p < 2; ++p) {
-            const float a0 = db.x * t0[S + p], a1 = db.y * t1[S + p];
-            sums[S + 1 + p] = a0 + a1;
-            htc = fmaf(a0, dw0[S + p], fmaf(a1, dw1[S + p], htc));
-          }
-        } else {
-          sums[S + 1] = sums[S + 2] = 0.0f;
-        }
-        sums[S + 3] = htc;
-        sums[S + 4] = fmaf(db.x, kc.nu4_0, db.y * kc.nu4_1);
-        sums[S + 5] = db.x + db.y;
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-          const float tot = wave_sum(sums[k]);
-          if (lane == 0) s_sums[l * NS + k] += (double)tot;
+        for (int j = 0; j < 16; ++j) {
+          const int row = 32 * ml + 8 * (j >> 2) + 4 * h + (j & 3);
+          if (row < L) dst[(size_t)row * npad] = acc[j];
         }
       }
     }
+    __syncthreads();   // the next tile overwrites dtau and tau_bar
   }
-  __syncthreads();
 
   // ---- write this chunk's partials
   const size_t pair = (size_t)b * C + chunk;
-  double* ls = aw.layer_sums + pair * Lp * NS;
-  for (int i = tid; i < Lp * NS; i += kBlockT) ls[i] = s_sums[i];
   float* pb = reinterpret_cast<float*>(aw.pbar) + pair * Lp * Lp;
 #pragma unroll
-  for (int q = 0; q < kPSlots; ++q) {
+  for (int q = 0; q < kPSlotsA; ++q) {
     const int mi = pt_mi[q], nl = pt_nl[q];
     if (mi < 0) continue;
 #pragma unroll
@@ -323,14 +252,11 @@ __global__ __launch_bounds__(kBlockT) void k_trans_adj_mixed(Model m, Work w, Ta
       pb[(size_t)row * Lp + 32 * nl + (lane & 31)] = pbar_acc[q][j];
     }
   }
-  double* ab = aw.abar + pair * Lp;
+  // abar: reduce over the 32 columns of each lane half, then over the two column blocks
 #pragma unroll
   for (int q = 0; q < kSlots; ++q) {
     const int mi = nth_bit(mine_t, q);
     if (mi < 0) continue;
-    // this wave holds rows of block mi for column block nb; the other wave pair
-    // member holds other rows, and the four column blocks are four waves:
-    // reduce over the 32 columns here, then over column blocks through LDS
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       float v = abar_acc[q][j];
@@ -338,10 +264,7 @@ __global__ __launch_bounds__(kBlockT) void k_trans_adj_mixed(Model m, Work w, Ta
       abar_acc[q][j] = v;
     }
   }
-  // column blocks 0..3 of the same rows live in waves nb = 0..3 with the same
-  // `part`; sum them in LDS (reuse s_sums region, all waves are past the loop)
-  double* s_ab = s_sums;   // [4][Lp]
-  __syncthreads();
+  double* s_ab = reinterpret_cast<double*>(lds);   // [2][Lp], all waves are past the loop
 #pragma unroll
   for (int q = 0; q < kSlots; ++q) {
     const int mi = nth_bit(mine_t, q);
@@ -355,8 +278,93 @@ __global__ __launch_bounds__(kBlockT) void k_trans_adj_mixed(Model m, Work w, Ta
     }
   }
   __syncthreads();
-  for (int i = tid; i < Lp; i += kBlockT)
-    ab[i] = i < 32 * MBe ? (s_ab[i] + s_ab[Lp + i]) + (s_ab[2 * Lp + i] + s_ab[3 * Lp + i]) : 0.0;
+  double* ab = aw.abar + pair * Lp;
+  for (int i = tid; i < Lp; i += kBlock) ab[i] = i < 32 * MBe ? s_ab[i] + s_ab[Lp + i] : 0.0;
+}
+
+// ============================================================================
+// reduced-precision per-layer sums: one wave per (sample, 4 layers, 8 tiles);
+// lanes hold two wavenumbers, partial sums stay in registers across the tiles
+// and are reduced over the wave once
+constexpr int kLsLayers = 4;
+constexpr int kLsTiles = 8;
+
+template <int S, bool CIA>
+__global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Tables tb, AdjWork aw, int B) {
+  constexpr int NS = n_sums(S);
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int NG = (m.L_max + kLsLayers - 1) / kLsLayers;
+  const int per_chunk = B * NG;
+  const int chunk = gw / per_chunk;
+  if (chunk >= aw.lsum_chunks) return;
+  const int rem = gw - chunk * per_chunk;
+  const int b = rem / NG, lg = rem - b * NG;
+  if (w.status[b]) return;
+  const int L = w.nlay[b];
+  const int l0 = lg * kLsLayers;
+  if (l0 >= L) return;
+  const int Lp = m.L_pad;
+  const size_t npad = (size_t)m.n_nu_pad;
+  TableGeom g;
+  g.row_bytes = (uint32_t)npad * 2u;
+  g.tstep = (uint32_t)m.n_p * g.row_bytes;
+  g.pstep = g.row_bytes;
+  const __amdgpu_buffer_rsrc_t rh = make_rsrc(tb.h, (size_t)S * m.n_t * m.n_p * npad * 2);
+  const __amdgpu_buffer_rsrc_t rhc = make_rsrc(CIA ? (const void*)tb.hc : (const void*)tb.h,
+                                               CIA ? (size_t)2 * m.n_tc * npad * 2 : 0);
+  const uint32_t voff = (uint32_t)lane * 4u;
+  const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * rec_len(S);
+  const int32_t* cells = w.cells + (size_t)b * Lp;
+  const float* dtb = aw.dtb + (size_t)b * m.L_max * npad;
+
+  float acc[kLsLayers][NS];
+#pragma unroll
+  for (int q = 0; q < kLsLayers; ++q)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) acc[q][k] = 0.0f;
+
+  const int t0 = chunk * kLsTiles, t1 = min(t0 + kLsTiles, m.n_tiles);
+  for (int tile = t0; tile < t1; ++tile) {
+    const int nu0 = tile * kTileNu;
+    const LaneConst<S> kc = load_lane<S, CIA>(m, tb, nu0 + 2 * lane);
+#pragma unroll
+    for (int q = 0; q < kLsLayers; ++q) {
+      const int l = l0 + q;
+      if (l >= L) continue;
+      const LayerCoef<S> c = load_layer<S>(m, cells, rec, l, (uint32_t)nu0 * 2u, g);
+      float d0, d1, t0_[S + 2], t1_[S + 2], dw0[S + 2], dw1[S + 2];
+      layer_terms<S, CIA, true>(c, kc, g, rh, rhc, voff, d0, d1, t0_, t1_, dw0, dw1);
+      const float2 db = *reinterpret_cast<const float2*>(dtb + (size_t)l * npad + nu0 + 2 * lane);
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const float a0 = db.x * t0_[s], a1 = db.y * t1_[s];
+        acc[q][s] += a0 + a1;
+        acc[q][S] = fmaf(a0, dw0[s], fmaf(a1, dw1[s], acc[q][S]));
+      }
+      if (CIA) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          const float a0 = db.x * t0_[S + p], a1 = db.y * t1_[S + p];
+          acc[q][S + 1 + p] += a0 + a1;
+          acc[q][S + 3] = fmaf(a0, dw0[S + p], fmaf(a1, dw1[S + p], acc[q][S + 3]));
+        }
+      }
+      acc[q][S + 4] = fmaf(db.x, kc.nu4_0, fmaf(db.y, kc.nu4_1, acc[q][S + 4]));
+      acc[q][S + 5] += db.x + db.y;
+    }
+  }
+  float* out = aw.lsum + ((size_t)b * aw.lsum_chunks + chunk) * Lp * NS;
+#pragma unroll
+  for (int q = 0; q < kLsLayers; ++q) {
+    const int l = l0 + q;
+    if (l >= L) continue;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const float tot = wave_sum(acc[q][k]);
+      if (lane == 0) out[(size_t)l * NS + k] = tot;
+    }
+  }
 }
 
 // ============================================================================
@@ -645,7 +653,11 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
     double sm[kMaxSpecies + kExtraSums];
     for (int k = 0; k < NS; ++k) {
       double v = 0.0;
-      for (int c = 0; c < C; ++c) v += aw.layer_sums[(((size_t)b * C + c) * Lp + l) * NS + k];
+      if constexpr (sizeof(PbarT) == 8) {
+        for (int c = 0; c < C; ++c) v += aw.layer_sums[(((size_t)b * C + c) * Lp + l) * NS + k];
+      } else {
+        for (int c = 0; c < aw.lsum_chunks; ++c) v += (double)aw.lsum[(((size_t)b * aw.lsum_chunks + c) * Lp + l) * NS + k];
+      }
       sm[k] = v;
     }
     const double t = s_t[l];
@@ -838,7 +850,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
 // ============================================================================
 // host side
 int adjoint_chunks(const Model& m, int B, bool fp64) {
-  const int tiles = fp64 ? m.n_tiles64 : m.n_tiles;
+  const int tiles = m.n_tiles64;   // both reverse kernels walk 64-wavenumber tiles
   int c = (1024 + B - 1) / B;
   return c < 1 ? 1 : (c > tiles ? tiles : c);
 }
@@ -852,16 +864,25 @@ bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std:
   for (int B = 1; B <= B_max; ++B) pairs = std::max(pairs, B * adjoint_chunks(m, B, fp64));
   aw.max_pairs = pairs;
   const size_t Lp = m.L_pad;
-  aw.layer_sums = (double*)alloc((size_t)pairs * Lp * n_sums(m.S) * sizeof(double));
   aw.pbar = alloc((size_t)pairs * Lp * Lp * (fp64 ? sizeof(double) : sizeof(float)));
   aw.abar = (double*)alloc((size_t)pairs * Lp * sizeof(double));
-  return aw.layer_sums && aw.pbar && aw.abar;
+  if (!aw.pbar || !aw.abar) return false;
+  if (fp64) {
+    aw.layer_sums = (double*)alloc((size_t)pairs * Lp * n_sums(m.S) * sizeof(double));
+    return aw.layer_sums != nullptr;
+  }
+  aw.lsum_chunks = (m.n_tiles + kLsTiles - 1) / kLsTiles;
+  aw.dtb = (float*)alloc((size_t)B_max * m.L_max * m.n_nu_pad * sizeof(float));
+  aw.dtau = (float*)alloc((size_t)B_max * m.L_max * m.n_nu_pad * sizeof(float));
+  aw.lsum = (float*)alloc((size_t)B_max * aw.lsum_chunks * Lp * n_sums(m.S) * sizeof(float));
+  return aw.dtb && aw.dtau && aw.lsum;
 }
 
 static size_t adj_lds_bytes(const Model& m, bool fp64) {
   const size_t Lp = m.L_pad, ns = n_sums(m.S);
   if (fp64) return (size_t)2 * kTile64 * (Lp + 1) * 8 + Lp * ns * 8;
-  return (size_t)4 * kTileNu * (Lp + 8) * 2 + Lp * ns * 8 + Lp * 4;
+  (void)ns;
+  return (size_t)2 * kTileA * (Lp + 4) * 4 + Lp * 4;
 }
 
 template <bool F64, int S, bool CIA>
@@ -874,6 +895,17 @@ template <bool F64>
 const void* adj_kernel_for(int S, bool cia) {
 #define EXOFWD_CASE(n) \
   case n: return cia ? adj_kernel<F64, n, true>() : adj_kernel<F64, n, false>();
+  switch (S) {
+    EXOFWD_CASE(1) EXOFWD_CASE(2) EXOFWD_CASE(3) EXOFWD_CASE(4)
+    EXOFWD_CASE(5) EXOFWD_CASE(6) EXOFWD_CASE(7) EXOFWD_CASE(8)
+  }
+#undef EXOFWD_CASE
+  return nullptr;
+}
+
+const void* ls_kernel_for(int S, bool cia) {
+#define EXOFWD_CASE(n) \
+  case n: return cia ? (const void*)k_layer_sums_mixed<n, true> : (const void*)k_layer_sums_mixed<n, false>;
   switch (S) {
     EXOFWD_CASE(1) EXOFWD_CASE(2) EXOFWD_CASE(3) EXOFWD_CASE(4)
     EXOFWD_CASE(5) EXOFWD_CASE(6) EXOFWD_CASE(7) EXOFWD_CASE(8)
@@ -896,7 +928,14 @@ void launch_trans_adjoint(const Model& m, const Work& w, const Tables& tb, const
   int C = adjoint_chunks(m, B, fp64);
   void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&aw, (void*)&B, (void*)&C};
   const void* k = fp64 ? adj_kernel_for<true>(m.S, m.has_cia) : adj_kernel_for<false>(m.S, m.has_cia);
-  hipLaunchKernel(k, dim3((unsigned)(B * C)), dim3(kBlockT), args, adj_lds_bytes(m, fp64), st);
+  hipLaunchKernel(k, dim3((unsigned)(B * C)), dim3(fp64 ? kBlockT : kBlock), args, adj_lds_bytes(m, fp64), st);
+}
+
+void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, hipStream_t st) {
+  const int NG = (m.L_max + kLsLayers - 1) / kLsLayers;
+  const long waves = (long)aw.lsum_chunks * B * NG;
+  void* args2[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&aw, (void*)&B};
+  hipLaunchKernel(ls_kernel_for(m.S, m.has_cia), dim3((unsigned)((waves + 3) / 4)), dim3(kBlock), args2, 0, st);
 }
 
 void launch_chain(const Model& m, const Work& w, const AdjWork& aw, int B, const double* params, const uint8_t* mask,

@@ -419,10 +419,19 @@ static exofwd_status check_call(exofwd_ctx* c, int32_t B, const double* params) 
   return EXOFWD_OK;
 }
 
+static exofwd_status run_forward(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers,
+                                 void* spectra, double* lnL, int32_t* status, void* hip_stream, float* dtau_out);
+
 exofwd_status exofwd_forward(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers, void* spectra,
                              double* lnL, int32_t* status, void* hip_stream) {
   exofwd_status s = check_call(c, B, params);
   if (s) return s;
+  return run_forward(c, B, params, n_layers, spectra, lnL, status, hip_stream, nullptr);
+}
+
+static exofwd_status run_forward(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers,
+                                 void* spectra, double* lnL, int32_t* status, void* hip_stream, float* dtau_out) {
+  exofwd_status s = EXOFWD_OK;
   hipStream_t st = (hipStream_t)hip_stream;
   const bool fp64 = c->precision == EXOFWD_PREC_FP64;
   void* spec = spectra ? spectra : c->w.spec;
@@ -432,7 +441,7 @@ exofwd_status exofwd_forward(exofwd_ctx* c, int32_t B, const double* params, con
   if ((s = check_hip(c, hipGetLastError(), "profile launch"))) return s;
   if (c->m.mode == kTransmission) {
     prof_begin(c, "trans_fwd", st);
-    launch_trans_fwd(c->m, c->w, c->tb, B, spec, fp64, st);
+    launch_trans_fwd(c->m, c->w, c->tb, B, spec, fp64, st, dtau_out);
   } else {
     prof_begin(c, "emis_fwd", st);
     launch_emission(c->m, c->w, c->tb, B, spec, fp64, st);
@@ -454,13 +463,21 @@ exofwd_status exofwd_grad(exofwd_ctx* c, int32_t B, const double* params, const 
   if (c->m.mode != kTransmission) return fail(c, EXOFWD_ERR_UNSUPPORTED, "the adjoint covers transmission only");
   if (!adjoint_supported(c->m))
     return fail(c, EXOFWD_ERR_UNSUPPORTED, "the adjoint needs n_layers_max <= 128 and a non-PCHIP profile");
-  if ((s = exofwd_forward(c, B, params, n_layers, spectra, lnL, status, hip_stream))) return s;
+  if ((s = run_forward(c, B, params, n_layers, spectra, lnL, status, hip_stream,
+                       c->precision == EXOFWD_PREC_MIXED ? c->aw.dtau : nullptr)))
+    return s;
   hipStream_t st = (hipStream_t)hip_stream;
   const bool fp64 = c->precision == EXOFWD_PREC_FP64;
   prof_begin(c, "trans_adj", st);
   launch_trans_adjoint(c->m, c->w, c->tb, c->aw, B, fp64, st);
   prof_end(c, st);
   if ((s = check_hip(c, hipGetLastError(), "adjoint launch"))) return s;
+  if (!fp64) {
+    prof_begin(c, "layer_sums", st);
+    launch_layer_sums(c->m, c->w, c->tb, c->aw, B, st);
+    prof_end(c, st);
+    if ((s = check_hip(c, hipGetLastError(), "layer-sum launch"))) return s;
+  }
   prof_begin(c, "chain", st);
   launch_chain(c->m, c->w, c->aw, B, params, c->d_mask, grad, fp64, st);
   prof_end(c, st);

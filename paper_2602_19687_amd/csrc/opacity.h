@@ -174,3 +174,73 @@ __device__ inline uint16_t bf16_bits_rn(float f) {
 __device__ inline float bf16_bits_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 }  // namespace exofwd
+
+namespace exofwd {
+
+// ---- one wavenumber per lane (reverse kernel tiles of 64)
+template <int S>
+struct LaneConst1 {
+  float c[S], cc[2], nu4;
+};
+
+template <int S, bool CIA>
+__device__ inline LaneConst1<S> load_lane1(const Model& m, const Tables& tb, int nu) {
+  LaneConst1<S> k;
+  const size_t np = (size_t)m.n_nu_pad;
+#pragma unroll
+  for (int s = 0; s < S; ++s) k.c[s] = tb.c[s * np + nu];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) k.cc[p] = CIA ? tb.cc[p * np + nu] : 0.0f;
+  k.nu4 = tb.nu4f[nu];
+  return k;
+}
+
+__device__ inline float load_h1(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return (float)__builtin_bit_cast(_Float16, (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+}
+
+// Vertical optical depth of one layer at one wavenumber per lane.
+template <int S, bool CIA>
+__device__ inline float layer_dtau1(const LayerCoef<S>& c, const LaneConst1<S>& k, const TableGeom& g,
+                                    __amdgpu_buffer_rsrc_t rh, __amdgpu_buffer_rsrc_t rhc, uint32_t voff) {
+  float d = fmaf(c.R, k.nu4, c.D);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    float v = k.c[s] + c.lam[s];
+    v = fmaf(c.w00, load_h1(rh, voff, c.row[s]), v);
+    v = fmaf(c.w10, load_h1(rh, voff, c.row[s] + g.tstep), v);
+    v = fmaf(c.w01, load_h1(rh, voff, c.row[s] + g.pstep), v);
+    v = fmaf(c.w11, load_h1(rh, voff, c.row[s] + g.tstep + g.pstep), v);
+    d += exp2_fast(v);
+  }
+  if (CIA) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      float v = k.cc[p] + c.lamc[p];
+      v = fmaf(1.0f - c.wtc, load_h1(rhc, voff, c.rowc[p]), v);
+      v = fmaf(c.wtc, load_h1(rhc, voff, c.rowc[p] + g.row_bytes), v);
+      d += exp2_fast(v);
+    }
+  }
+  return d;
+}
+
+// bf16x8 hi/lo split of eight consecutive floats
+__device__ inline void split8(const float* p, bf16x8& hi, bf16x8& lo) {
+  const float4 a = *reinterpret_cast<const float4*>(p);
+  const float4 b = *reinterpret_cast<const float4*>(p + 4);
+  const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+  uint32_t h[4], l[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint16_t h0 = bf16_bits_rn(v[2 * i]), h1 = bf16_bits_rn(v[2 * i + 1]);
+    const uint16_t l0 = bf16_bits_rn(v[2 * i] - bf16_bits_to_f(h0));
+    const uint16_t l1 = bf16_bits_rn(v[2 * i + 1] - bf16_bits_to_f(h1));
+    h[i] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+    l[i] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+  }
+  hi = __builtin_bit_cast(bf16x8, make_uint4(h[0], h[1], h[2], h[3]));
+  lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));
+}
+
+}  // namespace exofwd

@@ -34,7 +34,8 @@ __device__ inline unsigned mblocks_for(int part, int MBe, int KBe) {
 }
 
 template <int S, bool CIA>
-__global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Tables tb, int B, float* __restrict__ spec) {
+__global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Tables tb, int B, float* __restrict__ spec,
+                                                              float* __restrict__ dtau_out) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = logical % B, tile = logical / B;
@@ -73,7 +74,7 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
   const int KBe = (L + 15) >> 4;
   for (int o = wv; o < 2 * KBe; o += kBlockT / 64) {
     uint16_t h0[8], l0[8], h1[8], l1[8];
-#pragma unroll 2
+#pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int l = 8 * o + j;
       float d0 = 0.0f, d1 = 0.0f;
@@ -82,6 +83,9 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
         layer_terms<S, CIA, false>(c, kc, g, rh, rhc, voff, d0, d1);
         d0 = fminf(d0, 16384.0f);
         d1 = fminf(d1, 16384.0f);
+        // the reverse pass reads the layer optical depths back instead of recomputing them
+        if (dtau_out)
+          *reinterpret_cast<float2*>(dtau_out + ((size_t)b * m.L_max + l) * npad + nu0 + 2 * lane) = make_float2(d0, d1);
       }
       h0[j] = bf16_bits_rn(d0);
       l0[j] = bf16_bits_rn(d0 - bf16_bits_to_f(h0[j]));
@@ -244,13 +248,16 @@ hipError_t trans_fwd_configure(const Model& m, bool fp64) {
   return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)trans_fwd_lds_bytes(m, fp64));
 }
 
-void launch_trans_fwd(const Model& m, const Work& w, const Tables& tb, int B, void* spec, bool fp64, hipStream_t st) {
+void launch_trans_fwd(const Model& m, const Work& w, const Tables& tb, int B, void* spec, bool fp64, hipStream_t st,
+                      float* dtau_out) {
   const size_t lds = trans_fwd_lds_bytes(m, fp64);
-  void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec};
-  if (fp64)
+  if (fp64) {
+    void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec};
     hipLaunchKernel(fwd_kernel_for<true>(m.S, m.has_cia), dim3((unsigned)(m.n_tiles64 * B)), dim3(kBlock), args, lds, st);
-  else
+  } else {
+    void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec, (void*)&dtau_out};
     hipLaunchKernel(fwd_kernel_for<false>(m.S, m.has_cia), dim3((unsigned)(m.n_tiles * B)), dim3(kBlockT), args, lds, st);
+  }
 }
 
 }  // namespace exofwd
