@@ -23,8 +23,8 @@ struct AdjWork {
   void* pbar;          // [pair][L_pad][L_pad] d lnL / d P_il (row i, column l), float (mixed) or double (FP64)
   double* abar;        // [pair][L_pad] d lnL / d area_i
   // reduced-precision path: the fused kernel stores dtau_bar, a second kernel forms the layer sums
-  float* dtau;         // [B_max][L_max][n_nu_pad] layer optical depths stored by the forward kernel
-  float* dtb;          // [B_max][L_max][n_nu_pad] d lnL / d dtau_l(nu)
+  float* dtau;         // [B_max][L_pad][n_nu_pad] layer optical depths stored by the forward kernel
+  float* dtb;          // [B_max][L_pad][n_nu_pad] d lnL / d dtau_l(nu)
   float* lsum;         // [B_max][lsum_chunks][L_pad][n_sums] partial layer sums
   int lsum_chunks;     // wavenumber chunks of the layer-sum kernel
 };

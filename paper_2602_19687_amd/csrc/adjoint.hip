@@ -1,16 +1,19 @@
 // Reverse pass of the transmission path.
 //
-// For every (sample, wavenumber chunk) a fused kernel recomputes the layer
-// optical depths and the slant optical depth, forms the seeds
+// For every (sample, wavenumber chunk) a fused kernel takes the layer optical
+// depths (stored by the forward kernel in the reduced-precision path,
+// recomputed in FP64), forms the slant optical depth and the seeds
 //   delta_bar(nu) = (d lnL / d m_k) / N_k          (nu in bin k)
 //   tau_bar_i(nu) = delta_bar(nu) a_i e^{-tau_i(nu)}
 // and accumulates, over its wavenumbers,
 //   abar_i   = sum_nu delta_bar (1 - e^{-tau_i})                      (annulus areas)
 //   Pbar_il  = sum_nu tau_bar_i dtau_l                                (path matrix)
-//   dtau_bar = P^T tau_bar  and the per-layer sums of adjoint.h        (opacity)
-// The FP64 chain kernel then walks back through the path-matrix geometry,
-// the hydrostatic recursion, n = p/kT, chemistry, the cloud deck and the T-p
-// profile to d lnL / d params.
+//   dtau_bar = P^T tau_bar                                            (opacity)
+// The per-layer sums of adjoint.h over dtau_bar are formed in the same kernel
+// (FP64) or by a separate high-occupancy kernel from the stored dtau_bar
+// (reduced precision). The FP64 chain kernel then walks back through the
+// path-matrix geometry, the hydrostatic recursion, n = p/kT, chemistry, the
+// cloud deck and the T-p profile to d lnL / d params.
 #include "adjoint.h"
 #include "kernels.h"
 #include "opacity.h"
@@ -59,18 +62,6 @@ __device__ inline int nth_bit(unsigned mask, int q) {
   return -1;
 }
 
-__device__ inline uint32_t pack2(uint16_t a, uint16_t b) { return (uint32_t)a | ((uint32_t)b << 16); }
-
-// bf16x8 gathered from 8 wavenumber rows of a [nu][stride] bf16 array
-__device__ inline bf16x8 gather8(const uint16_t* base, int stride) {
-  uint4 p;
-  p.x = pack2(base[0], base[stride]);
-  p.y = pack2(base[2 * stride], base[3 * stride]);
-  p.z = pack2(base[4 * stride], base[5 * stride]);
-  p.w = pack2(base[6 * stride], base[7 * stride]);
-  return __builtin_bit_cast(bf16x8, p);
-}
-
 constexpr int kSlots = 2;    // 32-row blocks per wave (the greedy split gives at most 2 for L_pad <= 128)
 constexpr int kPSlots = 2;   // path-matrix adjoint tiles per wave
 
@@ -88,10 +79,10 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int Lp = m.L_pad, L = w.nlay[b];
-  const int ld = Lp + 4;                               // floats per wavenumber row (b128-conflict-free)
-  float* s_dt = reinterpret_cast<float*>(lds);         // dtau      [nu][ld]
-  float* s_tt = s_dt + kTileA * ld;                    // tau_bar   [nu][ld]
-  float* s_area = s_tt + kTileA * ld;                  // [Lp]
+  const int ld = Lp + 4;                               // dwords per wavenumber row (b128-conflict-free)
+  uint32_t* s_dt = reinterpret_cast<uint32_t*>(lds);   // dtau    [nu][ld] as packed bf16 hi/lo
+  uint32_t* s_tt = s_dt + kTileA * ld;                 // tau_bar [nu][ld] as packed bf16 hi/lo
+  float* s_area = reinterpret_cast<float*>(s_tt + kTileA * ld);   // [Lp]
 
   const float* area = reinterpret_cast<const float*>(w.area) + (size_t)b * Lp;
   for (int i = tid; i < Lp; i += kBlock) s_area[i] = area[i];
@@ -110,8 +101,18 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
 
   const int KBe = (L + 15) >> 4, MBe = (L + 31) >> 5, KB = Lp >> 4;
   const int nb = wv & 1, part = wv >> 1;
-  const unsigned mine_t = split_blocks(part, MBe, KBe, false);   // rows i of tau
-  const unsigned mine_d = split_blocks(part, MBe, KBe, true);    // rows l of dtau_bar
+  // row blocks of this wave (slot q -> block index or -1), fixed for the whole call;
+  // readfirstlane keeps them in scalar registers
+  int t_mi[kSlots], d_ml[kSlots];
+  {
+    const unsigned mine_t = split_blocks(part, MBe, KBe, false);   // rows i of tau
+    const unsigned mine_d = split_blocks(part, MBe, KBe, true);    // rows l of dtau_bar
+#pragma unroll
+    for (int q = 0; q < kSlots; ++q) {
+      t_mi[q] = __builtin_amdgcn_readfirstlane(nth_bit(mine_t, q));
+      d_ml[q] = __builtin_amdgcn_readfirstlane(nth_bit(mine_d, q));
+    }
+  }
   const size_t plane = (size_t)(Lp >> 5) * KB * 512;
   const uint16_t* fh = w.pfrag + (size_t)b * 2 * plane;
   const uint16_t* fl = fh + plane;
@@ -132,6 +133,11 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
           pt_mi[t >> 2] = mi;
           pt_nl[t >> 2] = nl;
         }
+#pragma unroll
+    for (int q = 0; q < kPSlotsA; ++q) {
+      pt_mi[q] = __builtin_amdgcn_readfirstlane(pt_mi[q]);
+      pt_nl[q] = __builtin_amdgcn_readfirstlane(pt_nl[q]);
+    }
   }
   f32x16 abar_acc[kSlots], pbar_acc[kPSlotsA];
 #pragma unroll
@@ -139,23 +145,29 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
 #pragma unroll
   for (int q = 0; q < kPSlotsA; ++q) pbar_acc[q] = f32x16{};
 
+  // this sample's stored optical depths and dtau_bar ([L_pad][n_nu_pad], rebased per tile)
+  const float* dtau_b = aw.dtau + (size_t)b * Lp * npad;
+  float* dtb_b = aw.dtb + (size_t)b * Lp * npad;
   const int ntiles = m.n_nu_pad / kTileA;
   const int t0 = chunk * ntiles / C, t1 = (chunk + 1) * ntiles / C;
   for (int tile = t0; tile < t1; ++tile) {
     const int nu0 = tile * kTileA;
     // ---- phase A: layer optical depths of the tile (stored by the forward kernel) -> LDS [nu][l]
     {
-      const float* src = aw.dtau + (size_t)b * m.L_max * npad + nu0 + lane;
+      const __amdgpu_buffer_rsrc_t rs_dt = make_rsrc(dtau_b + nu0, ((size_t)Lp * npad - nu0) * 4);
       for (int o = wv; o < 4 * MBe; o += kBlock / 64) {
         float d[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
+          // rows [L, 32 MBe) are padding: read row L-1 (in range) and discard it
           const int l = 8 * o + j;
-          d[j] = l < L ? src[(size_t)l * npad] : 0.0f;
+          const float v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                         rs_dt, (uint32_t)((min(l, L - 1) * npad + lane) * 4), 0, 0));
+          d[j] = l < L ? v : 0.0f;
         }
-        float* dst = s_dt + lane * ld + 8 * o;
-        *reinterpret_cast<float4*>(dst) = make_float4(d[0], d[1], d[2], d[3]);
-        *reinterpret_cast<float4*>(dst + 4) = make_float4(d[4], d[5], d[6], d[7]);
+        uint32_t* dst = s_dt + lane * ld + 8 * o;
+        *reinterpret_cast<uint4*>(dst) = make_uint4(pack_hl(d[0]), pack_hl(d[1]), pack_hl(d[2]), pack_hl(d[3]));
+        *reinterpret_cast<uint4*>(dst + 4) = make_uint4(pack_hl(d[4]), pack_hl(d[5]), pack_hl(d[6]), pack_hl(d[7]));
       }
     }
     __syncthreads();
@@ -167,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
       const float dbar = bin >= 0 ? (float)(dm[bin] * w.inv_cnt[bin]) : 0.0f;
 #pragma unroll
       for (int q = 0; q < kSlots; ++q) {
-        const int mi = nth_bit(mine_t, q);
+        const int mi = t_mi[q];
         if (mi < 0) continue;
         f32x16 acc = {};
 #pragma unroll 1
@@ -176,7 +188,12 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
           const bf16x8 ah = *reinterpret_cast<const bf16x8*>(fh + fo);
           const bf16x8 al = *reinterpret_cast<const bf16x8*>(fl + fo);
           bf16x8 bh, bl;
-          split8(s_dt + col * ld + 16 * kb + 8 * h, bh, bl);
+          {
+            const uint4 x0 = *reinterpret_cast<const uint4*>(s_dt + col * ld + 16 * kb + 8 * h);
+            const uint4 x1 = *reinterpret_cast<const uint4*>(s_dt + col * ld + 16 * kb + 8 * h + 4);
+            const uint32_t x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+            frag_hl(x, bh, bl);
+          }
           acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
           acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
           acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
@@ -192,29 +209,43 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
             abar_acc[q][j] = fmaf(dbar, 1.0f - e, abar_acc[q][j]);
             tv[r] = dbar * s_area[row] * e;
           }
-          *reinterpret_cast<float4*>(s_tt + col * ld + 32 * mi + 8 * qd + 4 * h) = make_float4(tv[0], tv[1], tv[2], tv[3]);
+          *reinterpret_cast<uint4*>(s_tt + col * ld + 32 * mi + 8 * qd + 4 * h) =
+              make_uint4(pack_hl(tv[0]), pack_hl(tv[1]), pack_hl(tv[2]), pack_hl(tv[3]));
         }
       }
     }
     __syncthreads();
 
-    // ---- phase E: Pbar += tau_bar dtau^T over the tile's wavenumbers (FP32 MFMA, k = wavenumber)
+    // ---- phase E: Pbar += tau_bar dtau^T over the tile's wavenumbers (bf16x3 MFMA, k = wavenumber);
+    // operands gathered from eight wavenumber rows of the packed hi/lo LDS arrays
 #pragma unroll
     for (int q = 0; q < kPSlotsA; ++q) {
       const int mi = pt_mi[q], nl = pt_nl[q];
       if (mi < 0) continue;
-      const float* pa = s_tt + h * ld + 32 * mi + (lane & 31);
-      const float* pbp = s_dt + h * ld + 32 * nl + (lane & 31);
-#pragma unroll 4
-      for (int ks = 0; ks < kTileA / 2; ++ks)
-        pbar_acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(pa[2 * ks * ld], pbp[2 * ks * ld], pbar_acc[q], 0, 0, 0);
+      const uint32_t* pa = s_tt + 8 * h * ld + 32 * mi + (lane & 31);
+      const uint32_t* pbp = s_dt + 8 * h * ld + 32 * nl + (lane & 31);
+#pragma unroll 1
+      for (int ks = 0; ks < kTileA / 16; ++ks) {
+        uint32_t va[8], vb[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          va[e] = pa[(16 * ks + e) * ld];
+          vb[e] = pbp[(16 * ks + e) * ld];
+        }
+        bf16x8 ah, al, bh, bl;
+        frag_hl(va, ah, al);
+        frag_hl(vb, bh, bl);
+        pbar_acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, pbar_acc[q], 0, 0, 0);
+        pbar_acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, pbar_acc[q], 0, 0, 0);
+        pbar_acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, pbar_acc[q], 0, 0, 0);
+      }
     }
     // ---- phase D: dtau_bar = P^T tau_bar (rows l, this wave's column block) -> HBM
     {
-      float* dst = aw.dtb + (size_t)b * m.L_max * npad + nu0 + col;
+      const __amdgpu_buffer_rsrc_t rs_db = make_rsrc(dtb_b + nu0, ((size_t)Lp * npad - nu0) * 4);
 #pragma unroll
       for (int q = 0; q < kSlots; ++q) {
-        const int ml = nth_bit(mine_d, q);
+        const int ml = d_ml[q];
         if (ml < 0) continue;
         f32x16 acc = {};
         const int kend = min(2 * ml + 2, KBe);
@@ -224,7 +255,12 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
           const bf16x8 ah = *reinterpret_cast<const bf16x8*>(th_ + fo);
           const bf16x8 al = *reinterpret_cast<const bf16x8*>(tl_ + fo);
           bf16x8 bh, bl;
-          split8(s_tt + col * ld + 16 * ki + 8 * h, bh, bl);
+          {
+            const uint4 x0 = *reinterpret_cast<const uint4*>(s_tt + col * ld + 16 * ki + 8 * h);
+            const uint4 x1 = *reinterpret_cast<const uint4*>(s_tt + col * ld + 16 * ki + 8 * h + 4);
+            const uint32_t x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+            frag_hl(x, bh, bl);
+          }
           acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
           acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
           acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
@@ -232,7 +268,10 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           const int row = 32 * ml + 8 * (j >> 2) + 4 * h + (j & 3);
-          if (row < L) dst[(size_t)row * npad] = acc[j];
+          // rows [L, 32 MBe) land in this sample's padding rows, which nothing reads
+          // element copied to a scalar first: a bit_cast of a vector element lowers to element 0
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((float)acc[j]), rs_db,
+                                                (uint32_t)((row * npad + col) * 4), 0, 0);
         }
       }
     }
@@ -255,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
   // abar: reduce over the 32 columns of each lane half, then over the two column blocks
 #pragma unroll
   for (int q = 0; q < kSlots; ++q) {
-    const int mi = nth_bit(mine_t, q);
+    const int mi = t_mi[q];
     if (mi < 0) continue;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
@@ -267,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
   double* s_ab = reinterpret_cast<double*>(lds);   // [2][Lp], all waves are past the loop
 #pragma unroll
   for (int q = 0; q < kSlots; ++q) {
-    const int mi = nth_bit(mine_t, q);
+    const int mi = t_mi[q];
     if (mi < 0) continue;
     if ((lane & 31) == 0) {
 #pragma unroll
@@ -316,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
   const uint32_t voff = (uint32_t)lane * 4u;
   const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * rec_len(S);
   const int32_t* cells = w.cells + (size_t)b * Lp;
-  const float* dtb = aw.dtb + (size_t)b * m.L_max * npad;
+  const float* dtb = aw.dtb + (size_t)b * Lp * npad;
 
   float acc[kLsLayers][NS];
 #pragma unroll
@@ -333,8 +372,8 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
       const int l = l0 + q;
       if (l >= L) continue;
       const LayerCoef<S> c = load_layer<S>(m, cells, rec, l, (uint32_t)nu0 * 2u, g);
-      float d0, d1, t0_[S + 2], t1_[S + 2], dw0[S + 2], dw1[S + 2];
-      layer_terms<S, CIA, true>(c, kc, g, rh, rhc, voff, d0, d1, t0_, t1_, dw0, dw1);
+      float t0_[S + 2], t1_[S + 2], dw0[S + 2], dw1[S + 2];
+      layer_terms_deriv<S, CIA>(c, kc, g, rh, rhc, voff, t0_, t1_, dw0, dw1);
       const float2 db = *reinterpret_cast<const float2*>(dtb + (size_t)l * npad + nu0 + 2 * lane);
 #pragma unroll
       for (int s = 0; s < S; ++s) {
@@ -872,8 +911,8 @@ bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std:
     return aw.layer_sums != nullptr;
   }
   aw.lsum_chunks = (m.n_tiles + kLsTiles - 1) / kLsTiles;
-  aw.dtb = (float*)alloc((size_t)B_max * m.L_max * m.n_nu_pad * sizeof(float));
-  aw.dtau = (float*)alloc((size_t)B_max * m.L_max * m.n_nu_pad * sizeof(float));
+  aw.dtb = (float*)alloc((size_t)B_max * m.L_pad * m.n_nu_pad * sizeof(float));
+  aw.dtau = (float*)alloc((size_t)B_max * m.L_pad * m.n_nu_pad * sizeof(float));
   aw.lsum = (float*)alloc((size_t)B_max * aw.lsum_chunks * Lp * n_sums(m.S) * sizeof(float));
   return aw.dtb && aw.dtau && aw.lsum;
 }

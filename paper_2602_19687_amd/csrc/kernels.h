@@ -16,7 +16,7 @@ __device__ inline int xcd_logical_block(int bid, int nblk) {
 
 void launch_profile(const Model& m, const Work& w, int B, const double* params, const int32_t* n_layers,
                     bool fp64, hipStream_t st);
-// dtau_out (reduced precision only, may be null): layer optical depths [B][L_max][n_nu_pad] for the reverse pass
+// dtau_out (reduced precision only, may be null): layer optical depths [B][L_pad][n_nu_pad] for the reverse pass
 void launch_trans_fwd(const Model& m, const Work& w, const Tables& tb, int B, void* spec, bool fp64,
                       hipStream_t st, float* dtau_out = nullptr);
 void launch_loglike(const Model& m, const Work& w, int B, const double* params, const void* spec, bool spec_f64,

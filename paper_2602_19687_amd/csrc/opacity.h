@@ -23,7 +23,7 @@ struct LayerCoef {
   uint32_t rowc[2];     // byte offset of the (pair, iTc) CIA row at the tile start
   float w00, w10, w01, w11, wtc, R, D;
   float lam[S], lamc[2];
-  float wt, inv_dt, inv_dtc;   // used by the adjoint (T derivative of the weights)
+  float wt, wp, omp;   // T and log p weights, 1 - wP (derivative form of the bilinear)
 };
 
 struct TableGeom {
@@ -42,6 +42,8 @@ __device__ inline LayerCoef<S> load_layer(const Model& m, const int32_t* __restr
   const float* rl = rec + (size_t)l * rec_len(S);
   const float wt = rl[0], wp = rl[1];
   c.wt = wt;
+  c.wp = wp;
+  c.omp = 1.0f - wp;
   c.w11 = wt * wp;
   c.w10 = wt - c.w11;
   c.w01 = wp - c.w11;
@@ -97,14 +99,13 @@ __device__ inline half2_t load_h2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint3
   return __builtin_bit_cast(half2_t, (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 
-// Line and CIA terms of one layer for two wavenumbers.  Terms and the
-// T-weight derivatives of their exponents are returned per source when
-// requested (the adjoint); the forward only needs the sums.
-template <int S, bool CIA, bool DERIV>
+// Optical depth of one layer at two wavenumbers: Rayleigh + grey cloud, the
+// VMR-weighted line terms (bilinear in T and log p of the log2 tables) and the
+// CIA pair terms (linear in T).
+template <int S, bool CIA>
 __device__ inline void layer_terms(const LayerCoef<S>& c, const LaneConst<S>& k, const TableGeom& g,
                                    __amdgpu_buffer_rsrc_t rh, __amdgpu_buffer_rsrc_t rhc, uint32_t voff,
-                                   float& d0, float& d1, float* t0 = nullptr, float* t1 = nullptr,
-                                   float* dw0 = nullptr, float* dw1 = nullptr) {
+                                   float& d0, float& d1) {
   d0 = fmaf(c.R, k.nu4_0, c.D);
   d1 = fmaf(c.R, k.nu4_1, c.D);
 #pragma unroll
@@ -123,18 +124,8 @@ __device__ inline void layer_terms(const LayerCoef<S>& c, const LaneConst<S>& k,
     v1 = fmaf(c.w01, (float)h01.y, v1);
     v0 = fmaf(c.w11, (float)h11.x, v0);
     v1 = fmaf(c.w11, (float)h11.y, v1);
-    const float e0 = exp2_fast(v0), e1 = exp2_fast(v1);
-    d0 += e0;
-    d1 += e1;
-    if (DERIV) {
-      t0[s] = e0;
-      t1[s] = e1;
-      // d(exponent)/d wT = (1 - wP)(h10 - h00) + wP (h11 - h01) = (w00 + w10)... expressed with the weights:
-      // wP = w01 + w11, 1 - wP = w00 + w10
-      const float omp = c.w00 + c.w10, wp = c.w01 + c.w11;
-      dw0[s] = omp * ((float)h10.x - (float)h00.x) + wp * ((float)h11.x - (float)h01.x);
-      dw1[s] = omp * ((float)h10.y - (float)h00.y) + wp * ((float)h11.y - (float)h01.y);
-    }
+    d0 += exp2_fast(v0);
+    d1 += exp2_fast(v1);
   }
   if (CIA) {
 #pragma unroll
@@ -147,15 +138,47 @@ __device__ inline void layer_terms(const LayerCoef<S>& c, const LaneConst<S>& k,
       v1 = fmaf(1.0f - c.wtc, (float)a.y, v1);
       v0 = fmaf(c.wtc, (float)b.x, v0);
       v1 = fmaf(c.wtc, (float)b.y, v1);
-      const float e0 = exp2_fast(v0), e1 = exp2_fast(v1);
-      d0 += e0;
-      d1 += e1;
-      if (DERIV) {
-        t0[S + p] = e0;
-        t1[S + p] = e1;
-        dw0[S + p] = (float)b.x - (float)a.x;
-        dw1[S + p] = (float)b.y - (float)a.y;
-      }
+      d0 += exp2_fast(v0);
+      d1 += exp2_fast(v1);
+    }
+  }
+}
+
+// Line and CIA terms of one layer for two wavenumbers together with the
+// derivative of each exponent with respect to the T weight, from the two
+// log p-interpolated rows u0 (at iT) and u1 (at iT+1), both offset by c + lam:
+//   exponent = u0 + wT (u1 - u0),  d exponent / d wT = u1 - u0.
+template <int S, bool CIA>
+__device__ inline void layer_terms_deriv(const LayerCoef<S>& c, const LaneConst<S>& k, const TableGeom& g,
+                                         __amdgpu_buffer_rsrc_t rh, __amdgpu_buffer_rsrc_t rhc, uint32_t voff,
+                                         float* t0, float* t1, float* dw0, float* dw1) {
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const half2_t h00 = load_h2(rh, voff, c.row[s]);
+    const half2_t h10 = load_h2(rh, voff, c.row[s] + g.tstep);
+    const half2_t h01 = load_h2(rh, voff, c.row[s] + g.pstep);
+    const half2_t h11 = load_h2(rh, voff, c.row[s] + g.tstep + g.pstep);
+    const float cl0 = k.c0[s] + c.lam[s], cl1 = k.c1[s] + c.lam[s];
+    const float u00 = fmaf(c.omp, (float)h00.x, fmaf(c.wp, (float)h01.x, cl0));
+    const float u10 = fmaf(c.omp, (float)h10.x, fmaf(c.wp, (float)h11.x, cl0));
+    const float u01 = fmaf(c.omp, (float)h00.y, fmaf(c.wp, (float)h01.y, cl1));
+    const float u11 = fmaf(c.omp, (float)h10.y, fmaf(c.wp, (float)h11.y, cl1));
+    dw0[s] = u10 - u00;
+    dw1[s] = u11 - u01;
+    t0[s] = exp2_fast(fmaf(c.wt, dw0[s], u00));
+    t1[s] = exp2_fast(fmaf(c.wt, dw1[s], u01));
+  }
+  if (CIA) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const half2_t a = load_h2(rhc, voff, c.rowc[p]);
+      const half2_t b = load_h2(rhc, voff, c.rowc[p] + g.row_bytes);
+      const float u0 = (float)a.x + (k.cc0[p] + c.lamc[p]);
+      const float u1 = (float)a.y + (k.cc1[p] + c.lamc[p]);
+      dw0[S + p] = (float)b.x - (float)a.x;
+      dw1[S + p] = (float)b.y - (float)a.y;
+      t0[S + p] = exp2_fast(fmaf(c.wtc, dw0[S + p], u0));
+      t1[S + p] = exp2_fast(fmaf(c.wtc, dw1[S + p], u1));
     }
   }
 }
@@ -173,71 +196,20 @@ __device__ inline uint16_t bf16_bits_rn(float f) {
 }
 __device__ inline float bf16_bits_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-}  // namespace exofwd
-
-namespace exofwd {
-
-// ---- one wavenumber per lane (reverse kernel tiles of 64)
-template <int S>
-struct LaneConst1 {
-  float c[S], cc[2], nu4;
-};
-
-template <int S, bool CIA>
-__device__ inline LaneConst1<S> load_lane1(const Model& m, const Tables& tb, int nu) {
-  LaneConst1<S> k;
-  const size_t np = (size_t)m.n_nu_pad;
-#pragma unroll
-  for (int s = 0; s < S; ++s) k.c[s] = tb.c[s * np + nu];
-#pragma unroll
-  for (int p = 0; p < 2; ++p) k.cc[p] = CIA ? tb.cc[p * np + nu] : 0.0f;
-  k.nu4 = tb.nu4f[nu];
-  return k;
+// A float as a packed (bf16 hi | bf16 lo << 16) pair, hi + lo ~ 16 significant bits.
+__device__ inline uint32_t pack_hl(float v) {
+  const uint16_t h = bf16_bits_rn(v);
+  const uint16_t l = bf16_bits_rn(v - bf16_bits_to_f(h));
+  return (uint32_t)h | ((uint32_t)l << 16);
 }
 
-__device__ inline float load_h1(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  return (float)__builtin_bit_cast(_Float16, (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
-}
-
-// Vertical optical depth of one layer at one wavenumber per lane.
-template <int S, bool CIA>
-__device__ inline float layer_dtau1(const LayerCoef<S>& c, const LaneConst1<S>& k, const TableGeom& g,
-                                    __amdgpu_buffer_rsrc_t rh, __amdgpu_buffer_rsrc_t rhc, uint32_t voff) {
-  float d = fmaf(c.R, k.nu4, c.D);
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    float v = k.c[s] + c.lam[s];
-    v = fmaf(c.w00, load_h1(rh, voff, c.row[s]), v);
-    v = fmaf(c.w10, load_h1(rh, voff, c.row[s] + g.tstep), v);
-    v = fmaf(c.w01, load_h1(rh, voff, c.row[s] + g.pstep), v);
-    v = fmaf(c.w11, load_h1(rh, voff, c.row[s] + g.tstep + g.pstep), v);
-    d += exp2_fast(v);
-  }
-  if (CIA) {
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      float v = k.cc[p] + c.lamc[p];
-      v = fmaf(1.0f - c.wtc, load_h1(rhc, voff, c.rowc[p]), v);
-      v = fmaf(c.wtc, load_h1(rhc, voff, c.rowc[p] + g.row_bytes), v);
-      d += exp2_fast(v);
-    }
-  }
-  return d;
-}
-
-// bf16x8 hi/lo split of eight consecutive floats
-__device__ inline void split8(const float* p, bf16x8& hi, bf16x8& lo) {
-  const float4 a = *reinterpret_cast<const float4*>(p);
-  const float4 b = *reinterpret_cast<const float4*>(p + 4);
-  const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+// hi and lo bf16x8 fragments from eight packed pairs
+__device__ inline void frag_hl(const uint32_t* x, bf16x8& hi, bf16x8& lo) {
   uint32_t h[4], l[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const uint16_t h0 = bf16_bits_rn(v[2 * i]), h1 = bf16_bits_rn(v[2 * i + 1]);
-    const uint16_t l0 = bf16_bits_rn(v[2 * i] - bf16_bits_to_f(h0));
-    const uint16_t l1 = bf16_bits_rn(v[2 * i + 1] - bf16_bits_to_f(h1));
-    h[i] = (uint32_t)h0 | ((uint32_t)h1 << 16);
-    l[i] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    h[i] = __builtin_amdgcn_perm(x[2 * i + 1], x[2 * i], 0x05040100u);
+    l[i] = __builtin_amdgcn_perm(x[2 * i + 1], x[2 * i], 0x07060302u);
   }
   hi = __builtin_bit_cast(bf16x8, make_uint4(h[0], h[1], h[2], h[3]));
   lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));

@@ -80,12 +80,12 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
       float d0 = 0.0f, d1 = 0.0f;
       if (l < L) {
         const LayerCoef<S> c = load_layer<S>(m, cells, rec, l, (uint32_t)nu0 * 2u, g);
-        layer_terms<S, CIA, false>(c, kc, g, rh, rhc, voff, d0, d1);
+        layer_terms<S, CIA>(c, kc, g, rh, rhc, voff, d0, d1);
         d0 = fminf(d0, 16384.0f);
         d1 = fminf(d1, 16384.0f);
         // the reverse pass reads the layer optical depths back instead of recomputing them
         if (dtau_out)
-          *reinterpret_cast<float2*>(dtau_out + ((size_t)b * m.L_max + l) * npad + nu0 + 2 * lane) = make_float2(d0, d1);
+          *reinterpret_cast<float2*>(dtau_out + ((size_t)b * Lp + l) * npad + nu0 + 2 * lane) = make_float2(d0, d1);
       }
       h0[j] = bf16_bits_rn(d0);
       l0[j] = bf16_bits_rn(d0 - bf16_bits_to_f(h0[j]));

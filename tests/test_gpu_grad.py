@@ -118,3 +118,26 @@ def test_invalid_samples_zero_gradient():
     lnl, g, st, _ = _grad(wl, "mixed", th)
     assert st[1] != 0 and lnl[1] == -1e300 and np.all(g[1] == 0)
     assert st[0] == 0 and np.all(np.isfinite(g[0])) and np.any(g[0] != 0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_ragged_layer_counts_after_full_call(prec):
+    """Per-sample layer counts below the maximum, run right after a call in which
+    every sample used all layers (nothing from the earlier call may leak in)."""
+    from paper_2602_19687_amd import ForwardModel
+    wl = reduced(3, n_nu=700, n_bins=14, batch=4, n_layers=110)
+    fm = ForwardModel(wl, precision=prec, batch_max=4)
+    th = torch.tensor(wl["params"], device="cuda")
+    fm.grad(th)
+    nl = np.array([110, 37, 64, 2], dtype=np.int32)
+    print(f"[gpu] ragged grad prec={prec} n_layers={nl.tolist()}", flush=True)
+    lnl, g, st, _ = fm.grad(th, n_layers=torch.tensor(nl, device="cuda"))
+    g = g.cpu().numpy()
+    st = st.cpu().numpy()
+    fm.close()
+    for b in range(4):
+        gref = oracle.grad_complex_step(wl, wl["params"][b], n_layers=int(nl[b]))
+        assert st[b] == 0
+        e = grad_err(g[b], gref)
+        print(f"ragged {prec} L={nl[b]}: grad err {e:.3e}")
+        assert e < TOL[prec]
