@@ -28,6 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # published MI355X FP32 vector peak (256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA) x 2 (packed));
 # this build disables packed FP32, so its attainable ceiling is half of it
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0   # dense
 
 
 def algorithmic_bytes_per_sample(L, S, n_nu, b_tab, b_out):
@@ -37,22 +38,61 @@ def algorithmic_bytes_per_sample(L, S, n_nu, b_tab, b_out):
     return (4 * L * S * n_nu + 4 * L * n_nu) * b_tab + 2 * n_nu * 4 + n_nu * b_out
 
 
-def vector_flops_per_element(S, kernel):
-    """Vector FP32 operations the method needs per (sample, layer, wavenumber),
-    counting an FMA as 2 and an exp2 as 1.
-      forward      : line source bilinear (4 FMA) + offset add + exp2 + accumulate = 11,
-                     CIA pair T lerp (2 FMA) + add + exp2 + accumulate = 7,
-                     Rayleigh + deck 1 FMA = 2, transit exp2 + FMA = 3
-      trans_adj    : the forward opacity again (11 S + 16) plus seeds and annulus
-                     terms (6)
-      layer_sums   : line source 20 (forward 11, T-weight derivative 2 sub + 2 FMA,
-                     2 FMA into the sums), CIA pair 11, Rayleigh + deck sums 4
-    Chord products run on MFMA and are not counted."""
+def kernel_model(kernel, B, L, S, n_nu):
+    """Roofline model of one launch of a hot kernel at (B, L, S, n_nu):
+    (bound, algorithmic amount, peak, unit).
+
+    trans_fwd, layer_sums: vector FP32 operations per (sample, layer, wavenumber),
+    counting an FMA as 2 and an exp2 as 1, against the FP32 vector peak:
+      trans_fwd  : line source bilinear (4 FMA) + offset add + exp2 + accumulate = 11 per
+                   source, CIA pair T lerp (2 FMA) + add + exp2 + accumulate = 7 per pair,
+                   Rayleigh + deck 1 FMA = 2, transit exp2 + FMA = 3   -> 11 S + 19
+      layer_sums : line source 20 (forward 11, T-weight derivative 2 sub + 2 FMA,
+                   2 FMA into the sums), CIA pair 11, Rayleigh + deck sums 4 -> 20 S + 26
+    trans_adj: the three triangular products tau = P dtau, Pbar = tau_bar dtau^T and
+    dtau_bar = P^T tau_bar, L(L+1)/2 FMA each per wavenumber, each done as three bf16
+    MFMA products (bf16x3), against the dense bf16 MFMA peak."""
+    elems = B * L * n_nu
     if kernel == "trans_fwd":
-        return 11 * S + 2 * 7 + 2 + 3
+        return "alu", (11 * S + 19) * elems, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
+    if kernel == "layer_sums":
+        return "alu", (20 * S + 26) * elems, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
     if kernel == "trans_adj":
-        return 11 * S + 2 * 7 + 2 + 6
-    return 20 * S + 2 * 11 + 4
+        return "mfma", 3 * 3 * (L * (L + 1) // 2) * 2 * n_nu * B, BF16_MFMA_PEAK_TFLOPS, "TFLOP/s"
+    raise ValueError(kernel)
+
+
+def sources_digest():
+    """SHA-256 over the kernel sources; a counter summary holds the digest of the
+    sources it was taken with."""
+    import hashlib
+    d = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2602_19687_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                d.update(name.encode() + b"\0" + f.read())
+    return d.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed PMC summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a copy-kernel calibration), or
+    None when the summary is missing or the kernel sources have changed since."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_transmission_ns_b1024.md")
+    if not os.path.exists(path):
+        return None
+    digest, traffic = None, {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("sources_sha256:"):
+                digest = line.split(":", 1)[1].strip()
+            elif line.startswith("traffic_bytes_per_launch:"):
+                k, v = line.split(":", 1)[1].split()
+                traffic[k] = float(v)
+    if digest != sources_digest():
+        return None
+    return traffic.get(kernel)
 
 
 _WL = {}
@@ -169,20 +209,24 @@ def main():
     per = {k: v[0] / max(1, v[1]) for k, v in mixed["kernels"].items() if v[1]}
     dom = max(("trans_fwd", "trans_adj", "layer_sums"), key=lambda k: per.get(k, 0.0))
     dom_ms = per[dom]
-    elems = B * L_ * n_nu
-    flops = vector_flops_per_element(S, dom) * elems
-    achieved_tf = flops / (dom_ms / 1e3) / 1e12
+    bound, amount, peak, unit = kernel_model(dom, B, L_, S, n_nu)
+    achieved = amount / (dom_ms / 1e3) / 1e12
+    traffic = measured_traffic(dom)
     alg_bytes = algorithmic_bytes_per_sample(L_, S, n_nu, 2, 4) * B
-    hbm_gbs = alg_bytes / (dom_ms / 1e3) / 1e9
-    roofline = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved_tf / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
-                "kernel": dom, "kernel_ms": round(dom_ms, 4), "flops_per_launch": flops,
-                "hbm_algorithmic": {"bytes_per_launch": alg_bytes, "achieved_gbs": round(hbm_gbs, 1),
-                                    "frac_of_8000_gbs": round(hbm_gbs / HBM_PEAK_GBS, 4)}}
-    if mixed["has_grad"]:
-        both = per.get("trans_fwd", 0.0) + per.get("trans_adj", 0.0) + per.get("layer_sums", 0.0)
-        roofline["hbm_algorithmic"]["forward_plus_adjoint_frac"] = round(
-            alg_bytes / (both / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": traffic,
+                "kernel": dom, "kernel_ms": round(dom_ms, 4), "flops_per_launch": amount}
+    for k in ("trans_fwd", "trans_adj", "layer_sums"):
+        if k in per:
+            bk, ak, pk, _ = kernel_model(k, B, L_, S, n_nu)
+            a = ak / (per[k] / 1e3) / 1e12
+            roofline.setdefault("kernels", {})[k] = {"bound": bk, "ms": round(per[k], 4), "achieved": round(a, 2),
+                                                     "peak": pk, "frac": round(a / pk, 4),
+                                                     "traffic": measured_traffic(k)}
+    # table-gather bytes the method needs (the forward pass), against the HBM peak
+    hbm_gbs = alg_bytes / (per["trans_fwd"] / 1e3) / 1e9
+    roofline["table_gather"] = {"bytes_per_launch": alg_bytes, "kernel": "trans_fwd",
+                                "achieved_gbs": round(hbm_gbs, 1), "frac_of_8000_gbs": round(hbm_gbs / HBM_PEAK_GBS, 4)}
 
     out = {
         "metric": "forward+grad spectra/sec at B=1024 (FP32/FP16 vs FP64 plain), max rel err"

@@ -66,12 +66,18 @@ constexpr int kSlots = 2;    // 32-row blocks per wave (the greedy split gives a
 constexpr int kPSlots = 2;   // path-matrix adjoint tiles per wave
 
 // ============================================================================
-// reduced-precision reverse kernel: 512 threads, 128-wavenumber tiles
-constexpr int kTileA = 64;     // wavenumbers per tile of the reduced-precision reverse kernel
-constexpr int kPSlotsA = 3;    // 32x32 Pbar tiles per wave (10 tiles over 4 waves for L_pad <= 128)
+// reduced-precision reverse kernel: 512 threads, 128-wavenumber tiles; each wave
+// owns one 32-wavenumber column block and half of the 32-row blocks, so every
+// path-matrix fragment it loads feeds the products of the whole tile
+constexpr int kTileA = 128;               // wavenumbers per tile
+constexpr int kBlockA = 512;              // threads per workgroup
+constexpr int kNbA = kTileA / 32;         // column blocks per tile (waves sharing a row-block split)
+constexpr int kWavesA = kBlockA / 64;
+constexpr int kPSlotsA = 2;               // 32x32 Pbar tiles per wave (10 tiles over 8 waves for L_pad <= 128)
+constexpr int kItemsA = 4;                // (layer octet, half tile) items per wave: 8 MBe <= 32 over 8 waves
 
 template <int S, bool CIA>
-__global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tables tb, AdjWork aw, int B, int C) {
+__global__ __launch_bounds__(kBlockA) void k_trans_adj_mixed(Model m, Work w, Tables tb, AdjWork aw, int B, int C) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = logical % B, chunk = logical / B;
@@ -85,22 +91,11 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
   float* s_area = reinterpret_cast<float*>(s_tt + kTileA * ld);   // [Lp]
 
   const float* area = reinterpret_cast<const float*>(w.area) + (size_t)b * Lp;
-  for (int i = tid; i < Lp; i += kBlock) s_area[i] = area[i];
+  for (int i = tid; i < Lp; i += kBlockA) s_area[i] = area[i];
 
-  const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * rec_len(S);
-  const int32_t* cells = w.cells + (size_t)b * Lp;
-  TableGeom g;
-  g.row_bytes = (uint32_t)m.n_nu_pad * 2u;
-  g.tstep = (uint32_t)m.n_p * g.row_bytes;
-  g.pstep = g.row_bytes;
   const size_t npad = (size_t)m.n_nu_pad;
-  const __amdgpu_buffer_rsrc_t rh = make_rsrc(tb.h, (size_t)S * m.n_t * m.n_p * npad * 2);
-  const __amdgpu_buffer_rsrc_t rhc = make_rsrc(CIA ? (const void*)tb.hc : (const void*)tb.h,
-                                               CIA ? (size_t)2 * m.n_tc * npad * 2 : 0);
-  const uint32_t voff = (uint32_t)lane * 2u;
-
   const int KBe = (L + 15) >> 4, MBe = (L + 31) >> 5, KB = Lp >> 4;
-  const int nb = wv & 1, part = wv >> 1;
+  const int nb = wv % kNbA, part = wv / kNbA;
   // row blocks of this wave (slot q -> block index or -1), fixed for the whole call;
   // readfirstlane keeps them in scalar registers
   int t_mi[kSlots], d_ml[kSlots];
@@ -114,10 +109,14 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
     }
   }
   const size_t plane = (size_t)(Lp >> 5) * KB * 512;
-  const uint16_t* fh = w.pfrag + (size_t)b * 2 * plane;
-  const uint16_t* fl = fh + plane;
-  const uint16_t* th_ = w.ptfrag + (size_t)b * 2 * plane;
-  const uint16_t* tl_ = th_ + plane;
+  // this sample's P and P^T fragments (hi plane, then lo plane); lanes address
+  // their 16 bytes with the vector offset, blocks with the scalar offset
+  const __amdgpu_buffer_rsrc_t rs_p = make_rsrc(w.pfrag + (size_t)b * 2 * plane, 2 * plane * 2);
+  const __amdgpu_buffer_rsrc_t rs_pt = make_rsrc(w.ptfrag + (size_t)b * 2 * plane, 2 * plane * 2);
+  const uint32_t lo_plane = (uint32_t)plane * 2u, voff_f = (uint32_t)lane * 16u;
+  auto frag = [&](__amdgpu_buffer_rsrc_t rs, int blk, uint32_t pl) {
+    return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, voff_f, (uint32_t)blk * 1024u + pl, 0));
+  };
   const int col = 32 * nb + (lane & 31);
   const int h = lane >> 5;
   const double* dm = w.dm + (size_t)b * m.K;
@@ -129,9 +128,9 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
     for (int q = 0; q < kPSlotsA; ++q) pt_mi[q] = pt_nl[q] = -1;
     for (int mi = 0; mi < MBe; ++mi)
       for (int nl = mi; nl < MBe; ++nl, ++t)
-        if ((t & 3) == wv && (t >> 2) < kPSlotsA) {
-          pt_mi[t >> 2] = mi;
-          pt_nl[t >> 2] = nl;
+        if (t % kWavesA == wv && t / kWavesA < kPSlotsA) {
+          pt_mi[t / kWavesA] = mi;
+          pt_nl[t / kWavesA] = nl;
         }
 #pragma unroll
     for (int q = 0; q < kPSlotsA; ++q) {
@@ -150,27 +149,55 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
   float* dtb_b = aw.dtb + (size_t)b * Lp * npad;
   const int ntiles = m.n_nu_pad / kTileA;
   const int t0 = chunk * ntiles / C, t1 = (chunk + 1) * ntiles / C;
+
+  // the stored optical depths of a tile are fetched into registers while the
+  // previous tile's Pbar product runs, then written to LDS as packed hi/lo:
+  // items (layer octet o, half of the tile), a lane takes one wavenumber of the half
+  float pf[kItemsA][8];
+  // row offsets go in the scalar offset (wave-uniform, recomputed per tile); rows
+  // [L, 32 MBe) lie inside the sample's L_pad rows and are replaced by zero when staged
+  const __amdgpu_buffer_rsrc_t rs_dt = make_rsrc(dtau_b, (size_t)Lp * npad * 4);
+  const uint32_t rowb = (uint32_t)npad * 4u;
+  auto fetch = [&](int tile) {
+#pragma unroll
+    for (int q = 0; q < kItemsA; ++q) {
+      const int it = wv + kWavesA * q;
+      if (it >= 8 * MBe) continue;
+      const int o = it >> 1;
+      const uint32_t voff = (uint32_t)(64 * (it & 1) + lane) * 4u;
+      const uint32_t soff = (uint32_t)((8 * o * npad + (size_t)tile * kTileA) * 4);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        pf[q][j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs_dt, voff, soff + j * rowb, 0));
+    }
+  };
+  auto stage = [&]() {
+    // L passed through an empty asm: the row tests below are then formed where
+    // they are used, instead of being hoisted out of the tile loop as 32 masks
+    int Lq = L;
+    asm volatile("" : "+s"(Lq));
+#pragma unroll
+    for (int q = 0; q < kItemsA; ++q) {
+      const int it = wv + kWavesA * q;
+      if (it >= 8 * MBe) continue;
+      const int o = it >> 1, nu = 64 * (it & 1) + lane;
+      float d[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) d[j] = 8 * o + j < Lq ? pf[q][j] : 0.0f;
+      uint32_t* dst = s_dt + nu * ld + 8 * o;
+      *reinterpret_cast<uint4*>(dst) = make_uint4(pack_hl(d[0]), pack_hl(d[1]), pack_hl(d[2]), pack_hl(d[3]));
+      *reinterpret_cast<uint4*>(dst + 4) = make_uint4(pack_hl(d[4]), pack_hl(d[5]), pack_hl(d[6]), pack_hl(d[7]));
+    }
+  };
+  // ---- phase A of the first tile
+  if (t0 < t1) {
+    fetch(t0);
+    stage();
+  }
+  __syncthreads();
+
   for (int tile = t0; tile < t1; ++tile) {
     const int nu0 = tile * kTileA;
-    // ---- phase A: layer optical depths of the tile (stored by the forward kernel) -> LDS [nu][l]
-    {
-      const __amdgpu_buffer_rsrc_t rs_dt = make_rsrc(dtau_b + nu0, ((size_t)Lp * npad - nu0) * 4);
-      for (int o = wv; o < 4 * MBe; o += kBlock / 64) {
-        float d[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          // rows [L, 32 MBe) are padding: read row L-1 (in range) and discard it
-          const int l = 8 * o + j;
-          const float v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                                         rs_dt, (uint32_t)((min(l, L - 1) * npad + lane) * 4), 0, 0));
-          d[j] = l < L ? v : 0.0f;
-        }
-        uint32_t* dst = s_dt + lane * ld + 8 * o;
-        *reinterpret_cast<uint4*>(dst) = make_uint4(pack_hl(d[0]), pack_hl(d[1]), pack_hl(d[2]), pack_hl(d[3]));
-        *reinterpret_cast<uint4*>(dst + 4) = make_uint4(pack_hl(d[4]), pack_hl(d[5]), pack_hl(d[6]), pack_hl(d[7]));
-      }
-    }
-    __syncthreads();
 
     // ---- phases B, C: tau = P dtau; seeds; tau_bar -> LDS [nu][i]; abar accumulation
     {
@@ -182,11 +209,15 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
         const int mi = t_mi[q];
         if (mi < 0) continue;
         f32x16 acc = {};
+        // path-matrix fragments are loaded one k-step ahead
+        bf16x8 nh = frag(rs_p, mi * KB + 2 * mi, 0), nl_ = frag(rs_p, mi * KB + 2 * mi, lo_plane);
 #pragma unroll 1
         for (int kb = 2 * mi; kb < KBe; ++kb) {
-          const size_t fo = ((size_t)(mi * KB + kb) * 64 + lane) * 8;
-          const bf16x8 ah = *reinterpret_cast<const bf16x8*>(fh + fo);
-          const bf16x8 al = *reinterpret_cast<const bf16x8*>(fl + fo);
+          const bf16x8 ah = nh, al = nl_;
+          if (kb + 1 < KBe) {
+            nh = frag(rs_p, mi * KB + kb + 1, 0);
+            nl_ = frag(rs_p, mi * KB + kb + 1, lo_plane);
+          }
           bf16x8 bh, bl;
           {
             const uint4 x0 = *reinterpret_cast<const uint4*>(s_dt + col * ld + 16 * kb + 8 * h);
@@ -215,6 +246,10 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
       }
     }
     __syncthreads();
+    // ---- phase A of the next tile, part 1: its optical depths are in flight
+    // while phase E (LDS and MFMA only) runs
+    const bool more = tile + 1 < t1;
+    if (more) fetch(tile + 1);
 
     // ---- phase E: Pbar += tau_bar dtau^T over the tile's wavenumbers (bf16x3 MFMA, k = wavenumber);
     // operands gathered from eight wavenumber rows of the packed hi/lo LDS arrays
@@ -240,6 +275,10 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
         pbar_acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, pbar_acc[q], 0, 0, 0);
       }
     }
+    // ---- phase A of the next tile, part 2: every wave is past phase E, the last
+    // reader of this tile's dtau
+    __syncthreads();
+    if (more) stage();
     // ---- phase D: dtau_bar = P^T tau_bar (rows l, this wave's column block) -> HBM
     {
       const __amdgpu_buffer_rsrc_t rs_db = make_rsrc(dtb_b + nu0, ((size_t)Lp * npad - nu0) * 4);
@@ -249,11 +288,14 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
         if (ml < 0) continue;
         f32x16 acc = {};
         const int kend = min(2 * ml + 2, KBe);
+        bf16x8 nh = frag(rs_pt, ml * KB, 0), nl_ = frag(rs_pt, ml * KB, lo_plane);
 #pragma unroll 1
         for (int ki = 0; ki < kend; ++ki) {
-          const size_t fo = ((size_t)(ml * KB + ki) * 64 + lane) * 8;
-          const bf16x8 ah = *reinterpret_cast<const bf16x8*>(th_ + fo);
-          const bf16x8 al = *reinterpret_cast<const bf16x8*>(tl_ + fo);
+          const bf16x8 ah = nh, al = nl_;
+          if (ki + 1 < kend) {
+            nh = frag(rs_pt, ml * KB + ki + 1, 0);
+            nl_ = frag(rs_pt, ml * KB + ki + 1, lo_plane);
+          }
           bf16x8 bh, bl;
           {
             const uint4 x0 = *reinterpret_cast<const uint4*>(s_tt + col * ld + 16 * ki + 8 * h);
@@ -275,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
         }
       }
     }
-    __syncthreads();   // the next tile overwrites dtau and tau_bar
+    __syncthreads();   // the next tile reads the staged dtau and overwrites tau_bar
   }
 
   // ---- write this chunk's partials
@@ -291,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
       pb[(size_t)row * Lp + 32 * nl + (lane & 31)] = pbar_acc[q][j];
     }
   }
-  // abar: reduce over the 32 columns of each lane half, then over the two column blocks
+  // abar: reduce over the 32 columns of each lane half, then over the column blocks
 #pragma unroll
   for (int q = 0; q < kSlots; ++q) {
     const int mi = t_mi[q];
@@ -303,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
       abar_acc[q][j] = v;
     }
   }
-  double* s_ab = reinterpret_cast<double*>(lds);   // [2][Lp], all waves are past the loop
+  double* s_ab = reinterpret_cast<double*>(lds);   // [kNbA][Lp], all waves are past the loop
 #pragma unroll
   for (int q = 0; q < kSlots; ++q) {
     const int mi = t_mi[q];
@@ -318,7 +360,13 @@ __global__ __launch_bounds__(kBlock) void k_trans_adj_mixed(Model m, Work w, Tab
   }
   __syncthreads();
   double* ab = aw.abar + pair * Lp;
-  for (int i = tid; i < Lp; i += kBlock) ab[i] = i < 32 * MBe ? s_ab[i] + s_ab[Lp + i] : 0.0;
+  for (int i = tid; i < Lp; i += kBlockA) {
+    double v = 0.0;
+    if (i < 32 * MBe)
+#pragma unroll
+      for (int n = 0; n < kNbA; ++n) v += s_ab[n * Lp + i];
+    ab[i] = v;
+  }
 }
 
 // ============================================================================
@@ -889,7 +937,8 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
 // ============================================================================
 // host side
 int adjoint_chunks(const Model& m, int B, bool fp64) {
-  const int tiles = m.n_tiles64;   // both reverse kernels walk 64-wavenumber tiles
+  // the FP64 reverse kernel walks 64-wavenumber tiles, the reduced-precision one 128
+  const int tiles = fp64 ? m.n_tiles64 : m.n_tiles;
   int c = (1024 + B - 1) / B;
   return c < 1 ? 1 : (c > tiles ? tiles : c);
 }
@@ -921,7 +970,7 @@ static size_t adj_lds_bytes(const Model& m, bool fp64) {
   const size_t Lp = m.L_pad, ns = n_sums(m.S);
   if (fp64) return (size_t)2 * kTile64 * (Lp + 1) * 8 + Lp * ns * 8;
   (void)ns;
-  return (size_t)2 * kTileA * (Lp + 4) * 4 + Lp * 4;
+  return std::max((size_t)2 * kTileA * (Lp + 4) * 4 + Lp * 4, (size_t)kNbA * Lp * 8);
 }
 
 template <bool F64, int S, bool CIA>
@@ -967,7 +1016,7 @@ void launch_trans_adjoint(const Model& m, const Work& w, const Tables& tb, const
   int C = adjoint_chunks(m, B, fp64);
   void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&aw, (void*)&B, (void*)&C};
   const void* k = fp64 ? adj_kernel_for<true>(m.S, m.has_cia) : adj_kernel_for<false>(m.S, m.has_cia);
-  hipLaunchKernel(k, dim3((unsigned)(B * C)), dim3(fp64 ? kBlockT : kBlock), args, adj_lds_bytes(m, fp64), st);
+  hipLaunchKernel(k, dim3((unsigned)(B * C)), dim3(fp64 ? kBlockT : kBlockA), args, adj_lds_bytes(m, fp64), st);
 }
 
 void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, hipStream_t st) {
