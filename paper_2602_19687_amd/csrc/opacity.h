@@ -188,19 +188,21 @@ __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, size_t bytes) 
                                            0x00020000);
 }
 
-// Round to nearest even bf16 and back (finite inputs).
-__device__ inline uint16_t bf16_bits_rn(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ inline float bf16_bits_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+typedef __attribute__((ext_vector_type(2))) float float2v;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 
-// A float as a packed (bf16 hi | bf16 lo << 16) pair, hi + lo ~ 16 significant bits.
+// A float as a packed (bf16 hi | bf16 lo << 16) pair, hi + lo ~ 16 significant
+// bits; both roundings are the hardware's round-to-nearest-even conversion.
 __device__ inline uint32_t pack_hl(float v) {
-  const uint16_t h = bf16_bits_rn(v);
-  const uint16_t l = bf16_bits_rn(v - bf16_bits_to_f(h));
-  return (uint32_t)h | ((uint32_t)l << 16);
+  const float hf = (float)(__bf16)v;
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){v, v - hf}, bf16x2));
+}
+
+// bf16 hi pair (a, b) and lo pair of two floats, each as one dword (a in the low half).
+__device__ inline void split_pair(float a, float b, uint32_t& hp, uint32_t& lp) {
+  hp = __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){a, b}, bf16x2));
+  const float ha = __uint_as_float(hp << 16), hb = __uint_as_float(hp & 0xffff0000u);
+  lp = __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){a - ha, b - hb}, bf16x2));
 }
 
 // hi and lo bf16x8 fragments from eight packed pairs

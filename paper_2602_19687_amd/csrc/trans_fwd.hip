@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
   const LaneConst<S> kc = load_lane<S, CIA>(m, tb, nu0 + 2 * lane);
   const int KBe = (L + 15) >> 4;
   for (int o = wv; o < 2 * KBe; o += kBlockT / 64) {
-    uint16_t h0[8], l0[8], h1[8], l1[8];
+    float e0[8], e1[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int l = 8 * o + j;
@@ -87,24 +87,21 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
         if (dtau_out)
           *reinterpret_cast<float2*>(dtau_out + ((size_t)b * Lp + l) * npad + nu0 + 2 * lane) = make_float2(d0, d1);
       }
-      h0[j] = bf16_bits_rn(d0);
-      l0[j] = bf16_bits_rn(d0 - bf16_bits_to_f(h0[j]));
-      h1[j] = bf16_bits_rn(d1);
-      l1[j] = bf16_bits_rn(d1 - bf16_bits_to_f(h1[j]));
+      e0[j] = d0;
+      e1[j] = d1;
     }
-    auto pack = [](const uint16_t* v) {
-      uint4 p;
-      p.x = v[0] | ((uint32_t)v[1] << 16);
-      p.y = v[2] | ((uint32_t)v[3] << 16);
-      p.z = v[4] | ((uint32_t)v[5] << 16);
-      p.w = v[6] | ((uint32_t)v[7] << 16);
-      return p;
-    };
+    // bf16 hi/lo planes, pairs of consecutive layers per dword
+    uint32_t h0[4], l0[4], h1[4], l1[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      split_pair(e0[2 * j], e0[2 * j + 1], h0[j], l0[j]);
+      split_pair(e1[2 * j], e1[2 * j + 1], h1[j], l1[j]);
+    }
     const int r0 = (2 * lane) * stride + 8 * o, r1 = r0 + stride;
-    *reinterpret_cast<uint4*>(s_bhi + r0) = pack(h0);
-    *reinterpret_cast<uint4*>(s_blo + r0) = pack(l0);
-    *reinterpret_cast<uint4*>(s_bhi + r1) = pack(h1);
-    *reinterpret_cast<uint4*>(s_blo + r1) = pack(l1);
+    *reinterpret_cast<uint4*>(s_bhi + r0) = make_uint4(h0[0], h0[1], h0[2], h0[3]);
+    *reinterpret_cast<uint4*>(s_blo + r0) = make_uint4(l0[0], l0[1], l0[2], l0[3]);
+    *reinterpret_cast<uint4*>(s_bhi + r1) = make_uint4(h1[0], h1[1], h1[2], h1[3]);
+    *reinterpret_cast<uint4*>(s_blo + r1) = make_uint4(l1[0], l1[1], l1[2], l1[3]);
   }
   __syncthreads();
 
