@@ -160,7 +160,6 @@ def main():
 
     import synth
     from paper_2602_19687_amd import ForwardModel
-    from paper_2602_19687_amd import _lib as L
 
     cid, B = 1, args.batch
     t_setup = time.perf_counter()
@@ -171,11 +170,7 @@ def main():
 
     def run(prec, steps, warmup):
         fm = ForwardModel(wl, precision=prec, batch_max=B)
-        try:
-            fm.grad(th[:1])
-            has_grad = True
-        except L.ExoError:
-            has_grad = False
+        has_grad = fm.has_grad
         step = (lambda: fm.grad(th)) if has_grad else (lambda: fm.forward(th, want_spectra=False))
         for _ in range(warmup):
             step()

@@ -135,6 +135,9 @@ int32_t exofwd_num_params(const exofwd_ctx* ctx);   /* P, or -1 for NULL */
 int32_t exofwd_num_nu(const exofwd_ctx* ctx);       /* n_nu, or -1 */
 int32_t exofwd_num_bins(const exofwd_ctx* ctx);     /* K, or -1 */
 int32_t exofwd_precision(const exofwd_ctx* ctx);    /* EXOFWD_PREC_*, or -1 */
+/* 1 if exofwd_grad supports this context's workload (transmission, padded layer
+ * count <= 128, isothermal or Guillot profile), 0 if not, -1 for a NULL context */
+int32_t exofwd_grad_supported(const exofwd_ctx* ctx);
 
 /*
  * Forward model for B samples (1 <= B <= batch_max).

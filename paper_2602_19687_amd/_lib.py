@@ -46,6 +46,7 @@ EXPORTS = {
     "exofwd_num_nu": (C.c_int32, [C.c_void_p]),
     "exofwd_num_bins": (C.c_int32, [C.c_void_p]),
     "exofwd_precision": (C.c_int32, [C.c_void_p]),
+    "exofwd_grad_supported": (C.c_int32, [C.c_void_p]),
     "exofwd_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p]),
     "exofwd_grad": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

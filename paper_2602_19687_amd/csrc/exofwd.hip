@@ -159,6 +159,7 @@ int32_t exofwd_num_params(const exofwd_ctx* c) { return c ? c->m.P : -1; }
 int32_t exofwd_num_nu(const exofwd_ctx* c) { return c ? c->m.n_nu : -1; }
 int32_t exofwd_num_bins(const exofwd_ctx* c) { return c ? c->m.K : -1; }
 int32_t exofwd_precision(const exofwd_ctx* c) { return c ? c->precision : -1; }
+int32_t exofwd_grad_supported(const exofwd_ctx* c) { return c ? (adjoint_supported(c->m) ? 1 : 0) : -1; }
 int64_t exofwd_device_bytes(const exofwd_ctx* c) { return c ? c->bytes : -1; }
 
 exofwd_status exofwd_destroy(exofwd_ctx* c) {

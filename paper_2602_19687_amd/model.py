@@ -86,6 +86,7 @@ class ForwardModel:
         self.n_params = self.lib.exofwd_num_params(ctx)
         self.n_nu = self.lib.exofwd_num_nu(ctx)
         self.n_bins = self.lib.exofwd_num_bins(ctx)
+        self.has_grad = self.lib.exofwd_grad_supported(ctx) == 1
         self.spec_dtype = torch.float64 if self.precision == L.PREC_FP64 else torch.float32
 
     # ------------------------------------------------------------------ helpers
