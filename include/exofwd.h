@@ -135,8 +135,9 @@ int32_t exofwd_num_params(const exofwd_ctx* ctx);   /* P, or -1 for NULL */
 int32_t exofwd_num_nu(const exofwd_ctx* ctx);       /* n_nu, or -1 */
 int32_t exofwd_num_bins(const exofwd_ctx* ctx);     /* K, or -1 */
 int32_t exofwd_precision(const exofwd_ctx* ctx);    /* EXOFWD_PREC_*, or -1 */
-/* 1 if exofwd_grad supports this context's workload (transmission, padded layer
- * count <= 128, isothermal or Guillot profile), 0 if not, -1 for a NULL context */
+/* 1 if exofwd_grad supports this context's workload (transmission, isothermal or
+ * Guillot profile, n_layers_max <= 160 in MIXED or <= 128 in FP64 precision),
+ * 0 if not, -1 for a NULL context */
 int32_t exofwd_grad_supported(const exofwd_ctx* ctx);
 
 /*
@@ -154,8 +155,9 @@ exofwd_status exofwd_forward(exofwd_ctx* ctx, int32_t B, const double* params,
 
 /*
  * lnL and its gradient with respect to every parameter for B samples, by the
- * hand-written adjoint (transmission only; emission returns
- * EXOFWD_ERR_UNSUPPORTED).
+ * hand-written adjoint.  Workloads outside exofwd_grad_supported (emission, the
+ * PCHIP profile, more layers than the precision allows) return
+ * EXOFWD_ERR_UNSUPPORTED.
  *   lnL      dev [B] double (required)
  *   grad     dev [B][P] double (required): d lnL / d params
  *   spectra  dev [B][n_nu] (type as in exofwd_forward) or NULL

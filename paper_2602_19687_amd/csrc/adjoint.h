@@ -17,7 +17,11 @@ namespace exofwd {
 constexpr int kExtraSums = 6;
 __host__ __device__ constexpr int n_sums(int s) { return s + kExtraSums; }
 
+// shapes of the reduced-precision reverse kernel: wavenumber tile x 32-row blocks
+enum : int { kAdjT128M4 = 0, kAdjT64M4 = 1, kAdjT64M5 = 2, kAdjVariants = 3 };
+
 struct AdjWork {
+  int variant;         // reduced-precision reverse kernel shape (kAdj*)
   int max_pairs;       // allocated (sample, chunk) pairs of the fused reverse kernel
   double* layer_sums;  // FP64 path: [pair][L_pad][n_sums]
   void* pbar;          // [pair][L_pad][L_pad] d lnL / d P_il (row i, column l), float (mixed) or double (FP64)
@@ -30,7 +34,7 @@ struct AdjWork {
 };
 
 // wavenumber chunks per sample for a batch of B (pair index = b * chunks + chunk)
-int adjoint_chunks(const Model& m, int B, bool fp64);
+int adjoint_chunks(const Model& m, const AdjWork& aw, int B, bool fp64);
 bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std::function<void*(size_t)>& alloc);
 hipError_t adjoint_configure(const Model& m, bool fp64);
 void launch_trans_adjoint(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, bool fp64,
@@ -39,7 +43,12 @@ void launch_trans_adjoint(const Model& m, const Work& w, const Tables& tb, const
 void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, hipStream_t st);
 void launch_chain(const Model& m, const Work& w, const AdjWork& aw, int B, const double* params, const uint8_t* mask,
                   double* grad, bool fp64, hipStream_t st);
-// whether the adjoint supports this workload (transmission, L_pad <= 128, no PCHIP profile)
-bool adjoint_supported(const Model& m);
+// whether the adjoint supports this workload (transmission, no PCHIP profile,
+// L_pad <= 160 in reduced precision, <= 128 in FP64)
+bool adjoint_supported(const Model& m, bool fp64);
+// default reverse-kernel shape, whether a shape serves this model, and switching shapes
+int adjoint_default_variant(const Model& m);
+bool adjoint_variant_fits(const Model& m, int variant);
+bool adjoint_set_variant(AdjWork& aw, const Model& m, int variant);
 
 }  // namespace exofwd

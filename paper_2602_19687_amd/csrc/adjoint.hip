@@ -35,12 +35,12 @@ __device__ inline double wave_sum(double v) {
 
 // cost-balanced split of 32-row blocks between two waves; `rev` costs rows by
 // their K extent in the transposed product (grows with the block index)
-__device__ inline unsigned split_blocks(int part, int MBe, int KBe, bool rev) {
+__host__ __device__ inline unsigned split_blocks(int part, int MBe, int KBe, bool rev) {
   unsigned mine = 0;
   int c0 = 0, c1 = 0;
   for (int q = 0; q < MBe; ++q) {
     const int mi = rev ? MBe - 1 - q : q;
-    const int cost = rev ? min(2 * mi + 2, KBe) : KBe - 2 * mi;
+    const int cost = rev ? (2 * mi + 2 < KBe ? 2 * mi + 2 : KBe) : KBe - 2 * mi;
     if (c0 <= c1) {
       if (part == 0) mine |= 1u << mi;
       c0 += cost;
@@ -62,22 +62,29 @@ __device__ inline int nth_bit(unsigned mask, int q) {
   return -1;
 }
 
-constexpr int kSlots = 2;    // 32-row blocks per wave (the greedy split gives at most 2 for L_pad <= 128)
-constexpr int kPSlots = 2;   // path-matrix adjoint tiles per wave
-
 // ============================================================================
-// reduced-precision reverse kernel: 512 threads, 128-wavenumber tiles; each wave
-// owns one 32-wavenumber column block and half of the 32-row blocks, so every
-// path-matrix fragment it loads feeds the products of the whole tile
-constexpr int kTileA = 128;               // wavenumbers per tile
-constexpr int kBlockA = 512;              // threads per workgroup
-constexpr int kNbA = kTileA / 32;         // column blocks per tile (waves sharing a row-block split)
-constexpr int kWavesA = kBlockA / 64;
-constexpr int kPSlotsA = 2;               // 32x32 Pbar tiles per wave (10 tiles over 8 waves for L_pad <= 128)
-constexpr int kItemsA = 4;                // (layer octet, half tile) items per wave: 8 MBe <= 32 over 8 waves
+// reduced-precision reverse kernel over TILE-wavenumber tiles for up to MB
+// 32-row blocks (L_pad <= 32 MB); each wave owns one 32-wavenumber column block
+// and one of two cost-balanced halves of the row blocks, so every path-matrix
+// fragment it loads feeds the products of its whole column block
+template <int TILE, int MB>
+struct AdjShape {
+  static constexpr int kTile = TILE;
+  static constexpr int kNb = TILE / 32;                           // column blocks per tile
+  static constexpr int kWaves = 2 * kNb;                          // two row-block halves per column block
+  static constexpr int kThreads = 64 * kWaves;
+  static constexpr int kHalves = TILE / 64;                       // 64-wavenumber halves (phase A items)
+  static constexpr int kSlots = (MB + 1) / 2;                     // row blocks per wave (checked on the host)
+  static constexpr int kPSlots = (MB * (MB + 1) / 2 + kWaves - 1) / kWaves;   // 32x32 Pbar tiles per wave
+  static constexpr int kItems = MB;                               // (layer octet, half) items per wave
+};
 
-template <int S, bool CIA>
-__global__ __launch_bounds__(kBlockA) void k_trans_adj_mixed(Model m, Work w, Tables tb, AdjWork aw, int B, int C) {
+template <int S, bool CIA, int TILE, int MB>
+__global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, Tables tb, AdjWork aw, int B, int C) {
+  using Sh = AdjShape<TILE, MB>;
+  static_assert(Sh::kThreads == 4 * TILE, "launch bound");
+  constexpr int kTileA = Sh::kTile, kBlockA = Sh::kThreads, kNbA = Sh::kNb, kWavesA = Sh::kWaves;
+  constexpr int kSlots = Sh::kSlots, kPSlotsA = Sh::kPSlots, kItemsA = Sh::kItems, kHalves = Sh::kHalves;
   extern __shared__ __align__(16) unsigned char lds[];
   const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = logical % B, chunk = logical / B;
@@ -121,7 +128,7 @@ __global__ __launch_bounds__(kBlockA) void k_trans_adj_mixed(Model m, Work w, Ta
   const int h = lane >> 5;
   const double* dm = w.dm + (size_t)b * m.K;
 
-  // Pbar tiles (32x32, column block >= row block), round-robin over the 4 waves
+  // Pbar tiles (32x32, column block >= row block), round-robin over the waves
   int pt_mi[kPSlotsA], pt_nl[kPSlotsA];
   {
     int t = 0;
@@ -163,8 +170,8 @@ __global__ __launch_bounds__(kBlockA) void k_trans_adj_mixed(Model m, Work w, Ta
     for (int q = 0; q < kItemsA; ++q) {
       const int it = wv + kWavesA * q;
       if (it >= 8 * MBe) continue;
-      const int o = it >> 1;
-      const uint32_t voff = (uint32_t)(64 * (it & 1) + lane) * 4u;
+      const int o = it / kHalves;
+      const uint32_t voff = (uint32_t)(64 * (it % kHalves) + lane) * 4u;
       const uint32_t soff = (uint32_t)((8 * o * npad + (size_t)tile * kTileA) * 4);
 #pragma unroll
       for (int j = 0; j < 8; ++j)
@@ -180,7 +187,7 @@ __global__ __launch_bounds__(kBlockA) void k_trans_adj_mixed(Model m, Work w, Ta
     for (int q = 0; q < kItemsA; ++q) {
       const int it = wv + kWavesA * q;
       if (it >= 8 * MBe) continue;
-      const int o = it >> 1, nu = 64 * (it & 1) + lane;
+      const int o = it / kHalves, nu = 64 * (it % kHalves) + lane;
       float d[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) d[j] = 8 * o + j < Lq ? pf[q][j] : 0.0f;
@@ -936,20 +943,45 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
 
 // ============================================================================
 // host side
-int adjoint_chunks(const Model& m, int B, bool fp64) {
-  // the FP64 reverse kernel walks 64-wavenumber tiles, the reduced-precision one 128
-  const int tiles = fp64 ? m.n_tiles64 : m.n_tiles;
+// reduced-precision reverse kernel shapes: (tile, row blocks)
+static int adj_tile(int variant) { return variant == kAdjT128M4 ? 128 : 64; }
+static int adj_mb(int variant) { return variant == kAdjT64M5 ? 5 : 4; }
+static int adj_threads(int variant) { return 4 * adj_tile(variant); }
+static int adj_slots(int variant) { return (adj_mb(variant) + 1) / 2; }
+
+int adjoint_chunks(const Model& m, const AdjWork& aw, int B, bool fp64) {
+  // the FP64 reverse kernel walks 64-wavenumber tiles
+  const int tiles = m.n_nu_pad / (fp64 ? kTile64 : adj_tile(aw.variant));
   int c = (1024 + B - 1) / B;
   return c < 1 ? 1 : (c > tiles ? tiles : c);
 }
 
-bool adjoint_supported(const Model& m) { return m.mode == kTransmission && m.L_pad <= 128 && m.tp_kind != kTpPchip; }
+bool adjoint_supported(const Model& m, bool fp64) {
+  return m.mode == kTransmission && m.tp_kind != kTpPchip && m.L_pad <= (fp64 ? 128 : 160);
+}
+
+int adjoint_default_variant(const Model& m) { return m.L_pad <= 128 ? kAdjT128M4 : kAdjT64M5; }
+
+bool adjoint_variant_fits(const Model& m, int variant) {
+  if (m.L_pad > 32 * adj_mb(variant)) return false;
+  // the greedy row-block split must never give a wave more blocks than it has slots
+  for (int L = 1; L <= m.L_max; ++L) {
+    const int KBe = (L + 15) >> 4, MBe = (L + 31) >> 5;
+    for (int part = 0; part < 2; ++part)
+      for (int rev = 0; rev < 2; ++rev)
+        if (__builtin_popcount(split_blocks(part, MBe, KBe, rev != 0)) > adj_slots(variant)) return false;
+  }
+  return true;
+}
 
 bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std::function<void*(size_t)>& alloc) {
   aw = AdjWork{};
-  if (!adjoint_supported(m)) return true;
+  if (!adjoint_supported(m, fp64)) return true;
+  // chunk counts of the narrowest tile bound those of every shape the context may switch to
+  aw.variant = fp64 ? kAdjT128M4 : (adjoint_variant_fits(m, kAdjT64M4) ? kAdjT64M4 : kAdjT64M5);
   int pairs = 0;
-  for (int B = 1; B <= B_max; ++B) pairs = std::max(pairs, B * adjoint_chunks(m, B, fp64));
+  for (int B = 1; B <= B_max; ++B) pairs = std::max(pairs, B * adjoint_chunks(m, aw, B, fp64));
+  aw.variant = adjoint_default_variant(m);
   aw.max_pairs = pairs;
   const size_t Lp = m.L_pad;
   aw.pbar = alloc((size_t)pairs * Lp * Lp * (fp64 ? sizeof(double) : sizeof(float)));
@@ -966,23 +998,33 @@ bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std:
   return aw.dtb && aw.dtau && aw.lsum;
 }
 
-static size_t adj_lds_bytes(const Model& m, bool fp64) {
+static size_t adj_lds_bytes(const Model& m, bool fp64, int variant) {
   const size_t Lp = m.L_pad, ns = n_sums(m.S);
   if (fp64) return (size_t)2 * kTile64 * (Lp + 1) * 8 + Lp * ns * 8;
-  (void)ns;
-  return std::max((size_t)2 * kTileA * (Lp + 4) * 4 + Lp * 4, (size_t)kNbA * Lp * 8);
+  const size_t tile = adj_tile(variant);
+  return std::max(2 * tile * (Lp + 4) * 4 + Lp * 4, tile / 32 * Lp * 8);
+}
+
+template <int S, bool CIA>
+const void* adj_mixed_kernel(int variant) {
+  switch (variant) {
+    case kAdjT128M4: return (const void*)k_trans_adj_mixed<S, CIA, 128, 4>;
+    case kAdjT64M4: return (const void*)k_trans_adj_mixed<S, CIA, 64, 4>;
+    case kAdjT64M5: return (const void*)k_trans_adj_mixed<S, CIA, 64, 5>;
+  }
+  return nullptr;
 }
 
 template <bool F64, int S, bool CIA>
-const void* adj_kernel() {
-  if constexpr (F64) return (const void*)k_trans_adj_fp64<S, CIA>;
-  else return (const void*)k_trans_adj_mixed<S, CIA>;
+const void* adj_kernel(int variant) {
+  if constexpr (F64) return (void)variant, (const void*)k_trans_adj_fp64<S, CIA>;
+  else return adj_mixed_kernel<S, CIA>(variant);
 }
 
 template <bool F64>
-const void* adj_kernel_for(int S, bool cia) {
+const void* adj_kernel_for(int S, bool cia, int variant) {
 #define EXOFWD_CASE(n) \
-  case n: return cia ? adj_kernel<F64, n, true>() : adj_kernel<F64, n, false>();
+  case n: return cia ? adj_kernel<F64, n, true>(variant) : adj_kernel<F64, n, false>(variant);
   switch (S) {
     EXOFWD_CASE(1) EXOFWD_CASE(2) EXOFWD_CASE(3) EXOFWD_CASE(4)
     EXOFWD_CASE(5) EXOFWD_CASE(6) EXOFWD_CASE(7) EXOFWD_CASE(8)
@@ -1003,20 +1045,41 @@ const void* ls_kernel_for(int S, bool cia) {
 }
 
 hipError_t adjoint_configure(const Model& m, bool fp64) {
-  if (!adjoint_supported(m)) return hipSuccess;
-  const void* k = fp64 ? adj_kernel_for<true>(m.S, m.has_cia) : adj_kernel_for<false>(m.S, m.has_cia);
-  if (!k) return hipErrorInvalidValue;
-  const size_t bytes = adj_lds_bytes(m, fp64);
-  if (bytes > 160 * 1024) return hipErrorInvalidValue;
-  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (!adjoint_supported(m, fp64)) return hipSuccess;
+  if (fp64) {
+    const void* k = adj_kernel_for<true>(m.S, m.has_cia, 0);
+    const size_t bytes = adj_lds_bytes(m, true, 0);
+    if (!k || bytes > 160 * 1024) return hipErrorInvalidValue;
+    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  }
+  bool any = false;
+  for (int v = 0; v < kAdjVariants; ++v) {
+    const size_t bytes = adj_lds_bytes(m, false, v);
+    if (!adjoint_variant_fits(m, v) || bytes > 160 * 1024) continue;
+    const void* k = adj_kernel_for<false>(m.S, m.has_cia, v);
+    if (!k) return hipErrorInvalidValue;
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    any = true;
+  }
+  return any ? hipSuccess : hipErrorInvalidValue;
+}
+
+bool adjoint_set_variant(AdjWork& aw, const Model& m, int variant) {
+  if (variant < 0 || variant >= kAdjVariants || !adjoint_variant_fits(m, variant) ||
+      adj_lds_bytes(m, false, variant) > 160 * 1024)
+    return false;
+  aw.variant = variant;
+  return true;
 }
 
 void launch_trans_adjoint(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, bool fp64,
                           hipStream_t st) {
-  int C = adjoint_chunks(m, B, fp64);
+  int C = adjoint_chunks(m, aw, B, fp64);
   void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&aw, (void*)&B, (void*)&C};
-  const void* k = fp64 ? adj_kernel_for<true>(m.S, m.has_cia) : adj_kernel_for<false>(m.S, m.has_cia);
-  hipLaunchKernel(k, dim3((unsigned)(B * C)), dim3(fp64 ? kBlockT : kBlockA), args, adj_lds_bytes(m, fp64), st);
+  const void* k = fp64 ? adj_kernel_for<true>(m.S, m.has_cia, 0) : adj_kernel_for<false>(m.S, m.has_cia, aw.variant);
+  hipLaunchKernel(k, dim3((unsigned)(B * C)), dim3(fp64 ? kBlockT : adj_threads(aw.variant)), args,
+                  adj_lds_bytes(m, fp64, aw.variant), st);
 }
 
 void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, hipStream_t st) {
@@ -1028,7 +1091,7 @@ void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const Ad
 
 void launch_chain(const Model& m, const Work& w, const AdjWork& aw, int B, const double* params, const uint8_t* mask,
                   double* grad, bool fp64, hipStream_t st) {
-  const int C = adjoint_chunks(m, B, fp64);
+  const int C = adjoint_chunks(m, aw, B, fp64);
   if (fp64)
     hipLaunchKernelGGL(k_chain<double>, dim3(B), dim3(kBlock), 0, st, m, w, aw, C, params, mask, grad);
   else

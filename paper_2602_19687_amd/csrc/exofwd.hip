@@ -159,7 +159,9 @@ int32_t exofwd_num_params(const exofwd_ctx* c) { return c ? c->m.P : -1; }
 int32_t exofwd_num_nu(const exofwd_ctx* c) { return c ? c->m.n_nu : -1; }
 int32_t exofwd_num_bins(const exofwd_ctx* c) { return c ? c->m.K : -1; }
 int32_t exofwd_precision(const exofwd_ctx* c) { return c ? c->precision : -1; }
-int32_t exofwd_grad_supported(const exofwd_ctx* c) { return c ? (adjoint_supported(c->m) ? 1 : 0) : -1; }
+int32_t exofwd_grad_supported(const exofwd_ctx* c) {
+  return c ? (adjoint_supported(c->m, c->precision == EXOFWD_PREC_FP64) ? 1 : 0) : -1;
+}
 int64_t exofwd_device_bytes(const exofwd_ctx* c) { return c ? c->bytes : -1; }
 
 exofwd_status exofwd_destroy(exofwd_ctx* c) {
@@ -462,8 +464,9 @@ exofwd_status exofwd_grad(exofwd_ctx* c, int32_t B, const double* params, const 
   if (s) return s;
   if (!lnL || !grad) return fail(c, EXOFWD_ERR_ARG, "lnL and grad are required");
   if (c->m.mode != kTransmission) return fail(c, EXOFWD_ERR_UNSUPPORTED, "the adjoint covers transmission only");
-  if (!adjoint_supported(c->m))
-    return fail(c, EXOFWD_ERR_UNSUPPORTED, "the adjoint needs n_layers_max <= 128 and a non-PCHIP profile");
+  if (!adjoint_supported(c->m, c->precision == EXOFWD_PREC_FP64))
+    return fail(c, EXOFWD_ERR_UNSUPPORTED,
+                "the adjoint needs a non-PCHIP profile and n_layers_max <= 160 (reduced precision) or <= 128 (FP64)");
   if ((s = run_forward(c, B, params, n_layers, spectra, lnL, status, hip_stream,
                        c->precision == EXOFWD_PREC_MIXED ? c->aw.dtau : nullptr)))
     return s;

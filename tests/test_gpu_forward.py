@@ -151,3 +151,38 @@ def test_mixed_matches_oracle_with_decoded_fp16_tables(cid, tol):
 
 if __name__ == "__main__":
     sys.exit(pytest.main([__file__, "-v", "-s"]))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_c4_reduced_ragged(prec):
+    """High-resolution configuration cut to 3000 wavenumbers (23 full tiles + a
+    ragged tail), its own per-sample layer counts (60-150), every sample."""
+    wl = reduced(4, n_nu=3000, n_bins=20, batch=8, n_layers=150, start=100000)
+    nl = synth.workload(4, batch=8)["n_layers_per_sample"]
+    spec, lnl, st = _run(wl, prec, wl["params"], n_layers=nl)
+    errs = []
+    for b in range(8):
+        ref = oracle.forward(wl, wl["params"][b], n_layers=int(nl[b]))
+        assert st[b] == ref["status"]
+        if ref["status"]:
+            continue
+        errs.append(rel_err(spec[b], ref["spectrum"]))
+        assert abs(lnl[b] - ref["lnL"]) <= LNL_TOL[prec] * abs(ref["lnL"])
+    print(f"c4 reduced {prec}: spectrum max rel err {max(errs):.3e}")
+    assert max(errs) < SPEC_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["mixed"])
+def test_c4_full_size_sampled(prec):
+    """The full high-resolution batch (B = 64, 400000 wavenumbers, 60-150 layers);
+    two samples against the oracle, the rest finite."""
+    wl = synth.workload(4)
+    nl = wl["n_layers_per_sample"]
+    spec, lnl, st = _run(wl, prec, wl["params"], n_layers=nl)
+    assert np.all(st == 0) and np.all(np.isfinite(spec))
+    for b in (int(np.argmax(nl)), int(np.argmin(nl))):
+        ref = oracle.forward(wl, wl["params"][b], n_layers=int(nl[b]))
+        err = rel_err(spec[b], ref["spectrum"])
+        lerr = abs(lnl[b] - ref["lnL"]) / abs(ref["lnL"])
+        print(f"c4 full {prec} sample {b} L={nl[b]}: spectrum rel err {err:.3e} lnL rel err {lerr:.3e}")
+        assert err < SPEC_TOL[prec] and lerr < LNL_TOL[prec]

@@ -141,3 +141,38 @@ def test_ragged_layer_counts_after_full_call(prec):
         e = grad_err(g[b], gref)
         print(f"ragged {prec} L={nl[b]}: grad err {e:.3e}")
         assert e < TOL[prec]
+
+
+def test_grad_up_to_150_layers():
+    """Padded layer count 160 (five 32-row blocks): the reduced-precision reverse
+    kernel's 64-wavenumber, five-block shape; the FP64 adjoint stops at 128."""
+    from paper_2602_19687_amd import ForwardModel
+    from paper_2602_19687_amd import _lib as L
+    wl = reduced(3, n_nu=700, n_bins=14, batch=4, n_layers=150)
+    fm64 = ForwardModel(wl, precision="fp64", batch_max=4)
+    assert not fm64.has_grad
+    with pytest.raises(L.ExoError):
+        fm64.grad(torch.tensor(wl["params"], device="cuda"))
+    fm64.close()
+    nl = np.array([150, 129, 97, 33], dtype=np.int32)
+    lnl, g, st, lnl_f = _grad(wl, "mixed", wl["params"], n_layers=torch.tensor(nl, device="cuda"))
+    for b in range(4):
+        gref = oracle.grad_complex_step(wl, wl["params"][b], n_layers=int(nl[b]))
+        assert st[b] == 0
+        e = grad_err(g[b], gref)
+        print(f"L={nl[b]} (L_pad 160): grad err {e:.3e}")
+        assert e < TOL["mixed"]
+
+
+def test_c4_reduced_grad():
+    """High-resolution configuration (4 absorbers, 8x8 tables, 0.016 cm^-1 grid),
+    cut to 1500 wavenumbers, per-sample layer counts of the configuration."""
+    wl = reduced(4, n_nu=1500, n_bins=12, batch=3, n_layers=150, start=200000)
+    nl = synth.workload(4, batch=3)["n_layers_per_sample"]
+    lnl, g, st, _ = _grad(wl, "mixed", wl["params"], n_layers=torch.tensor(nl, device="cuda"))
+    for b in range(3):
+        gref = oracle.grad_complex_step(wl, wl["params"][b], n_layers=int(nl[b]))
+        assert st[b] == 0
+        e = grad_err(g[b], gref)
+        print(f"c4 reduced L={nl[b]}: grad err {e:.3e}")
+        assert e < TOL["mixed"]
