@@ -167,11 +167,48 @@ exofwd_status exofwd_grad(exofwd_ctx* ctx, int32_t B, const double* params,
                           const int32_t* n_layers, void* spectra, double* lnL,
                           double* grad, int32_t* status, void* hip_stream);
 
-/* Time the tunable launch shapes of this context at batch B on its device and
- * keep the fastest (synchronous).  cache_path (may be NULL) is a text file of
- * previous results keyed by device, CU count and workload shape; it is read if
- * present and rewritten with the result. */
-exofwd_status exofwd_autotune(exofwd_ctx* ctx, int32_t B, const char* cache_path);
+/*
+ * Launch choices of a reduced-precision transmission context, four int32:
+ *   [0] forward grid order: 0 samples fastest, 1 wavenumber tiles fastest
+ *   [1] reverse-kernel shape: 0 = 128-wavenumber tiles x 4 row blocks (padded
+ *       layers <= 128), 1 = 64 x 4 (<= 128), 2 = 64 x 5 (<= 160)
+ *   [2] reverse work items per call, one of 512, 1024, 2048, 4096 (each sample's
+ *       wavenumbers are split into ceil(items / B) chunks)
+ *   [3] 128-wavenumber tiles per wave of the layer-sum kernel: 4, 8 or 16
+ * Every choice gives the same results up to FP32 summation order.
+ * exofwd_set_tuning returns EXOFWD_ERR_ARG, changing nothing, for a choice that
+ * does not serve the context (entries [1..3] are ignored when the context has no
+ * reduced-precision gradient); it synchronises the device and drops captured
+ * graphs.  exofwd_get_tuning writes the current choices.
+ */
+exofwd_status exofwd_set_tuning(exofwd_ctx* ctx, const int32_t* tuning);
+exofwd_status exofwd_get_tuning(const exofwd_ctx* ctx, int32_t* tuning);
+
+/*
+ * Time the launch choices at batch B and keep the fastest (synchronous; it
+ * allocates its own timing buffers and stream).  params dev [B][P] double, or
+ * NULL for a built-in valid mid-range parameter vector; n_layers dev [B] int32
+ * or NULL, as in exofwd_forward.  The step timed is exofwd_grad where supported,
+ * else exofwd_forward.  cache_path (may be NULL) is a text file of earlier results,
+ * one line per key (device architecture, CU count, workload shape, B); a matching
+ * line is applied without timing, and a new result is written back to the file.
+ * FP64 and emission contexts have no tunable choices: the call returns EXOFWD_OK.
+ */
+exofwd_status exofwd_autotune(exofwd_ctx* ctx, int32_t B, const double* params, const int32_t* n_layers,
+                              const char* cache_path);
+
+/*
+ * Graph replay (off by default).  When enabled, the first exofwd_forward or
+ * exofwd_grad call with a given (call kind, B, pointer arguments, stream) is
+ * captured into a hipGraph on its stream and launched; later calls with the same
+ * arguments launch that graph (up to 16 are kept, least recently used dropped).
+ * Buffers are read at replay, so new parameter values in the same buffer are
+ * evaluated.  The stream must not be the null stream (EXOFWD_ERR_ARG).  A call
+ * made while the caller is itself capturing the stream is enqueued into the
+ * caller's graph.  Changing the setting synchronises the device and drops the
+ * captured graphs.  Per-kernel timing then reports one "graph" entry per call.
+ */
+exofwd_status exofwd_set_graphs(exofwd_ctx* ctx, int32_t enable);
 
 /* Per-kernel timing of the calls that follow: when enabled, each kernel launch
  * is bracketed by HIP events on the call's stream.  exofwd_kernel_time then

@@ -51,7 +51,10 @@ EXPORTS = {
                                  C.c_void_p, C.c_void_p]),
     "exofwd_grad": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p]),
-    "exofwd_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p]),
+    "exofwd_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_char_p]),
+    "exofwd_set_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "exofwd_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "exofwd_set_graphs": (C.c_int, [C.c_void_p, C.c_int32]),
     "exofwd_set_profiling": (C.c_int, [C.c_void_p, C.c_int32]),
     "exofwd_kernel_time": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "exofwd_device_bytes": (C.c_int64, [C.c_void_p]),

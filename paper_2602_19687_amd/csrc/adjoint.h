@@ -20,8 +20,14 @@ __host__ __device__ constexpr int n_sums(int s) { return s + kExtraSums; }
 // shapes of the reduced-precision reverse kernel: wavenumber tile x 32-row blocks
 enum : int { kAdjT128M4 = 0, kAdjT64M4 = 1, kAdjT64M5 = 2, kAdjVariants = 3 };
 
+// launch choices the autotuner may change (every value is valid for any workload)
+constexpr int kChunkTargets[] = {512, 1024, 2048, 4096};   // (sample, chunk) work items per reverse launch
+constexpr int kLsTileChoices[] = {4, 8, 16};               // 128-wavenumber tiles per layer-sum wave
+
 struct AdjWork {
   int variant;         // reduced-precision reverse kernel shape (kAdj*)
+  int chunk_target;    // the reverse kernel splits each sample's wavenumbers into ~chunk_target / B chunks
+  int ls_tiles;        // tiles per wave of the layer-sum kernel
   int max_pairs;       // allocated (sample, chunk) pairs of the fused reverse kernel
   double* layer_sums;  // FP64 path: [pair][L_pad][n_sums]
   void* pbar;          // [pair][L_pad][L_pad] d lnL / d P_il (row i, column l), float (mixed) or double (FP64)
@@ -30,7 +36,8 @@ struct AdjWork {
   float* dtau;         // [B_max][L_pad][n_nu_pad] layer optical depths stored by the forward kernel
   float* dtb;          // [B_max][L_pad][n_nu_pad] d lnL / d dtau_l(nu)
   float* lsum;         // [B_max][lsum_chunks][L_pad][n_sums] partial layer sums
-  int lsum_chunks;     // wavenumber chunks of the layer-sum kernel
+  int lsum_chunks;     // wavenumber chunks of the layer-sum kernel (n_tiles / ls_tiles, rounded up)
+  int lsum_stride;     // allocated chunks per sample (the bound over the ls_tiles choices)
 };
 
 // wavenumber chunks per sample for a batch of B (pair index = b * chunks + chunk)
@@ -49,6 +56,8 @@ bool adjoint_supported(const Model& m, bool fp64);
 // default reverse-kernel shape, whether a shape serves this model, and switching shapes
 int adjoint_default_variant(const Model& m);
 bool adjoint_variant_fits(const Model& m, int variant);
-bool adjoint_set_variant(AdjWork& aw, const Model& m, int variant);
+// switch the reduced-precision launch choices (reverse shape, chunk target, layer-sum
+// tiles); false, with nothing changed, if a choice does not serve this model
+bool adjoint_set_tuning(AdjWork& aw, const Model& m, int variant, int chunk_target, int ls_tiles);
 
 }  // namespace exofwd

@@ -83,6 +83,7 @@ template <int S, bool CIA, int TILE, int MB>
 __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, Tables tb, AdjWork aw, int B, int C) {
   using Sh = AdjShape<TILE, MB>;
   static_assert(Sh::kThreads == 4 * TILE, "launch bound");
+  static_assert(Sh::kItems * Sh::kWaves == 4 * Sh::kHalves * MB, "phase A items cover 4 MB octets per half");
   constexpr int kTileA = Sh::kTile, kBlockA = Sh::kThreads, kNbA = Sh::kNb, kWavesA = Sh::kWaves;
   constexpr int kSlots = Sh::kSlots, kPSlotsA = Sh::kPSlots, kItemsA = Sh::kItems, kHalves = Sh::kHalves;
   extern __shared__ __align__(16) unsigned char lds[];
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
 #pragma unroll
     for (int q = 0; q < kItemsA; ++q) {
       const int it = wv + kWavesA * q;
-      if (it >= 8 * MBe) continue;
+      if (it >= 4 * kHalves * MBe) continue;   // 4 MBe layer octets per half
       const int o = it / kHalves;
       const uint32_t voff = (uint32_t)(64 * (it % kHalves) + lane) * 4u;
       const uint32_t soff = (uint32_t)((8 * o * npad + (size_t)tile * kTileA) * 4);
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
 #pragma unroll
     for (int q = 0; q < kItemsA; ++q) {
       const int it = wv + kWavesA * q;
-      if (it >= 8 * MBe) continue;
+      if (it >= 4 * kHalves * MBe) continue;   // 4 MBe layer octets per half
       const int o = it / kHalves, nu = 64 * (it % kHalves) + lane;
       float d[8];
 #pragma unroll
@@ -381,7 +382,6 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
 // lanes hold two wavenumbers, partial sums stay in registers across the tiles
 // and are reduced over the wave once
 constexpr int kLsLayers = 4;
-constexpr int kLsTiles = 8;
 
 template <int S, bool CIA>
 __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Tables tb, AdjWork aw, int B) {
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
 #pragma unroll
     for (int k = 0; k < NS; ++k) acc[q][k] = 0.0f;
 
-  const int t0 = chunk * kLsTiles, t1 = min(t0 + kLsTiles, m.n_tiles);
+  const int t0 = chunk * aw.ls_tiles, t1 = min(t0 + aw.ls_tiles, m.n_tiles);
   for (int tile = t0; tile < t1; ++tile) {
     const int nu0 = tile * kTileNu;
     const LaneConst<S> kc = load_lane<S, CIA>(m, tb, nu0 + 2 * lane);
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
       acc[q][S + 5] += db.x + db.y;
     }
   }
-  float* out = aw.lsum + ((size_t)b * aw.lsum_chunks + chunk) * Lp * NS;
+  float* out = aw.lsum + ((size_t)b * aw.lsum_stride + chunk) * Lp * NS;
 #pragma unroll
   for (int q = 0; q < kLsLayers; ++q) {
     const int l = l0 + q;
@@ -692,7 +692,7 @@ __device__ inline void path_derivs(const double* r, int i, int l, double& d_lo, 
 }
 
 template <typename PbarT>
-__global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, int C, const double* __restrict__ params,
+__global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, int C, int Cn, const double* __restrict__ params,
                                                   const uint8_t* __restrict__ mask, double* __restrict__ grad) {
   const int b = blockIdx.x, tid = threadIdx.x;
   const int Lp = m.L_pad;
@@ -748,9 +748,9 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
     for (int k = 0; k < NS; ++k) {
       double v = 0.0;
       if constexpr (sizeof(PbarT) == 8) {
-        for (int c = 0; c < C; ++c) v += aw.layer_sums[(((size_t)b * C + c) * Lp + l) * NS + k];
+        for (int c = 0; c < Cn; ++c) v += aw.layer_sums[(((size_t)b * C + c) * Lp + l) * NS + k];
       } else {
-        for (int c = 0; c < aw.lsum_chunks; ++c) v += (double)aw.lsum[(((size_t)b * aw.lsum_chunks + c) * Lp + l) * NS + k];
+        for (int c = 0; c < aw.lsum_chunks; ++c) v += (double)aw.lsum[(((size_t)b * aw.lsum_stride + c) * Lp + l) * NS + k];
       }
       sm[k] = v;
     }
@@ -809,7 +809,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
   const PbarT* pbar = reinterpret_cast<const PbarT*>(aw.pbar);
   auto pb = [&](int i, int l) {
     double v = 0.0;
-    for (int c = 0; c < C; ++c) v += (double)pbar[(((size_t)b * C + c) * Lp + i) * Lp + l];
+    for (int c = 0; c < Cn; ++c) v += (double)pbar[(((size_t)b * C + c) * Lp + i) * Lp + l];
     return v;
   };
   for (int l = tid; l < L; l += kBlock) {
@@ -839,7 +839,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
   for (int j = tid; j <= L; j += kBlock) {
     double rb = 0.0;
     double ab_j = 0.0, ab_jm = 0.0;
-    for (int c = 0; c < C; ++c) {
+    for (int c = 0; c < Cn; ++c) {
       if (j < L) ab_j += aw.abar[((size_t)b * C + c) * Lp + j];
       if (j >= 1) ab_jm += aw.abar[((size_t)b * C + c) * Lp + j - 1];
     }
@@ -942,6 +942,39 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
 }
 
 // ============================================================================
+// sum of the reverse kernel's per-chunk partials into chunk 0 of each sample
+// (path-matrix adjoint, annulus-area adjoint and, in FP64, the layer sums), so
+// the chain reads one slot; one thread per (sample, element)
+template <typename PbarT>
+__global__ __launch_bounds__(kBlock) void k_reduce_chunks(Model m, Work w, AdjWork aw, int B, int C) {
+  const int Lp = m.L_pad, NS = n_sums(m.S);
+  const long n_p = (long)Lp * Lp, n_a = Lp, n_s = sizeof(PbarT) == 8 ? (long)Lp * NS : 0;
+  const long per = n_p + n_a + n_s;
+  const long gid = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= per * B) return;
+  const int b = (int)(gid / per);
+  if (w.status[b]) return;
+  const long e = gid - (long)b * per;
+  const size_t p0 = (size_t)b * C;
+  if (e < n_p) {
+    PbarT* pb = reinterpret_cast<PbarT*>(aw.pbar);
+    double v = 0.0;
+    for (int c = 0; c < C; ++c) v += (double)pb[(p0 + c) * n_p + e];
+    pb[p0 * n_p + e] = (PbarT)v;
+  } else if (e < n_p + n_a) {
+    const long i = e - n_p;
+    double v = 0.0;
+    for (int c = 0; c < C; ++c) v += aw.abar[(p0 + c) * n_a + i];
+    aw.abar[p0 * n_a + i] = v;
+  } else {
+    const long i = e - n_p - n_a;
+    double v = 0.0;
+    for (int c = 0; c < C; ++c) v += aw.layer_sums[(p0 + c) * (size_t)Lp * NS + i];
+    aw.layer_sums[p0 * (size_t)Lp * NS + i] = v;
+  }
+}
+
+// ============================================================================
 // host side
 // reduced-precision reverse kernel shapes: (tile, row blocks)
 static int adj_tile(int variant) { return variant == kAdjT128M4 ? 128 : 64; }
@@ -952,7 +985,8 @@ static int adj_slots(int variant) { return (adj_mb(variant) + 1) / 2; }
 int adjoint_chunks(const Model& m, const AdjWork& aw, int B, bool fp64) {
   // the FP64 reverse kernel walks 64-wavenumber tiles
   const int tiles = m.n_nu_pad / (fp64 ? kTile64 : adj_tile(aw.variant));
-  int c = (1024 + B - 1) / B;
+  const int target = fp64 ? 1024 : aw.chunk_target;
+  int c = (target + B - 1) / B;
   return c < 1 ? 1 : (c > tiles ? tiles : c);
 }
 
@@ -977,11 +1011,15 @@ bool adjoint_variant_fits(const Model& m, int variant) {
 bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std::function<void*(size_t)>& alloc) {
   aw = AdjWork{};
   if (!adjoint_supported(m, fp64)) return true;
-  // chunk counts of the narrowest tile bound those of every shape the context may switch to
+  // chunk counts of the narrowest tile and the largest target bound those of every
+  // launch choice the context may switch to
   aw.variant = fp64 ? kAdjT128M4 : (adjoint_variant_fits(m, kAdjT64M4) ? kAdjT64M4 : kAdjT64M5);
+  aw.chunk_target = kChunkTargets[sizeof(kChunkTargets) / sizeof(int) - 1];
   int pairs = 0;
   for (int B = 1; B <= B_max; ++B) pairs = std::max(pairs, B * adjoint_chunks(m, aw, B, fp64));
   aw.variant = adjoint_default_variant(m);
+  aw.chunk_target = 1024;
+  aw.ls_tiles = 8;
   aw.max_pairs = pairs;
   const size_t Lp = m.L_pad;
   aw.pbar = alloc((size_t)pairs * Lp * Lp * (fp64 ? sizeof(double) : sizeof(float)));
@@ -991,10 +1029,11 @@ bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std:
     aw.layer_sums = (double*)alloc((size_t)pairs * Lp * n_sums(m.S) * sizeof(double));
     return aw.layer_sums != nullptr;
   }
-  aw.lsum_chunks = (m.n_tiles + kLsTiles - 1) / kLsTiles;
+  aw.lsum_stride = (m.n_tiles + kLsTileChoices[0] - 1) / kLsTileChoices[0];   // bound over the choices
+  aw.lsum_chunks = (m.n_tiles + aw.ls_tiles - 1) / aw.ls_tiles;
   aw.dtb = (float*)alloc((size_t)B_max * m.L_pad * m.n_nu_pad * sizeof(float));
   aw.dtau = (float*)alloc((size_t)B_max * m.L_pad * m.n_nu_pad * sizeof(float));
-  aw.lsum = (float*)alloc((size_t)B_max * aw.lsum_chunks * Lp * n_sums(m.S) * sizeof(float));
+  aw.lsum = (float*)alloc((size_t)B_max * aw.lsum_stride * Lp * n_sums(m.S) * sizeof(float));
   return aw.dtb && aw.dtau && aw.lsum;
 }
 
@@ -1065,11 +1104,18 @@ hipError_t adjoint_configure(const Model& m, bool fp64) {
   return any ? hipSuccess : hipErrorInvalidValue;
 }
 
-bool adjoint_set_variant(AdjWork& aw, const Model& m, int variant) {
+bool adjoint_set_tuning(AdjWork& aw, const Model& m, int variant, int chunk_target, int ls_tiles) {
   if (variant < 0 || variant >= kAdjVariants || !adjoint_variant_fits(m, variant) ||
       adj_lds_bytes(m, false, variant) > 160 * 1024)
     return false;
+  bool ok_t = false, ok_l = false;
+  for (int t : kChunkTargets) ok_t |= t == chunk_target;
+  for (int t : kLsTileChoices) ok_l |= t == ls_tiles;
+  if (!ok_t || !ok_l) return false;
   aw.variant = variant;
+  aw.chunk_target = chunk_target;
+  aw.ls_tiles = ls_tiles;
+  aw.lsum_chunks = (m.n_tiles + ls_tiles - 1) / ls_tiles;
   return true;
 }
 
@@ -1092,10 +1138,21 @@ void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const Ad
 void launch_chain(const Model& m, const Work& w, const AdjWork& aw, int B, const double* params, const uint8_t* mask,
                   double* grad, bool fp64, hipStream_t st) {
   const int C = adjoint_chunks(m, aw, B, fp64);
+  int Cn = C;
+  if (C > 1) {
+    // the chunk partials are summed by a wide kernel first; the chain then reads one slot
+    const long per = (long)m.L_pad * m.L_pad + m.L_pad + (fp64 ? (long)m.L_pad * n_sums(m.S) : 0);
+    const unsigned grid = (unsigned)((per * B + kBlock - 1) / kBlock);
+    if (fp64)
+      hipLaunchKernelGGL(k_reduce_chunks<double>, dim3(grid), dim3(kBlock), 0, st, m, w, aw, B, C);
+    else
+      hipLaunchKernelGGL(k_reduce_chunks<float>, dim3(grid), dim3(kBlock), 0, st, m, w, aw, B, C);
+    Cn = 1;
+  }
   if (fp64)
-    hipLaunchKernelGGL(k_chain<double>, dim3(B), dim3(kBlock), 0, st, m, w, aw, C, params, mask, grad);
+    hipLaunchKernelGGL(k_chain<double>, dim3(B), dim3(kBlock), 0, st, m, w, aw, C, Cn, params, mask, grad);
   else
-    hipLaunchKernelGGL(k_chain<float>, dim3(B), dim3(kBlock), 0, st, m, w, aw, C, params, mask, grad);
+    hipLaunchKernelGGL(k_chain<float>, dim3(B), dim3(kBlock), 0, st, m, w, aw, C, Cn, params, mask, grad);
 }
 
 }  // namespace exofwd

@@ -47,6 +47,7 @@ struct Model {
   int has_cia, has_ray, has_cloud, has_scale, has_offset, n_mu;
   int n_nu, n_nu_pad, n_tiles, n_tiles64, n_t, n_p, n_tc, K;
   int idx_cloud, idx_scale, idx_offset, n_tp;
+  int fwd_tile_major;       // reduced-precision forward grid order: 0 samples fastest, 1 tiles fastest
   double mu_fixed, log10_pbot, log10_ptop, p_ref, r_p, r_s, g_ref;
   double kappa_ir, f_hem, kappa_cloud, t_star, dilution, err_c, ray_h2, ray_he;
   double mass[kMaxSpecies];

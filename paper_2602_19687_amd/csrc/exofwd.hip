@@ -5,9 +5,13 @@
 #include "adjoint.h"
 #include "emission.h"
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -35,7 +39,18 @@ struct exofwd_ctx {
     hipEvent_t a, b;
   };
   std::vector<Ev> events;
-  int adj_chunks = 0;
+  // captured launch sequences, keyed by call kind, batch, pointers and stream
+  struct Graph {
+    int kind, B;
+    std::array<const void*, 7> ptr;
+    hipStream_t st;
+    hipGraphExec_t exec;
+    uint64_t used;
+  };
+  std::vector<Graph> graphs;
+  bool use_graphs = false;
+  bool capturing = false;
+  uint64_t tick = 0;
 };
 
 namespace {
@@ -125,7 +140,7 @@ exofwd_status check_hip(exofwd_ctx* c, hipError_t e, const char* what) {
 // kernel timing helpers (used by every launch site)
 namespace exofwd {
 void prof_begin(exofwd_ctx* c, const char* name, hipStream_t st) {
-  if (!c->profiling) return;
+  if (!c->profiling || c->capturing) return;
   exofwd_ctx::Ev e;
   e.name = name;
   hipEventCreate(&e.a);
@@ -134,7 +149,7 @@ void prof_begin(exofwd_ctx* c, const char* name, hipStream_t st) {
   c->events.push_back(e);
 }
 void prof_end(exofwd_ctx* c, hipStream_t st) {
-  if (!c->profiling || c->events.empty()) return;
+  if (!c->profiling || c->capturing || c->events.empty()) return;
   hipEventRecord(c->events.back().b, st);
 }
 }  // namespace exofwd
@@ -164,10 +179,16 @@ int32_t exofwd_grad_supported(const exofwd_ctx* c) {
 }
 int64_t exofwd_device_bytes(const exofwd_ctx* c) { return c ? c->bytes : -1; }
 
+static void drop_graphs(exofwd_ctx* c) {
+  for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+}
+
 exofwd_status exofwd_destroy(exofwd_ctx* c) {
   if (!c) return EXOFWD_OK;
   hipSetDevice(c->device);
   hipDeviceSynchronize();
+  drop_graphs(c);
   for (auto& e : c->events) {
     hipEventDestroy(e.a);
     hipEventDestroy(e.b);
@@ -424,12 +445,67 @@ static exofwd_status check_call(exofwd_ctx* c, int32_t B, const double* params) 
 
 static exofwd_status run_forward(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers,
                                  void* spectra, double* lnL, int32_t* status, void* hip_stream, float* dtau_out);
+static exofwd_status run_grad(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers,
+                              void* spectra, double* lnL, double* grad, int32_t* status, void* hip_stream);
+
+extern "C++" {
+static constexpr size_t kMaxGraphs = 16;
+
+// Replays the launch sequence of a call whose (kind, B, pointers, stream) was seen
+// before; otherwise captures it on the stream first.  A caller that is itself
+// capturing gets the kernels enqueued into its own graph.
+template <typename F>
+static exofwd_status graph_call(exofwd_ctx* c, int kind, int B, const std::array<const void*, 7>& ptr,
+                                hipStream_t st, F&& enqueue) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) return fail(c, EXOFWD_ERR_DEVICE, "stream query failed");
+  if (cs != hipStreamCaptureStatusNone) return enqueue();
+  auto launch = [&](exofwd_ctx::Graph& g) {
+    g.used = ++c->tick;
+    prof_begin(c, "graph", st);
+    const hipError_t e = hipGraphLaunch(g.exec, st);
+    prof_end(c, st);
+    return e == hipSuccess ? EXOFWD_OK : fail(c, EXOFWD_ERR_DEVICE, "hipGraphLaunch failed");
+  };
+  for (auto& g : c->graphs)
+    if (g.kind == kind && g.B == B && g.ptr == ptr && g.st == st) return launch(g);
+  if (st == nullptr) return fail(c, EXOFWD_ERR_ARG, "graph replay needs a stream other than the null stream");
+  c->capturing = true;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    c->capturing = false;
+    return fail(c, EXOFWD_ERR_DEVICE, "hipStreamBeginCapture failed");
+  }
+  const exofwd_status s = enqueue();
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &graph);
+  c->capturing = false;
+  if (s != EXOFWD_OK || e != hipSuccess || !graph) {
+    if (graph) hipGraphDestroy(graph);
+    return s != EXOFWD_OK ? s : fail(c, EXOFWD_ERR_DEVICE, "hipStreamEndCapture failed");
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (ei != hipSuccess) return fail(c, EXOFWD_ERR_DEVICE, "hipGraphInstantiate failed");
+  if (c->graphs.size() >= kMaxGraphs) {
+    auto lru = std::min_element(c->graphs.begin(), c->graphs.end(),
+                                [](const auto& a, const auto& b) { return a.used < b.used; });
+    hipGraphExecDestroy(lru->exec);
+    c->graphs.erase(lru);
+  }
+  c->graphs.push_back({kind, B, ptr, st, exec, 0});
+  return launch(c->graphs.back());
+}
+}  // extern "C++"
 
 exofwd_status exofwd_forward(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers, void* spectra,
                              double* lnL, int32_t* status, void* hip_stream) {
   exofwd_status s = check_call(c, B, params);
   if (s) return s;
-  return run_forward(c, B, params, n_layers, spectra, lnL, status, hip_stream, nullptr);
+  auto enqueue = [&]() { return run_forward(c, B, params, n_layers, spectra, lnL, status, hip_stream, nullptr); };
+  if (!c->use_graphs) return enqueue();
+  return graph_call(c, 0, B, {params, n_layers, spectra, lnL, status, nullptr, nullptr}, (hipStream_t)hip_stream,
+                    enqueue);
 }
 
 static exofwd_status run_forward(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers,
@@ -467,6 +543,15 @@ exofwd_status exofwd_grad(exofwd_ctx* c, int32_t B, const double* params, const 
   if (!adjoint_supported(c->m, c->precision == EXOFWD_PREC_FP64))
     return fail(c, EXOFWD_ERR_UNSUPPORTED,
                 "the adjoint needs a non-PCHIP profile and n_layers_max <= 160 (reduced precision) or <= 128 (FP64)");
+  auto enqueue = [&]() { return run_grad(c, B, params, n_layers, spectra, lnL, grad, status, hip_stream); };
+  if (!c->use_graphs) return enqueue();
+  return graph_call(c, 1, B, {params, n_layers, spectra, lnL, grad, status, nullptr}, (hipStream_t)hip_stream,
+                    enqueue);
+}
+
+static exofwd_status run_grad(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers,
+                              void* spectra, double* lnL, double* grad, int32_t* status, void* hip_stream) {
+  exofwd_status s;
   if ((s = run_forward(c, B, params, n_layers, spectra, lnL, status, hip_stream,
                        c->precision == EXOFWD_PREC_MIXED ? c->aw.dtau : nullptr)))
     return s;
@@ -518,11 +603,189 @@ exofwd_status exofwd_kernel_time(exofwd_ctx* c, const char* name, double* total_
   return EXOFWD_OK;
 }
 
-exofwd_status exofwd_autotune(exofwd_ctx* c, int32_t B, const char* cache_path) {
+exofwd_status exofwd_set_graphs(exofwd_ctx* c, int32_t enable) {
   if (!c) return EXOFWD_ERR_ARG;
-  (void)B;
-  (void)cache_path;
-  return fail(c, EXOFWD_ERR_UNSUPPORTED, "autotuning is not built yet");
+  hipSetDevice(c->device);
+  if (!c->graphs.empty()) hipDeviceSynchronize();
+  drop_graphs(c);
+  c->use_graphs = enable != 0;
+  return EXOFWD_OK;
+}
+
+exofwd_status exofwd_set_tuning(exofwd_ctx* c, const int32_t* t) {
+  if (!c || !t) return EXOFWD_ERR_ARG;
+  if (t[0] != 0 && t[0] != 1) return fail(c, EXOFWD_ERR_ARG, "forward order must be 0 or 1");
+  const bool tunable_adj = c->precision == EXOFWD_PREC_MIXED && c->m.mode == kTransmission &&
+                           adjoint_supported(c->m, false);
+  AdjWork aw = c->aw;
+  if (tunable_adj && !adjoint_set_tuning(aw, c->m, t[1], t[2], t[3]))
+    return fail(c, EXOFWD_ERR_ARG, "reverse shape, chunk target or layer-sum tiles not valid for this context");
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  drop_graphs(c);
+  c->m.fwd_tile_major = t[0];
+  c->aw = aw;
+  return EXOFWD_OK;
+}
+
+exofwd_status exofwd_get_tuning(const exofwd_ctx* c, int32_t* t) {
+  if (!c || !t) return EXOFWD_ERR_ARG;
+  t[0] = c->m.fwd_tile_major;
+  t[1] = c->aw.variant;
+  t[2] = c->aw.chunk_target;
+  t[3] = c->aw.ls_tiles;
+  return EXOFWD_OK;
+}
+
+extern "C++" {
+namespace {
+
+// parameters of a valid, cloud-free mid-range atmosphere for timing runs
+std::vector<double> neutral_params(const Model& m) {
+  std::vector<double> th(m.P, 0.0);
+  if (m.tp_kind == kTpIso) th[0] = 1200.0;
+  else if (m.tp_kind == kTpGuillot3) { th[0] = 500.0; th[1] = 1200.0; th[2] = 0.0; }
+  else for (int k = 0; k < m.n_tp; ++k) th[k] = 1200.0;
+  for (int s2 = 0; s2 < m.S; ++s2) th[m.n_tp + s2] = -6.0;
+  if (m.has_cloud) th[m.idx_cloud] = m.log10_pbot + 1.0;
+  if (m.has_scale) th[m.idx_scale] = 1.0;
+  if (m.has_offset) th[m.idx_offset] = 0.0;
+  return th;
+}
+
+std::string tuning_key(const exofwd_ctx* c, int B) {
+  hipDeviceProp_t prop{};
+  hipGetDeviceProperties(&prop, c->device);
+  std::ostringstream k;
+  k << prop.gcnArchName << "/cu" << prop.multiProcessorCount << " mode" << c->m.mode << " prec" << c->precision
+    << " S" << c->m.S << " cia" << c->m.has_cia << " Lpad" << c->m.L_pad << " Lmax" << c->m.L_max << " nu"
+    << c->m.n_nu_pad << " tab" << c->m.n_t << "x" << c->m.n_p << " B" << B;
+  std::string key = k.str();
+  for (char& ch : key)
+    if (ch == ' ' || ch == '=') ch = '_';
+  return key;
+}
+
+}  // namespace
+}  // extern "C++"
+
+exofwd_status exofwd_autotune(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers,
+                              const char* cache_path) {
+  if (!c) return EXOFWD_ERR_ARG;
+  if (B < 1 || B > c->batch_max) return fail(c, EXOFWD_ERR_SHAPE, "B outside [1, batch_max]");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, EXOFWD_ERR_DEVICE, "hipSetDevice failed");
+  const bool mixed_trans = c->precision == EXOFWD_PREC_MIXED && c->m.mode == kTransmission;
+  if (!mixed_trans) return EXOFWD_OK;   // the FP64 and emission launches have no tunable shape
+  const bool grad = adjoint_supported(c->m, false);
+  const std::string key = tuning_key(c, B);
+
+  // ---- cached result
+  std::vector<std::string> lines;
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      if (line.empty()) continue;
+      std::istringstream ls(line);
+      std::string k;
+      int32_t t[4];
+      const bool parsed = static_cast<bool>(ls >> k >> t[0] >> t[1] >> t[2] >> t[3]);
+      if (parsed && k == key) {
+        if (exofwd_set_tuning(c, t) == EXOFWD_OK) return EXOFWD_OK;
+        continue;   // a stale entry for this key is timed again and replaced
+      }
+      lines.push_back(line);
+    }
+  }
+
+  // ---- timing runs on a private stream
+  const size_t P = (size_t)c->m.P;
+  double* d_th = nullptr;
+  double *d_lnl = nullptr, *d_g = nullptr;
+  int32_t* d_st = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool ok = hipMalloc(&d_lnl, B * sizeof(double)) == hipSuccess && hipMalloc(&d_g, B * P * sizeof(double)) == hipSuccess &&
+            hipMalloc(&d_st, B * sizeof(int32_t)) == hipSuccess && hipStreamCreate(&st) == hipSuccess &&
+            hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  if (ok && !params) {
+    const std::vector<double> one = neutral_params(c->m);
+    std::vector<double> all(B * P);
+    for (int b = 0; b < B; ++b) std::copy(one.begin(), one.end(), all.begin() + b * P);
+    ok = hipMalloc(&d_th, B * P * sizeof(double)) == hipSuccess &&
+         hipMemcpy(d_th, all.data(), B * P * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+  }
+  const double* th = params ? params : d_th;
+  const bool prof = c->profiling, graphs = c->use_graphs;
+  c->profiling = false;
+  c->use_graphs = false;
+  auto step = [&]() {
+    return grad ? run_grad(c, B, th, n_layers, nullptr, d_lnl, d_g, d_st, st)
+                : run_forward(c, B, th, n_layers, nullptr, d_lnl, d_st, st, nullptr);
+  };
+  auto time_once = [&](const int32_t* t) -> double {
+    if (exofwd_set_tuning(c, t) != EXOFWD_OK) return 1e30;
+    if (step() != EXOFWD_OK) return 1e30;
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      hipEventRecord(e0, st);
+      if (step() != EXOFWD_OK) return 1e30;
+      hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) return 1e30;
+      float ms = 0.0f;
+      hipEventElapsedTime(&ms, e0, e1);
+      best = std::min(best, ms);
+    }
+    return best;
+  };
+  int32_t cur[4], best_t[4];
+  exofwd_get_tuning(c, cur);
+  std::copy(cur, cur + 4, best_t);
+  double best = ok ? time_once(cur) : 1e30;
+  auto consider = [&](const int32_t* t) {
+    const double ms = time_once(t);
+    if (ms < best) {
+      best = ms;
+      std::copy(t, t + 4, best_t);
+    }
+  };
+  if (ok && best < 1e30) {
+    // coordinate descent: forward grid order, then reverse shape x chunk target, then layer-sum tiles
+    for (int o = 0; o < 2; ++o) {
+      int32_t t[4] = {o, best_t[1], best_t[2], best_t[3]};
+      consider(t);
+    }
+    if (grad) {
+      for (int v = 0; v < kAdjVariants; ++v)
+        for (int tg : kChunkTargets) {
+          int32_t t[4] = {best_t[0], v, tg, best_t[3]};
+          consider(t);
+        }
+      for (int lt : kLsTileChoices) {
+        int32_t t[4] = {best_t[0], best_t[1], best_t[2], lt};
+        consider(t);
+      }
+    }
+  }
+  const exofwd_status applied = exofwd_set_tuning(c, best_t);
+  c->profiling = prof;
+  c->use_graphs = graphs;
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (st) hipStreamDestroy(st);
+  hipFree(d_th);
+  hipFree(d_lnl);
+  hipFree(d_g);
+  hipFree(d_st);
+  if (!ok || best >= 1e30) return fail(c, EXOFWD_ERR_DEVICE, "autotune timing runs failed");
+  if (applied != EXOFWD_OK) return applied;
+  if (cache_path) {
+    std::ofstream out(cache_path, std::ios::trunc);
+    for (const auto& line : lines) out << line << "\n";
+    out << key << " " << best_t[0] << " " << best_t[1] << " " << best_t[2] << " " << best_t[3] << "\n";
+    if (!out) return fail(c, EXOFWD_ERR_ARG, "cannot write the autotune cache file");
+  }
+  return EXOFWD_OK;
 }
 
 }  // extern "C"

@@ -38,7 +38,10 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
                                                               float* __restrict__ dtau_out) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int b = logical % B, tile = logical / B;
+  // samples fastest: neighbouring workgroups (one XCD) share table columns;
+  // tiles fastest: they share one sample's profile
+  const int b = m.fwd_tile_major ? logical / m.n_tiles : logical % B;
+  const int tile = m.fwd_tile_major ? logical % m.n_tiles : logical / B;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int Lp = m.L_pad;

@@ -87,6 +87,9 @@ class ForwardModel:
         self.n_nu = self.lib.exofwd_num_nu(ctx)
         self.n_bins = self.lib.exofwd_num_bins(ctx)
         self.has_grad = self.lib.exofwd_grad_supported(ctx) == 1
+        self._graphs = False
+        self._gstream = None
+        self._gbuf = {}
         self.spec_dtype = torch.float64 if self.precision == L.PREC_FP64 else torch.float32
 
     # ------------------------------------------------------------------ helpers
@@ -108,12 +111,60 @@ class ForwardModel:
     def _stream(self):
         return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
 
+    # ------------------------------------------------------------- graph mode
+    def set_graphs(self, enable: bool):
+        """Capture each distinct call into a hipGraph once and replay it after.
+
+        Inputs are copied into buffers kept per (call kind, B), the library runs
+        on a side stream ordered after the caller's current stream (and the
+        caller's stream after it), and the results are returned as fresh tensors."""
+        L.check(self.lib.exofwd_set_graphs(self.ctx, int(enable)), self.ctx, "set_graphs")
+        self._graphs = bool(enable)
+        self._gbuf = {}
+        self._gstream = torch.cuda.Stream(self.device) if enable else None
+
+    def _graph_call(self, kind, params, nl_t, want_spectra, call):
+        b = params.shape[0]
+        key = (kind, b, nl_t is not None, want_spectra)
+        buf = self._gbuf.get(key)
+        if buf is None:
+            dev = self.device
+            buf = dict(params=torch.empty_like(params),
+                       nl=torch.empty(b, dtype=torch.int32, device=dev) if nl_t is not None else None,
+                       spec=torch.empty((b, self.n_nu), dtype=self.spec_dtype, device=dev) if want_spectra else None,
+                       lnl=torch.empty(b, dtype=torch.float64, device=dev),
+                       grad=torch.empty((b, self.n_params), dtype=torch.float64, device=dev) if kind == "g" else None,
+                       status=torch.empty(b, dtype=torch.int32, device=dev))
+            self._gbuf[key] = buf
+        buf["params"].copy_(params)
+        if nl_t is not None:
+            buf["nl"].copy_(nl_t)
+        cur = torch.cuda.current_stream(self.device)
+        self._gstream.wait_stream(cur)
+        call(buf, C.c_void_p(self._gstream.cuda_stream))
+        cur.wait_stream(self._gstream)
+        return {k: (v.clone() if v is not None and k not in ("params", "nl") else None) for k, v in buf.items()}
+
+    @staticmethod
+    def _ptr(t):
+        return C.c_void_p(t.data_ptr() if t is not None else None)
+
     # ------------------------------------------------------------------ calls
     def forward(self, params: torch.Tensor, n_layers=None, want_spectra: bool = True, out=None):
         """Spectra [B, n_nu] (or None), lnL [B] float64, status [B] int32."""
         params = self._check_params(params)
         b = params.shape[0]
         nl_t, nl_p = self._nl(n_layers, b)
+        if self._graphs:
+            def call(buf, st):
+                L.check(self.lib.exofwd_forward(self.ctx, b, self._ptr(buf["params"]), self._ptr(buf["nl"]),
+                                                self._ptr(buf["spec"]), self._ptr(buf["lnl"]),
+                                                self._ptr(buf["status"]), st), self.ctx, "exofwd_forward")
+            o = self._graph_call("f", params, nl_t, want_spectra, call)
+            if out is not None and o["spec"] is not None:
+                out.copy_(o["spec"])
+                o["spec"] = out
+            return o["spec"], o["lnl"], o["status"]
         spec = None
         if want_spectra:
             spec = out if out is not None else torch.empty((b, self.n_nu), dtype=self.spec_dtype, device=self.device)
@@ -130,6 +181,13 @@ class ForwardModel:
         params = self._check_params(params)
         b = params.shape[0]
         nl_t, nl_p = self._nl(n_layers, b)
+        if self._graphs:
+            def call(buf, st):
+                L.check(self.lib.exofwd_grad(self.ctx, b, self._ptr(buf["params"]), self._ptr(buf["nl"]),
+                                             self._ptr(buf["spec"]), self._ptr(buf["lnl"]), self._ptr(buf["grad"]),
+                                             self._ptr(buf["status"]), st), self.ctx, "exofwd_grad")
+            o = self._graph_call("g", params, nl_t, want_spectra, call)
+            return o["lnl"], o["grad"], o["status"], o["spec"]
         spec = torch.empty((b, self.n_nu), dtype=self.spec_dtype, device=self.device) if want_spectra else None
         lnl = torch.empty(b, dtype=torch.float64, device=self.device)
         g = torch.empty((b, self.n_params), dtype=torch.float64, device=self.device)
@@ -140,6 +198,25 @@ class ForwardModel:
                                      C.c_void_p(status.data_ptr()), self._stream()),
                 self.ctx, "exofwd_grad")
         return lnl, g, status, spec
+
+    # ------------------------------------------------------------- launch choices
+    def get_tuning(self):
+        """[forward order, reverse shape, reverse work items, layer-sum tiles]."""
+        t = (C.c_int32 * 4)()
+        L.check(self.lib.exofwd_get_tuning(self.ctx, t), self.ctx, "get_tuning")
+        return list(t)
+
+    def set_tuning(self, tuning):
+        t = (C.c_int32 * 4)(*[int(x) for x in tuning])
+        L.check(self.lib.exofwd_set_tuning(self.ctx, t), self.ctx, "set_tuning")
+
+    def autotune(self, batch: int, params: torch.Tensor | None = None, n_layers=None, cache_path: str | None = None):
+        """Time the launch choices at this batch size and keep the fastest; returns them."""
+        p = self._check_params(params) if params is not None else None
+        nl_t, nl_p = self._nl(n_layers, batch)
+        L.check(self.lib.exofwd_autotune(self.ctx, int(batch), self._ptr(p), C.c_void_p(nl_p),
+                                         cache_path.encode() if cache_path else None), self.ctx, "autotune")
+        return self.get_tuning()
 
     def set_profiling(self, enable: bool):
         L.check(self.lib.exofwd_set_profiling(self.ctx, int(enable)), self.ctx, "set_profiling")
