@@ -38,9 +38,9 @@ def algorithmic_bytes_per_sample(L, S, n_nu, b_tab, b_out):
     return (4 * L * S * n_nu + 4 * L * n_nu) * b_tab + 2 * n_nu * 4 + n_nu * b_out
 
 
-def kernel_model(kernel, B, L, S, n_nu):
-    """Roofline model of one launch of a hot kernel at (B, L, S, n_nu):
-    (bound, algorithmic amount, peak, unit).
+def kernel_model(kernel, Ls, S, n_nu):
+    """Roofline model of one launch of a hot kernel over samples with layer
+    counts Ls, S sources and n_nu wavenumbers: (bound, algorithmic amount, peak, unit).
 
     trans_fwd, layer_sums: vector FP32 operations per (sample, layer, wavenumber),
     counting an FMA as 2 and an exp2 as 1, against the FP32 vector peak:
@@ -52,13 +52,15 @@ def kernel_model(kernel, B, L, S, n_nu):
     trans_adj: the three triangular products tau = P dtau, Pbar = tau_bar dtau^T and
     dtau_bar = P^T tau_bar, L(L+1)/2 FMA each per wavenumber, each done as three bf16
     MFMA products (bf16x3), against the dense bf16 MFMA peak."""
-    elems = B * L * n_nu
+    import numpy as np
+    Ls = np.asarray(Ls, dtype=np.int64)
+    elems = int(Ls.sum()) * n_nu
     if kernel == "trans_fwd":
         return "alu", (11 * S + 19) * elems, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
     if kernel == "layer_sums":
         return "alu", (20 * S + 26) * elems, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
     if kernel == "trans_adj":
-        return "mfma", 3 * 3 * (L * (L + 1) // 2) * 2 * n_nu * B, BF16_MFMA_PEAK_TFLOPS, "TFLOP/s"
+        return "mfma", 3 * 3 * int((Ls * (Ls + 1) // 2).sum()) * 2 * n_nu, BF16_MFMA_PEAK_TFLOPS, "TFLOP/s"
     raise ValueError(kernel)
 
 
@@ -75,11 +77,11 @@ def sources_digest():
     return d.hexdigest()
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload_tag="transmission_ns_b1024"):
     """HBM bytes per launch of `kernel` from the committed PMC summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by a copy-kernel calibration), or
     None when the summary is missing or the kernel sources have changed since."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_transmission_ns_b1024.md")
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload_tag}.md")
     if not os.path.exists(path):
         return None
     digest, traffic = None, {}
@@ -134,7 +136,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--config", type=int, default=1, choices=(1, 4),
+                    help="1: the JWST-like transmission batch (default); 4: the high-resolution ragged batch")
+    ap.add_argument("--batch", type=int, default=None, help="default 1024 (config 1) or 64 (config 4)")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -161,17 +167,26 @@ def main():
     import synth
     from paper_2602_19687_amd import ForwardModel
 
-    cid, B = 1, args.batch
+    cid = args.config
+    B = args.batch or (1024 if cid == 1 else 64)
     t_setup = time.perf_counter()
     wl = synth.workload(cid, batch=B)
     L_, S, n_nu = wl["n_layers"], wl["n_species"], len(wl["nu"])
     th = torch.tensor(wl["params"], dtype=torch.float64, device="cuda")
+    nl_np = wl["n_layers_per_sample"]
+    nl = torch.tensor(nl_np, dtype=torch.int32, device="cuda") if nl_np is not None else None
+    Ls = nl_np if nl_np is not None else np.full(B, L_)
     print(f"[bench] workload ready in {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
 
     def run(prec, steps, warmup):
         fm = ForwardModel(wl, precision=prec, batch_max=B)
         has_grad = fm.has_grad
-        step = (lambda: fm.grad(th)) if has_grad else (lambda: fm.forward(th, want_spectra=False))
+        tuning = None
+        if prec == "mixed" and not args.no_autotune:
+            t0 = time.perf_counter()
+            tuning = fm.autotune(B, th, nl)
+            print(f"[bench] autotune {tuning} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+        step = (lambda: fm.grad(th, n_layers=nl)) if has_grad else (lambda: fm.forward(th, n_layers=nl, want_spectra=False))
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
@@ -182,11 +197,24 @@ def main():
             out = step()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        kern = {k: fm.kernel_time(k) for k in ("profile", "trans_fwd", "loglike", "trans_adj", "layer_sums", "chain")}
+        kern = {k: fm.kernel_time(k) for k in ("profile", "trans_fwd", "emis_fwd", "loglike", "trans_adj", "layer_sums",
+                                               "chain")}
         fm.set_profiling(False)
-        spec, lnl, status = fm.forward(th)
+        graph_ms = None
+        if not args.no_graphs:
+            # the same step captured once into a hipGraph and replayed
+            fm.set_graphs(True)
+            step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            graph_ms = (time.perf_counter() - t0) / steps * 1e3
+            fm.set_graphs(False)
+        spec, lnl, status = fm.forward(th, n_layers=nl)
         torch.cuda.synchronize()
-        res = dict(ms_per_step=dt / steps * 1e3, has_grad=has_grad, kernels=kern,
+        res = dict(ms_per_step=dt / steps * 1e3, has_grad=has_grad, kernels=kern, graph_ms=graph_ms, tuning=tuning,
                    spec=spec.double().cpu().numpy(), lnl=lnl.cpu().numpy(), status=status.cpu().numpy(),
                    grad=out[1].cpu().numpy() if has_grad else None, bytes=fm.device_bytes())
         fm.close()
@@ -195,7 +223,8 @@ def main():
     mixed = run("mixed", args.steps, args.warmup)
     print(f"[bench] mixed {mixed['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     fp64 = None
-    if not args.no_fp64:
+    # the FP64 adjoint stops at 128 padded layers, so the high-resolution batch has no FP64 comparison
+    if not args.no_fp64 and cid == 1:
         fp64 = run("fp64", max(2, args.steps // 4), 1)
         print(f"[bench] fp64 {fp64['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
 
@@ -204,37 +233,48 @@ def main():
     per = {k: v[0] / max(1, v[1]) for k, v in mixed["kernels"].items() if v[1]}
     dom = max(("trans_fwd", "trans_adj", "layer_sums"), key=lambda k: per.get(k, 0.0))
     dom_ms = per[dom]
-    bound, amount, peak, unit = kernel_model(dom, B, L_, S, n_nu)
+    tag = "transmission_ns_b1024" if (cid == 1 and B == 1024) else f"transmission_c{cid}_b{B}"
+    bound, amount, peak, unit = kernel_model(dom, Ls, S, n_nu)
     achieved = amount / (dom_ms / 1e3) / 1e12
-    traffic = measured_traffic(dom)
-    alg_bytes = algorithmic_bytes_per_sample(L_, S, n_nu, 2, 4) * B
+    traffic = measured_traffic(dom, tag)
+    alg_bytes = sum(algorithmic_bytes_per_sample(int(l), S, n_nu, 2, 4) for l in Ls)
     roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": dom, "kernel_ms": round(dom_ms, 4), "flops_per_launch": amount}
     for k in ("trans_fwd", "trans_adj", "layer_sums"):
         if k in per:
-            bk, ak, pk, _ = kernel_model(k, B, L_, S, n_nu)
+            bk, ak, pk, _ = kernel_model(k, Ls, S, n_nu)
             a = ak / (per[k] / 1e3) / 1e12
             roofline.setdefault("kernels", {})[k] = {"bound": bk, "ms": round(per[k], 4), "achieved": round(a, 2),
                                                      "peak": pk, "frac": round(a / pk, 4),
-                                                     "traffic": measured_traffic(k)}
+                                                     "traffic": measured_traffic(k, tag)}
     # table-gather bytes the method needs (the forward pass), against the HBM peak
     hbm_gbs = alg_bytes / (per["trans_fwd"] / 1e3) / 1e9
     roofline["table_gather"] = {"bytes_per_launch": alg_bytes, "kernel": "trans_fwd",
                                 "achieved_gbs": round(hbm_gbs, 1), "frac_of_8000_gbs": round(hbm_gbs / HBM_PEAK_GBS, 4)}
 
+    if cid == 1:
+        workload = ("jwst-like transmission, 6 absorbers, 20x20x30000 FP16 tables, 100 layers, 400 bins, 12 params")
+    else:
+        workload = (f"high-resolution transmission, 4 absorbers, 8x8x400000 FP16 tables, {int(Ls.min())}-{int(Ls.max())} "
+                    f"layers per sample, 400 bins, {th.shape[1]} params")
     out = {
-        "metric": "forward+grad spectra/sec at B=1024 (FP32/FP16 vs FP64 plain), max rel err"
-        if mixed["has_grad"] else "forward spectra/sec at B=1024 (FP32/FP16 vs FP64 plain), max rel err",
+        "metric": ("forward+grad spectra/sec at B=1024 (FP32/FP16 vs FP64 plain), max rel err"
+                   if mixed["has_grad"] else "forward spectra/sec at B=1024 (FP32/FP16 vs FP64 plain), max rel err")
+        if cid == 1 else f"forward+grad spectra/sec, high-resolution ragged batch B={B} (FP32/FP16)",
         "value": round(value, 1), "unit": "spectra/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(mixed["ms_per_step"], 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "jwst-like transmission, 6 absorbers, 20x20x30000 FP16 tables, 100 layers, "
-                               "400 bins, 12 params", "batch": B, "n_nu": n_nu, "n_layers": L_, "n_species": S,
-                   "precision": "fp16 tables / fp32 opacity / bf16x3 mfma chord / fp64 profile+lnL"},
+        "config": {"workload": workload, "batch": B, "n_nu": n_nu, "n_layers": L_ if nl_np is None else
+                   f"{int(Ls.min())}-{int(Ls.max())} (mean {float(Ls.mean()):.1f})", "n_species": S,
+                   "precision": "fp16 tables / fp32 opacity / bf16x3 mfma chord / fp64 profile+lnL",
+                   "launch_choices": mixed["tuning"]},
         "roofline": roofline,
         "kernel_ms_per_step": {k: round(v[0] / max(1, v[1]), 4) for k, v in mixed["kernels"].items() if v[1]},
     }
+    if mixed["graph_ms"] is not None:
+        out["graph_replay"] = {"ms_per_step": round(mixed["graph_ms"], 4),
+                               "spectra_per_s": round(B / (mixed["graph_ms"] / 1e3), 1)}
     if fp64 is not None:
         out["fp64_plain"] = {"spectra_per_s": round(B / (fp64["ms_per_step"] / 1e3), 1),
                              "ms_per_step": round(fp64["ms_per_step"], 3),
@@ -244,7 +284,7 @@ def main():
         ok = (mixed["status"] == 0) & (fp64["status"] == 0)
         out["max_rel_err_vs_fp64_gpu"] = float(np.max(np.abs(mixed["spec"][ok] - fp64["spec"][ok])
                                                       / np.abs(fp64["spec"][ok])))
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and cid == 1:
         res, dt, cores = cpu_baseline(cid, B, args.cpu_samples, mixed["has_grad"])
         n = len(res)
         errs, lerrs, gerrs = [], [], []
