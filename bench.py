@@ -140,6 +140,8 @@ def main():
                     help="1: the JWST-like transmission batch (default); 4: the high-resolution ragged batch")
     ap.add_argument("--batch", type=int, default=None, help="default 1024 (config 1) or 64 (config 4)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning", type=str, default=None,
+                    help="launch choices a,b,c,d to use instead of autotuning (see exofwd_set_tuning)")
     ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -182,7 +184,10 @@ def main():
         fm = ForwardModel(wl, precision=prec, batch_max=B)
         has_grad = fm.has_grad
         tuning = None
-        if prec == "mixed" and not args.no_autotune:
+        if prec == "mixed" and args.tuning:
+            fm.set_tuning([int(x) for x in args.tuning.split(",")])
+            tuning = fm.get_tuning()
+        elif prec == "mixed" and not args.no_autotune:
             t0 = time.perf_counter()
             tuning = fm.autotune(B, th, nl)
             print(f"[bench] autotune {tuning} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)

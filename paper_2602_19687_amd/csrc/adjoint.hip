@@ -430,19 +430,25 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
       float t0_[S + 2], t1_[S + 2], dw0[S + 2], dw1[S + 2];
       layer_terms_deriv<S, CIA>(c, kc, g, rh, rhc, voff, t0_, t1_, dw0, dw1);
       const float2 db = *reinterpret_cast<const float2*>(dtb + (size_t)l * npad + nu0 + 2 * lane);
+      // G_s += db t_s per wavenumber; the T-weight sums take db once per wavenumber
+      // times z = sum_s t_s dw_s
+      float z0 = 0.0f, z1 = 0.0f;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        const float a0 = db.x * t0_[s], a1 = db.y * t1_[s];
-        acc[q][s] += a0 + a1;
-        acc[q][S] = fmaf(a0, dw0[s], fmaf(a1, dw1[s], acc[q][S]));
+        acc[q][s] = fmaf(db.x, t0_[s], fmaf(db.y, t1_[s], acc[q][s]));
+        z0 = fmaf(t0_[s], dw0[s], z0);
+        z1 = fmaf(t1_[s], dw1[s], z1);
       }
+      acc[q][S] = fmaf(db.x, z0, fmaf(db.y, z1, acc[q][S]));
       if (CIA) {
+        float y0 = 0.0f, y1 = 0.0f;
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
-          const float a0 = db.x * t0_[S + p], a1 = db.y * t1_[S + p];
-          acc[q][S + 1 + p] += a0 + a1;
-          acc[q][S + 3] = fmaf(a0, dw0[S + p], fmaf(a1, dw1[S + p], acc[q][S + 3]));
+          acc[q][S + 1 + p] = fmaf(db.x, t0_[S + p], fmaf(db.y, t1_[S + p], acc[q][S + 1 + p]));
+          y0 = fmaf(t0_[S + p], dw0[S + p], y0);
+          y1 = fmaf(t1_[S + p], dw1[S + p], y1);
         }
+        acc[q][S + 3] = fmaf(db.x, y0, fmaf(db.y, y1, acc[q][S + 3]));
       }
       acc[q][S + 4] = fmaf(db.x, kc.nu4_0, fmaf(db.y, kc.nu4_1, acc[q][S + 4]));
       acc[q][S + 5] += db.x + db.y;
