@@ -378,10 +378,10 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
 }
 
 // ============================================================================
-// reduced-precision per-layer sums: one wave per (sample, 4 layers, 8 tiles);
+// reduced-precision per-layer sums: one wave per (sample, kLsLayers layers, ls_tiles tiles);
 // lanes hold two wavenumbers, partial sums stay in registers across the tiles
 // and are reduced over the wave once
-constexpr int kLsLayers = 4;
+constexpr int kLsLayers = 5;
 
 template <int S, bool CIA>
 __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Tables tb, AdjWork aw, int B) {
