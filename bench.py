@@ -38,7 +38,7 @@ def algorithmic_bytes_per_sample(L, S, n_nu, b_tab, b_out):
     return (4 * L * S * n_nu + 4 * L * n_nu) * b_tab + 2 * n_nu * 4 + n_nu * b_out
 
 
-def kernel_model(kernel, Ls, S, n_nu):
+def kernel_model(kernel, Ls, S, n_nu, n_mu=4):
     """Roofline model of one launch of a hot kernel over samples with layer
     counts Ls, S sources and n_nu wavenumbers: (bound, algorithmic amount, peak, unit).
 
@@ -59,6 +59,10 @@ def kernel_model(kernel, Ls, S, n_nu):
         return "alu", (11 * S + 19) * elems, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
     if kernel == "layer_sums":
         return "alu", (20 * S + 26) * elems, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
+    if kernel == "emis_fwd":
+        # opacity as in trans_fwd without Rayleigh and deck (11 S + 14), Planck at the levels (5), and per
+        # Gauss angle the sweep step x = dtau/mu, exp, linear-source update (12)
+        return "alu", (11 * S + 14 + 5 + 12 * n_mu) * elems, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
     if kernel == "trans_adj":
         return "mfma", 3 * 3 * int((Ls * (Ls + 1) // 2).sum()) * 2 * n_nu, BF16_MFMA_PEAK_TFLOPS, "TFLOP/s"
     raise ValueError(kernel)
@@ -136,8 +140,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=1, choices=(1, 4),
-                    help="1: the JWST-like transmission batch (default); 4: the high-resolution ragged batch")
+    ap.add_argument("--config", type=int, default=1, choices=(1, 2, 4),
+                    help="1: the JWST-like transmission batch (default); 2: the emission batch (forward); "
+                         "4: the high-resolution ragged batch")
     ap.add_argument("--batch", type=int, default=None, help="default 1024 (config 1) or 64 (config 4)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", type=str, default=None,
@@ -170,7 +175,7 @@ def main():
     from paper_2602_19687_amd import ForwardModel
 
     cid = args.config
-    B = args.batch or (1024 if cid == 1 else 64)
+    B = args.batch or (64 if cid == 4 else 1024)
     t_setup = time.perf_counter()
     wl = synth.workload(cid, batch=B)
     L_, S, n_nu = wl["n_layers"], wl["n_species"], len(wl["nu"])
@@ -229,16 +234,18 @@ def main():
     print(f"[bench] mixed {mixed['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     fp64 = None
     # the FP64 adjoint stops at 128 padded layers, so the high-resolution batch has no FP64 comparison
-    if not args.no_fp64 and cid == 1:
+    if not args.no_fp64 and cid in (1, 2):
         fp64 = run("fp64", max(2, args.steps // 4), 1)
         print(f"[bench] fp64 {fp64['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
 
     value = B / (mixed["ms_per_step"] / 1e3)
     # dominant kernel of the step by time
     per = {k: v[0] / max(1, v[1]) for k, v in mixed["kernels"].items() if v[1]}
-    dom = max(("trans_fwd", "trans_adj", "layer_sums"), key=lambda k: per.get(k, 0.0))
+    hot = ("emis_fwd",) if cid == 2 else ("trans_fwd", "trans_adj", "layer_sums")
+    dom = max(hot, key=lambda k: per.get(k, 0.0))
     dom_ms = per[dom]
-    tag = "transmission_ns_b1024" if (cid == 1 and B == 1024) else f"transmission_c{cid}_b{B}"
+    tag = ("transmission_ns_b1024" if (cid == 1 and B == 1024) else
+           f"emission_c2_b{B}" if cid == 2 else f"transmission_c{cid}_b{B}")
     bound, amount, peak, unit = kernel_model(dom, Ls, S, n_nu)
     achieved = amount / (dom_ms / 1e3) / 1e12
     traffic = measured_traffic(dom, tag)
@@ -246,7 +253,7 @@ def main():
     roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": dom, "kernel_ms": round(dom_ms, 4), "flops_per_launch": amount}
-    for k in ("trans_fwd", "trans_adj", "layer_sums"):
+    for k in hot:
         if k in per:
             bk, ak, pk, _ = kernel_model(k, Ls, S, n_nu)
             a = ak / (per[k] / 1e3) / 1e12
@@ -254,19 +261,26 @@ def main():
                                                      "peak": pk, "frac": round(a / pk, 4),
                                                      "traffic": measured_traffic(k, tag)}
     # table-gather bytes the method needs (the forward pass), against the HBM peak
-    hbm_gbs = alg_bytes / (per["trans_fwd"] / 1e3) / 1e9
-    roofline["table_gather"] = {"bytes_per_launch": alg_bytes, "kernel": "trans_fwd",
+    fwd_kernel = "emis_fwd" if cid == 2 else "trans_fwd"
+    if cid == 2:
+        alg_bytes = sum((4 * int(l) * S * n_nu + 4 * int(l) * n_nu) * 2 + n_nu * 4 for l in Ls)
+    hbm_gbs = alg_bytes / (per[fwd_kernel] / 1e3) / 1e9
+    roofline["table_gather"] = {"bytes_per_launch": alg_bytes, "kernel": fwd_kernel,
                                 "achieved_gbs": round(hbm_gbs, 1), "frac_of_8000_gbs": round(hbm_gbs / HBM_PEAK_GBS, 4)}
 
     if cid == 1:
         workload = ("jwst-like transmission, 6 absorbers, 20x20x30000 FP16 tables, 100 layers, 400 bins, 12 params")
+    elif cid == 2:
+        workload = ("emission, 8 absorbers, 20x20x20000 FP16 tables, 100 layers, 4 Gauss-Legendre angles, "
+                    "5-knot PCHIP profile, 400 bins")
     else:
         workload = (f"high-resolution transmission, 4 absorbers, 8x8x400000 FP16 tables, {int(Ls.min())}-{int(Ls.max())} "
                     f"layers per sample, 400 bins, {th.shape[1]} params")
     out = {
         "metric": ("forward+grad spectra/sec at B=1024 (FP32/FP16 vs FP64 plain), max rel err"
                    if mixed["has_grad"] else "forward spectra/sec at B=1024 (FP32/FP16 vs FP64 plain), max rel err")
-        if cid == 1 else f"forward+grad spectra/sec, high-resolution ragged batch B={B} (FP32/FP16)",
+        if cid == 1 else (f"emission forward spectra/sec at B={B} (FP32/FP16 vs FP64 plain)" if cid == 2 else
+                          f"forward+grad spectra/sec, high-resolution ragged batch B={B} (FP32/FP16)"),
         "value": round(value, 1), "unit": "spectra/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(mixed["ms_per_step"], 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",

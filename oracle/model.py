@@ -372,7 +372,8 @@ def emission_intensity(dtau, b_lev, mu):
     for l in range(dtau.shape[0]):
         x = dtau[l] / mu
         e = np.exp(-x)
-        i_nu = i_nu * e + b_lev[l + 1] * (1.0 - e) + (b_lev[l] - b_lev[l + 1]) * _lin_source_factor(x)
+        # 1 - e^-x as -expm1(-x): a thin hot layer's emission is B (1 - e^-x)
+        i_nu = i_nu * e - b_lev[l + 1] * np.expm1(-x) + (b_lev[l] - b_lev[l + 1]) * _lin_source_factor(x)
     return i_nu
 
 
@@ -424,20 +425,28 @@ def split_params(wl, theta):
     return out
 
 
-def decode_fp16_tables(wl):
+def decode_fp16_tables(wl, pairs=None):
     """The tables as the reduced-precision path stores them, decoded to FP64.
 
     Storage rule of the reduced-precision path: per species (or CIA pair) and
     wavenumber, c = float32((min + max)/2) of log2 sigma over the (T, p) grid;
-    each entry is float16(log2 sigma - c).  The decoded value is
-    (c + h) / log2(10) in log10 units, so forward(..., tables=...) isolates the
-    storage error from the arithmetic error.
+    each entry is float16(log2 sigma - c).  Emission stores each entry as the
+    pair hi = float16(v), lo = float16(v - hi) of v = log2 sigma - c (``pairs``,
+    by default for emission workloads).  The decoded value is (c + h [+ lo]) /
+    log2(10) in log10 units, so forward(..., tables=...) isolates the storage
+    error from the arithmetic error.
     """
+    if pairs is None:
+        pairs = wl["mode"] == 1
+
     def dec(tab, axes):
         l2 = tab * np.log2(10.0)
         c = (0.5 * (l2.min(axis=axes, keepdims=True) + l2.max(axis=axes, keepdims=True))).astype(np.float32)
-        h = (l2 - c.astype(np.float64)).astype(np.float16)
-        return (c.astype(np.float64) + h.astype(np.float64)) / np.log2(10.0)
+        v = l2 - c.astype(np.float64)
+        h = v.astype(np.float16).astype(np.float64)
+        if pairs:
+            h = h + (v - h).astype(np.float16).astype(np.float64)
+        return (c.astype(np.float64) + h) / np.log2(10.0)
     xs = dec(wl["log10_xsec"], (1, 2))
     cia = dec(wl["log10_cia"], (1,)) if wl["log10_cia"] is not None else None
     return xs, cia

@@ -1,43 +1,18 @@
-// Emission forward kernel: per (sample, 64-wavenumber tile) the vertical
+// Emission forward kernels: per (sample, 64-wavenumber tile) the vertical
 // optical depth of every layer (pure absorption: line tables and CIA), the
 // Planck intensity at every level, the upward linear-in-tau intensity sweep
 // for each Gauss-Legendre angle and the planet/star flux ratio (Eq. 45).
 // One thread owns one (wavenumber, angle) pair during the sweep.
+//
+// Reduced precision: the tables are stored as FP16 (hi, lo) pairs of
+// log2 sigma - c (hi = fp16(v), lo = fp16(v - hi)), one 4-byte word per entry,
+// so the stored value keeps about 22 significant bits: emitted flux is far
+// more sensitive to opacity errors than the transit depth.
 #include "emission.h"
 #include "kernels.h"
+#include "opacity.h"
 
 namespace exofwd {
-
-__device__ inline float opacity_mixed_e(const Model& m, const Tables& tb, int cells, const float* __restrict__ rl,
-                                        int nu, const float* cs, const float* ccs) {
-  const int it = cells & 255, ip = (cells >> 8) & 255, itc = cells >> 16;
-  const float wt = rl[0], wp = rl[1];
-  const float w11 = wt * wp, w10 = wt - w11, w01 = wp - w11, w00 = 1.0f - wt - wp + w11;
-  const size_t npad = (size_t)m.n_nu_pad;
-  float acc = 0.0f;
-  const _Float16* __restrict__ h = reinterpret_cast<const _Float16*>(tb.h);
-  for (int s = 0; s < m.S; ++s) {
-    const _Float16* p = h + (((size_t)s * m.n_t + it) * m.n_p + ip) * npad + nu;
-    float v = cs[s] + rl[kRecFixed + s];
-    v = fmaf(w00, (float)p[0], v);
-    v = fmaf(w10, (float)p[(size_t)m.n_p * npad], v);
-    v = fmaf(w01, (float)p[npad], v);
-    v = fmaf(w11, (float)p[(size_t)(m.n_p + 1) * npad], v);
-    acc += exp2f(v);
-  }
-  if (m.has_cia) {
-    const float wtc = rl[2];
-    const _Float16* __restrict__ hc = reinterpret_cast<const _Float16*>(tb.hc);
-    for (int c = 0; c < 2; ++c) {
-      const _Float16* p = hc + ((size_t)c * m.n_tc + itc) * npad + nu;
-      float v = ccs[c] + rl[5 + c];
-      v = fmaf(1.0f - wtc, (float)p[0], v);
-      v = fmaf(wtc, (float)p[npad], v);
-      acc += exp2f(v);
-    }
-  }
-  return acc;
-}
 
 __device__ inline double opacity_fp64_e(const Model& m, const Tables& tb, int cells, const double* __restrict__ rl,
                                         int nu) {
@@ -83,8 +58,10 @@ __device__ inline Real lin_source(Real x, Real e) {
   }
 }
 
+// plain FP64 path
 template <typename Real>
 __global__ __launch_bounds__(kBlock) void k_emission(Model m, Work w, Tables tb, int B, Real* __restrict__ spec) {
+  static_assert(sizeof(Real) == 8, "the reduced-precision path is k_emission_mixed");
   extern __shared__ __align__(16) unsigned char lds[];
   const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = logical % B, tile = logical / B;
@@ -106,17 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_emission(Model m, Work w, Tables tb,
   const int nu = nu0 + lane;
   const double* t_lev = w.t_lev + (size_t)b * (Lp + 1);
   const Real nuv = Real(m.nu[nu]);
-  if constexpr (sizeof(Real) == 4) {
-    float cs[kMaxSpecies], ccs[2] = {0.0f, 0.0f};
-    for (int s = 0; s < m.S; ++s) cs[s] = tb.c[(size_t)s * m.n_nu_pad + nu];
-    if (m.has_cia) {
-      ccs[0] = tb.cc[nu];
-      ccs[1] = tb.cc[(size_t)m.n_nu_pad + nu];
-    }
-    for (int l = wv; l < L; l += 4) s_dt[l * kTile64 + lane] = opacity_mixed_e(m, tb, cells[l], rec + (size_t)l * RL, nu, cs, ccs);
-  } else {
-    for (int l = wv; l < L; l += 4) s_dt[l * kTile64 + lane] = opacity_fp64_e(m, tb, cells[l], rec + (size_t)l * RL, nu);
-  }
+  for (int l = wv; l < L; l += 4) s_dt[l * kTile64 + lane] = opacity_fp64_e(m, tb, cells[l], rec + (size_t)l * RL, nu);
   for (int j = wv; j <= L; j += 4) s_b[j * kTile64 + lane] = planck<Real>(Real(t_lev[j]), nuv);
   __syncthreads();
 
@@ -131,7 +98,8 @@ __global__ __launch_bounds__(kBlock) void k_emission(Model m, Work w, Tables tb,
       Real e;
       if constexpr (sizeof(Real) == 8) e = exp(-x); else e = __expf(-x);
       const Real bb = s_b[l * kTile64 + lane], bt = s_b[(l + 1) * kTile64 + lane];
-      inten = inten * e + bt * (Real(1) - e) + (bb - bt) * lin_source<Real>(x, e);
+      // I e^-x + B_top (1 - e^-x) + (B_bot - B_top) src, as an increment of I
+      inten += -expm1(-x) * (bt - inten) + (bb - bt) * lin_source<Real>(x, e);
     }
     flux += Real(2.0 * M_PI * m.mu_weights[k]) * mu * inten;
   }
@@ -144,6 +112,145 @@ __global__ __launch_bounds__(kBlock) void k_emission(Model m, Work w, Tables tb,
   }
 }
 
+
+// reduced precision: 256 threads, 64-wavenumber tile, one wavenumber per lane
+template <int S, bool CIA>
+__global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tables tb, int B, float* __restrict__ spec) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int b = logical % B, tile = logical / B;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nu0 = tile * kTile64;
+  float* out = spec + (size_t)b * m.n_nu;
+  if (w.status[b]) {
+    if (tid < kTile64 && nu0 + tid < m.n_nu) out[nu0 + tid] = __builtin_nanf("");
+    return;
+  }
+  const int L = w.nlay[b], Lp = m.L_pad;
+  float* s_dt = reinterpret_cast<float*>(lds);     // [Lp][64] layer optical depths
+  float* s_b = s_dt + (size_t)Lp * kTile64;        // [Lp+1][64] Planck at the levels
+  float* s_f = s_b + (size_t)(Lp + 1) * kTile64;   // [4][64] flux partials
+  constexpr int RL = rec_len(S);
+  const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * RL;
+  const int32_t* cells = w.cells + (size_t)b * Lp;
+  const size_t npad = (size_t)m.n_nu_pad;
+  const int nu = nu0 + lane;
+  // pair tables: 4 bytes per (row, wavenumber)
+  const uint32_t row_bytes = (uint32_t)npad * 4u, tstep = (uint32_t)m.n_p * row_bytes;
+  const __amdgpu_buffer_rsrc_t rh = make_rsrc(tb.h, (size_t)S * m.n_t * m.n_p * npad * 4);
+  const __amdgpu_buffer_rsrc_t rhc = make_rsrc(CIA ? (const void*)tb.hc : (const void*)tb.h,
+                                               CIA ? (size_t)2 * m.n_tc * npad * 4 : 0);
+  const uint32_t voff = (uint32_t)lane * 4u, nu0_bytes = (uint32_t)nu0 * 4u;
+  float cs[S], ccs[2];
+#pragma unroll
+  for (int s2 = 0; s2 < S; ++s2) cs[s2] = tb.c[(size_t)s2 * npad + nu];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) ccs[p] = CIA ? tb.cc[(size_t)p * npad + nu] : 0.0f;
+
+  for (int l = wv; l < L; l += 4) {
+    const int cl = cells[l];
+    const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
+    const float* rl = rec + (size_t)l * RL;
+    const float wt = rl[0], wp = rl[1];
+    const float w11 = wt * wp, w10 = wt - w11, w01 = wp - w11, w00 = 1.0f - wt - wp + w11;
+    float d = 0.0f;
+#pragma unroll
+    for (int s2 = 0; s2 < S; ++s2) {
+      const uint32_t row = (uint32_t)((s2 * m.n_t + it) * m.n_p + ip) * row_bytes + nu0_bytes;
+      const half2_t p00 = load_h2(rh, voff, row), p10 = load_h2(rh, voff, row + tstep);
+      const half2_t p01 = load_h2(rh, voff, row + row_bytes), p11 = load_h2(rh, voff, row + tstep + row_bytes);
+      float v = cs[s2] + rl[kRecFixed + s2];
+      v = fmaf(w00, (float)p00.x, v);
+      v = fmaf(w10, (float)p10.x, v);
+      v = fmaf(w01, (float)p01.x, v);
+      v = fmaf(w11, (float)p11.x, v);
+      v = fmaf(w00, (float)p00.y, v);
+      v = fmaf(w10, (float)p10.y, v);
+      v = fmaf(w01, (float)p01.y, v);
+      v = fmaf(w11, (float)p11.y, v);
+      d += exp2_fast(v);
+    }
+    if (CIA) {
+      const float wtc = rl[2];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const uint32_t row = (uint32_t)(p * m.n_tc + itc) * row_bytes + nu0_bytes;
+        const half2_t a = load_h2(rhc, voff, row), c2 = load_h2(rhc, voff, row + row_bytes);
+        float v = ccs[p] + rl[5 + p];
+        v = fmaf(1.0f - wtc, (float)a.x, v);
+        v = fmaf(wtc, (float)c2.x, v);
+        v = fmaf(1.0f - wtc, (float)a.y, v);
+        v = fmaf(wtc, (float)c2.y, v);
+        d += exp2_fast(v);
+      }
+    }
+    s_dt[l * kTile64 + lane] = d;
+  }
+  // Planck intensity per unit wavenumber at the levels: 2 h c^2 nu^3 / (exp(y) - 1),
+  // y = h c nu / k T; below y = 0.01 exp(y) - 1 is taken from its series
+  const double* t_lev = w.t_lev + (size_t)b * (Lp + 1);
+  const float nuv = (float)m.nu[nu];
+  const float c1n3 = (float)(2.0 * kHpl * kC * kC) * nuv * nuv * nuv;
+  const float c2n = (float)(kHpl * kC / kB) * nuv;
+  for (int j = wv; j <= L; j += 4) {
+    const float y = c2n * __builtin_amdgcn_rcpf((float)t_lev[j]);
+    const float em1 = y < 0.01f ? y * (1.0f + y * (0.5f + y * (1.0f / 6.0f)))
+                                : exp2_fast(1.4426950408889634f * y) - 1.0f;
+    s_b[j * kTile64 + lane] = c1n3 * __builtin_amdgcn_rcpf(em1);
+  }
+  __syncthreads();
+
+  // upward sweep, one (wavenumber, angle) per thread
+  float flux = 0.0f;
+  for (int k = wv; k < m.n_mu; k += 4) {
+    const float mu = (float)m.mu_nodes[k];
+    const float inv_mu = 1.0f / mu;
+    float inten = s_b[lane];
+    for (int l = 0; l < L; ++l) {
+      const float x = s_dt[l * kTile64 + lane] * inv_mu;
+      const float e = exp2_fast(-1.4426950408889634f * x);
+      const float bb = s_b[l * kTile64 + lane], bt = s_b[(l + 1) * kTile64 + lane];
+      // 1 - e^-x and (1 - e^-x)/x - e^-x by their Taylor series for thin layers: there
+      // the differences cancel in FP32, and a thin hot layer above a cold one can
+      // carry most of the emergent intensity
+      float om, src;
+      if (x < 0.1f) {
+        om = x * (1.0f + x * (-0.5f + x * (1.0f / 6.0f + x * (-1.0f / 24.0f + x * (1.0f / 120.0f + x * (-1.0f / 720.0f))))));
+        src = x * (0.5f + x * (-1.0f / 3.0f + x * (0.125f + x * (-1.0f / 30.0f + x * (1.0f / 144.0f + x * (-1.0f / 840.0f))))));
+      } else {
+        om = 1.0f - e;
+        src = om * __builtin_amdgcn_rcpf(x) - e;
+      }
+      // I e^-x + B_top (1 - e^-x) + (B_bot - B_top) src, as an increment of I
+      inten = fmaf(om, bt - inten, fmaf(bb - bt, src, inten));
+    }
+    flux = fmaf((float)(2.0 * M_PI * m.mu_weights[k]) * mu, inten, flux);
+  }
+  s_f[wv * kTile64 + lane] = flux;
+  __syncthreads();
+  if (tid < kTile64 && nu0 + tid < m.n_nu) {
+    const float f = (s_f[tid] + s_f[kTile64 + tid]) + (s_f[2 * kTile64 + tid] + s_f[3 * kTile64 + tid]);
+    const double nd = m.nu[nu0 + tid];
+    const double fstar = M_PI * 2.0 * kHpl * kC * kC * nd * nd * nd / expm1(kHpl * kC * nd / (kB * m.t_star));
+    out[nu0 + tid] = (float)(m.dilution * (double)f / fstar * w.core[b]);
+  }
+}
+
+template <int S, bool CIA>
+const void* emis_kernel() { return (const void*)k_emission_mixed<S, CIA>; }
+
+const void* emis_kernel_for(int S, bool cia) {
+#define EXOFWD_CASE(n) \
+  case n: return cia ? emis_kernel<n, true>() : emis_kernel<n, false>();
+  switch (S) {
+    EXOFWD_CASE(1) EXOFWD_CASE(2) EXOFWD_CASE(3) EXOFWD_CASE(4)
+    EXOFWD_CASE(5) EXOFWD_CASE(6) EXOFWD_CASE(7) EXOFWD_CASE(8)
+  }
+#undef EXOFWD_CASE
+  return nullptr;
+}
+
 size_t emission_lds_bytes(const Model& m, bool fp64) {
   const size_t rs = fp64 ? 8 : 4;
   return rs * ((size_t)m.L_pad * kTile64 + (size_t)(m.L_pad + 1) * kTile64 + 4 * kTile64);
@@ -153,16 +260,20 @@ hipError_t emission_configure(const Model& m, bool fp64) {
   const size_t bytes = emission_lds_bytes(m, fp64);
   if (bytes > 160 * 1024) return hipErrorInvalidValue;
   if (fp64) return hipFuncSetAttribute((const void*)k_emission<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  return hipFuncSetAttribute((const void*)k_emission<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const void* k = emis_kernel_for(m.S, m.has_cia);
+  if (!k) return hipErrorInvalidValue;
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 void launch_emission(const Model& m, const Work& w, const Tables& tb, int B, void* spec, bool fp64, hipStream_t st) {
   const dim3 grid((unsigned)(m.n_tiles64 * B));
   const size_t lds = emission_lds_bytes(m, fp64);
-  if (fp64)
+  if (fp64) {
     hipLaunchKernelGGL(k_emission<double>, grid, dim3(kBlock), lds, st, m, w, tb, B, (double*)spec);
-  else
-    hipLaunchKernelGGL(k_emission<float>, grid, dim3(kBlock), lds, st, m, w, tb, B, (float*)spec);
+  } else {
+    void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec};
+    hipLaunchKernel(emis_kernel_for(m.S, m.has_cia), grid, dim3(kBlock), args, lds, st);
+  }
 }
 
 }  // namespace exofwd

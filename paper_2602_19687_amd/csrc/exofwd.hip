@@ -105,10 +105,13 @@ void gauss_legendre(int n, double* x, double* wgt) {
 }
 
 // Reduced-precision table storage: per (source, nu) offset c = float((min+max)/2)
-// of log2 sigma over the interpolation axes, entries float16(log2 sigma - c).
+// of log2 sigma over the interpolation axes, entries float16(log2 sigma - c);
+// with `pairs` each entry is the (hi, lo) pair hi = fp16(v), lo = fp16(v - hi),
+// stored next to each other (emission, whose flux is sensitive to opacity error).
 void encode_fp16(const double* log10_tab, int n_src, int n_rows, int n_nu, int n_nu_pad, std::vector<_Float16>& h,
-                 std::vector<float>& c) {
-  h.assign((size_t)n_src * n_rows * n_nu_pad, (_Float16)0.0f);
+                 std::vector<float>& c, bool pairs = false) {
+  const int k = pairs ? 2 : 1;
+  h.assign((size_t)n_src * n_rows * n_nu_pad * k, (_Float16)0.0f);
   c.assign((size_t)n_src * n_nu_pad, -1000.0f);
   for (int s = 0; s < n_src; ++s) {
     const double* t = log10_tab + (size_t)s * n_rows * n_nu;
@@ -123,7 +126,14 @@ void encode_fp16(const double* log10_tab, int n_src, int n_rows, int n_nu, int n
       c[(size_t)s * n_nu_pad + i] = cf;
       for (int r = 0; r < n_rows; ++r) {
         double v = t[(size_t)r * n_nu + i] * kLog2_10 - (double)cf;
-        h[((size_t)s * n_rows + r) * n_nu_pad + i] = (_Float16)v;
+        const size_t e = ((size_t)s * n_rows + r) * n_nu_pad + i;
+        if (pairs) {
+          const _Float16 hi = (_Float16)v;
+          h[2 * e] = hi;
+          h[2 * e + 1] = (_Float16)(v - (double)hi);
+          continue;
+        }
+        h[e] = (_Float16)v;
       }
     }
   }
@@ -341,7 +351,8 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   } else {
     std::vector<_Float16> h;
     std::vector<float> off;
-    encode_fp16(g.log10_xsec, m.S, rows, g.n_nu, (int)np, h, off);
+    const bool pairs = m.mode == kEmission;
+    encode_fp16(g.log10_xsec, m.S, rows, g.n_nu, (int)np, h, off, pairs);
     uint16_t* dh = A(dalloc<uint16_t>(c, h.size()));
     float* dc = A(dalloc<float>(c, off.size()));
     float* dn4 = A(dalloc<float>(c, np));
@@ -354,7 +365,7 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
     c->tb.c = dc;
     c->tb.nu4f = dn4;
     if (m.has_cia) {
-      encode_fp16(g.log10_cia, 2, m.n_tc, g.n_nu, (int)np, h, off);
+      encode_fp16(g.log10_cia, 2, m.n_tc, g.n_nu, (int)np, h, off, pairs);
       uint16_t* dhc = A(dalloc<uint16_t>(c, h.size()));
       float* dcc = A(dalloc<float>(c, off.size()));
       if (ok) ok = upload(dhc, reinterpret_cast<const uint16_t*>(h.data()), h.size()) && upload(dcc, off.data(), off.size());

@@ -186,3 +186,37 @@ def test_c4_full_size_sampled(prec):
         lerr = abs(lnl[b] - ref["lnL"]) / abs(ref["lnL"])
         print(f"c4 full {prec} sample {b} L={nl[b]}: spectrum rel err {err:.3e} lnL rel err {lerr:.3e}")
         assert err < SPEC_TOL[prec] and lerr < LNL_TOL[prec]
+
+
+def test_emission_high_wavenumber_end_every_sample():
+    """The short-wavelength end of the emission grid, where the flux ratio falls to
+    ~1e-9 of its peak and thin hot upper layers can carry the emergent intensity."""
+    wl = reduced(2, n_nu=1000, n_bins=25, batch=16, start=19000)
+    spec, lnl, st = _run(wl, "mixed", wl["params"])
+    errs = []
+    for b in range(16):
+        ref = oracle.forward(wl, wl["params"][b])
+        assert st[b] == ref["status"]
+        if ref["status"]:
+            continue
+        errs.append(rel_err(spec[b], ref["spectrum"]))
+    print(f"c2 high-nu mixed: spectrum max rel err {max(errs):.3e}")
+    assert max(errs) < 1e-4
+
+
+def test_emission_full_batch_mixed_vs_fp64():
+    """Every sample and wavenumber of the emission batch: the reduced-precision path
+    against the FP64 GPU path (itself pinned to the oracle), and the worst sample
+    against the oracle."""
+    wl = synth.workload(2)
+    a, _, sa = _run(wl, "mixed", wl["params"])
+    b, _, sb = _run(wl, "fp64", wl["params"])
+    ok = (sa == 0) & (sb == 0)
+    rel = np.abs(a[ok] - b[ok]) / np.abs(b[ok])
+    per = rel.max(axis=1)
+    worst = int(np.flatnonzero(ok)[np.argmax(per)])
+    print(f"c2 full batch: max rel err mixed vs fp64 {per.max():.3e}, median {np.median(per):.3e}, worst sample {worst}")
+    assert per.max() < 1e-4
+    ref = oracle.forward(wl, wl["params"][worst])
+    assert rel_err(b[worst], ref["spectrum"]) < 1e-10
+    assert rel_err(a[worst], ref["spectrum"]) < 1e-4
