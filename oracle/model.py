@@ -12,6 +12,7 @@ differentiation).
 from __future__ import annotations
 
 import numpy as np
+from scipy import special
 
 # CODATA 2018 / IAU 2015 constants in cgs; the paper works in cgs but gives none
 K_B = 1.380649e-16          # erg K^-1
@@ -258,6 +259,99 @@ def cloud_fraction(p_bottom, p_top, p_cloud):
     return f
 
 
+# ---------------------------------------------------------------------------
+# non-grey aerosol opacity (Section "Non-grey aerosol opacity")
+CLOUD_GREY_DECK = 0       # slab deck from P_cloud down, Q_ext = 2, fixed kappa (R9)
+CLOUD_NONGREY = 1         # q_c(p) profile and Q_ext(x, lambda), Eqs. 18-29
+QPROF_UNIFORM, QPROF_SLAB, QPROF_POWER = 0, 1, 2
+QEXT_FIT, QEXT_FIT_FEATURE, QEXT_GREY = 0, 1, 2
+X0_FEATURE = 0.5          # transition size parameter of the feature window (Eq. 29)
+Q_MAX = 2.0               # cap of the total extinction efficiency (Eq. 27)
+
+
+def nongrey_param_count(wl):
+    """[log10 r_eff/um, a, log10 Q0] (fit), profile parameters (1 or 3), feature (4)."""
+    n = 1 if wl["cloud_qext"] == QEXT_GREY else 3
+    n += 1 if wl["cloud_profile"] == QPROF_UNIFORM else 3
+    n += 4 if wl["cloud_qext"] == QEXT_FIT_FEATURE else 0
+    return n
+
+
+def layer_coverage(p_bottom, p_top, p_hi, p_lo):
+    """Fraction, in ln p, of the layer between levels p_bottom > p_top that lies
+    inside the pressure range [p_lo, p_hi] (the same rule as the grey deck's
+    partial layer, so the profile's edges move the optical depth continuously)."""
+    lb, lt = np.log(p_bottom), np.log(p_top)
+    hi = np.log(p_hi) if np.real(np.log(p_hi)) < np.real(lb) else lb
+    lo = np.log(p_lo) if np.real(np.log(p_lo)) > np.real(lt) else lt
+    f = (hi - lo) / (lb - lt)
+    return f if np.real(f) > 0.0 else 0.0 * f
+
+
+def condensate_profile(wl, cp, p_lev, p_lay):
+    """Effective condensate mass mixing ratio of every layer (Eqs. 18-20).
+
+    uniform : q_l = q                                               (Eq. 18)
+    slab    : q between p_top and p_top + dp, else 0                (Eq. 19)
+    power   : q_base (p / p_base)^alpha above p_base, 0 below       (Eq. 20)
+    The power law is taken at the layer pressure; slab and power-law edges
+    cover the layers that straddle them by their ln p fraction.
+    """
+    prof = wl["cloud_profile"]
+    n_lay = len(p_lay)
+    q = [None] * n_lay
+    if prof == QPROF_UNIFORM:
+        for l in range(n_lay):
+            q[l] = 10.0 ** cp["q"][0] * np.ones(1)[0]
+    elif prof == QPROF_SLAB:
+        p_top = 10.0 ** cp["q"][1] * BAR
+        p_bot = p_top + 10.0 ** cp["q"][2] * BAR
+        for l in range(n_lay):
+            q[l] = 10.0 ** cp["q"][0] * layer_coverage(p_lev[l], p_lev[l + 1], p_bot, p_top)
+    else:
+        p_base = 10.0 ** cp["q"][1] * BAR
+        for l in range(n_lay):
+            cov = layer_coverage(p_lev[l], p_lev[l + 1], p_base, p_lev[-1] * 1e-3)
+            q[l] = 10.0 ** cp["q"][0] * (p_lay[l] / p_base) ** cp["q"][2] * cov
+    return np.array(q)
+
+
+def feature_efficiency(feat, lam_um):
+    """Skew-normal absorption feature (Eq. 28): 2 A exp(-z^2/2) Phi(xi z),
+    z = (lambda - lambda0) / omega, Phi the standard normal CDF; feat is
+    (A, lambda0 [um], log10 omega [um], xi)."""
+    amp, lam0, log_w, xi = feat
+    z = (lam_um - lam0) / 10.0 ** log_w
+    return 2.0 * amp * np.exp(-0.5 * z * z) * 0.5 * (1.0 + special.erf(xi * z / np.sqrt(2.0)))
+
+
+def extinction_efficiency(wl, cp, nu):
+    """Q_ext(nu) of the effective particle size r_eff (Eqs. 24, 27-29), with the
+    material factor Q1 folded into the effective mixing ratio (Eq. 25):
+      fit     : Q = 1 / (Q0 x^-a + x^0.2),  x = 2 pi r_eff / lambda
+      feature : Q = min(fit + W(x) Q_feat(lambda), Q_max), W = exp(-x / x0),
+                Q_feat = 2 A exp(-z^2/2) Phi(xi z), z = (lambda - lambda0) / omega
+      grey    : Q = 2 (geometric-optics limit)."""
+    r = 1.0e-4 * 10.0 ** cp["r"]
+    if wl["cloud_qext"] == QEXT_GREY:
+        return 2.0 + 0.0 * nu * r, r
+    x = 2.0 * np.pi * r * nu
+    q = 1.0 / (10.0 ** cp["q0"] * x ** (-cp["a"]) + x ** 0.2)
+    if wl["cloud_qext"] == QEXT_FIT_FEATURE:
+        q = q + np.exp(-x / X0_FEATURE) * feature_efficiency(cp["feat"], 1.0e4 / nu)
+        q = np.where(np.real(q) < Q_MAX, q, Q_MAX + 0.0 * q)
+    return q, r
+
+
+def nongrey_cloud_dtau(wl, cp, p_lev, p_lay, t_lay, mu, dr, nu):
+    """Cloud optical depth dtau[l, nu] = q_l rho_l dr_l 3 Q(nu) / (4 r_eff) (Eq. 23)."""
+    q_lay = condensate_profile(wl, cp, p_lev, p_lay)
+    q_nu, r = extinction_efficiency(wl, cp, nu)
+    rho = mu * M_U * p_lay / (K_B * t_lay)
+    col = q_lay * rho * dr * 0.75 / r
+    return col[:, None] * q_nu[None, :]
+
+
 def layer_optical_depth(wl, t_lay, p_lev, p_lay, r_lev, x, x_h2, x_he, mu, log10_pc=None,
                         tables=None):
     """Vertical optical depth of every layer, dtau[l, nu] = kappa_l(nu) dr_l.
@@ -291,10 +385,12 @@ def layer_optical_depth(wl, t_lay, p_lev, p_lay, r_lev, x, x_h2, x_he, mu, log10
             kap = kap + n_l * n_l * (x_h2 * x_h2 * k1 + x_h2 * x_he * k2)
         if wl["rayleigh"] and not emission:
             kap = kap + n_l * (x_h2 * wl["ray_h2"] + x_he * wl["ray_he"]) * nu4
-        if wl["cloud"] and not emission:
+        if wl["cloud"] and not emission and wl.get("cloud_model", CLOUD_GREY_DECK) == CLOUD_GREY_DECK:
             f = cloud_fraction(p_lev[l], p_lev[l + 1], 10.0 ** log10_pc * BAR)
             kap = kap + wl["kappa_cloud"] * mu * M_U * n_l * f
         out[l] = kap * dr[l]
+    if wl["cloud"] and not emission and wl.get("cloud_model", CLOUD_GREY_DECK) == CLOUD_NONGREY:
+        out = out + nongrey_cloud_dtau(wl, log10_pc, p_lev, p_lay, t_lay, mu, dr, nu)
     return out
 
 
@@ -414,8 +510,28 @@ def split_params(wl, theta):
     k += ntp
     out["logx"] = theta[k:k + wl["n_species"]]
     k += wl["n_species"]
-    out["log10_pc"] = theta[k] if wl["cloud"] else None
-    k += int(wl["cloud"])
+    if wl["cloud"] and wl.get("cloud_model", CLOUD_GREY_DECK) == CLOUD_NONGREY:
+        # non-grey cloud: the whole group travels under "log10_pc" to the opacity
+        n_c = nongrey_param_count(wl)
+        g = theta[k:k + n_c]
+        j = 0
+        cp = {}
+        if wl["cloud_qext"] == QEXT_GREY:
+            cp["r"] = g[0]
+            j = 1
+        else:
+            cp["r"], cp["a"], cp["q0"] = g[0], g[1], g[2]
+            j = 3
+        nq = 1 if wl["cloud_profile"] == QPROF_UNIFORM else 3
+        cp["q"] = g[j:j + nq]
+        j += nq
+        if wl["cloud_qext"] == QEXT_FIT_FEATURE:
+            cp["feat"] = g[j:j + 4]
+        out["log10_pc"] = cp
+        k += n_c
+    else:
+        out["log10_pc"] = theta[k] if wl["cloud"] else None
+        k += int(wl["cloud"])
     out["scale"] = theta[k] if wl["scale"] else 1.0
     k += int(wl["scale"])
     out["offset"] = theta[k] if wl["offset"] else 0.0

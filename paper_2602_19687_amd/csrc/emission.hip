@@ -113,29 +113,31 @@ __global__ __launch_bounds__(kBlock) void k_emission(Model m, Work w, Tables tb,
 }
 
 
-// reduced precision: 256 threads, 64-wavenumber tile, one wavenumber per lane
+// reduced precision: one wave per (sample, 64-wavenumber tile), one wavenumber per
+// lane, streaming up the layers: each layer's optical depth and its upper level's
+// Planck intensity are formed where the angle sweeps need them, so nothing is
+// staged in LDS and waves never wait for each other.  A workgroup holds four
+// neighbouring tiles of one sample.
 template <int S, bool CIA>
 __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tables tb, int B, float* __restrict__ spec) {
-  extern __shared__ __align__(16) unsigned char lds[];
   const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int b = logical % B, tile = logical / B;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int nu0 = tile * kTile64;
+  const int b = logical % B;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tile = (logical / B) * 4 + wv;
+  if (tile >= m.n_tiles64) return;
+  const int nu0 = tile * kTile64, nu = nu0 + lane;
   float* out = spec + (size_t)b * m.n_nu;
   if (w.status[b]) {
-    if (tid < kTile64 && nu0 + tid < m.n_nu) out[nu0 + tid] = __builtin_nanf("");
+    if (nu < m.n_nu) out[nu] = __builtin_nanf("");
     return;
   }
   const int L = w.nlay[b], Lp = m.L_pad;
-  float* s_dt = reinterpret_cast<float*>(lds);     // [Lp][64] layer optical depths
-  float* s_b = s_dt + (size_t)Lp * kTile64;        // [Lp+1][64] Planck at the levels
-  float* s_f = s_b + (size_t)(Lp + 1) * kTile64;   // [4][64] flux partials
   constexpr int RL = rec_len(S);
   const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * RL;
   const int32_t* cells = w.cells + (size_t)b * Lp;
+  const double* t_lev = w.t_lev + (size_t)b * (Lp + 1);
   const size_t npad = (size_t)m.n_nu_pad;
-  const int nu = nu0 + lane;
   // pair tables: 4 bytes per (row, wavenumber)
   const uint32_t row_bytes = (uint32_t)npad * 4u, tstep = (uint32_t)m.n_p * row_bytes;
   const __amdgpu_buffer_rsrc_t rh = make_rsrc(tb.h, (size_t)S * m.n_t * m.n_p * npad * 4);
@@ -148,7 +150,28 @@ __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tabl
 #pragma unroll
   for (int p = 0; p < 2; ++p) ccs[p] = CIA ? tb.cc[(size_t)p * npad + nu] : 0.0f;
 
-  for (int l = wv; l < L; l += 4) {
+  // Planck intensity per unit wavenumber, 2 h c^2 nu^3 / (exp(y) - 1), y = h c nu / k T;
+  // below y = 0.01 exp(y) - 1 is taken from its series
+  const float nuv = (float)m.nu[nu];
+  const float c1n3 = (float)(2.0 * kHpl * kC * kC) * nuv * nuv * nuv;
+  const float c2n = (float)(kHpl * kC / kB) * nuv;
+  auto planck_at = [&](int j) {
+    const float y = c2n * __builtin_amdgcn_rcpf((float)t_lev[j]);
+    const float em1 = y < 0.01f ? y * (1.0f + y * (0.5f + y * (1.0f / 6.0f)))
+                                : exp2_fast(1.4426950408889634f * y) - 1.0f;
+    return c1n3 * __builtin_amdgcn_rcpf(em1);
+  };
+  const int n_mu = m.n_mu;
+  float inv_mu[kMaxMu], inten[kMaxMu];
+  float b_bot = planck_at(0);
+#pragma unroll
+  for (int k = 0; k < kMaxMu; ++k) {
+    inv_mu[k] = k < n_mu ? (float)(1.0 / m.mu_nodes[k]) : 0.0f;
+    inten[k] = b_bot;
+  }
+
+  for (int l = 0; l < L; ++l) {
+    // ---- optical depth of layer l
     const int cl = cells[l];
     const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
     const float* rl = rec + (size_t)l * RL;
@@ -185,32 +208,14 @@ __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tabl
         d += exp2_fast(v);
       }
     }
-    s_dt[l * kTile64 + lane] = d;
-  }
-  // Planck intensity per unit wavenumber at the levels: 2 h c^2 nu^3 / (exp(y) - 1),
-  // y = h c nu / k T; below y = 0.01 exp(y) - 1 is taken from its series
-  const double* t_lev = w.t_lev + (size_t)b * (Lp + 1);
-  const float nuv = (float)m.nu[nu];
-  const float c1n3 = (float)(2.0 * kHpl * kC * kC) * nuv * nuv * nuv;
-  const float c2n = (float)(kHpl * kC / kB) * nuv;
-  for (int j = wv; j <= L; j += 4) {
-    const float y = c2n * __builtin_amdgcn_rcpf((float)t_lev[j]);
-    const float em1 = y < 0.01f ? y * (1.0f + y * (0.5f + y * (1.0f / 6.0f)))
-                                : exp2_fast(1.4426950408889634f * y) - 1.0f;
-    s_b[j * kTile64 + lane] = c1n3 * __builtin_amdgcn_rcpf(em1);
-  }
-  __syncthreads();
-
-  // upward sweep, one (wavenumber, angle) per thread
-  float flux = 0.0f;
-  for (int k = wv; k < m.n_mu; k += 4) {
-    const float mu = (float)m.mu_nodes[k];
-    const float inv_mu = 1.0f / mu;
-    float inten = s_b[lane];
-    for (int l = 0; l < L; ++l) {
-      const float x = s_dt[l * kTile64 + lane] * inv_mu;
+    // ---- the sweep through layer l for every angle
+    const float b_top = planck_at(l + 1);
+    const float db = b_bot - b_top;
+#pragma unroll
+    for (int k = 0; k < kMaxMu; ++k) {
+      if (k >= n_mu) break;
+      const float x = d * inv_mu[k];
       const float e = exp2_fast(-1.4426950408889634f * x);
-      const float bb = s_b[l * kTile64 + lane], bt = s_b[(l + 1) * kTile64 + lane];
       // 1 - e^-x and (1 - e^-x)/x - e^-x by their Taylor series for thin layers: there
       // the differences cancel in FP32, and a thin hot layer above a cold one can
       // carry most of the emergent intensity
@@ -223,17 +228,18 @@ __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tabl
         src = om * __builtin_amdgcn_rcpf(x) - e;
       }
       // I e^-x + B_top (1 - e^-x) + (B_bot - B_top) src, as an increment of I
-      inten = fmaf(om, bt - inten, fmaf(bb - bt, src, inten));
+      inten[k] = fmaf(om, b_top - inten[k], fmaf(db, src, inten[k]));
     }
-    flux = fmaf((float)(2.0 * M_PI * m.mu_weights[k]) * mu, inten, flux);
+    b_bot = b_top;
   }
-  s_f[wv * kTile64 + lane] = flux;
-  __syncthreads();
-  if (tid < kTile64 && nu0 + tid < m.n_nu) {
-    const float f = (s_f[tid] + s_f[kTile64 + tid]) + (s_f[2 * kTile64 + tid] + s_f[3 * kTile64 + tid]);
-    const double nd = m.nu[nu0 + tid];
+  float flux = 0.0f;
+#pragma unroll
+  for (int k = 0; k < kMaxMu; ++k)
+    if (k < n_mu) flux = fmaf((float)(2.0 * M_PI * m.mu_weights[k] * m.mu_nodes[k]), inten[k], flux);
+  if (nu < m.n_nu) {
+    const double nd = m.nu[nu];
     const double fstar = M_PI * 2.0 * kHpl * kC * kC * nd * nd * nd / expm1(kHpl * kC * nd / (kB * m.t_star));
-    out[nu0 + tid] = (float)(m.dilution * (double)f / fstar * w.core[b]);
+    out[nu] = (float)(m.dilution * (double)flux / fstar * w.core[b]);
   }
 }
 
@@ -252,7 +258,8 @@ const void* emis_kernel_for(int S, bool cia) {
 }
 
 size_t emission_lds_bytes(const Model& m, bool fp64) {
-  const size_t rs = fp64 ? 8 : 4;
+  if (!fp64) return 0;   // the reduced-precision kernel streams without LDS
+  const size_t rs = 8;
   return rs * ((size_t)m.L_pad * kTile64 + (size_t)(m.L_pad + 1) * kTile64 + 4 * kTile64);
 }
 
@@ -266,11 +273,13 @@ hipError_t emission_configure(const Model& m, bool fp64) {
 }
 
 void launch_emission(const Model& m, const Work& w, const Tables& tb, int B, void* spec, bool fp64, hipStream_t st) {
-  const dim3 grid((unsigned)(m.n_tiles64 * B));
   const size_t lds = emission_lds_bytes(m, fp64);
   if (fp64) {
-    hipLaunchKernelGGL(k_emission<double>, grid, dim3(kBlock), lds, st, m, w, tb, B, (double*)spec);
+    hipLaunchKernelGGL(k_emission<double>, dim3((unsigned)(m.n_tiles64 * B)), dim3(kBlock), lds, st, m, w, tb, B,
+                       (double*)spec);
   } else {
+    // four 64-wavenumber tiles (one per wave) of one sample per workgroup
+    const dim3 grid((unsigned)((m.n_tiles64 + 3) / 4 * B));
     void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec};
     hipLaunchKernel(emis_kernel_for(m.S, m.has_cia), grid, dim3(kBlock), args, lds, st);
   }

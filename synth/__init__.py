@@ -162,6 +162,9 @@ _BASE = dict(
     ray_h2=8.0e-29,          # H2 Rayleigh cross section at 1e4 cm^-1 [cm^2], scales as nu^4
     ray_he=6.0e-30,          # He Rayleigh cross section at 1e4 cm^-1 [cm^2]
     n_mu=4,                  # Gauss-Legendre angles (emission)
+    cloud_model=0,           # 0: grey deck (log10 P_cloud); 1: non-grey (profile + Q_ext)
+    cloud_profile=0,         # non-grey q_c(p): 0 uniform, 1 slab, 2 base + power law
+    cloud_qext=0,            # non-grey Q_ext: 0 fit, 1 fit + mid-IR feature, 2 grey Q = 2
     sigma_ppm=50.0,          # observational error per bin [ppm]
 )
 
@@ -191,10 +194,17 @@ CONFIGS = {
             t_grid=np.linspace(300.0, 3500.0, 8), logp_grid=np.linspace(-7.0, 2.0, 8),
             n_lines=2000, cia=True, rayleigh=True, cloud=True, scale=True, offset=True,
             mu_fixed=0.0, n_bins=400, batch=64, ragged=(60, 150)),
+    # the transmission setup of 1 with a non-grey cloud: power-law condensate profile
+    # and the fitted extinction efficiency with a mid-infrared feature
+    5: dict(mode=MODE_TRANSMISSION, tp=TP_GUILLOT3, n_layers=100, p_bot=100.0, p_top=1.0e-7,
+            n_species=6, n_nu=30000, nu_min=1.0e4 / 5.3, nu_max=1.0e4 / 0.6,
+            t_grid=np.linspace(300.0, 3500.0, 20), logp_grid=np.linspace(-7.0, 2.0, 20),
+            n_lines=2000, cia=True, rayleigh=True, cloud=True, scale=True, offset=True,
+            mu_fixed=0.0, n_bins=400, batch=128, cloud_model=1, cloud_profile=2, cloud_qext=1),
 }
 
 # configs 1 and 3 share tables (same seeds) so the spec batch reuses them
-_TABLE_CID = {0: 0, 1: 1, 2: 2, 3: 1, 4: 4}
+_TABLE_CID = {0: 0, 1: 1, 2: 2, 3: 1, 4: 4, 5: 1}
 
 
 def param_names(cfg) -> list:
@@ -206,7 +216,13 @@ def param_names(cfg) -> list:
     else:
         names = [f"T_knot{k}" for k in range(cfg["n_knots"])]
     names += [f"log10_X_{SPECIES[i]}" for i in range(s)]
-    if cfg["cloud"]:
+    if cfg["cloud"] and cfg.get("cloud_model", 0) == 1:
+        names += ["log10_r_eff_um"] + ([] if cfg["cloud_qext"] == 2 else ["a_slope", "log10_Q0"])
+        names += [["log10_q"], ["log10_q", "log10_p_top_bar", "log10_dp_bar"],
+                  ["log10_q_base", "log10_p_base_bar", "alpha"]][cfg["cloud_profile"]]
+        if cfg["cloud_qext"] == 1:
+            names += ["feature_A", "feature_lambda0_um", "log10_feature_width_um", "feature_skew"]
+    elif cfg["cloud"]:
         names.append("log10_P_cloud_bar")
     if cfg["scale"]:
         names.append("R_p_scale")
@@ -225,7 +241,16 @@ def param_bounds(cfg):
     else:
         b = [(800.0, 2500.0)] * cfg["n_knots"]
     b += [(-8.0, -2.0)] * s if cfg["tp"] != TP_ISOTHERMAL else [(-3.0, -3.0)] * s
-    if cfg["cloud"]:
+    if cfg["cloud"] and cfg.get("cloud_model", 0) == 1:
+        b.append((-1.5, 0.5))
+        if cfg["cloud_qext"] != 2:
+            b += [(2.0, 5.0), (0.5, 1.5)]
+        b += [[(-7.0, -4.0)], [(-7.0, -4.0), (-4.0, 0.0), (-3.0, 0.5)],
+              [(-7.0, -4.0), (-3.0, 0.0), (0.5, 3.0)]][cfg["cloud_profile"]]
+        if cfg["cloud_qext"] == 1:
+            # amplitude below 0.8 keeps fit + feature under the Q_max = 2 cap
+            b += [(0.0, 0.8), (2.5, 4.5), (-1.0, -0.3), (-2.0, 2.0)]
+    elif cfg["cloud"]:
         b.append((-6.0, 2.0))
     if cfg["scale"]:
         b.append((0.95, 1.05))

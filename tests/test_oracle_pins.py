@@ -489,3 +489,111 @@ def test_fp16_pair_decoded_tables_within_pair_bound():
     assert np.all(err <= np.abs(v) * 2.0 ** -21 + 2.0 ** -24 + 1e-12)
     single, _ = oracle.decode_fp16_tables(wl, pairs=False)
     assert np.max(err) < 0.01 * np.max(np.abs(single * np.log2(10.0) - l2))
+
+
+# ---------------------------------------------------------------------------
+# non-grey aerosol opacity
+def _nongrey_slice(cid=5, n_nu=1500, batch=4):
+    wl = synth.workload(cid, batch=batch, require_obs=False)
+    w2 = dict(wl)
+    sl = slice(0, n_nu)
+    w2["nu"] = wl["nu"][sl]
+    w2["log10_xsec"] = wl["log10_xsec"][..., sl]
+    w2["log10_cia"] = wl["log10_cia"][..., sl]
+    w2["bin_lo"] = np.arange(0, n_nu, 100, dtype=np.int32)
+    w2["bin_hi"] = w2["bin_lo"] + 100
+    k = len(w2["bin_lo"])
+    w2["y_obs"] = np.full(k, 0.0125)
+    w2["y_err"] = np.full(k, 5e-5)
+    w2["offset_mask"] = (np.arange(k) % 2).astype(np.uint8)
+    return w2
+
+
+def test_grey_q_slab_to_the_bottom_is_the_grey_deck():
+    """Q_ext = 2 (geometric-optics limit), a slab from p_top down past the bottom and
+    q_eff = q / rho_d give kappa = 3 q Q / (4 rho_d r) (Eq. 23): with q = 1e-2,
+    rho_d = 2.5 g cm^-3 and r = 1 um this is the grey deck's 60 cm^2 g^-1."""
+    deck = _nongrey_slice(1)
+    ng = dict(deck, cloud_model=oracle.CLOUD_NONGREY, cloud_profile=oracle.QPROF_SLAB,
+              cloud_qext=oracle.QEXT_GREY)
+    for b in range(2):
+        th = deck["params"][b].copy()
+        k_pc = 3 + 6
+        log_pc = th[k_pc]
+        ng_th = np.concatenate([th[:k_pc], [0.0, np.log10(1e-2 / 2.5), log_pc, 6.0], th[k_pc + 1:]])
+        a = oracle.forward(deck, th)["spectrum"]
+        c = oracle.forward(ng, ng_th)["spectrum"]
+        assert np.max(np.abs(a - c) / a) < 1e-12
+
+
+def test_feature_symmetric_limit_and_area():
+    """Skew-normal feature (Eq. 28): xi = 0 gives the Gaussian of amplitude A; for
+    any xi the area over lambda is A omega sqrt(2 pi) (a skew-normal density
+    integrates to one)."""
+    from scipy import integrate
+    amp, lam0, log_w = 0.7, 3.2, -0.6
+    w = 10.0 ** log_w
+    lam = np.linspace(lam0 - 3 * w, lam0 + 3 * w, 7)
+    g = oracle.feature_efficiency((amp, lam0, log_w, 0.0), lam)
+    np.testing.assert_allclose(g, amp * np.exp(-0.5 * ((lam - lam0) / w) ** 2), rtol=1e-14)
+    for xi in (-3.0, 0.0, 1.5):
+        area, _ = integrate.quad(lambda x: oracle.feature_efficiency((amp, lam0, log_w, xi), x),
+                                 lam0 - 12 * w, lam0 + 12 * w, limit=200)
+        assert abs(area - amp * w * np.sqrt(2 * np.pi)) < 1e-9
+
+
+def test_fit_efficiency_limits():
+    """Eq. 24 with Q1 folded into q_eff: Q -> x^a / Q0 for x << 1 (small particles)
+    and Q -> x^-0.2 for x >> 1; the feature window W = exp(-x/x0) leaves the
+    feature whole for x -> 0 and removes it for x >> x0; Q never exceeds Q_max."""
+    wl = {"cloud_qext": oracle.QEXT_FIT}
+    cp = {"r": -3.0, "a": 4.0, "q0": 1.0}
+    nu = np.array([1000.0, 2000.0])
+    q, r = oracle.extinction_efficiency(wl, cp, nu)
+    x = 2 * np.pi * r * nu
+    np.testing.assert_allclose(q, x ** 4 / 10.0, rtol=1e-6)
+    cp_big = {"r": 3.0, "a": 4.0, "q0": 1.0}
+    q, r = oracle.extinction_efficiency(wl, cp_big, nu)
+    np.testing.assert_allclose(q, (2 * np.pi * r * nu) ** -0.2, rtol=1e-9)
+    wf = {"cloud_qext": oracle.QEXT_FIT_FEATURE}
+    feat = (0.5, 1.0e4 / 1500.0, -0.5, 0.0)
+    small = {"r": -4.0, "a": 4.0, "q0": 1.0, "feat": feat}
+    q, _ = oracle.extinction_efficiency(wf, small, np.array([1500.0]))
+    assert abs(q[0] - 0.5) < 1e-3
+    large = {"r": 1.5, "a": 4.0, "q0": 1.0, "feat": feat}
+    q_f, _ = oracle.extinction_efficiency(wf, large, np.array([1500.0]))
+    q_n, _ = oracle.extinction_efficiency(wl, large, np.array([1500.0]))
+    assert abs(q_f[0] - q_n[0]) < 1e-12
+    capped = {"r": -4.0, "a": 4.0, "q0": 1.0, "feat": (3.0, 1.0e4 / 1500.0, -0.5, 0.0)}
+    q, _ = oracle.extinction_efficiency(wf, capped, np.array([1500.0]))
+    assert q[0] == oracle.Q_MAX
+
+
+def test_condensate_profile_columns():
+    """Eqs. 19-20 with partial layers: the slab's ln-p weighted layer coverage sums
+    to ln((p_top + dp)/p_top); the power law equals q_base (p/p_base)^alpha in
+    every layer wholly above p_base and is zero below it."""
+    wl = {"cloud_profile": oracle.QPROF_SLAB}
+    p_lev, p_lay = oracle.level_pressures(100.0, 1e-7, 100)
+    dlnp = np.log(p_lev[:-1] / p_lev[1:])
+    p_top, dp = 1e-3, 0.05
+    q = oracle.condensate_profile(wl, {"q": np.array([0.0, np.log10(p_top), np.log10(dp)])}, p_lev, p_lay)
+    assert abs(np.sum(q * dlnp) - np.log((p_top + dp) / p_top)) < 1e-12
+    wl = {"cloud_profile": oracle.QPROF_POWER}
+    p_base, alpha = 0.2, 1.7
+    q = oracle.condensate_profile(wl, {"q": np.array([-4.0, np.log10(p_base), alpha])}, p_lev, p_lay)
+    above = p_lev[:-1] <= p_base * oracle.BAR
+    below = p_lev[1:] >= p_base * oracle.BAR
+    np.testing.assert_allclose(q[above], 1e-4 * (p_lay[above] / (p_base * oracle.BAR)) ** alpha, rtol=1e-13)
+    assert np.all(q[below] == 0.0)
+
+
+def test_nongrey_complex_step_matches_central_differences():
+    wl = _nongrey_slice()
+    wl["n_layers"] = 40
+    for b in range(2):
+        th = wl["params"][b]
+        gc = oracle.grad_complex_step(wl, th)
+        gf = oracle.grad_central_fd(wl, th)
+        scale = np.maximum(np.abs(gc), 1e-3 * np.max(np.abs(gc)))
+        assert np.max(np.abs(gc - gf) / scale) < 1e-5, (gc, gf)
