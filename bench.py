@@ -140,10 +140,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=1, choices=(1, 2, 4),
+    ap.add_argument("--config", type=int, default=1, choices=(1, 2, 4, 5),
                     help="1: the JWST-like transmission batch (default); 2: the emission batch (forward); "
-                         "4: the high-resolution ragged batch")
-    ap.add_argument("--batch", type=int, default=None, help="default 1024 (config 1) or 64 (config 4)")
+                         "4: the high-resolution ragged batch; 5: the transmission batch with a non-grey cloud")
+    ap.add_argument("--batch", type=int, default=None, help="default 1024 (configs 1, 2, 5) or 64 (config 4)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", type=str, default=None,
                     help="launch choices a,b,c,d to use instead of autotuning (see exofwd_set_tuning)")
@@ -273,6 +273,9 @@ def main():
     elif cid == 2:
         workload = ("emission, 8 absorbers, 20x20x20000 FP16 tables, 100 layers, 4 Gauss-Legendre angles, "
                     "5-knot PCHIP profile, 400 bins")
+    elif cid == 5:
+        workload = ("jwst-like transmission with a non-grey cloud (power-law condensate profile, fitted Q_ext with "
+                    f"a mid-IR feature), 6 absorbers, 20x20x30000 FP16 tables, 100 layers, 400 bins, {th.shape[1]} params")
     else:
         workload = (f"high-resolution transmission, 4 absorbers, 8x8x400000 FP16 tables, {int(Ls.min())}-{int(Ls.max())} "
                     f"layers per sample, 400 bins, {th.shape[1]} params")
@@ -280,7 +283,8 @@ def main():
         "metric": ("forward+grad spectra/sec at B=1024 (FP32/FP16 vs FP64 plain), max rel err"
                    if mixed["has_grad"] else "forward spectra/sec at B=1024 (FP32/FP16 vs FP64 plain), max rel err")
         if cid == 1 else (f"emission forward spectra/sec at B={B} (FP32/FP16 vs FP64 plain)" if cid == 2 else
-                          f"forward+grad spectra/sec, high-resolution ragged batch B={B} (FP32/FP16)"),
+                          f"forward+grad spectra/sec, non-grey cloud transmission batch B={B} (FP32/FP16)" if cid == 5
+                          else f"forward+grad spectra/sec, high-resolution ragged batch B={B} (FP32/FP16)"),
         "value": round(value, 1), "unit": "spectra/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(mixed["ms_per_step"], 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",

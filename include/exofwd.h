@@ -64,6 +64,14 @@ enum { EXOFWD_PREC_FP64 = 0, EXOFWD_PREC_MIXED = 1 };
 
 enum { EXOFWD_TP_ISOTHERMAL = 0, EXOFWD_TP_GUILLOT3 = 1, EXOFWD_TP_PCHIP = 2 };
 
+/* Cloud models (transmission).  GREY_DECK: a slab from P_cloud down with a
+ * fixed grey opacity kappa_cloud.  NONGREY: a condensate profile q_c(p)
+ * (Eqs. 18-20) and the extinction efficiency Q_ext of an effective particle
+ * size (Eqs. 23-25, 27-29): dtau_cloud = q_c rho dr 3 Q_ext / (4 r_eff). */
+enum { EXOFWD_CLOUD_GREY_DECK = 0, EXOFWD_CLOUD_NONGREY = 1 };
+enum { EXOFWD_QPROF_UNIFORM = 0, EXOFWD_QPROF_SLAB = 1, EXOFWD_QPROF_POWER = 2 };
+enum { EXOFWD_QEXT_FIT = 0, EXOFWD_QEXT_FIT_FEATURE = 1, EXOFWD_QEXT_GREY = 2 };
+
 /* per-sample status bits */
 enum {
   EXOFWD_S_BAD_VMR = 1,      /* sum of absorber mixing ratios >= 1 */
@@ -82,7 +90,15 @@ enum {
  *         pchip       -> [T_0 .. T_{n_knots-1}], knot k at log10 p equally
  *                        spaced from p_top (k = 0) to p_bot
  *   then  log10 X_s for s = 0..n_species-1                       (Eq. 35)
- *   then  log10 P_cloud [bar]   if has_cloud
+ *   then  cloud parameters      if has_cloud:
+ *           GREY_DECK: [log10 P_cloud/bar]
+ *           NONGREY:   [log10 r_eff/um]
+ *                      + [a, log10 Q0]                 unless QEXT_GREY (Eq. 24)
+ *                      + [log10 q]                       (QPROF_UNIFORM, Eq. 18)
+ *                        [log10 q, log10 p_top/bar, log10 dp/bar]   (SLAB, Eq. 19)
+ *                        [log10 q_base, log10 p_base/bar, alpha]    (POWER, Eq. 20)
+ *                      + [A, lambda0/um, log10 omega/um, xi]   if QEXT_FIT_FEATURE
+ *                        (Eqs. 27-29; the window's x0 is 0.5 and Q_max is 2)
  *   then  R_p scale factor      if has_scale  (R_ref = scale * r_p)
  *   then  offset [ppm]          if has_offset (added to bins with offset_mask)
  */
@@ -96,6 +112,9 @@ typedef struct exofwd_config {
   int32_t batch_max;         /* B_max: largest B any call may pass */
   int32_t has_cia, has_rayleigh, has_cloud, has_scale, has_offset;
   int32_t n_mu;              /* emission Gauss-Legendre angles, 1..8 */
+  int32_t cloud_model;       /* EXOFWD_CLOUD_* (has_cloud; NONGREY for transmission only) */
+  int32_t cloud_profile;     /* EXOFWD_QPROF_* (NONGREY) */
+  int32_t cloud_qext;        /* EXOFWD_QEXT_* (NONGREY) */
   double mu_fixed;           /* > 0: fixed mean molecular weight [amu]; else from composition */
   double p_bot_bar, p_top_bar, p_ref_bar;   /* grid bottom/top, reference pressure [bar] */
   double r_p, r_s, g_ref;    /* reference radius [cm], stellar radius [cm], gravity at r_p [cm s^-2] */

@@ -13,9 +13,13 @@ namespace exofwd {
 //   S+1,2   Gc_p  = sum_nu dtau_bar_l t_lp           (CIA pairs H2-H2, H2-He)
 //   S+3     HTc   = sum_nu dtau_bar_l sum_p t_lp dv_lp/dwTc
 //   S+4     GR    = sum_nu dtau_bar_l (nu/1e4)^4
-//   S+5     GD    = sum_nu dtau_bar_l
+//   S+5     GD    = sum_nu dtau_bar_l               (non-grey cloud: sum_nu dtau_bar_l Q_ext(nu))
+// and, with the non-grey cloud (reduced precision), kCloudSpec more:
+//   S+6+k   HQ_k  = sum over a group of layers of D_l sum_nu dtau_bar_l dQ_ext/dp_k,
+//                   stored at the group's first layer and zero at the others
 constexpr int kExtraSums = 6;
 __host__ __device__ constexpr int n_sums(int s) { return s + kExtraSums; }
+__host__ __device__ inline int n_lsums(const Model& m) { return n_sums(m.S) + (m.cloud_ng ? kCloudSpec : 0); }
 
 // shapes of the reduced-precision reverse kernel: wavenumber tile x 32-row blocks
 enum : int { kAdjT128M4 = 0, kAdjT64M4 = 1, kAdjT64M5 = 2, kAdjVariants = 3 };
@@ -35,7 +39,7 @@ struct AdjWork {
   // reduced-precision path: the fused kernel stores dtau_bar, a second kernel forms the layer sums
   float* dtau;         // [B_max][L_pad][n_nu_pad] layer optical depths stored by the forward kernel
   float* dtb;          // [B_max][L_pad][n_nu_pad] d lnL / d dtau_l(nu)
-  float* lsum;         // [B_max][lsum_chunks][L_pad][n_sums] partial layer sums
+  float* lsum;         // [B_max][lsum_chunks][L_pad][n_lsums] partial layer sums
   int lsum_chunks;     // wavenumber chunks of the layer-sum kernel (n_tiles / ls_tiles, rounded up)
   int lsum_stride;     // allocated chunks per sample (the bound over the ls_tiles choices)
 };
@@ -51,7 +55,7 @@ void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const Ad
 void launch_chain(const Model& m, const Work& w, const AdjWork& aw, int B, const double* params, const uint8_t* mask,
                   double* grad, bool fp64, hipStream_t st);
 // whether the adjoint supports this workload (transmission, no PCHIP profile,
-// L_pad <= 160 in reduced precision, <= 128 in FP64)
+// L_pad <= 160 in reduced precision, <= 128 and no non-grey cloud in FP64)
 bool adjoint_supported(const Model& m, bool fp64);
 // default reverse-kernel shape, whether a shape serves this model, and switching shapes
 int adjoint_default_variant(const Model& m);

@@ -16,6 +16,7 @@
 // cloud deck and the T-p profile to d lnL / d params.
 #include "adjoint.h"
 #include "kernels.h"
+#include "cloud.h"
 #include "opacity.h"
 
 namespace exofwd {
@@ -383,9 +384,10 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
 // and are reduced over the wave once
 constexpr int kLsLayers = 5;
 
-template <int S, bool CIA>
+template <int S, bool CIA, bool NGC>
 __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Tables tb, AdjWork aw, int B) {
   constexpr int NS = n_sums(S);
+  constexpr int NT = NS + (NGC ? kCloudSpec : 0);   // stride of the stored sums
   const int lane = threadIdx.x & 63;
   const int gw = blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int NG = (m.L_max + kLsLayers - 1) / kLsLayers;
@@ -417,11 +419,21 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
   for (int q = 0; q < kLsLayers; ++q)
 #pragma unroll
     for (int k = 0; k < NS; ++k) acc[q][k] = 0.0f;
+  // non-grey cloud: Q_ext at the lane's two wavenumbers weights the cloud sum;
+  // hq accumulates sum_nu (sum_q D_q dtau_bar_q) dQ/dp_k over the group
+  float hq[NGC ? kCloudSpec : 1] = {};
+  const float* cq = NGC ? w.cloud_q + (size_t)b * (1 + kCloudSpec) * npad : nullptr;
 
   const int t0 = chunk * aw.ls_tiles, t1 = min(t0 + aw.ls_tiles, m.n_tiles);
   for (int tile = t0; tile < t1; ++tile) {
     const int nu0 = tile * kTileNu;
     const LaneConst<S> kc = load_lane<S, CIA>(m, tb, nu0 + 2 * lane);
+    float q0 = 1.0f, q1 = 1.0f, g0 = 0.0f, g1 = 0.0f;
+    if constexpr (NGC) {
+      const float2 q = *reinterpret_cast<const float2*>(cq + nu0 + 2 * lane);
+      q0 = q.x;
+      q1 = q.y;
+    }
 #pragma unroll
     for (int q = 0; q < kLsLayers; ++q) {
       const int l = l0 + q;
@@ -451,10 +463,23 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
         acc[q][S + 3] = fmaf(db.x, y0, fmaf(db.y, y1, acc[q][S + 3]));
       }
       acc[q][S + 4] = fmaf(db.x, kc.nu4_0, fmaf(db.y, kc.nu4_1, acc[q][S + 4]));
-      acc[q][S + 5] += db.x + db.y;
+      if constexpr (NGC) {
+        acc[q][S + 5] = fmaf(db.x, q0, fmaf(db.y, q1, acc[q][S + 5]));
+        g0 = fmaf(c.D, db.x, g0);
+        g1 = fmaf(c.D, db.y, g1);
+      } else {
+        acc[q][S + 5] += db.x + db.y;
+      }
+    }
+    if constexpr (NGC) {
+#pragma unroll
+      for (int k = 0; k < kCloudSpec; ++k) {
+        const float2 d = *reinterpret_cast<const float2*>(cq + (size_t)(1 + k) * npad + nu0 + 2 * lane);
+        hq[k] = fmaf(g0, d.x, fmaf(g1, d.y, hq[k]));
+      }
     }
   }
-  float* out = aw.lsum + ((size_t)b * aw.lsum_stride + chunk) * Lp * NS;
+  float* out = aw.lsum + ((size_t)b * aw.lsum_stride + chunk) * Lp * NT;
 #pragma unroll
   for (int q = 0; q < kLsLayers; ++q) {
     const int l = l0 + q;
@@ -462,7 +487,14 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const float tot = wave_sum(acc[q][k]);
-      if (lane == 0) out[(size_t)l * NS + k] = tot;
+      if (lane == 0) out[(size_t)l * NT + k] = tot;
+    }
+    if constexpr (NGC) {
+#pragma unroll
+      for (int k = 0; k < kCloudSpec; ++k) {
+        const float tot = q == 0 ? wave_sum(hq[k]) : 0.0f;
+        if (lane == 0) out[(size_t)l * NT + NS + k] = tot;
+      }
     }
   }
 }
@@ -703,6 +735,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
   const int b = blockIdx.x, tid = threadIdx.x;
   const int Lp = m.L_pad;
   const int NS = n_sums(m.S);
+  const int NT = sizeof(PbarT) == 8 ? NS : n_lsums(m);   // stride of the stored layer sums
   double* gout = grad + (size_t)b * m.P;
   if (w.status[b]) {
     for (int k = tid; k < m.P; k += kBlock) gout[k] = 0.0;
@@ -741,6 +774,18 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
   auto logp_lev = [&](int j) { return j == L ? m.log10_ptop : m.log10_pbot + j * step; };
   const double rs2 = m.r_s * m.r_s;
   const double log10_pc = m.has_cloud ? th[m.idx_cloud] : 0.0;
+  // non-grey cloud: D_l = q_l rho_l dr_l 3 / (4 r_eff); profile parameters start at q_first
+  const int q_first = m.idx_cloud + (m.cloud_qext == kQextGrey ? 1 : 3);
+  const double r_eff = m.cloud_ng ? 1.0e-4 * exp10(th[m.idx_cloud]) : 1.0;
+  auto layer_sum = [&](int l, int k) {
+    double v = 0.0;
+    if constexpr (sizeof(PbarT) == 8) {
+      for (int c = 0; c < Cn; ++c) v += aw.layer_sums[(((size_t)b * C + c) * Lp + l) * NS + k];
+    } else {
+      for (int c = 0; c < aw.lsum_chunks; ++c) v += (double)aw.lsum[(((size_t)b * aw.lsum_stride + c) * Lp + l) * NT + k];
+    }
+    return v;
+  };
   __syncthreads();
 
   // per-layer sums reduced over chunks, and the per-layer chain through
@@ -751,22 +796,17 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
   for (int k = 0; k < NR; ++k) s_red[k * kBlock + tid] = 0.0;
   for (int l = tid; l < L; l += kBlock) {
     double sm[kMaxSpecies + kExtraSums];
-    for (int k = 0; k < NS; ++k) {
-      double v = 0.0;
-      if constexpr (sizeof(PbarT) == 8) {
-        for (int c = 0; c < Cn; ++c) v += aw.layer_sums[(((size_t)b * C + c) * Lp + l) * NS + k];
-      } else {
-        for (int c = 0; c < aw.lsum_chunks; ++c) v += (double)aw.lsum[(((size_t)b * aw.lsum_stride + c) * Lp + l) * NS + k];
-      }
-      sm[k] = v;
-    }
+    for (int k = 0; k < NS; ++k) sm[k] = layer_sum(l, k);
     const double t = s_t[l];
     const double lp_bar = 0.5 * (logp_lev(l) + logp_lev(l + 1));
     const double n = exp10(lp_bar) * kBar / (kB * t);
     const double dr = s_r[l + 1] - s_r[l];
     const double rr = (m.has_ray ? n * (xh2 * m.ray_h2 + xhe * m.ray_he) * dr : 0.0);
     double f = 0.0, dd = 0.0;
-    if (m.has_cloud) {
+    if (m.cloud_ng) {
+      dd = condensate_q(m.cloud_profile, th + q_first, logp_lev(l), logp_lev(l + 1), lp_bar, nullptr) * mu * kMu * n *
+           dr * 0.75 / r_eff;
+    } else if (m.has_cloud) {
       f = (logp_lev(l) - log10_pc) * ln10 / dlnp;
       f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
       dd = m.kappa_cloud * mu * kMu * n * f * dr;
@@ -803,13 +843,35 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
     s_red[(m.S + 2) * kBlock + tid] += gr * n * dr * m.ray_h2;
     s_red[(m.S + 3) * kBlock + tid] += gr * n * dr * m.ray_he;
     s_red[(m.S + 4) * kBlock + tid] += gd * dd;
-    if (m.has_cloud && f > 0.0 && f < 1.0)
+    if (m.has_cloud && !m.cloud_ng && f > 0.0 && f < 1.0)
       s_red[(m.S + 5) * kBlock + tid] += gd * m.kappa_cloud * mu * kMu * n * dr * (-ln10 / dlnp);
   }
   block_sum(s_red, tid, NR);
   double chem[kMaxSpecies + 6];
   for (int k = 0; k < NR; ++k) chem[k] = s_red[k * kBlock];
   __syncthreads();
+
+  // non-grey cloud parameters: rows [0, kCloudSpec) the spectral parameters
+  // (log10 r also through the column's 1/r_eff), then the three profile parameters
+  __shared__ double s_cloud[kCloudSpec + 3];
+  if (m.cloud_ng) {
+    constexpr int NC = kCloudSpec + 3;
+    for (int k = 0; k < NC; ++k) s_red[k * kBlock + tid] = 0.0;
+    for (int l = tid; l < L; l += kBlock) {
+      const double gd = layer_sum(l, m.S + 5);
+      for (int k = 0; k < kCloudSpec; ++k) s_red[k * kBlock + tid] += layer_sum(l, NS + k);
+      const double lp_bar = 0.5 * (logp_lev(l) + logp_lev(l + 1));
+      const double n = exp10(lp_bar) * kBar / (kB * s_t[l]);
+      const double col = mu * kMu * n * (s_r[l + 1] - s_r[l]) * 0.75 / r_eff;
+      double dq[3];
+      const double q = condensate_q(m.cloud_profile, th + q_first, logp_lev(l), logp_lev(l + 1), lp_bar, dq);
+      s_red[tid] -= ln10 * gd * q * col;
+      for (int k = 0; k < 3; ++k) s_red[(kCloudSpec + k) * kBlock + tid] += gd * col * dq[k];
+    }
+    block_sum(s_red, tid, NC);
+    if (tid < NC) s_cloud[tid] = s_red[tid * kBlock];
+    __syncthreads();
+  }
 
   // path-matrix adjoint: column pass (r_l, r_{l+1}) and row pass (b_i)
   const PbarT* pbar = reinterpret_cast<const PbarT*>(aw.pbar);
@@ -936,7 +998,17 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
       const double xb = chem[s] / x[s] + mu_bar * m.mass[s] - xh2_bar / (1.0 + kHeH2);
       gout[m.n_tp + s] = xb * x[s] * ln10;
     }
-    if (m.has_cloud) gout[m.idx_cloud] = chem[m.S + 5];
+    if (m.has_cloud && !m.cloud_ng) gout[m.idx_cloud] = chem[m.S + 5];
+    if (m.cloud_ng) {
+      // theta order: log10 r, [a, log10 Q0], profile (1 or 3), [A, lambda0, log10 omega, xi]
+      int k = m.idx_cloud;
+      gout[k++] = s_cloud[0];
+      if (m.cloud_qext != kQextGrey) { gout[k++] = s_cloud[1]; gout[k++] = s_cloud[2]; }
+      const int np = m.cloud_profile == kQprofUniform ? 1 : 3;
+      for (int j = 0; j < np; ++j) gout[k++] = s_cloud[kCloudSpec + j];
+      if (m.cloud_qext == kQextFeature)
+        for (int j = 3; j < kCloudSpec; ++j) gout[k++] = s_cloud[j];
+    }
     if (m.has_scale) gout[m.idx_scale] = s_scal[0] * m.r_p;
     if (m.has_offset) {
       double o = 0.0;
@@ -997,7 +1069,7 @@ int adjoint_chunks(const Model& m, const AdjWork& aw, int B, bool fp64) {
 }
 
 bool adjoint_supported(const Model& m, bool fp64) {
-  return m.mode == kTransmission && m.tp_kind != kTpPchip && m.L_pad <= (fp64 ? 128 : 160);
+  return m.mode == kTransmission && m.tp_kind != kTpPchip && m.L_pad <= (fp64 ? 128 : 160) && !(fp64 && m.cloud_ng);
 }
 
 int adjoint_default_variant(const Model& m) { return m.L_pad <= 128 ? kAdjT128M4 : kAdjT64M5; }
@@ -1039,7 +1111,7 @@ bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std:
   aw.lsum_chunks = (m.n_tiles + aw.ls_tiles - 1) / aw.ls_tiles;
   aw.dtb = (float*)alloc((size_t)B_max * m.L_pad * m.n_nu_pad * sizeof(float));
   aw.dtau = (float*)alloc((size_t)B_max * m.L_pad * m.n_nu_pad * sizeof(float));
-  aw.lsum = (float*)alloc((size_t)B_max * aw.lsum_stride * Lp * n_sums(m.S) * sizeof(float));
+  aw.lsum = (float*)alloc((size_t)B_max * aw.lsum_stride * Lp * n_lsums(m) * sizeof(float));
   return aw.dtb && aw.dtau && aw.lsum;
 }
 
@@ -1078,9 +1150,11 @@ const void* adj_kernel_for(int S, bool cia, int variant) {
   return nullptr;
 }
 
-const void* ls_kernel_for(int S, bool cia) {
+const void* ls_kernel_for(int S, bool cia, bool ng) {
 #define EXOFWD_CASE(n) \
-  case n: return cia ? (const void*)k_layer_sums_mixed<n, true> : (const void*)k_layer_sums_mixed<n, false>;
+  case n:                                                                                          \
+    return ng ? (cia ? (const void*)k_layer_sums_mixed<n, true, true> : (const void*)k_layer_sums_mixed<n, false, true>) \
+              : (cia ? (const void*)k_layer_sums_mixed<n, true, false> : (const void*)k_layer_sums_mixed<n, false, false>);
   switch (S) {
     EXOFWD_CASE(1) EXOFWD_CASE(2) EXOFWD_CASE(3) EXOFWD_CASE(4)
     EXOFWD_CASE(5) EXOFWD_CASE(6) EXOFWD_CASE(7) EXOFWD_CASE(8)
@@ -1138,7 +1212,7 @@ void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const Ad
   const int NG = (m.L_max + kLsLayers - 1) / kLsLayers;
   const long waves = (long)aw.lsum_chunks * B * NG;
   void* args2[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&aw, (void*)&B};
-  hipLaunchKernel(ls_kernel_for(m.S, m.has_cia), dim3((unsigned)((waves + 3) / 4)), dim3(kBlock), args2, 0, st);
+  hipLaunchKernel(ls_kernel_for(m.S, m.has_cia, m.cloud_ng), dim3((unsigned)((waves + 3) / 4)), dim3(kBlock), args2, 0, st);
 }
 
 void launch_chain(const Model& m, const Work& w, const AdjWork& aw, int B, const double* params, const uint8_t* mask,

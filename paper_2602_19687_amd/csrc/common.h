@@ -29,7 +29,9 @@ constexpr int kBlockT = 512;      // threads per workgroup of the reduced-precis
 // per-layer record of the opacity kernels (one per sample and layer)
 //   [0] wT, [1] wP, [2] wTc, [3] Rayleigh coefficient R_l (x (nu/1e4)^4),
 //   [4] cloud term D_l, [5] lam_c1, [6] lam_c2, [7..7+S) lam_s
-// with lam = log2 of the per-layer prefactor (n X dr, n^2 X X dr)
+// with lam = log2 of the per-layer prefactor (n X dr, n^2 X X dr).  D_l is the
+// grey deck's optical depth, or for the non-grey cloud the layer's column
+// q_l rho_l dr_l 3 / (4 r_eff) that multiplies Q_ext(nu).
 constexpr int kRecFixed = 7;
 __host__ __device__ constexpr int rec_len(int s) { return kRecFixed + s; }
 
@@ -39,6 +41,9 @@ __host__ __device__ inline int pack_cells(int it, int ip, int itc) { return it |
 enum : int { kTransmission = 0, kEmission = 1 };
 enum : int { kFP64 = 0, kMixed = 1 };
 enum : int { kTpIso = 0, kTpGuillot3 = 1, kTpPchip = 2 };
+enum : int { kQprofUniform = 0, kQprofSlab = 1, kQprofPower = 2 };
+enum : int { kQextFit = 0, kQextFeature = 1, kQextGrey = 2 };
+constexpr int kCloudSpec = 7;   // spectral cloud parameters: log10 r, a, log10 Q0, A, lambda0, log10 omega, xi
 enum : int { kBadVmr = 1, kUnbound = 2, kNonfinite = 4, kBadT = 8, kBadLayers = 16 };
 
 // Everything a kernel needs to know about the workload (by value).
@@ -48,6 +53,8 @@ struct Model {
   int n_nu, n_nu_pad, n_tiles, n_tiles64, n_t, n_p, n_tc, K;
   int idx_cloud, idx_scale, idx_offset, n_tp;
   int fwd_tile_major;       // reduced-precision forward grid order: 0 samples fastest, 1 tiles fastest
+  int cloud_ng;             // 1: non-grey cloud (q_c profile x Q_ext(nu)); 0: grey deck or none
+  int cloud_profile, cloud_qext, n_cloud;   // kQprof*, kQext*, cloud parameters in theta
   double mu_fixed, log10_pbot, log10_ptop, p_ref, r_p, r_s, g_ref;
   double kappa_ir, f_hem, kappa_cloud, t_star, dilution, err_c, ray_h2, ray_he;
   double mass[kMaxSpecies];
@@ -66,6 +73,8 @@ struct Work {
   double* t_lev;        // [B][L_pad+1]
   double* r_lev;        // [B][L_pad+1]
   double* core;         // [B] r_0^2 / R_s^2
+  double* cloud;        // [B][kCloudSpec] non-grey cloud: r_eff [cm], a, Q0, A, lambda0 [um], omega [um], xi
+  float* cloud_q;       // reduced precision, non-grey: [B][1 + kCloudSpec][n_nu_pad] Q_ext(nu), dQ_ext/dp_k
   int32_t* cells;       // [B][L_pad] packed cells
   void* rec;            // [B][L_pad][rec_len] float (mixed) or double (fp64)
   void* area;           // [B][L_pad] (r_{i+1}^2 - r_i^2)/R_s^2, float or double

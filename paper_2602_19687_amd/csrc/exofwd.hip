@@ -238,6 +238,13 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   if (!(g.p_bot_bar > g.p_top_bar) || !(g.p_top_bar > 0.0) || !(g.p_ref_bar > 0.0)) return EXOFWD_ERR_CONFIG;
   if (!(g.r_p > 0.0) || !(g.r_s > 0.0) || !(g.g_ref > 0.0)) return EXOFWD_ERR_CONFIG;
   if (g.mode == EXOFWD_EMISSION && (g.n_mu < 1 || g.n_mu > kMaxMu || !(g.t_star > 0.0))) return EXOFWD_ERR_CONFIG;
+  if (g.has_cloud) {
+    if (g.cloud_model != EXOFWD_CLOUD_GREY_DECK && g.cloud_model != EXOFWD_CLOUD_NONGREY) return EXOFWD_ERR_CONFIG;
+    if (g.cloud_model == EXOFWD_CLOUD_NONGREY &&
+        (g.mode != EXOFWD_TRANSMISSION || g.cloud_profile < EXOFWD_QPROF_UNIFORM || g.cloud_profile > EXOFWD_QPROF_POWER ||
+         g.cloud_qext < EXOFWD_QEXT_FIT || g.cloud_qext > EXOFWD_QEXT_GREY))
+      return EXOFWD_ERR_CONFIG;
+  }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || g.device < 0 || g.device >= ndev) return EXOFWD_ERR_DEVICE;
 
@@ -259,6 +266,14 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   m.has_cia = g.has_cia ? 1 : 0;
   m.has_ray = g.has_rayleigh ? 1 : 0;
   m.has_cloud = g.has_cloud ? 1 : 0;
+  m.cloud_ng = (g.has_cloud && g.cloud_model == EXOFWD_CLOUD_NONGREY) ? 1 : 0;
+  m.cloud_profile = m.cloud_ng ? g.cloud_profile : 0;
+  m.cloud_qext = m.cloud_ng ? g.cloud_qext : 0;
+  // non-grey: [log10 r] + [a, log10 Q0] (fitted Q) + profile (1 or 3) + feature (4)
+  m.n_cloud = !m.has_cloud ? 0
+              : !m.cloud_ng ? 1
+                            : (m.cloud_qext == kQextGrey ? 1 : 3) + (m.cloud_profile == kQprofUniform ? 1 : 3) +
+                                  (m.cloud_qext == kQextFeature ? 4 : 0);
   m.has_scale = g.has_scale ? 1 : 0;
   m.has_offset = g.has_offset ? 1 : 0;
   m.n_mu = g.mode == EXOFWD_EMISSION ? g.n_mu : 0;
@@ -272,7 +287,8 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   m.K = g.n_bins;
   m.n_tp = g.tp_kind == EXOFWD_TP_ISOTHERMAL ? 1 : (g.tp_kind == EXOFWD_TP_GUILLOT3 ? 3 : g.n_knots);
   int k = m.n_tp + m.S;
-  m.idx_cloud = m.has_cloud ? k++ : -1;
+  m.idx_cloud = m.has_cloud ? k : -1;
+  k += m.n_cloud;
   m.idx_scale = m.has_scale ? k++ : -1;
   m.idx_offset = m.has_offset ? k++ : -1;
   m.P = k;
@@ -396,6 +412,9 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   w.t_lev = A(dalloc<double>(c, (size_t)B * (Lp + 1)));
   w.r_lev = A(dalloc<double>(c, (size_t)B * (Lp + 1)));
   w.core = A(dalloc<double>(c, B));
+  w.cloud = A(dalloc<double>(c, (size_t)B * kCloudSpec));
+  if (m.cloud_ng && g.precision == EXOFWD_PREC_MIXED)
+    w.cloud_q = A(dalloc<float>(c, (size_t)B * (1 + kCloudSpec) * m.n_nu_pad));
   w.cells = A(dalloc<int32_t>(c, (size_t)B * Lp));
   w.rec = A(dalloc<unsigned char>(c, (size_t)B * Lp * RL * rs));
   w.area = A(dalloc<unsigned char>(c, (size_t)B * Lp * rs));
@@ -658,7 +677,17 @@ std::vector<double> neutral_params(const Model& m) {
   else if (m.tp_kind == kTpGuillot3) { th[0] = 500.0; th[1] = 1200.0; th[2] = 0.0; }
   else for (int k = 0; k < m.n_tp; ++k) th[k] = 1200.0;
   for (int s2 = 0; s2 < m.S; ++s2) th[m.n_tp + s2] = -6.0;
-  if (m.has_cloud) th[m.idx_cloud] = m.log10_pbot + 1.0;
+  if (m.has_cloud && !m.cloud_ng) th[m.idx_cloud] = m.log10_pbot + 1.0;
+  if (m.cloud_ng) {
+    // thin haze of 1 um particles over the whole column (every cloud term still evaluated)
+    int k = m.idx_cloud;
+    th[k++] = 0.0;
+    if (m.cloud_qext != kQextGrey) { th[k++] = 4.0; th[k++] = 1.0; }
+    th[k++] = -8.0;
+    if (m.cloud_profile == kQprofSlab) { th[k++] = m.log10_ptop; th[k++] = m.log10_pbot; }
+    else if (m.cloud_profile == kQprofPower) { th[k++] = m.log10_pbot; th[k++] = 1.0; }
+    if (m.cloud_qext == kQextFeature) { th[k++] = 0.5; th[k++] = 10.0; th[k++] = 0.0; th[k++] = 0.0; }
+  }
   if (m.has_scale) th[m.idx_scale] = 1.0;
   if (m.has_offset) th[m.idx_offset] = 0.0;
   return th;
@@ -669,7 +698,7 @@ std::string tuning_key(const exofwd_ctx* c, int B) {
   hipGetDeviceProperties(&prop, c->device);
   std::ostringstream k;
   k << prop.gcnArchName << "/cu" << prop.multiProcessorCount << " mode" << c->m.mode << " prec" << c->precision
-    << " S" << c->m.S << " cia" << c->m.has_cia << " Lpad" << c->m.L_pad << " Lmax" << c->m.L_max << " nu"
+    << " S" << c->m.S << " cia" << c->m.has_cia << " ng" << c->m.cloud_ng << " Lpad" << c->m.L_pad << " Lmax" << c->m.L_max << " nu"
     << c->m.n_nu_pad << " tab" << c->m.n_t << "x" << c->m.n_p << " B" << B;
   std::string key = k.str();
   for (char& ch : key)

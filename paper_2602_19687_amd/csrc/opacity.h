@@ -6,7 +6,8 @@
 //   dtau = D + R nu4 + sum_s 2^(c_s + bilinear(h_s) + lam_s) + sum_pairs 2^(c_p + lerp_T(h_p) + lam_p)
 // with FP16 table entries h = log2 sigma - c (c per source and wavenumber),
 // bilinear weights in (T, log p), lam = log2 of the layer prefactor
-// (n X dr for lines, n^2 X X dr for CIA), R the Rayleigh and D the cloud term.
+// (n X dr for lines, n^2 X X dr for CIA), R the Rayleigh and D the cloud term
+// (the non-grey cloud's D is a column that multiplies Q_ext(nu)).
 #pragma once
 #include "common.h"
 
@@ -99,15 +100,22 @@ __device__ inline half2_t load_h2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint3
   return __builtin_bit_cast(half2_t, (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 
-// Optical depth of one layer at two wavenumbers: Rayleigh + grey cloud, the
+// Optical depth of one layer at two wavenumbers: Rayleigh + cloud, the
 // VMR-weighted line terms (bilinear in T and log p of the log2 tables) and the
 // CIA pair terms (linear in T).
-template <int S, bool CIA>
+// With the non-grey cloud (NGC) D is the layer's cloud column and q0, q1 the
+// extinction efficiency Q_ext at the two wavenumbers.
+template <int S, bool CIA, bool NGC = false>
 __device__ inline void layer_terms(const LayerCoef<S>& c, const LaneConst<S>& k, const TableGeom& g,
                                    __amdgpu_buffer_rsrc_t rh, __amdgpu_buffer_rsrc_t rhc, uint32_t voff,
-                                   float& d0, float& d1) {
-  d0 = fmaf(c.R, k.nu4_0, c.D);
-  d1 = fmaf(c.R, k.nu4_1, c.D);
+                                   float& d0, float& d1, float q0 = 1.0f, float q1 = 1.0f) {
+  if constexpr (NGC) {
+    d0 = fmaf(c.D, q0, c.R * k.nu4_0);
+    d1 = fmaf(c.D, q1, c.R * k.nu4_1);
+  } else {
+    d0 = fmaf(c.R, k.nu4_0, c.D);
+    d1 = fmaf(c.R, k.nu4_1, c.D);
+  }
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const half2_t h00 = load_h2(rh, voff, c.row[s]);

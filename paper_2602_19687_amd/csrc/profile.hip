@@ -1,6 +1,7 @@
 // Per-sample atmospheric profile in FP64: T-p profile, free chemistry,
 // hydrostatic altitudes, per-layer opacity records, path matrix and annulus
 // areas.  One workgroup of 256 threads per sample.
+#include "cloud.h"
 #include "kernels.h"
 
 namespace exofwd {
@@ -228,6 +229,21 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
   Real* rec = reinterpret_cast<Real*>(w.rec) + (size_t)b * Lp * RL;
   Real* area = reinterpret_cast<Real*>(w.area) + (size_t)b * Lp;
   const double log10_pc = m.has_cloud ? th[m.idx_cloud] : 0.0;
+  // non-grey cloud: per-sample constants of Q_ext and where the profile's parameters start
+  const int q_first = m.idx_cloud + (m.cloud_qext == kQextGrey ? 1 : 3);
+  const double r_eff = m.cloud_ng ? 1.0e-4 * exp10(th[m.idx_cloud]) : 1.0;
+  if (m.cloud_ng && tid == 0) {
+    double* cl = w.cloud + (size_t)b * kCloudSpec;
+    const bool fit = m.cloud_qext != kQextGrey, feat = m.cloud_qext == kQextFeature;
+    const int f0 = q_first + (m.cloud_profile == kQprofUniform ? 1 : 3);
+    cl[0] = r_eff;
+    cl[1] = fit ? th[m.idx_cloud + 1] : 0.0;
+    cl[2] = fit ? exp10(th[m.idx_cloud + 2]) : 0.0;
+    cl[3] = feat ? th[f0] : 0.0;
+    cl[4] = feat ? th[f0 + 1] : 1.0;
+    cl[5] = feat ? exp10(th[f0 + 2]) : 1.0;
+    cl[6] = feat ? th[f0 + 3] : 0.0;
+  }
   for (int l = tid; l < Lp; l += kBlock) {
     Real* rl = rec + (size_t)l * RL;
     if (l >= L) {
@@ -254,7 +270,11 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
     const bool trans = m.mode == kTransmission;
     rl[3] = Real((trans && m.has_ray) ? n * (xh2 * m.ray_h2 + xhe * m.ray_he) * dr : 0.0);
     double dcl = 0.0;
-    if (trans && m.has_cloud) {
+    if (m.cloud_ng) {
+      // column q_l rho_l dr_l 3 / (4 r_eff); the kernels multiply it by Q_ext(nu) (Eq. 23)
+      dcl = condensate_q(m.cloud_profile, th + q_first, logp_lev(l), logp_lev(l + 1), lp_bar, nullptr) * mu * kMu *
+            n * dr * 0.75 / r_eff;
+    } else if (trans && m.has_cloud) {
       double f = (logp_lev(l) - log10_pc) * 2.302585092994045684017991454684 / dlnp;
       f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
       dcl = m.kappa_cloud * mu * kMu * n * f * dr;
@@ -308,12 +328,31 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
   }
 }
 
+// Non-grey cloud, reduced precision: Q_ext and its derivatives once per (sample,
+// wavenumber), read by the forward kernel (Q_ext) and the layer sums (both).
+// One thread per wavenumber; grid (n_nu_pad / kBlock, B).
+__global__ __launch_bounds__(kBlock) void k_cloud_q(Model m, Work w) {
+  const int b = blockIdx.y;
+  const int nu = blockIdx.x * kBlock + threadIdx.x;
+  if (nu >= m.n_nu_pad || w.status[b]) return;
+  float dq[kCloudSpec];
+  const float q = cloud_q<float>(m.cloud_qext, load_cloud<float>(w.cloud + (size_t)b * kCloudSpec), (float)m.nu[nu], dq);
+  float* out = w.cloud_q + (size_t)b * (1 + kCloudSpec) * m.n_nu_pad + nu;
+  out[0] = q;
+#pragma unroll
+  for (int k = 0; k < kCloudSpec; ++k) out[(size_t)(1 + k) * m.n_nu_pad] = dq[k];
+}
+
 void launch_profile(const Model& m, const Work& w, int B, const double* params, const int32_t* n_layers,
                     bool fp64, hipStream_t st) {
-  if (fp64)
+  if (fp64) {
     hipLaunchKernelGGL(k_profile<double>, dim3(B), dim3(kBlock), 0, st, m, w, params, n_layers);
-  else
+  } else {
     hipLaunchKernelGGL(k_profile<float>, dim3(B), dim3(kBlock), 0, st, m, w, params, n_layers);
+    if (m.cloud_ng)
+      hipLaunchKernelGGL(k_cloud_q, dim3((unsigned)((m.n_nu_pad + kBlock - 1) / kBlock), (unsigned)B), dim3(kBlock), 0,
+                         st, m, w);
+  }
 }
 
 }  // namespace exofwd

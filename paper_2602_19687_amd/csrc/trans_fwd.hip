@@ -10,6 +10,7 @@
 // (hi*hi + hi*lo + lo*hi, FP32 accumulation).
 // FP64 instance (256 threads, 64 wavenumbers per tile): FP64 tables and
 // arithmetic, chord product on the FP64 VALU.
+#include "cloud.h"
 #include "kernels.h"
 #include "opacity.h"
 
@@ -33,7 +34,7 @@ __device__ inline unsigned mblocks_for(int part, int MBe, int KBe) {
   return mine;
 }
 
-template <int S, bool CIA>
+template <int S, bool CIA, bool NGC>
 __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Tables tb, int B, float* __restrict__ spec,
                                                               float* __restrict__ dtau_out) {
   extern __shared__ __align__(16) unsigned char lds[];
@@ -74,6 +75,12 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
                                                CIA ? (size_t)2 * m.n_tc * npad * 2 : 0);
   const uint32_t voff = (uint32_t)lane * 4u;
   const LaneConst<S> kc = load_lane<S, CIA>(m, tb, nu0 + 2 * lane);
+  float q0 = 1.0f, q1 = 1.0f;
+  if constexpr (NGC) {
+    const float2 q = *reinterpret_cast<const float2*>(w.cloud_q + (size_t)b * (1 + kCloudSpec) * npad + nu0 + 2 * lane);
+    q0 = q.x;
+    q1 = q.y;
+  }
   const int KBe = (L + 15) >> 4;
   for (int o = wv; o < 2 * KBe; o += kBlockT / 64) {
     float e0[8], e1[8];
@@ -83,7 +90,7 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
       float d0 = 0.0f, d1 = 0.0f;
       if (l < L) {
         const LayerCoef<S> c = load_layer<S>(m, cells, rec, l, (uint32_t)nu0 * 2u, g);
-        layer_terms<S, CIA>(c, kc, g, rh, rhc, voff, d0, d1);
+        layer_terms<S, CIA, NGC>(c, kc, g, rh, rhc, voff, d0, d1, q0, q1);
         d0 = fminf(d0, 16384.0f);
         d1 = fminf(d1, 16384.0f);
         // the reverse pass reads the layer optical depths back instead of recomputing them
@@ -153,11 +160,11 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
 // FP64 element: bilinear log10 sigma, 2^(v log2 10 + lam)
 template <int S, bool CIA>
 __device__ inline double opacity_fp64(const Model& m, const Tables& tb, int cl, const double* __restrict__ rl, int nu,
-                                      double nu4) {
+                                      double nu4, double qext) {
   const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
   const double wt = rl[0], wp = rl[1];
   const size_t npad = (size_t)m.n_nu_pad;
-  double acc = rl[3] * nu4 + rl[4];
+  double acc = rl[3] * nu4 + rl[4] * qext;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const double* p = tb.t64 + (((size_t)s * m.n_t + it) * m.n_p + ip) * npad + nu;
@@ -197,8 +204,12 @@ __global__ __launch_bounds__(kBlock) void k_trans_fwd_fp64(Model m, Work w, Tabl
   const int32_t* cells = w.cells + (size_t)b * Lp;
   const int nu = nu0 + lane;
   const double nu4 = tb.nu4d[nu];
+  // grey deck: the record holds the optical depth; non-grey: the column times Q_ext(nu)
+  const double qext =
+      m.cloud_ng ? cloud_q<double>(m.cloud_qext, load_cloud<double>(w.cloud + (size_t)b * kCloudSpec), m.nu[nu], nullptr)
+                 : 1.0;
   for (int l = wv; l < L; l += 4)
-    s_dt[l * kTile64 + lane] = opacity_fp64<S, CIA>(m, tb, cells[l], rec + (size_t)l * rec_len(S), nu, nu4);
+    s_dt[l * kTile64 + lane] = opacity_fp64<S, CIA>(m, tb, cells[l], rec + (size_t)l * rec_len(S), nu, nu4, qext);
   __syncthreads();
   const double* pm = w.pm64 + (size_t)b * Lp * Lp;
   const double* area = reinterpret_cast<const double*>(w.area) + (size_t)b * Lp;
@@ -220,15 +231,15 @@ __global__ __launch_bounds__(kBlock) void k_trans_fwd_fp64(Model m, Work w, Tabl
 // ---------------------------------------------------------------------------
 // host side: one instance per (species count, CIA present)
 template <bool F64, int S, bool CIA>
-const void* fwd_kernel() {
+const void* fwd_kernel(bool ng) {
   if constexpr (F64) return (const void*)k_trans_fwd_fp64<S, CIA>;
-  else return (const void*)k_trans_fwd_mixed<S, CIA>;
+  else return ng ? (const void*)k_trans_fwd_mixed<S, CIA, true> : (const void*)k_trans_fwd_mixed<S, CIA, false>;
 }
 
 template <bool F64>
-const void* fwd_kernel_for(int S, bool cia) {
+const void* fwd_kernel_for(int S, bool cia, bool ng) {
 #define EXOFWD_CASE(n) \
-  case n: return cia ? fwd_kernel<F64, n, true>() : fwd_kernel<F64, n, false>();
+  case n: return cia ? fwd_kernel<F64, n, true>(ng) : fwd_kernel<F64, n, false>(ng);
   switch (S) {
     EXOFWD_CASE(1) EXOFWD_CASE(2) EXOFWD_CASE(3) EXOFWD_CASE(4)
     EXOFWD_CASE(5) EXOFWD_CASE(6) EXOFWD_CASE(7) EXOFWD_CASE(8)
@@ -243,7 +254,7 @@ size_t trans_fwd_lds_bytes(const Model& m, bool fp64) {
 }
 
 hipError_t trans_fwd_configure(const Model& m, bool fp64) {
-  const void* k = fp64 ? fwd_kernel_for<true>(m.S, m.has_cia) : fwd_kernel_for<false>(m.S, m.has_cia);
+  const void* k = fp64 ? fwd_kernel_for<true>(m.S, m.has_cia, m.cloud_ng) : fwd_kernel_for<false>(m.S, m.has_cia, m.cloud_ng);
   if (!k) return hipErrorInvalidValue;
   return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)trans_fwd_lds_bytes(m, fp64));
 }
@@ -253,10 +264,10 @@ void launch_trans_fwd(const Model& m, const Work& w, const Tables& tb, int B, vo
   const size_t lds = trans_fwd_lds_bytes(m, fp64);
   if (fp64) {
     void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec};
-    hipLaunchKernel(fwd_kernel_for<true>(m.S, m.has_cia), dim3((unsigned)(m.n_tiles64 * B)), dim3(kBlock), args, lds, st);
+    hipLaunchKernel(fwd_kernel_for<true>(m.S, m.has_cia, m.cloud_ng), dim3((unsigned)(m.n_tiles64 * B)), dim3(kBlock), args, lds, st);
   } else {
     void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec, (void*)&dtau_out};
-    hipLaunchKernel(fwd_kernel_for<false>(m.S, m.has_cia), dim3((unsigned)(m.n_tiles * B)), dim3(kBlockT), args, lds, st);
+    hipLaunchKernel(fwd_kernel_for<false>(m.S, m.has_cia, m.cloud_ng), dim3((unsigned)(m.n_tiles * B)), dim3(kBlockT), args, lds, st);
   }
 }
 

@@ -18,6 +18,61 @@ def _dptr(a: np.ndarray, ctype):
     return a.ctypes.data_as(C.POINTER(ctype))
 
 
+def build_config(wl, precision: int, batch_max: int, device: int = 0, n_layers_max: int | None = None):
+    """The exofwd_config of a workload; returns (config, arrays it points into).
+
+    The arrays must stay alive until exofwd_create has returned."""
+    keep = []
+
+    def arr(x, dt):
+        a = np.ascontiguousarray(np.asarray(x, dtype=dt))
+        keep.append(a)
+        return a
+
+    nu = arr(wl["nu"], np.float64)
+    cfg = L.Config()
+    cfg.mode = int(wl["mode"])
+    cfg.precision = precision
+    cfg.tp_kind = int(wl["tp"])
+    cfg.n_knots = int(wl.get("n_knots", 0) or 0)
+    cfg.n_species = int(wl["n_species"])
+    cfg.n_layers_max = int(n_layers_max or wl["n_layers"])
+    cfg.batch_max = batch_max
+    cfg.has_cia = int(bool(wl["cia"]))
+    cfg.has_rayleigh = int(bool(wl["rayleigh"]))
+    cfg.has_cloud = int(bool(wl["cloud"]))
+    cfg.has_scale = int(bool(wl["scale"]))
+    cfg.has_offset = int(bool(wl["offset"]))
+    cfg.n_mu = int(wl["n_mu"])
+    cfg.cloud_model = int(wl.get("cloud_model", 0))
+    cfg.cloud_profile = int(wl.get("cloud_profile", 0))
+    cfg.cloud_qext = int(wl.get("cloud_qext", 0))
+    for k in ("mu_fixed", "r_p", "r_s", "g_ref", "kappa_ir", "f_hem", "kappa_cloud", "t_star", "dilution",
+              "err_c", "ray_h2", "ray_he"):
+        setattr(cfg, k, float(wl[k]))
+    cfg.p_bot_bar, cfg.p_top_bar, cfg.p_ref_bar = float(wl["p_bot"]), float(wl["p_top"]), float(wl["p_ref_bar"])
+    cfg.n_nu = len(nu)
+    cfg.nu = _dptr(nu, C.c_double)
+    tg, pg = arr(wl["t_grid"], np.float64), arr(wl["logp_grid"], np.float64)
+    cfg.n_t, cfg.n_p = len(tg), len(pg)
+    cfg.t_grid, cfg.logp_grid = _dptr(tg, C.c_double), _dptr(pg, C.c_double)
+    cfg.log10_xsec = _dptr(arr(wl["log10_xsec"], np.float64), C.c_double)
+    cfg.species_mass = _dptr(arr(wl["species_mass"], np.float64), C.c_double)
+    if wl["cia"]:
+        tc = arr(wl["tc_grid"], np.float64)
+        cfg.n_tc = len(tc)
+        cfg.tc_grid = _dptr(tc, C.c_double)
+        cfg.log10_cia = _dptr(arr(wl["log10_cia"], np.float64), C.c_double)
+    cfg.n_bins = len(wl["bin_lo"])
+    cfg.bin_lo = _dptr(arr(wl["bin_lo"], np.int32), C.c_int32)
+    cfg.bin_hi = _dptr(arr(wl["bin_hi"], np.int32), C.c_int32)
+    cfg.y_obs = _dptr(arr(wl["y_obs"], np.float64), C.c_double)
+    cfg.y_err = _dptr(arr(wl["y_err"], np.float64), C.c_double)
+    cfg.offset_mask = _dptr(arr(wl["offset_mask"], np.uint8), C.c_uint8)
+    cfg.device = device
+    return cfg, keep
+
+
 class ForwardModel:
     """One library context built from a workload description.
 
@@ -34,51 +89,7 @@ class ForwardModel:
         self.device = torch.device("cuda", device)
         self.precision = {"mixed": L.PREC_MIXED, "fp64": L.PREC_FP64}[precision]
         self.batch_max = int(batch_max or wl["batch"])
-        keep = []
-
-        def arr(x, dt):
-            a = np.ascontiguousarray(np.asarray(x, dtype=dt))
-            keep.append(a)
-            return a
-
-        nu = arr(wl["nu"], np.float64)
-        cfg = L.Config()
-        cfg.mode = int(wl["mode"])
-        cfg.precision = self.precision
-        cfg.tp_kind = int(wl["tp"])
-        cfg.n_knots = int(wl.get("n_knots", 0) or 0)
-        cfg.n_species = int(wl["n_species"])
-        cfg.n_layers_max = int(n_layers_max or wl["n_layers"])
-        cfg.batch_max = self.batch_max
-        cfg.has_cia = int(bool(wl["cia"]))
-        cfg.has_rayleigh = int(bool(wl["rayleigh"]))
-        cfg.has_cloud = int(bool(wl["cloud"]))
-        cfg.has_scale = int(bool(wl["scale"]))
-        cfg.has_offset = int(bool(wl["offset"]))
-        cfg.n_mu = int(wl["n_mu"])
-        for k in ("mu_fixed", "r_p", "r_s", "g_ref", "kappa_ir", "f_hem", "kappa_cloud", "t_star", "dilution",
-                  "err_c", "ray_h2", "ray_he"):
-            setattr(cfg, k, float(wl[k]))
-        cfg.p_bot_bar, cfg.p_top_bar, cfg.p_ref_bar = float(wl["p_bot"]), float(wl["p_top"]), float(wl["p_ref_bar"])
-        cfg.n_nu = len(nu)
-        cfg.nu = _dptr(nu, C.c_double)
-        tg, pg = arr(wl["t_grid"], np.float64), arr(wl["logp_grid"], np.float64)
-        cfg.n_t, cfg.n_p = len(tg), len(pg)
-        cfg.t_grid, cfg.logp_grid = _dptr(tg, C.c_double), _dptr(pg, C.c_double)
-        cfg.log10_xsec = _dptr(arr(wl["log10_xsec"], np.float64), C.c_double)
-        cfg.species_mass = _dptr(arr(wl["species_mass"], np.float64), C.c_double)
-        if wl["cia"]:
-            tc = arr(wl["tc_grid"], np.float64)
-            cfg.n_tc = len(tc)
-            cfg.tc_grid = _dptr(tc, C.c_double)
-            cfg.log10_cia = _dptr(arr(wl["log10_cia"], np.float64), C.c_double)
-        cfg.n_bins = len(wl["bin_lo"])
-        cfg.bin_lo = _dptr(arr(wl["bin_lo"], np.int32), C.c_int32)
-        cfg.bin_hi = _dptr(arr(wl["bin_hi"], np.int32), C.c_int32)
-        cfg.y_obs = _dptr(arr(wl["y_obs"], np.float64), C.c_double)
-        cfg.y_err = _dptr(arr(wl["y_err"], np.float64), C.c_double)
-        cfg.offset_mask = _dptr(arr(wl["offset_mask"], np.uint8), C.c_uint8)
-        cfg.device = device
+        cfg, self._keep = build_config(wl, self.precision, self.batch_max, device, n_layers_max)
         ctx = C.c_void_p()
         with torch.cuda.device(self.device):
             L.check(self.lib.exofwd_create(C.byref(cfg), C.byref(ctx)), None, "exofwd_create")

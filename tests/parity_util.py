@@ -4,11 +4,11 @@ import numpy as np
 import synth
 
 
-def reduced(cid, n_nu, n_bins, batch, n_layers=None, start=0):
-    """Config ``cid`` cut to ``n_nu`` wavenumbers (from index ``start``) and
-    ``n_bins`` index-uniform bins; y_obs is the full observation's level."""
+def reduced(cid, n_nu, n_bins, batch, n_layers=None, start=0, step=1):
+    """Config ``cid`` cut to ``n_nu`` wavenumbers (every ``step``-th from index
+    ``start``) and ``n_bins`` index-uniform bins; y_obs is the full observation's level."""
     wl = dict(synth.workload(cid, batch=batch))
-    sl = slice(start, start + n_nu)
+    sl = slice(start, start + n_nu * step, step)
     wl["nu"] = wl["nu"][sl]
     wl["log10_xsec"] = np.ascontiguousarray(wl["log10_xsec"][..., sl])
     if wl["log10_cia"] is not None:

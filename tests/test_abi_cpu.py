@@ -65,3 +65,31 @@ def test_product_path_fails_loudly_without_library(tmp_path):
         finally:
             L._lib = None
             L.load()
+
+
+@pytest.mark.parametrize("change,ok", [
+    ({}, True),
+    ({"cloud_profile": 1, "cloud_qext": 2}, True),
+    ({"cloud_model": 2}, False),
+    ({"cloud_profile": 3}, False),
+    ({"cloud_qext": -1}, False),
+    ({"mode": 1, "n_mu": 4, "tp": 1}, False),     # the non-grey cloud is a transmission model
+])
+def test_cloud_options_validated_before_device(change, ok):
+    import synth
+    from paper_2602_19687_amd.model import build_config
+    lib = pkg.load()
+    wl = dict(synth.workload(5, batch=2))
+    wl.update(change)
+    cfg, keep = build_config(wl, L.PREC_MIXED, 2)
+    ctx = C.c_void_p()
+    rc = lib.exofwd_create(C.byref(cfg), C.byref(ctx))
+    if ok:
+        # valid: fails only for want of a device (or succeeds where there is one)
+        assert rc in (L.OK, L.ERR_DEVICE)
+        if rc == L.OK:
+            assert lib.exofwd_num_params(ctx) == len(synth.param_names({**synth.CONFIGS[5], **change}))
+            lib.exofwd_destroy(ctx)
+    else:
+        assert rc == L.ERR_CONFIG
+        assert ctx.value is None

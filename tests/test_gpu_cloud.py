@@ -1,0 +1,139 @@
+"""GPU parity of the non-grey cloud (condensate profile x Q_ext(nu)) against the
+FP64 oracle: forward spectra and likelihoods in both precisions, the
+reduced-precision adjoint against the oracle's complex-step gradient.
+
+The reduced workloads take every 30th (50th) wavenumber of the cloudy
+transmission setup (30k points, 1.9-16.7 um^-1) so the mid-infrared feature
+(lambda0 in 2.5-4.5 um) and both ends of the fit lie inside, with a ragged
+last tile.  Tolerances: spectra and lnL 1e-5 (FP64) / 1e-3 (mixed); gradients
+1e-3 per component, relative to max(|g*_j|, 1e-3 max|g*|).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity_util import reduced, rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SPEC_TOL = {"fp64": 1e-5, "mixed": 1e-3}
+GRAD_TOL = 1e-3
+
+# (condensate profile, extinction model): 0/1/2 = uniform/slab/power, fit/fit+feature/grey
+VARIANTS = [(2, 1), (0, 0), (1, 2), (1, 1), (0, 2), (2, 0)]
+
+
+def cloud_wl(profile, qext, batch, n_nu, step, n_bins=37):
+    wl = reduced(5, n_nu=n_nu, n_bins=n_bins, batch=batch, step=step)
+    cfg = {**synth.CONFIGS[5], "cloud_profile": profile, "cloud_qext": qext}
+    bounds = synth.param_bounds(cfg)
+    u = np.random.default_rng(1000 + 3 * profile + qext).uniform(size=(batch, len(bounds)))
+    wl.update(cloud_profile=profile, cloud_qext=qext, param_bounds=bounds, param_names=synth.param_names(cfg),
+              params=bounds[:, 0] + u * (bounds[:, 1] - bounds[:, 0]))
+    return wl
+
+
+_REF = {}
+
+
+def oracle_forward(key, wl):
+    if key not in _REF:
+        _REF[key] = [oracle.forward(wl, th) for th in wl["params"]]
+    return _REF[key]
+
+
+def _model(wl, prec, batch_max):
+    from paper_2602_19687_amd import ForwardModel
+    return ForwardModel(wl, precision=prec, batch_max=batch_max)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("variant", VARIANTS, ids=[f"prof{p}-q{q}" for p, q in VARIANTS])
+def test_cloud_forward_every_sample(prec, variant):
+    wl = cloud_wl(*variant, batch=8, n_nu=1000, step=30)
+    print(f"[gpu] cloud forward {variant} {prec}", flush=True)
+    fm = _model(wl, prec, 8)
+    assert fm.n_params == len(wl["param_names"])
+    spec, lnl, st = fm.forward(torch.tensor(wl["params"], device="cuda"))
+    spec, lnl, st = spec.double().cpu().numpy(), lnl.cpu().numpy(), st.cpu().numpy()
+    fm.close()
+    errs = []
+    for b, ref in enumerate(oracle_forward(variant, wl)):
+        assert st[b] == ref["status"]
+        if ref["status"]:
+            continue
+        errs.append(rel_err(spec[b], ref["spectrum"]))
+        assert abs(lnl[b] - ref["lnL"]) <= SPEC_TOL[prec] * abs(ref["lnL"]), (b, lnl[b], ref["lnL"])
+    print(f"cloud {variant} {prec}: spectrum max rel err {max(errs):.3e}")
+    assert len(errs) >= 6 and max(errs) < SPEC_TOL[prec]
+
+
+def test_cloud_changes_the_spectrum():
+    # the cloud term is live: a thick haze flattens the spectrum against a thin one
+    wl = cloud_wl(0, 0, batch=2, n_nu=400, step=75)
+    k = wl["param_names"].index("log10_q")
+    th = np.array([wl["params"][0], wl["params"][0]])
+    th[0, k], th[1, k] = -9.0, -3.0
+    fm = _model(wl, "mixed", 2)
+    spec, _, st = fm.forward(torch.tensor(th, device="cuda"))
+    spec = spec.double().cpu().numpy()
+    fm.close()
+    assert np.all(st.cpu().numpy() == 0)
+    for b in range(2):
+        ref = oracle.forward(wl, th[b])["spectrum"]
+        assert rel_err(spec[b], ref) < SPEC_TOL["mixed"]
+    assert np.ptp(spec[1]) < 0.5 * np.ptp(spec[0]) and spec[1].mean() > spec[0].mean()
+
+
+def grad_err(g, gref):
+    scale = np.maximum(np.abs(gref), 1e-3 * np.max(np.abs(gref)))
+    return np.max(np.abs(g - gref) / scale)
+
+
+@pytest.mark.parametrize("variant", VARIANTS, ids=[f"prof{p}-q{q}" for p, q in VARIANTS])
+def test_cloud_grad_vs_complex_step(variant):
+    wl = cloud_wl(*variant, batch=3, n_nu=600, step=50, n_bins=30)
+    print(f"[gpu] cloud grad {variant}", flush=True)
+    fm = _model(wl, "mixed", 3)
+    assert fm.has_grad
+    th = torch.tensor(wl["params"], device="cuda")
+    lnl, g, st, _ = fm.grad(th)
+    g, st = g.cpu().numpy(), st.cpu().numpy()
+    fm.close()
+    worst = 0.0
+    for b in range(3):
+        assert st[b] == 0
+        gref = oracle.grad_complex_step(wl, wl["params"][b])
+        e = grad_err(g[b], gref)
+        worst = max(worst, e)
+        assert e < GRAD_TOL, (b, np.array2string(np.abs(g[b] - gref) / np.maximum(np.abs(gref), 1e-30)))
+    print(f"cloud grad {variant}: max err {worst:.3e}")
+
+
+def test_cloud_fp64_gradient_unsupported():
+    from paper_2602_19687_amd import _lib as L
+    wl = cloud_wl(2, 1, batch=2, n_nu=200, step=150, n_bins=10)
+    fm = _model(wl, "fp64", 2)
+    assert not fm.has_grad
+    with pytest.raises((L.ExoError, RuntimeError)):
+        fm.grad(torch.tensor(wl["params"], device="cuda"))
+    fm.close()
+
+
+def test_cloud_full_size_sampled():
+    # the full cloudy transmission workload (B=128, 30k wavenumbers, 100 layers)
+    wl = synth.workload(5)
+    print("[gpu] cloud full size", flush=True)
+    fm = _model(wl, "mixed", wl["batch"])
+    spec, lnl, st = fm.forward(torch.tensor(wl["params"], device="cuda"))
+    spec, lnl, st = spec.double().cpu().numpy(), lnl.cpu().numpy(), st.cpu().numpy()
+    fm.close()
+    for b in (0, 77):
+        ref = oracle.forward(wl, wl["params"][b])
+        assert st[b] == ref["status"] == 0
+        err = rel_err(spec[b], ref["spectrum"])
+        print(f"cloud full b={b}: spectrum max rel err {err:.3e}")
+        assert err < SPEC_TOL["mixed"]
+        assert abs(lnl[b] - ref["lnL"]) <= SPEC_TOL["mixed"] * abs(ref["lnL"])
