@@ -532,6 +532,9 @@ def split_params(wl, theta):
     else:
         out["log10_pc"] = theta[k] if wl["cloud"] else None
         k += int(wl["cloud"])
+    fc = bool(wl.get("fcld", False))
+    out["fcld"] = theta[k] if fc else 1.0
+    k += int(fc)
     out["scale"] = theta[k] if wl["scale"] else 1.0
     k += int(wl["scale"])
     out["offset"] = theta[k] if wl["offset"] else 0.0
@@ -606,6 +609,12 @@ def forward(wl, theta, n_layers=None, tables=None, want_internals=False):
     if wl["mode"] == 0:
         pm = path_matrix(r_lev)
         spec = transit_depth(pm, dtau, r_lev, wl["r_s"])
+        if wl.get("fcld", False):
+            # Eq. 26: a fraction f_cld of the limb is cloudy, the rest clear
+            dtau_cf = layer_optical_depth(dict(wl, cloud=False), t_lay, p_lev, p_lay, r_lev, x, x_h2, x_he, mu,
+                                          None, tables=tables)
+            spec_cf = transit_depth(pm, dtau_cf, r_lev, wl["r_s"])
+            spec = ps["fcld"] * spec + (1.0 - ps["fcld"]) * spec_cf
     else:
         spec = emission_ratio(dtau, t_lev, wl["nu"], r_ref, wl["r_s"], wl["t_star"],
                               wl["n_mu"], wl["dilution"])

@@ -165,6 +165,7 @@ _BASE = dict(
     cloud_model=0,           # 0: grey deck (log10 P_cloud); 1: non-grey (profile + Q_ext)
     cloud_profile=0,         # non-grey q_c(p): 0 uniform, 1 slab, 2 base + power law
     cloud_qext=0,            # non-grey Q_ext: 0 fit, 1 fit + mid-IR feature, 2 grey Q = 2
+    fcld=False,              # cloudy fraction f_cld of the limb (Eq. 26) as a parameter
     sigma_ppm=50.0,          # observational error per bin [ppm]
 )
 
@@ -201,10 +202,16 @@ CONFIGS = {
             t_grid=np.linspace(300.0, 3500.0, 20), logp_grid=np.linspace(-7.0, 2.0, 20),
             n_lines=2000, cia=True, rayleigh=True, cloud=True, scale=True, offset=True,
             mu_fixed=0.0, n_bins=400, batch=128, cloud_model=1, cloud_profile=2, cloud_qext=1),
+    # 5 with a partly cloudy limb (Eq. 26): a slab profile and the fitted Q_ext
+    6: dict(mode=MODE_TRANSMISSION, tp=TP_GUILLOT3, n_layers=100, p_bot=100.0, p_top=1.0e-7,
+            n_species=6, n_nu=30000, nu_min=1.0e4 / 5.3, nu_max=1.0e4 / 0.6,
+            t_grid=np.linspace(300.0, 3500.0, 20), logp_grid=np.linspace(-7.0, 2.0, 20),
+            n_lines=2000, cia=True, rayleigh=True, cloud=True, scale=True, offset=True,
+            mu_fixed=0.0, n_bins=400, batch=128, cloud_model=1, cloud_profile=1, cloud_qext=0, fcld=True),
 }
 
 # configs 1 and 3 share tables (same seeds) so the spec batch reuses them
-_TABLE_CID = {0: 0, 1: 1, 2: 2, 3: 1, 4: 4, 5: 1}
+_TABLE_CID = {0: 0, 1: 1, 2: 2, 3: 1, 4: 4, 5: 1, 6: 1}
 
 
 def param_names(cfg) -> list:
@@ -224,6 +231,8 @@ def param_names(cfg) -> list:
             names += ["feature_A", "feature_lambda0_um", "log10_feature_width_um", "feature_skew"]
     elif cfg["cloud"]:
         names.append("log10_P_cloud_bar")
+    if cfg.get("fcld", False):
+        names.append("f_cld")
     if cfg["scale"]:
         names.append("R_p_scale")
     if cfg["offset"]:
@@ -252,6 +261,8 @@ def param_bounds(cfg):
             b += [(0.0, 0.8), (2.5, 4.5), (-1.0, -0.3), (-2.0, 2.0)]
     elif cfg["cloud"]:
         b.append((-6.0, 2.0))
+    if cfg.get("fcld", False):
+        b.append((0.0, 1.0))
     if cfg["scale"]:
         b.append((0.95, 1.05))
     if cfg["offset"]:

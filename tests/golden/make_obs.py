@@ -31,4 +31,4 @@ def main(cids):
 
 
 if __name__ == "__main__":
-    main([int(a) for a in sys.argv[1:]] or [0, 1, 2, 3, 4])
+    main([int(a) for a in sys.argv[1:]] or [0, 1, 2, 3, 4, 5, 6])

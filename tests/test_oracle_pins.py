@@ -597,3 +597,41 @@ def test_nongrey_complex_step_matches_central_differences():
         gf = oracle.grad_central_fd(wl, th)
         scale = np.maximum(np.abs(gc), 1e-3 * np.max(np.abs(gc)))
         assert np.max(np.abs(gc - gf) / scale) < 1e-5, (gc, gf)
+
+
+def test_cloud_fraction_limits_are_the_cloudy_and_clear_models():
+    """Eq. 26: f_cld = 1 is the fully cloudy model (the same workload without the
+    fraction parameter) and f_cld = 0 the model with no cloud at all (a workload
+    with the cloud switched off and its parameters removed); between them the
+    spectrum is the f_cld-weighted mean of the two."""
+    wl = _nongrey_slice(6)
+    names = wl["param_names"]
+    k_f = names.index("f_cld")
+    cloud_idx = [i for i, n in enumerate(names) if i >= 9 and i < k_f]
+    cloudy = dict(wl, fcld=False)
+    clear = dict(wl, fcld=False, cloud=False)
+    for b in range(2):
+        th = wl["params"][b].copy()
+        th[k_f] = 1.0
+        a = oracle.forward(wl, th)
+        c = oracle.forward(cloudy, np.delete(th, k_f))
+        assert a["status"] == c["status"] == 0
+        assert np.array_equal(a["spectrum"], c["spectrum"])
+        th[k_f] = 0.0
+        a0 = oracle.forward(wl, th)
+        c0 = oracle.forward(clear, np.delete(th, cloud_idx + [k_f]))
+        assert np.max(np.abs(a0["spectrum"] - c0["spectrum"]) / c0["spectrum"]) < 1e-15
+        assert np.min(c["spectrum"] - c0["spectrum"]) >= 0.0   # a cloud only adds opacity
+        th[k_f] = 0.3
+        mid = oracle.forward(wl, th)["spectrum"]
+        np.testing.assert_allclose(mid, 0.3 * c["spectrum"] + 0.7 * c0["spectrum"], rtol=1e-14)
+
+
+def test_cloud_fraction_complex_step_matches_central_differences():
+    wl = _nongrey_slice(6)
+    wl["n_layers"] = 40
+    th = wl["params"][0]
+    gc = oracle.grad_complex_step(wl, th)
+    gf = oracle.grad_central_fd(wl, th)
+    scale = np.maximum(np.abs(gc), 1e-3 * np.max(np.abs(gc)))
+    assert np.max(np.abs(gc - gf) / scale) < 1e-5, (gc, gf)
