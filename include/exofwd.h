@@ -99,6 +99,8 @@ enum {
  *                        [log10 q_base, log10 p_base/bar, alpha]    (POWER, Eq. 20)
  *                      + [A, lambda0/um, log10 omega/um, xi]   if QEXT_FIT_FEATURE
  *                        (Eqs. 27-29; the window's x0 is 0.5 and Q_max is 2)
+ *   then  f_cld                 if has_fcld: cloudy fraction of the limb in [0, 1] (Eq. 26);
+ *                               the spectrum is f_cld x (cloudy) + (1 - f_cld) x (cloud-free)
  *   then  R_p scale factor      if has_scale  (R_ref = scale * r_p)
  *   then  offset [ppm]          if has_offset (added to bins with offset_mask)
  */
@@ -115,6 +117,8 @@ typedef struct exofwd_config {
   int32_t cloud_model;       /* EXOFWD_CLOUD_* (has_cloud; NONGREY for transmission only) */
   int32_t cloud_profile;     /* EXOFWD_QPROF_* (NONGREY) */
   int32_t cloud_qext;        /* EXOFWD_QEXT_* (NONGREY) */
+  int32_t has_fcld;          /* cloudy/clear mixing, Eq. 26 (transmission with has_cloud); each sample
+                                costs two spectra */
   double mu_fixed;           /* > 0: fixed mean molecular weight [amu]; else from composition */
   double p_bot_bar, p_top_bar, p_ref_bar;   /* grid bottom/top, reference pressure [bar] */
   double r_p, r_s, g_ref;    /* reference radius [cm], stellar radius [cm], gravity at r_p [cm s^-2] */

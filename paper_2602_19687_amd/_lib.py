@@ -25,6 +25,7 @@ class Config(C.Structure):
         ("has_cia", C.c_int32), ("has_rayleigh", C.c_int32), ("has_cloud", C.c_int32),
         ("has_scale", C.c_int32), ("has_offset", C.c_int32), ("n_mu", C.c_int32),
         ("cloud_model", C.c_int32), ("cloud_profile", C.c_int32), ("cloud_qext", C.c_int32),
+        ("has_fcld", C.c_int32),
         ("mu_fixed", C.c_double), ("p_bot_bar", C.c_double), ("p_top_bar", C.c_double),
         ("p_ref_bar", C.c_double), ("r_p", C.c_double), ("r_s", C.c_double), ("g_ref", C.c_double),
         ("kappa_ir", C.c_double), ("f_hem", C.c_double), ("kappa_cloud", C.c_double),

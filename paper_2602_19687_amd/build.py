@@ -14,7 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "libexofwd.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["exofwd.hip", "profile.hip", "trans_fwd.hip", "loglike.hip", "emission.hip", "adjoint.hip"]
+SOURCES = ["exofwd.hip", "profile.hip", "trans_fwd.hip", "loglike.hip", "emission.hip", "emission_adj.hip",
+           "adjoint.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

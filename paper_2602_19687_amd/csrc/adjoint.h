@@ -14,12 +14,9 @@ namespace exofwd {
 //   S+3     HTc   = sum_nu dtau_bar_l sum_p t_lp dv_lp/dwTc
 //   S+4     GR    = sum_nu dtau_bar_l (nu/1e4)^4
 //   S+5     GD    = sum_nu dtau_bar_l               (non-grey cloud: sum_nu dtau_bar_l Q_ext(nu))
-// and, with the non-grey cloud (reduced precision), kCloudSpec more:
-//   S+6+k   HQ_k  = sum over a group of layers of D_l sum_nu dtau_bar_l dQ_ext/dp_k,
-//                   stored at the group's first layer and zero at the others
 constexpr int kExtraSums = 6;
 __host__ __device__ constexpr int n_sums(int s) { return s + kExtraSums; }
-__host__ __device__ inline int n_lsums(const Model& m) { return n_sums(m.S) + (m.cloud_ng ? kCloudSpec : 0); }
+__host__ __device__ inline int n_lsums(const Model& m) { return n_sums(m.S); }
 
 // shapes of the reduced-precision reverse kernel: wavenumber tile x 32-row blocks
 enum : int { kAdjT128M4 = 0, kAdjT64M4 = 1, kAdjT64M5 = 2, kAdjVariants = 3 };
@@ -40,6 +37,9 @@ struct AdjWork {
   float* dtau;         // [B_max][L_pad][n_nu_pad] layer optical depths stored by the forward kernel
   float* dtb;          // [B_max][L_pad][n_nu_pad] d lnL / d dtau_l(nu)
   float* lsum;         // [B_max][lsum_chunks][L_pad][n_lsums] partial layer sums
+  float* hq;           // non-grey cloud: [B_max][lsum_stride][kCloudSpec] per-chunk sums over nu of
+                       //   (sum_l D_l dtau_bar_l) dQ_ext/dp_k
+  float* psum;         // emission: [B_max][n_tiles64][L_pad+1] per-tile sums over nu of d lnL/dB_j dB_j/dT_j
   int lsum_chunks;     // wavenumber chunks of the layer-sum kernel (n_tiles / ls_tiles, rounded up)
   int lsum_stride;     // allocated chunks per sample (the bound over the ls_tiles choices)
 };
@@ -54,8 +54,11 @@ void launch_trans_adjoint(const Model& m, const Work& w, const Tables& tb, const
 void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, hipStream_t st);
 void launch_chain(const Model& m, const Work& w, const AdjWork& aw, int B, const double* params, const uint8_t* mask,
                   double* grad, bool fp64, hipStream_t st);
-// whether the adjoint supports this workload (transmission, no PCHIP profile,
-// L_pad <= 160 in reduced precision, <= 128 and no non-grey cloud in FP64)
+// whether the adjoint supports this workload: transmission with L_pad <= 160 in
+// reduced precision, <= 128 and no non-grey cloud in FP64; emission in reduced
+// precision with L_pad <= 160
+void launch_emis_adjoint(const Model& m, const Work& w, const AdjWork& aw, int B, hipStream_t st);
+void launch_layer_sums_emis(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, hipStream_t st);
 bool adjoint_supported(const Model& m, bool fp64);
 // default reverse-kernel shape, whether a shape serves this model, and switching shapes
 int adjoint_default_variant(const Model& m);

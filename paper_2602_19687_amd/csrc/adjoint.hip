@@ -387,7 +387,6 @@ constexpr int kLsLayers = 5;
 template <int S, bool CIA, bool NGC>
 __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Tables tb, AdjWork aw, int B) {
   constexpr int NS = n_sums(S);
-  constexpr int NT = NS + (NGC ? kCloudSpec : 0);   // stride of the stored sums
   const int lane = threadIdx.x & 63;
   const int gw = blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int NG = (m.L_max + kLsLayers - 1) / kLsLayers;
@@ -419,16 +418,16 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
   for (int q = 0; q < kLsLayers; ++q)
 #pragma unroll
     for (int k = 0; k < NS; ++k) acc[q][k] = 0.0f;
-  // non-grey cloud: Q_ext at the lane's two wavenumbers weights the cloud sum;
-  // hq accumulates sum_nu (sum_q D_q dtau_bar_q) dQ/dp_k over the group
-  float hq[NGC ? kCloudSpec : 1] = {};
+  // non-grey cloud: Q_ext at the lane's two wavenumbers weights the cloud sum (its
+  // spectral parameters are summed by k_cloud_spectral: more live registers here
+  // would cost this kernel its load pipelining)
   const float* cq = NGC ? w.cloud_q + (size_t)b * (1 + kCloudSpec) * npad : nullptr;
 
   const int t0 = chunk * aw.ls_tiles, t1 = min(t0 + aw.ls_tiles, m.n_tiles);
   for (int tile = t0; tile < t1; ++tile) {
     const int nu0 = tile * kTileNu;
     const LaneConst<S> kc = load_lane<S, CIA>(m, tb, nu0 + 2 * lane);
-    float q0 = 1.0f, q1 = 1.0f, g0 = 0.0f, g1 = 0.0f;
+    float q0 = 1.0f, q1 = 1.0f;
     if constexpr (NGC) {
       const float2 q = *reinterpret_cast<const float2*>(cq + nu0 + 2 * lane);
       q0 = q.x;
@@ -465,21 +464,12 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
       acc[q][S + 4] = fmaf(db.x, kc.nu4_0, fmaf(db.y, kc.nu4_1, acc[q][S + 4]));
       if constexpr (NGC) {
         acc[q][S + 5] = fmaf(db.x, q0, fmaf(db.y, q1, acc[q][S + 5]));
-        g0 = fmaf(c.D, db.x, g0);
-        g1 = fmaf(c.D, db.y, g1);
       } else {
         acc[q][S + 5] += db.x + db.y;
       }
     }
-    if constexpr (NGC) {
-#pragma unroll
-      for (int k = 0; k < kCloudSpec; ++k) {
-        const float2 d = *reinterpret_cast<const float2*>(cq + (size_t)(1 + k) * npad + nu0 + 2 * lane);
-        hq[k] = fmaf(g0, d.x, fmaf(g1, d.y, hq[k]));
-      }
-    }
   }
-  float* out = aw.lsum + ((size_t)b * aw.lsum_stride + chunk) * Lp * NT;
+  float* out = aw.lsum + ((size_t)b * aw.lsum_stride + chunk) * Lp * NS;
 #pragma unroll
   for (int q = 0; q < kLsLayers; ++q) {
     const int l = l0 + q;
@@ -487,15 +477,45 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const float tot = wave_sum(acc[q][k]);
-      if (lane == 0) out[(size_t)l * NT + k] = tot;
+      if (lane == 0) out[(size_t)l * NS + k] = tot;
     }
-    if constexpr (NGC) {
+  }
+}
+
+// Non-grey cloud: sums over wavenumber of G(nu) dQ_ext/dp_k with
+// G(nu) = sum_l D_l dtau_bar_l(nu), the derivative of lnL along the cloud's
+// spectral shape; one wave per (sample, layer-sum chunk), two wavenumbers per lane.
+__global__ __launch_bounds__(kBlock) void k_cloud_spectral(Model m, Work w, AdjWork aw, int B) {
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int b = gw / aw.lsum_chunks, chunk = gw - b * aw.lsum_chunks;
+  if (b >= B || w.status[b]) return;
+  const int L = w.nlay[b], Lp = m.L_pad;
+  const size_t npad = (size_t)m.n_nu_pad;
+  const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * rec_len(m.S);
+  const float* dtb = aw.dtb + (size_t)b * Lp * npad;
+  const float* cq = w.cloud_q + (size_t)b * (1 + kCloudSpec) * npad;
+  float hq[kCloudSpec] = {};
+  const int t0 = chunk * aw.ls_tiles, t1 = min(t0 + aw.ls_tiles, m.n_tiles);
+  for (int tile = t0; tile < t1; ++tile) {
+    const int nu = tile * kTileNu + 2 * lane;
+    float g0 = 0.0f, g1 = 0.0f;
+    for (int l = 0; l < L; ++l) {
+      const float dl = rec[(size_t)l * rec_len(m.S) + 4];
+      const float2 d = *reinterpret_cast<const float2*>(dtb + (size_t)l * npad + nu);
+      g0 = fmaf(dl, d.x, g0);
+      g1 = fmaf(dl, d.y, g1);
+    }
 #pragma unroll
-      for (int k = 0; k < kCloudSpec; ++k) {
-        const float tot = q == 0 ? wave_sum(hq[k]) : 0.0f;
-        if (lane == 0) out[(size_t)l * NT + NS + k] = tot;
-      }
+    for (int k = 0; k < kCloudSpec; ++k) {
+      const float2 d = *reinterpret_cast<const float2*>(cq + (size_t)(1 + k) * npad + nu);
+      hq[k] = fmaf(g0, d.x, fmaf(g1, d.y, hq[k]));
     }
+  }
+#pragma unroll
+  for (int k = 0; k < kCloudSpec; ++k) {
+    const float tot = wave_sum(hq[k]);
+    if (lane == 0) aw.hq[((size_t)b * aw.lsum_stride + chunk) * kCloudSpec + k] = tot;
   }
 }
 
@@ -729,6 +749,54 @@ __device__ inline void path_derivs(const double* r, int i, int l, double& d_lo, 
   d_b = f * bb * (1.0 / sup + 1.0 / slo);
 }
 
+// Slopes of the monotone cubic Hermite interpolant through (xk, yk) and their
+// Jacobian J[k][j] = d slope_k / d y_j, following the branches of the slope rule
+// used by the profile kernel (Fritsch-Butland weighted harmonic mean inside,
+// three-point shape-preserving ends).
+__device__ void pchip_slopes_jac(const double* xk, const double* yk, int n, double* d, double* J) {
+  double h[kMaxKnots], del[kMaxKnots];
+  for (int k = 0; k < n - 1; ++k) { h[k] = xk[k + 1] - xk[k]; del[k] = (yk[k + 1] - yk[k]) / h[k]; }
+  for (int i = 0; i < n * n; ++i) J[i] = 0.0;
+  // d del_k / d y_k = -1/h_k, d del_k / d y_{k+1} = 1/h_k
+  auto add_del = [&](int row, int k, double c) {
+    J[row * n + k] -= c / h[k];
+    J[row * n + k + 1] += c / h[k];
+  };
+  if (n == 2) {
+    d[0] = d[1] = del[0];
+    add_del(0, 0, 1.0);
+    add_del(1, 0, 1.0);
+    return;
+  }
+  for (int k = 1; k < n - 1; ++k) {
+    const double a = del[k - 1], b = del[k];
+    if (a == 0.0 || b == 0.0 || (a > 0.0) != (b > 0.0)) {
+      d[k] = 0.0;
+    } else {
+      const double w1 = 2.0 * h[k] + h[k - 1], w2 = h[k] + 2.0 * h[k - 1];
+      const double den = w1 / a + w2 / b;
+      d[k] = (w1 + w2) / den;
+      add_del(k, k - 1, (w1 + w2) * w1 / (a * a * den * den));
+      add_del(k, k, (w1 + w2) * w2 / (b * b * den * den));
+    }
+  }
+  auto end = [&](int row, int i0, int i1) {
+    const double h0 = h[i0], h1 = h[i1], m0 = del[i0], m1 = del[i1];
+    const double dd = ((2.0 * h0 + h1) * m0 - h0 * m1) / (h0 + h1);
+    auto sgn = [](double v) { return (v > 0.0) - (v < 0.0); };
+    if (sgn(dd) != sgn(m0)) return 0.0;
+    if (sgn(m0) != sgn(m1) && fabs(dd) > fabs(3.0 * m0)) {
+      add_del(row, i0, 3.0);
+      return 3.0 * m0;
+    }
+    add_del(row, i0, (2.0 * h0 + h1) / (h0 + h1));
+    add_del(row, i1, -h0 / (h0 + h1));
+    return dd;
+  };
+  d[0] = end(0, 0, 1);
+  d[n - 1] = end(n - 1, n - 2, n - 3);
+}
+
 template <typename PbarT>
 __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, int C, int Cn, const double* __restrict__ params,
                                                   const uint8_t* __restrict__ mask, double* __restrict__ grad) {
@@ -742,7 +810,10 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
     return;
   }
   const int L = w.nlay[b];
-  const double* th = params + (size_t)b * m.P;
+  // virtual sample b of real sample real_sample(m, b); a clear one has no cloud terms
+  const double* th = params + (size_t)real_sample(m, b) * m.P;
+  const bool cloudy = m.has_cloud && !clear_sample(m, b);
+  const bool ng = m.cloud_ng && cloudy;
   __shared__ double s_r[kMaxLayers + 1], s_rb[kMaxLayers + 1], s_ub[kMaxLayers + 1];
   __shared__ double s_t[kMaxLayers], s_tb[kMaxLayers], s_lndr[kMaxLayers];
   __shared__ double s_clo[kMaxLayers], s_cup[kMaxLayers], s_bb[kMaxLayers];
@@ -803,10 +874,10 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
     const double dr = s_r[l + 1] - s_r[l];
     const double rr = (m.has_ray ? n * (xh2 * m.ray_h2 + xhe * m.ray_he) * dr : 0.0);
     double f = 0.0, dd = 0.0;
-    if (m.cloud_ng) {
+    if (ng) {
       dd = condensate_q(m.cloud_profile, th + q_first, logp_lev(l), logp_lev(l + 1), lp_bar, nullptr) * mu * kMu * n *
            dr * 0.75 / r_eff;
-    } else if (m.has_cloud) {
+    } else if (cloudy) {
       f = (logp_lev(l) - log10_pc) * ln10 / dlnp;
       f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
       dd = m.kappa_cloud * mu * kMu * n * f * dr;
@@ -843,7 +914,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
     s_red[(m.S + 2) * kBlock + tid] += gr * n * dr * m.ray_h2;
     s_red[(m.S + 3) * kBlock + tid] += gr * n * dr * m.ray_he;
     s_red[(m.S + 4) * kBlock + tid] += gd * dd;
-    if (m.has_cloud && !m.cloud_ng && f > 0.0 && f < 1.0)
+    if (cloudy && !m.cloud_ng && f > 0.0 && f < 1.0)
       s_red[(m.S + 5) * kBlock + tid] += gd * m.kappa_cloud * mu * kMu * n * dr * (-ln10 / dlnp);
   }
   block_sum(s_red, tid, NR);
@@ -857,9 +928,8 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
   if (m.cloud_ng) {
     constexpr int NC = kCloudSpec + 3;
     for (int k = 0; k < NC; ++k) s_red[k * kBlock + tid] = 0.0;
-    for (int l = tid; l < L; l += kBlock) {
+    for (int l = tid; l < (ng ? L : 0); l += kBlock) {   // a clear virtual sample keeps zeros
       const double gd = layer_sum(l, m.S + 5);
-      for (int k = 0; k < kCloudSpec; ++k) s_red[k * kBlock + tid] += layer_sum(l, NS + k);
       const double lp_bar = 0.5 * (logp_lev(l) + logp_lev(l + 1));
       const double n = exp10(lp_bar) * kBar / (kB * s_t[l]);
       const double col = mu * kMu * n * (s_r[l + 1] - s_r[l]) * 0.75 / r_eff;
@@ -868,6 +938,9 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
       s_red[tid] -= ln10 * gd * q * col;
       for (int k = 0; k < 3; ++k) s_red[(kCloudSpec + k) * kBlock + tid] += gd * col * dq[k];
     }
+    // spectral parameters: the per-chunk sums of k_cloud_spectral
+    for (int i = tid; i < (ng ? aw.lsum_chunks * kCloudSpec : 0); i += kBlock)
+      s_red[(i % kCloudSpec) * kBlock + tid] += (double)aw.hq[((size_t)b * aw.lsum_stride) * kCloudSpec + i];
     block_sum(s_red, tid, NC);
     if (tid < NC) s_cloud[tid] = s_red[tid * kBlock];
     __syncthreads();
@@ -880,7 +953,8 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
     for (int c = 0; c < Cn; ++c) v += (double)pbar[(((size_t)b * C + c) * Lp + i) * Lp + l];
     return v;
   };
-  for (int l = tid; l < L; l += kBlock) {
+  const bool trans = m.mode == kTransmission;
+  for (int l = tid; l < (trans ? L : 0); l += kBlock) {
     double clo = 0.0, cup = 0.0;
     for (int i = 0; i <= l; ++i) {
       double dlo, dup, db;
@@ -892,7 +966,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
     s_clo[l] = clo;
     s_cup[l] = cup;
   }
-  for (int i = tid; i < L; i += kBlock) {
+  for (int i = tid; i < (trans ? L : 0); i += kBlock) {
     double acc = 0.0;
     for (int l = i + 1; l < L; ++l) {
       double dlo, dup, db;
@@ -901,19 +975,21 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
     }
     s_bb[i] = acc;
   }
+  // emission: no chord; the levels move the optical depths only through dr
+  for (int l = tid; l < (trans ? 0 : L); l += kBlock) s_clo[l] = s_cup[l] = s_bb[l] = 0.0;
   double core_bar = 0.0;
   for (int k = 0; k < m.K; ++k) core_bar += w.dm[(size_t)b * m.K + k];
   __syncthreads();
   for (int j = tid; j <= L; j += kBlock) {
     double rb = 0.0;
     double ab_j = 0.0, ab_jm = 0.0;
-    for (int c = 0; c < Cn; ++c) {
+    for (int c = 0; c < (trans ? Cn : 0); ++c) {
       if (j < L) ab_j += aw.abar[((size_t)b * C + c) * Lp + j];
       if (j >= 1) ab_jm += aw.abar[((size_t)b * C + c) * Lp + j - 1];
     }
     if (j < L) rb += s_clo[j] + 0.5 * s_bb[j] - 2.0 * s_r[j] * ab_j / rs2 - s_lndr[j];
     if (j >= 1) rb += s_cup[j - 1] + 0.5 * s_bb[j - 1] + 2.0 * s_r[j] * ab_jm / rs2 + s_lndr[j - 1];
-    if (j == 0) rb += 2.0 * s_r[0] * core_bar / rs2;
+    if (j == 0 && trans) rb += 2.0 * s_r[0] * core_bar / rs2;
     s_rb[j] = rb;
     s_ub[j] = -rb * s_r[j] * s_r[j];
   }
@@ -960,20 +1036,31 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
       s_tb[l] -= kk * dlnp * suf;
     }
     s_scal[0] = -ub_ref / (r_ref * r_ref) - 2.0 * kbar * kk / r_ref;   // d lnL / d R_ref
+    // emission: the ratio carries (R_ref/R_s)^2, and sum_nu dlnL/dspec spec = mdot
+    if (!trans) s_scal[0] += 2.0 * w.mdot[b] / r_ref;
     s_scal[1] = -kbar * kk;                                            // d lnL / d ln mu (hydrostatics)
   }
   __syncthreads();
 
-  // T-p profile
-  for (int k = 0; k < 4; ++k) s_red[k * kBlock + tid] = 0.0;
-  for (int l = tid; l < L; l += kBlock) {
-    const double tbar = s_tb[l];
+  // T-p profile: layer temperatures (opacity, hydrostatics) and, in emission, the
+  // level temperatures of the Planck sources, each at its own pressure
+  __shared__ double s_kx[kMaxKnots], s_ky[kMaxKnots], s_kd[kMaxKnots], s_kj[kMaxKnots * kMaxKnots];
+  if (m.tp_kind == kTpPchip && tid == 0) {
+    for (int k = 0; k < m.n_knots; ++k) {
+      s_kx[k] = m.n_knots == 1 ? m.log10_ptop : m.log10_ptop + k * ((m.log10_pbot - m.log10_ptop) / (m.n_knots - 1));
+      s_ky[k] = th[k];
+    }
+    s_kx[m.n_knots - 1] = m.log10_pbot;
+    pchip_slopes_jac(s_kx, s_ky, m.n_knots, s_kd, s_kj);
+  }
+  for (int k = 0; k < m.n_tp; ++k) s_red[k * kBlock + tid] = 0.0;
+  __syncthreads();
+  auto tp_grad = [&](double lp, double t, double tbar) {
     if (m.tp_kind == kTpIso) {
       s_red[tid] += tbar;
-    } else {
-      const double lp_bar = 0.5 * (logp_lev(l) + logp_lev(l + 1));
-      const double tau = m.kappa_ir * exp10(lp_bar) * kBar / m.g_ref;
-      const double t = s_t[l], t3 = t * t * t;
+    } else if (m.tp_kind == kTpGuillot3) {
+      const double tau = m.kappa_ir * exp10(lp) * kBar / m.g_ref;
+      const double t3 = t * t * t;
       const double s3 = 1.7320508075688772935274463415059;
       const double gam = exp10(th[2]);
       const double e = exp(-gam * tau * s3);
@@ -984,9 +1071,33 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
       s_red[tid] += tbar * 3.0 * ti * ti * ti * (2.0 / 3.0 + tau) / (4.0 * t3);
       s_red[kBlock + tid] += tbar * 12.0 * m.f_hem * te * te * te * bk / (4.0 * t3);
       s_red[2 * kBlock + tid] += tbar * 3.0 * m.f_hem * te * te * te * te * dbk * gam * ln10 / (4.0 * t3);
+    } else {
+      // T = h00 y_k + h10 h d_k + h01 y_k+1 + h11 h d_k+1 on the knot interval holding lp
+      const int n = m.n_knots;
+      int k = 0;
+      while (k < n - 2 && s_kx[k + 1] <= lp) ++k;
+      const double hk = s_kx[k + 1] - s_kx[k];
+      const double u = (lp - s_kx[k]) / hk, omu = 1.0 - u;
+      const double h00 = (1.0 + 2.0 * u) * omu * omu, h10 = u * omu * omu, h01 = u * u * (3.0 - 2.0 * u),
+                   h11 = u * u * (u - 1.0);
+      for (int j = 0; j < n; ++j) {
+        double dtdy = hk * (h10 * s_kj[k * n + j] + h11 * s_kj[(k + 1) * n + j]);
+        if (j == k) dtdy += h00;
+        if (j == k + 1) dtdy += h01;
+        s_red[j * kBlock + tid] += tbar * dtdy;
+      }
+    }
+  };
+  for (int l = tid; l < L; l += kBlock) tp_grad(0.5 * (logp_lev(l) + logp_lev(l + 1)), s_t[l], s_tb[l]);
+  if (!trans) {
+    const double* tlev = w.t_lev + (size_t)b * (Lp + 1);
+    for (int j = tid; j <= L; j += kBlock) {
+      double tb = 0.0;
+      for (int t = 0; t < m.n_tiles64; ++t) tb += (double)aw.psum[((size_t)b * m.n_tiles64 + t) * (Lp + 1) + j];
+      tp_grad(logp_lev(j), tlev[j], tb);
     }
   }
-  block_sum(s_red, tid, 3);
+  block_sum(s_red, tid, m.n_tp);
   if (tid == 0) {
     for (int k = 0; k < m.n_tp; ++k) gout[k] = s_red[k * kBlock];
     // chemistry: X_H2 = (1 - sum X)/1.164, X_He = 0.164 X_H2, mu = sum X m
@@ -1061,6 +1172,7 @@ static int adj_threads(int variant) { return 4 * adj_tile(variant); }
 static int adj_slots(int variant) { return (adj_mb(variant) + 1) / 2; }
 
 int adjoint_chunks(const Model& m, const AdjWork& aw, int B, bool fp64) {
+  if (m.mode == kEmission) return 1;   // the emission reverse pass keeps no per-chunk partials
   // the FP64 reverse kernel walks 64-wavenumber tiles
   const int tiles = m.n_nu_pad / (fp64 ? kTile64 : adj_tile(aw.variant));
   const int target = fp64 ? 1024 : aw.chunk_target;
@@ -1069,7 +1181,8 @@ int adjoint_chunks(const Model& m, const AdjWork& aw, int B, bool fp64) {
 }
 
 bool adjoint_supported(const Model& m, bool fp64) {
-  return m.mode == kTransmission && m.tp_kind != kTpPchip && m.L_pad <= (fp64 ? 128 : 160) && !(fp64 && m.cloud_ng);
+  if (m.mode == kEmission) return !fp64 && m.L_pad <= 160;
+  return m.L_pad <= (fp64 ? 128 : 160) && !(fp64 && m.cloud_ng);
 }
 
 int adjoint_default_variant(const Model& m) { return m.L_pad <= 128 ? kAdjT128M4 : kAdjT64M5; }
@@ -1100,6 +1213,15 @@ bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std:
   aw.ls_tiles = 8;
   aw.max_pairs = pairs;
   const size_t Lp = m.L_pad;
+  if (m.mode == kEmission) {
+    aw.lsum_stride = (m.n_tiles + kLsTileChoices[0] - 1) / kLsTileChoices[0];
+    aw.lsum_chunks = (m.n_tiles + aw.ls_tiles - 1) / aw.ls_tiles;
+    aw.dtb = (float*)alloc((size_t)B_max * m.L_pad * m.n_nu_pad * sizeof(float));
+    aw.dtau = (float*)alloc((size_t)B_max * m.L_pad * m.n_nu_pad * sizeof(float));
+    aw.lsum = (float*)alloc((size_t)B_max * aw.lsum_stride * Lp * n_lsums(m) * sizeof(float));
+    aw.psum = (float*)alloc((size_t)B_max * m.n_tiles64 * (Lp + 1) * sizeof(float));
+    return aw.dtb && aw.dtau && aw.lsum && aw.psum;
+  }
   aw.pbar = alloc((size_t)pairs * Lp * Lp * (fp64 ? sizeof(double) : sizeof(float)));
   aw.abar = (double*)alloc((size_t)pairs * Lp * sizeof(double));
   if (!aw.pbar || !aw.abar) return false;
@@ -1112,6 +1234,10 @@ bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std:
   aw.dtb = (float*)alloc((size_t)B_max * m.L_pad * m.n_nu_pad * sizeof(float));
   aw.dtau = (float*)alloc((size_t)B_max * m.L_pad * m.n_nu_pad * sizeof(float));
   aw.lsum = (float*)alloc((size_t)B_max * aw.lsum_stride * Lp * n_lsums(m) * sizeof(float));
+  if (m.cloud_ng) {
+    aw.hq = (float*)alloc((size_t)B_max * aw.lsum_stride * kCloudSpec * sizeof(float));
+    if (!aw.hq) return false;
+  }
   return aw.dtb && aw.dtau && aw.lsum;
 }
 
@@ -1164,7 +1290,7 @@ const void* ls_kernel_for(int S, bool cia, bool ng) {
 }
 
 hipError_t adjoint_configure(const Model& m, bool fp64) {
-  if (!adjoint_supported(m, fp64)) return hipSuccess;
+  if (!adjoint_supported(m, fp64) || m.mode == kEmission) return hipSuccess;
   if (fp64) {
     const void* k = adj_kernel_for<true>(m.S, m.has_cia, 0);
     const size_t bytes = adj_lds_bytes(m, true, 0);
@@ -1209,10 +1335,18 @@ void launch_trans_adjoint(const Model& m, const Work& w, const Tables& tb, const
 }
 
 void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, hipStream_t st) {
+  if (m.mode == kEmission) {
+    launch_layer_sums_emis(m, w, tb, aw, B, st);
+    return;
+  }
   const int NG = (m.L_max + kLsLayers - 1) / kLsLayers;
   const long waves = (long)aw.lsum_chunks * B * NG;
   void* args2[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&aw, (void*)&B};
   hipLaunchKernel(ls_kernel_for(m.S, m.has_cia, m.cloud_ng), dim3((unsigned)((waves + 3) / 4)), dim3(kBlock), args2, 0, st);
+  if (m.cloud_ng) {
+    const long cw = (long)B * aw.lsum_chunks;
+    hipLaunchKernelGGL(k_cloud_spectral, dim3((unsigned)((cw + 3) / 4)), dim3(kBlock), 0, st, m, w, aw, B);
+  }
 }
 
 void launch_chain(const Model& m, const Work& w, const AdjWork& aw, int B, const double* params, const uint8_t* mask,

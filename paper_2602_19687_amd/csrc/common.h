@@ -55,6 +55,7 @@ struct Model {
   int fwd_tile_major;       // reduced-precision forward grid order: 0 samples fastest, 1 tiles fastest
   int cloud_ng;             // 1: non-grey cloud (q_c profile x Q_ext(nu)); 0: grey deck or none
   int cloud_profile, cloud_qext, n_cloud;   // kQprof*, kQext*, cloud parameters in theta
+  int has_fcld, idx_fcld;   // cloudy/clear mixing: sample b runs as virtual samples 2b (cloudy) and 2b+1 (clear)
   double mu_fixed, log10_pbot, log10_ptop, p_ref, r_p, r_s, g_ref;
   double kappa_ir, f_hem, kappa_cloud, t_star, dilution, err_c, ray_h2, ray_he;
   double mass[kMaxSpecies];
@@ -65,7 +66,12 @@ struct Model {
   const double* nu;         // [n_nu_pad] (padded with the last value)
 };
 
-// Workspace of one context, sized for batch_max x L_pad.
+// real sample and cloud-free flag of a virtual sample
+__host__ __device__ inline int real_sample(const Model& m, int b) { return m.has_fcld ? b >> 1 : b; }
+__host__ __device__ inline bool clear_sample(const Model& m, int b) { return m.has_fcld && (b & 1); }
+
+// Workspace of one context, sized for batch_max x L_pad (2 batch_max virtual
+// samples with the cloudy/clear mixing).
 struct Work {
   int32_t* status;      // [B]
   int32_t* nlay;        // [B] layers used per sample
@@ -84,6 +90,9 @@ struct Work {
   void* spec;           // [B][n_nu] internal spectrum when the caller passes none
   double* dm;           // [B][K] d lnL / d m_k
   double* lnl_tmp;      // [B]
+  double* gv;           // cloudy/clear mixing: [2B][P] gradients of the virtual samples
+  double* fbar;         // cloudy/clear mixing: [B] d lnL / d f_cld
+  double* mdot;         // [B] sum_k d lnL/dm_k (m_k - offset_k): d lnL / d ln(spectrum scale)
   const int32_t* bin_of;  // [n_nu_pad] bin holding each wavenumber, -1 if none
   const double* inv_cnt;  // [K] 1 / (hi_k - lo_k)
 };

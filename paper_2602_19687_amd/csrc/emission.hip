@@ -119,7 +119,8 @@ __global__ __launch_bounds__(kBlock) void k_emission(Model m, Work w, Tables tb,
 // staged in LDS and waves never wait for each other.  A workgroup holds four
 // neighbouring tiles of one sample.
 template <int S, bool CIA>
-__global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tables tb, int B, float* __restrict__ spec) {
+__global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tables tb, int B, float* __restrict__ spec,
+                                                           float* __restrict__ dtau_out) {
   const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = logical % B;
   const int lane = threadIdx.x & 63;
@@ -150,16 +151,12 @@ __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tabl
 #pragma unroll
   for (int p = 0; p < 2; ++p) ccs[p] = CIA ? tb.cc[(size_t)p * npad + nu] : 0.0f;
 
-  // Planck intensity per unit wavenumber, 2 h c^2 nu^3 / (exp(y) - 1), y = h c nu / k T;
-  // below y = 0.01 exp(y) - 1 is taken from its series
   const float nuv = (float)m.nu[nu];
   const float c1n3 = (float)(2.0 * kHpl * kC * kC) * nuv * nuv * nuv;
   const float c2n = (float)(kHpl * kC / kB) * nuv;
   auto planck_at = [&](int j) {
-    const float y = c2n * __builtin_amdgcn_rcpf((float)t_lev[j]);
-    const float em1 = y < 0.01f ? y * (1.0f + y * (0.5f + y * (1.0f / 6.0f)))
-                                : exp2_fast(1.4426950408889634f * y) - 1.0f;
-    return c1n3 * __builtin_amdgcn_rcpf(em1);
+    float y, em1;
+    return planck_f32(c1n3, c2n, (float)t_lev[j], y, em1);
   };
   const int n_mu = m.n_mu;
   float inv_mu[kMaxMu], inten[kMaxMu];
@@ -208,6 +205,8 @@ __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tabl
         d += exp2_fast(v);
       }
     }
+    // the reverse pass reads the layer optical depths back
+    if (dtau_out) dtau_out[((size_t)b * Lp + l) * npad + nu] = d;
     // ---- the sweep through layer l for every angle
     const float b_top = planck_at(l + 1);
     const float db = b_bot - b_top;
@@ -216,17 +215,8 @@ __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tabl
       if (k >= n_mu) break;
       const float x = d * inv_mu[k];
       const float e = exp2_fast(-1.4426950408889634f * x);
-      // 1 - e^-x and (1 - e^-x)/x - e^-x by their Taylor series for thin layers: there
-      // the differences cancel in FP32, and a thin hot layer above a cold one can
-      // carry most of the emergent intensity
       float om, src;
-      if (x < 0.1f) {
-        om = x * (1.0f + x * (-0.5f + x * (1.0f / 6.0f + x * (-1.0f / 24.0f + x * (1.0f / 120.0f + x * (-1.0f / 720.0f))))));
-        src = x * (0.5f + x * (-1.0f / 3.0f + x * (0.125f + x * (-1.0f / 30.0f + x * (1.0f / 144.0f + x * (-1.0f / 840.0f))))));
-      } else {
-        om = 1.0f - e;
-        src = om * __builtin_amdgcn_rcpf(x) - e;
-      }
+      slab_terms(x, e, om, src);
       // I e^-x + B_top (1 - e^-x) + (B_bot - B_top) src, as an increment of I
       inten[k] = fmaf(om, b_top - inten[k], fmaf(db, src, inten[k]));
     }
@@ -272,7 +262,8 @@ hipError_t emission_configure(const Model& m, bool fp64) {
   return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-void launch_emission(const Model& m, const Work& w, const Tables& tb, int B, void* spec, bool fp64, hipStream_t st) {
+void launch_emission(const Model& m, const Work& w, const Tables& tb, int B, void* spec, bool fp64, hipStream_t st,
+                     float* dtau_out) {
   const size_t lds = emission_lds_bytes(m, fp64);
   if (fp64) {
     hipLaunchKernelGGL(k_emission<double>, dim3((unsigned)(m.n_tiles64 * B)), dim3(kBlock), lds, st, m, w, tb, B,
@@ -280,7 +271,7 @@ void launch_emission(const Model& m, const Work& w, const Tables& tb, int B, voi
   } else {
     // four 64-wavenumber tiles (one per wave) of one sample per workgroup
     const dim3 grid((unsigned)((m.n_tiles64 + 3) / 4 * B));
-    void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec};
+    void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec, (void*)&dtau_out};
     hipLaunchKernel(emis_kernel_for(m.S, m.has_cia), grid, dim3(kBlock), args, lds, st);
   }
 }

@@ -245,6 +245,7 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
          g.cloud_qext < EXOFWD_QEXT_FIT || g.cloud_qext > EXOFWD_QEXT_GREY))
       return EXOFWD_ERR_CONFIG;
   }
+  if (g.has_fcld && (!g.has_cloud || g.mode != EXOFWD_TRANSMISSION)) return EXOFWD_ERR_CONFIG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || g.device < 0 || g.device >= ndev) return EXOFWD_ERR_DEVICE;
 
@@ -289,6 +290,8 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   int k = m.n_tp + m.S;
   m.idx_cloud = m.has_cloud ? k : -1;
   k += m.n_cloud;
+  m.has_fcld = g.has_fcld ? 1 : 0;
+  m.idx_fcld = m.has_fcld ? k++ : -1;
   m.idx_scale = m.has_scale ? k++ : -1;
   m.idx_offset = m.has_offset ? k++ : -1;
   m.P = k;
@@ -318,7 +321,8 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   }
 
   const bool fp64 = g.precision == EXOFWD_PREC_FP64;
-  const int Lp = m.L_pad, B = g.batch_max, RL = rec_len(m.S);
+  // per-sample buffers hold the virtual samples (two per sample with the cloudy/clear mixing)
+  const int Lp = m.L_pad, B = g.batch_max * (m.has_fcld ? 2 : 1), RL = rec_len(m.S);
   const size_t np = (size_t)m.n_nu_pad;
   bool ok = true;
   auto A = [&](auto* p) { ok = ok && p != nullptr; return p; };
@@ -430,6 +434,11 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   w.spec = A(dalloc<unsigned char>(c, (size_t)B * m.n_nu * rs));
   w.dm = A(dalloc<double>(c, (size_t)B * m.K));
   w.lnl_tmp = A(dalloc<double>(c, B));
+  w.mdot = A(dalloc<double>(c, B));
+  if (m.has_fcld) {
+    w.gv = A(dalloc<double>(c, (size_t)B * m.P));
+    w.fbar = A(dalloc<double>(c, B));
+  }
   {
     int32_t* d_bin = A(dalloc<int32_t>(c, np));
     double* d_inv = A(dalloc<double>(c, m.K));
@@ -443,7 +452,7 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
     w.bin_of = d_bin;
     w.inv_cnt = d_inv;
   }
-  if (ok && m.mode == kTransmission) ok = adjoint_alloc(c->aw, m, B, fp64, [&](size_t bytes) {
+  if (ok) ok = adjoint_alloc(c->aw, m, B, fp64, [&](size_t bytes) {
     return (void*)dalloc<unsigned char>(c, bytes);
   });
   if (!ok) {
@@ -451,7 +460,7 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
     return EXOFWD_ERR_NOMEM;
   }
   hipError_t e = m.mode == kTransmission ? trans_fwd_configure(m, fp64) : emission_configure(m, fp64);
-  if (e == hipSuccess && m.mode == kTransmission) e = adjoint_configure(m, fp64);
+  if (e == hipSuccess) e = adjoint_configure(m, fp64);
   if (e != hipSuccess) {
     exofwd_destroy(c);
     return EXOFWD_ERR_DEVICE;
@@ -543,23 +552,26 @@ static exofwd_status run_forward(exofwd_ctx* c, int32_t B, const double* params,
   exofwd_status s = EXOFWD_OK;
   hipStream_t st = (hipStream_t)hip_stream;
   const bool fp64 = c->precision == EXOFWD_PREC_FP64;
-  void* spec = spectra ? spectra : c->w.spec;
+  // with the cloudy/clear mixing the kernels run 2B virtual samples into the internal
+  // spectra; the likelihood kernel mixes each pair into the caller's spectrum
+  const int Bv = c->m.has_fcld ? 2 * B : B;
+  void* spec = (spectra && !c->m.has_fcld) ? spectra : c->w.spec;
   prof_begin(c, "profile", st);
-  launch_profile(c->m, c->w, B, params, n_layers, fp64, st);
+  launch_profile(c->m, c->w, Bv, params, n_layers, fp64, st);
   prof_end(c, st);
   if ((s = check_hip(c, hipGetLastError(), "profile launch"))) return s;
   if (c->m.mode == kTransmission) {
     prof_begin(c, "trans_fwd", st);
-    launch_trans_fwd(c->m, c->w, c->tb, B, spec, fp64, st, dtau_out);
+    launch_trans_fwd(c->m, c->w, c->tb, Bv, spec, fp64, st, dtau_out);
   } else {
     prof_begin(c, "emis_fwd", st);
-    launch_emission(c->m, c->w, c->tb, B, spec, fp64, st);
+    launch_emission(c->m, c->w, c->tb, Bv, spec, fp64, st, dtau_out);
   }
   prof_end(c, st);
   if ((s = check_hip(c, hipGetLastError(), "spectrum launch"))) return s;
   prof_begin(c, "loglike", st);
-  launch_loglike(c->m, c->w, B, params, spec, fp64, c->d_lo, c->d_hi, c->d_y, c->d_yerr,
-                 c->m.has_offset ? c->d_mask : nullptr, lnL, status, st);
+  launch_loglike(c->m, c->w, B, params, spec, c->m.has_fcld ? spectra : nullptr, fp64, c->d_lo, c->d_hi, c->d_y,
+                 c->d_yerr, c->m.has_offset ? c->d_mask : nullptr, lnL, status, st);
   prof_end(c, st);
   return check_hip(c, hipGetLastError(), "loglike launch");
 }
@@ -569,10 +581,10 @@ exofwd_status exofwd_grad(exofwd_ctx* c, int32_t B, const double* params, const 
   exofwd_status s = check_call(c, B, params);
   if (s) return s;
   if (!lnL || !grad) return fail(c, EXOFWD_ERR_ARG, "lnL and grad are required");
-  if (c->m.mode != kTransmission) return fail(c, EXOFWD_ERR_UNSUPPORTED, "the adjoint covers transmission only");
   if (!adjoint_supported(c->m, c->precision == EXOFWD_PREC_FP64))
     return fail(c, EXOFWD_ERR_UNSUPPORTED,
-                "the adjoint needs a non-PCHIP profile and n_layers_max <= 160 (reduced precision) or <= 128 (FP64)");
+                "the adjoint needs n_layers_max <= 160 (reduced precision) or <= 128 (FP64, transmission without the "
+                "non-grey cloud); the emission adjoint is reduced-precision only");
   auto enqueue = [&]() { return run_grad(c, B, params, n_layers, spectra, lnL, grad, status, hip_stream); };
   if (!c->use_graphs) return enqueue();
   return graph_call(c, 1, B, {params, n_layers, spectra, lnL, grad, status, nullptr}, (hipStream_t)hip_stream,
@@ -587,18 +599,25 @@ static exofwd_status run_grad(exofwd_ctx* c, int32_t B, const double* params, co
     return s;
   hipStream_t st = (hipStream_t)hip_stream;
   const bool fp64 = c->precision == EXOFWD_PREC_FP64;
-  prof_begin(c, "trans_adj", st);
-  launch_trans_adjoint(c->m, c->w, c->tb, c->aw, B, fp64, st);
+  const int Bv = c->m.has_fcld ? 2 * B : B;
+  if (c->m.mode == kTransmission) {
+    prof_begin(c, "trans_adj", st);
+    launch_trans_adjoint(c->m, c->w, c->tb, c->aw, Bv, fp64, st);
+  } else {
+    prof_begin(c, "emis_adj", st);
+    launch_emis_adjoint(c->m, c->w, c->aw, Bv, st);
+  }
   prof_end(c, st);
   if ((s = check_hip(c, hipGetLastError(), "adjoint launch"))) return s;
   if (!fp64) {
     prof_begin(c, "layer_sums", st);
-    launch_layer_sums(c->m, c->w, c->tb, c->aw, B, st);
+    launch_layer_sums(c->m, c->w, c->tb, c->aw, Bv, st);
     prof_end(c, st);
     if ((s = check_hip(c, hipGetLastError(), "layer-sum launch"))) return s;
   }
   prof_begin(c, "chain", st);
-  launch_chain(c->m, c->w, c->aw, B, params, c->d_mask, grad, fp64, st);
+  launch_chain(c->m, c->w, c->aw, Bv, params, c->d_mask, c->m.has_fcld ? c->w.gv : grad, fp64, st);
+  if (c->m.has_fcld) launch_mix_grad(c->m, c->w, B, grad, st);
   prof_end(c, st);
   return check_hip(c, hipGetLastError(), "chain launch");
 }
@@ -688,6 +707,7 @@ std::vector<double> neutral_params(const Model& m) {
     else if (m.cloud_profile == kQprofPower) { th[k++] = m.log10_pbot; th[k++] = 1.0; }
     if (m.cloud_qext == kQextFeature) { th[k++] = 0.5; th[k++] = 10.0; th[k++] = 0.0; th[k++] = 0.0; }
   }
+  if (m.has_fcld) th[m.idx_fcld] = 0.5;
   if (m.has_scale) th[m.idx_scale] = 1.0;
   if (m.has_offset) th[m.idx_offset] = 0.0;
   return th;
@@ -698,7 +718,7 @@ std::string tuning_key(const exofwd_ctx* c, int B) {
   hipGetDeviceProperties(&prop, c->device);
   std::ostringstream k;
   k << prop.gcnArchName << "/cu" << prop.multiProcessorCount << " mode" << c->m.mode << " prec" << c->precision
-    << " S" << c->m.S << " cia" << c->m.has_cia << " ng" << c->m.cloud_ng << " Lpad" << c->m.L_pad << " Lmax" << c->m.L_max << " nu"
+    << " S" << c->m.S << " cia" << c->m.has_cia << " ng" << c->m.cloud_ng << " fcld" << c->m.has_fcld << " Lpad" << c->m.L_pad << " Lmax" << c->m.L_max << " nu"
     << c->m.n_nu_pad << " tab" << c->m.n_t << "x" << c->m.n_p << " B" << B;
   std::string key = k.str();
   for (char& ch : key)

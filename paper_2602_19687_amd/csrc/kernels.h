@@ -19,9 +19,13 @@ void launch_profile(const Model& m, const Work& w, int B, const double* params, 
 // dtau_out (reduced precision only, may be null): layer optical depths [B][L_pad][n_nu_pad] for the reverse pass
 void launch_trans_fwd(const Model& m, const Work& w, const Tables& tb, int B, void* spec, bool fp64,
                       hipStream_t st, float* dtau_out = nullptr);
-void launch_loglike(const Model& m, const Work& w, int B, const double* params, const void* spec, bool spec_f64,
-                    const int32_t* bin_lo, const int32_t* bin_hi, const double* y, const double* yerr,
+// B real samples; with the cloudy/clear mixing spec holds the 2B virtual spectra and the
+// mixed spectrum goes to spec_out (may be null)
+void launch_loglike(const Model& m, const Work& w, int B, const double* params, const void* spec, void* spec_out,
+                    bool spec_f64, const int32_t* bin_lo, const int32_t* bin_hi, const double* y, const double* yerr,
                     const uint8_t* mask, double* lnl, int32_t* status_out, hipStream_t st);
+// cloudy/clear mixing: grad[b] = gv[2b] + gv[2b+1], with d lnL / d f_cld from the likelihood kernel
+void launch_mix_grad(const Model& m, const Work& w, int B, double* grad, hipStream_t st);
 size_t trans_fwd_lds_bytes(const Model& m, bool fp64);
 hipError_t trans_fwd_configure(const Model& m, bool fp64);
 

@@ -106,8 +106,11 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
   __shared__ int s_status;
   __shared__ int s_badt;
 
-  const double* th = params + (size_t)b * m.P;
-  int L = n_layers ? n_layers[b] : m.L_max;
+  // virtual sample b of real sample bs; a clear one (cloudy/clear mixing) has no cloud
+  const int bs = real_sample(m, b);
+  const bool cloudy = m.has_cloud && !clear_sample(m, b);
+  const double* th = params + (size_t)bs * m.P;
+  int L = n_layers ? n_layers[bs] : m.L_max;
   int status = 0;
   if (L < 1 || L > m.L_max) {
     status = kBadLayers;
@@ -270,11 +273,11 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
     const bool trans = m.mode == kTransmission;
     rl[3] = Real((trans && m.has_ray) ? n * (xh2 * m.ray_h2 + xhe * m.ray_he) * dr : 0.0);
     double dcl = 0.0;
-    if (m.cloud_ng) {
+    if (m.cloud_ng && cloudy) {
       // column q_l rho_l dr_l 3 / (4 r_eff); the kernels multiply it by Q_ext(nu) (Eq. 23)
       dcl = condensate_q(m.cloud_profile, th + q_first, logp_lev(l), logp_lev(l + 1), lp_bar, nullptr) * mu * kMu *
             n * dr * 0.75 / r_eff;
-    } else if (trans && m.has_cloud) {
+    } else if (trans && cloudy && !m.cloud_ng) {
       double f = (logp_lev(l) - log10_pc) * 2.302585092994045684017991454684 / dlnp;
       f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
       dcl = m.kappa_cloud * mu * kMu * n * f * dr;

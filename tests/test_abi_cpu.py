@@ -74,6 +74,8 @@ def test_product_path_fails_loudly_without_library(tmp_path):
     ({"cloud_profile": 3}, False),
     ({"cloud_qext": -1}, False),
     ({"mode": 1, "n_mu": 4, "tp": 1}, False),     # the non-grey cloud is a transmission model
+    ({"fcld": True}, True),
+    ({"fcld": True, "cloud": False}, False),     # the cloudy fraction needs a cloud
 ])
 def test_cloud_options_validated_before_device(change, ok):
     import synth

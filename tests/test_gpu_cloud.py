@@ -137,3 +137,74 @@ def test_cloud_full_size_sampled():
         print(f"cloud full b={b}: spectrum max rel err {err:.3e}")
         assert err < SPEC_TOL["mixed"]
         assert abs(lnl[b] - ref["lnL"]) <= SPEC_TOL["mixed"] * abs(ref["lnL"])
+
+
+# ---------------------------------------------------------------------------
+# cloudy/clear mixing (Eq. 26): the grey deck (config 3) and the non-grey slab (config 6)
+
+def fcld_wl(cid, batch, n_nu, step, n_bins=30):
+    wl = reduced(cid, n_nu=n_nu, n_bins=n_bins, batch=batch, step=step)
+    cfg = {**synth.CONFIGS[cid], "fcld": True}
+    bounds = synth.param_bounds(cfg)
+    u = np.random.default_rng(2000 + cid).uniform(size=(batch, len(bounds)))
+    wl.update(fcld=True, param_bounds=bounds, param_names=synth.param_names(cfg),
+              params=bounds[:, 0] + u * (bounds[:, 1] - bounds[:, 0]))
+    return wl
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("cid", [3, 6])
+def test_fcld_forward_every_sample(prec, cid):
+    wl = fcld_wl(cid, batch=8, n_nu=1000, step=30)
+    print(f"[gpu] fcld forward c{cid} {prec}", flush=True)
+    fm = _model(wl, prec, 8)
+    assert fm.n_params == len(wl["param_names"])
+    spec, lnl, st = fm.forward(torch.tensor(wl["params"], device="cuda"))
+    spec, lnl, st = spec.double().cpu().numpy(), lnl.cpu().numpy(), st.cpu().numpy()
+    fm.close()
+    errs = []
+    for b, ref in enumerate(oracle_forward(("fcld", cid), wl)):
+        assert st[b] == ref["status"]
+        if ref["status"]:
+            continue
+        errs.append(rel_err(spec[b], ref["spectrum"]))
+        assert abs(lnl[b] - ref["lnL"]) <= SPEC_TOL[prec] * abs(ref["lnL"]), (b, lnl[b], ref["lnL"])
+    print(f"fcld c{cid} {prec}: spectrum max rel err {max(errs):.3e}")
+    assert len(errs) >= 6 and max(errs) < SPEC_TOL[prec]
+
+
+@pytest.mark.parametrize("prec,cid", [("fp64", 3), ("mixed", 3), ("mixed", 6)])
+def test_fcld_grad_vs_complex_step(prec, cid):
+    wl = fcld_wl(cid, batch=3, n_nu=600, step=50)
+    print(f"[gpu] fcld grad c{cid} {prec}", flush=True)
+    fm = _model(wl, prec, 3)
+    assert fm.has_grad
+    lnl, g, st, _ = fm.grad(torch.tensor(wl["params"], device="cuda"))
+    g, st = g.cpu().numpy(), st.cpu().numpy()
+    fm.close()
+    tol = 1e-5 if prec == "fp64" else GRAD_TOL
+    worst = 0.0
+    for b in range(3):
+        assert st[b] == 0
+        gref = oracle.grad_complex_step(wl, wl["params"][b])
+        worst = max(worst, grad_err(g[b], gref))
+    print(f"fcld grad c{cid} {prec}: max err {worst:.3e}")
+    assert worst < tol
+
+
+def test_fcld_one_is_the_cloudy_model():
+    # f_cld = 1: the mixed spectrum, lnL and gradient equal those of the model without
+    # the fraction (the clear twin contributes exact zeros)
+    wl = fcld_wl(6, batch=4, n_nu=400, step=75)
+    k = wl["param_names"].index("f_cld")
+    th = wl["params"].copy()
+    th[:, k] = 1.0
+    plain = dict(wl, fcld=False)
+    a_fm, b_fm = _model(wl, "mixed", 4), _model(plain, "mixed", 4)
+    la, ga, sa, spa = a_fm.grad(torch.tensor(th, device="cuda"), want_spectra=True)
+    lb, gb, sb, spb = b_fm.grad(torch.tensor(np.delete(th, k, axis=1), device="cuda"), want_spectra=True)
+    a_fm.close()
+    b_fm.close()
+    assert torch.equal(spa, spb) and torch.equal(la, lb) and torch.equal(sa, sb)
+    ga, gb = ga.cpu().numpy(), gb.cpu().numpy()
+    np.testing.assert_allclose(np.delete(ga, k, axis=1), gb, rtol=1e-12, atol=0.0)
