@@ -207,6 +207,10 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
 
   for (int tile = t0; tile < t1; ++tile) {
     const int nu0 = tile * kTileA;
+    // row blocks below mi0 hold only opaque chords (tau > kOpaqueTau across the
+    // forward pass's 128-wavenumber tile): their seeds are exactly zero, so their
+    // products are skipped and the results are those of the full computation
+    const int mi0 = __builtin_amdgcn_readfirstlane(w.front[(size_t)b * m.n_tiles + nu0 / kTileNu]);
 
     // ---- phases B, C: tau = P dtau; seeds; tau_bar -> LDS [nu][i]; abar accumulation
     {
@@ -217,6 +221,15 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
       for (int q = 0; q < kSlots; ++q) {
         const int mi = t_mi[q];
         if (mi < 0) continue;
+        if (mi < mi0) {
+          // e^-tau = 0: abar takes dbar (1 - 0), tau_bar is 0
+#pragma unroll
+          for (int j = 0; j < 16; ++j) abar_acc[q][j] += dbar;
+#pragma unroll
+          for (int qd = 0; qd < 4; ++qd)
+            *reinterpret_cast<uint4*>(s_tt + col * ld + 32 * mi + 8 * qd + 4 * h) = make_uint4(0u, 0u, 0u, 0u);
+          continue;
+        }
         f32x16 acc = {};
         // path-matrix fragments are loaded one k-step ahead
         bf16x8 nh = frag(rs_p, mi * KB + 2 * mi, 0), nl_ = frag(rs_p, mi * KB + 2 * mi, lo_plane);
@@ -265,7 +278,7 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
 #pragma unroll
     for (int q = 0; q < kPSlotsA; ++q) {
       const int mi = pt_mi[q], nl = pt_nl[q];
-      if (mi < 0) continue;
+      if (mi < mi0) continue;   // also the empty slots (mi = -1): zero seeds add nothing
       const uint32_t* pa = s_tt + 8 * h * ld + 32 * mi + (lane & 31);
       const uint32_t* pbp = s_dt + 8 * h * ld + 32 * nl + (lane & 31);
 #pragma unroll 1
@@ -297,9 +310,11 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
         if (ml < 0) continue;
         f32x16 acc = {};
         const int kend = min(2 * ml + 2, KBe);
-        bf16x8 nh = frag(rs_pt, ml * KB, 0), nl_ = frag(rs_pt, ml * KB, lo_plane);
+        // the seed rows of blocks below mi0 are zero: the sum starts at row 32 mi0
+        const int kbeg = min(2 * mi0, kend);
+        bf16x8 nh = frag(rs_pt, ml * KB + kbeg, 0), nl_ = frag(rs_pt, ml * KB + kbeg, lo_plane);
 #pragma unroll 1
-        for (int ki = 0; ki < kend; ++ki) {
+        for (int ki = kbeg; ki < kend; ++ki) {
           const bf16x8 ah = nh, al = nl_;
           if (ki + 1 < kend) {
             nh = frag(rs_pt, ml * KB + ki + 1, 0);
@@ -426,6 +441,17 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
   const int t0 = chunk * aw.ls_tiles, t1 = min(t0 + aw.ls_tiles, m.n_tiles);
   for (int tile = t0; tile < t1; ++tile) {
     const int nu0 = tile * kTileNu;
+    // every chord through the group's layers opaque across the tile: dtau_bar is
+    // exactly zero there and the tile adds nothing (the deep layers of most atmospheres)
+    float2 dbq[kLsLayers];
+    bool live = false;
+#pragma unroll
+    for (int q = 0; q < kLsLayers; ++q) {
+      dbq[q] = l0 + q < L ? *reinterpret_cast<const float2*>(dtb + (size_t)(l0 + q) * npad + nu0 + 2 * lane)
+                          : make_float2(0.0f, 0.0f);
+      live |= dbq[q].x != 0.0f || dbq[q].y != 0.0f;
+    }
+    if (__builtin_amdgcn_ballot_w64(live) == 0) continue;
     const LaneConst<S> kc = load_lane<S, CIA>(m, tb, nu0 + 2 * lane);
     float q0 = 1.0f, q1 = 1.0f;
     if constexpr (NGC) {
@@ -437,10 +463,10 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
     for (int q = 0; q < kLsLayers; ++q) {
       const int l = l0 + q;
       if (l >= L) continue;
+      const float2 db = dbq[q];
       const LayerCoef<S> c = load_layer<S>(m, cells, rec, l, (uint32_t)nu0 * 2u, g);
       float t0_[S + 2], t1_[S + 2], dw0[S + 2], dw1[S + 2];
       layer_terms_deriv<S, CIA>(c, kc, g, rh, rhc, voff, t0_, t1_, dw0, dw1);
-      const float2 db = *reinterpret_cast<const float2*>(dtb + (size_t)l * npad + nu0 + 2 * lane);
       // G_s += db t_s per wavenumber; the T-weight sums take db once per wavenumber
       // times z = sum_s t_s dw_s
       float z0 = 0.0f, z1 = 0.0f;

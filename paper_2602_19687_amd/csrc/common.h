@@ -25,6 +25,9 @@ constexpr int kTileNu = 128;      // wavenumbers per tile of the reduced-precisi
 constexpr int kTile64 = 64;       // wavenumbers per tile of the FP64 and emission kernels
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kBlockT = 512;      // threads per workgroup of the reduced-precision transmission kernels
+// a chord optical depth beyond which e^-tau is zero in FP32 with a wide margin
+// (e^-103.3 is already below the smallest denormal): its adjoint seed is exactly 0
+constexpr float kOpaqueTau = 110.0f;
 
 // per-layer record of the opacity kernels (one per sample and layer)
 //   [0] wT, [1] wP, [2] wTc, [3] Rayleigh coefficient R_l (x (nu/1e4)^4),
@@ -82,6 +85,9 @@ struct Work {
   double* cloud;        // [B][kCloudSpec] non-grey cloud: r_eff [cm], a, Q0, A, lambda0 [um], omega [um], xi
   float* cloud_q;       // reduced precision, non-grey: [B][1 + kCloudSpec][n_nu_pad] Q_ext(nu), dQ_ext/dp_k
   int32_t* cells;       // [B][L_pad] packed cells
+  int32_t* front;       // reduced precision: [B][n_tiles] opaque 32-row chord blocks at the bottom of
+                        //   each 128-wavenumber tile (every tau > kOpaqueTau), set by a forward pass
+                        //   that stores the layer optical depths
   void* rec;            // [B][L_pad][rec_len] float (mixed) or double (fp64)
   void* area;           // [B][L_pad] (r_{i+1}^2 - r_i^2)/R_s^2, float or double
   double* pm64;         // fp64: [B][L_pad][L_pad] path matrix

@@ -175,11 +175,14 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_emis(Model m, Work w, Tab
     for (int q = 0; q < kLayers; ++q) {
       const int l = l0 + q;
       if (l >= L) continue;
+      const float db = dtb[(size_t)l * npad + nu];
+      // a layer seen through no transmission at any wavenumber of the tile adds
+      // nothing (the skip is per layer: the opaque depth varies across a tile)
+      if (__builtin_amdgcn_ballot_w64(db != 0.0f) == 0) continue;
       const int cl = cells[l];
       const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
       const float* rl = rec + (size_t)l * RL;
       const float wt = rl[0], wp = rl[1], omp = 1.0f - wp;
-      const float db = dtb[(size_t)l * npad + nu];
       float z = 0.0f;
 #pragma unroll
       for (int s = 0; s < S; ++s) {

@@ -58,6 +58,8 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
   uint16_t* s_blo = s_bhi + kTileNu * stride;
   float* s_area = reinterpret_cast<float*>(s_blo + kTileNu * stride);
   float* s_red = s_area + Lp;   // [8][32]
+  int* s_live = reinterpret_cast<int*>(s_red + 8 * 32);   // [8] row block holds a chord below kOpaqueTau
+  if (tid < 8) s_live[tid] = 0;
 
   const float* area = reinterpret_cast<const float*>(w.area) + (size_t)b * Lp;
   for (int i = tid; i < Lp; i += kBlockT) s_area[i] = area[i];
@@ -141,11 +143,15 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
     }
     // phase C: annulus-weighted absorption 1 - e^-tau, summed over rows
+    bool live = false;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int row = 32 * mi + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
       dsum = fmaf(s_area[row], 1.0f - exp2_fast(-1.4426950408889634f * acc[j]), dsum);
+      live |= !(acc[j] > kOpaqueTau);
     }
+    // the reverse pass skips row blocks whose chords are all opaque across the tile
+    if (dtau_out && __builtin_amdgcn_ballot_w64(live) != 0 && lane == 0) s_live[mi] = 1;
   }
   dsum += __shfl_xor(dsum, 32);
   if (lane < 32) s_red[wv * 32 + lane] = dsum;
@@ -154,6 +160,11 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
     const int h = tid >> 5, c = tid & 31;
     const float tot = s_red[h * 32 + c] + s_red[(h + 4) * 32 + c];
     if (nu0 + tid < m.n_nu) out[nu0 + tid] = (float)w.core[b] + tot;
+  }
+  if (dtau_out && tid == 0) {
+    int f = 0;
+    while (f < MBe && !s_live[f]) ++f;
+    w.front[(size_t)b * m.n_tiles + tile] = f;
   }
 }
 
@@ -250,7 +261,7 @@ const void* fwd_kernel_for(int S, bool cia, bool ng) {
 
 size_t trans_fwd_lds_bytes(const Model& m, bool fp64) {
   if (fp64) return (size_t)m.L_pad * kTile64 * 8 + 4 * kTile64 * 8;
-  return (size_t)2 * kTileNu * (m.L_pad + 8) * 2 + (size_t)m.L_pad * 4 + 8 * 32 * 4;
+  return (size_t)2 * kTileNu * (m.L_pad + 8) * 2 + (size_t)m.L_pad * 4 + 8 * 32 * 4 + 8 * 4;
 }
 
 hipError_t trans_fwd_configure(const Model& m, bool fp64) {
