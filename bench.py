@@ -235,14 +235,17 @@ def main():
     # reduced-precision forward+gradient step is timed beside it
     mixed = run("mixed", args.steps, args.warmup, want_grad=cid != 2)
     print(f"[bench] mixed {mixed['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
-    emis_grad = None
+    emis_grad = emis_grad64 = None
     if cid == 2:
         emis_grad = run("mixed", max(2, args.steps // 2), 1, want_grad=True)
         print(f"[bench] mixed forward+grad {emis_grad['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+        if not args.no_fp64:
+            emis_grad64 = run("fp64", 2, 1, want_grad=True)
+            print(f"[bench] fp64 forward+grad {emis_grad64['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     fp64 = None
     # the FP64 adjoint stops at 128 padded layers, so the high-resolution batch has no FP64 comparison
     if not args.no_fp64 and cid in (1, 2):
-        fp64 = run("fp64", max(2, args.steps // 4), 1)
+        fp64 = run("fp64", max(2, args.steps // 4), 1, want_grad=cid != 2)
         print(f"[bench] fp64 {fp64['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
 
     value = B / (mixed["ms_per_step"] / 1e3)
@@ -312,6 +315,13 @@ def main():
                                "ms_per_step": round(emis_grad["ms_per_step"], 4),
                                "kernel_ms_per_step": {k: round(v[0] / max(1, v[1]), 4)
                                                       for k, v in emis_grad["kernels"].items() if v[1]}}
+        if emis_grad64 is not None and emis_grad64["has_grad"]:
+            out["forward_grad"]["fp64_ms_per_step"] = round(emis_grad64["ms_per_step"], 3)
+            out["forward_grad"]["speedup_vs_fp64"] = round(emis_grad64["ms_per_step"] / emis_grad["ms_per_step"], 3)
+            ok = (emis_grad["status"] == 0) & (emis_grad64["status"] == 0)
+            gm, g64 = emis_grad["grad"][ok], emis_grad64["grad"][ok]
+            scale = np.maximum(np.abs(g64), 1e-3 * np.max(np.abs(g64), axis=1, keepdims=True))
+            out["forward_grad"]["max_grad_err_vs_fp64_gpu"] = float(np.max(np.abs(gm - g64) / scale))
     if mixed["graph_ms"] is not None:
         out["graph_replay"] = {"ms_per_step": round(mixed["graph_ms"], 4),
                                "spectra_per_s": round(B / (mixed["graph_ms"] / 1e3), 1)}

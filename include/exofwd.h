@@ -148,7 +148,9 @@ typedef struct exofwd_config {
 
 /* Validate the configuration, upload and encode the tables, allocate the
  * workspace for batch_max samples of n_layers_max layers.  Synchronous.
- * On success *out owns all device memory of the context. */
+ * On success *out owns all device memory of the context.  EXOFWD_ERR_CONFIG for
+ * an invalid description, EXOFWD_ERR_UNSUPPORTED for FP64 emission with more than
+ * 128 padded layers, EXOFWD_ERR_DEVICE / EXOFWD_ERR_NOMEM for device failures. */
 exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out);
 
 /* Free everything the context owns (synchronises its device). NULL is a no-op. */
@@ -158,9 +160,10 @@ int32_t exofwd_num_params(const exofwd_ctx* ctx);   /* P, or -1 for NULL */
 int32_t exofwd_num_nu(const exofwd_ctx* ctx);       /* n_nu, or -1 */
 int32_t exofwd_num_bins(const exofwd_ctx* ctx);     /* K, or -1 */
 int32_t exofwd_precision(const exofwd_ctx* ctx);    /* EXOFWD_PREC_*, or -1 */
-/* 1 if exofwd_grad supports this context's workload (transmission, isothermal or
- * Guillot profile, n_layers_max <= 160 in MIXED or <= 128 in FP64 precision),
- * 0 if not, -1 for a NULL context */
+/* 1 if exofwd_grad supports this context's workload, 0 if not, -1 for a NULL
+ * context.  Supported: transmission with n_layers_max <= 160 in MIXED precision or
+ * <= 128 in FP64 (FP64 without the non-grey cloud); emission with n_layers_max
+ * <= 160 in MIXED or <= 128 in FP64; every T-p profile. */
 int32_t exofwd_grad_supported(const exofwd_ctx* ctx);
 
 /*
@@ -178,8 +181,7 @@ exofwd_status exofwd_forward(exofwd_ctx* ctx, int32_t B, const double* params,
 
 /*
  * lnL and its gradient with respect to every parameter for B samples, by the
- * hand-written adjoint.  Workloads outside exofwd_grad_supported (emission, the
- * PCHIP profile, more layers than the precision allows) return
+ * hand-written adjoint.  Workloads outside exofwd_grad_supported return
  * EXOFWD_ERR_UNSUPPORTED.
  *   lnL      dev [B] double (required)
  *   grad     dev [B][P] double (required): d lnL / d params

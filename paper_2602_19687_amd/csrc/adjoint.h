@@ -40,6 +40,11 @@ struct AdjWork {
   float* hq;           // non-grey cloud: [B_max][lsum_stride][kCloudSpec] per-chunk sums over nu of
                        //   (sum_l D_l dtau_bar_l) dQ_ext/dp_k
   float* psum;         // emission: [B_max][n_tiles64][L_pad+1] per-tile sums over nu of d lnL/dB_j dB_j/dT_j
+  // FP64 emission: the same buffers in double (dtau, dtau_bar, per-level and per-layer sums)
+  double* dtau64;
+  double* dtb64;
+  double* psum64;
+  double* lsum64;      // [B_max][lsum_chunks][L_pad][n_sums]
   int lsum_chunks;     // wavenumber chunks of the layer-sum kernel (n_tiles / ls_tiles, rounded up)
   int lsum_stride;     // allocated chunks per sample (the bound over the ls_tiles choices)
 };
@@ -50,15 +55,17 @@ bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std:
 hipError_t adjoint_configure(const Model& m, bool fp64);
 void launch_trans_adjoint(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, bool fp64,
                           hipStream_t st);
-// reduced-precision path only: per-layer sums from the stored dtau_bar
-void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, hipStream_t st);
+// per-layer sums from the stored dtau_bar (reduced-precision transmission, emission in both precisions)
+void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, bool fp64,
+                       hipStream_t st);
 void launch_chain(const Model& m, const Work& w, const AdjWork& aw, int B, const double* params, const uint8_t* mask,
                   double* grad, bool fp64, hipStream_t st);
 // whether the adjoint supports this workload: transmission with L_pad <= 160 in
-// reduced precision, <= 128 and no non-grey cloud in FP64; emission in reduced
-// precision with L_pad <= 160
-void launch_emis_adjoint(const Model& m, const Work& w, const AdjWork& aw, int B, hipStream_t st);
-void launch_layer_sums_emis(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, hipStream_t st);
+// reduced precision, <= 128 and no non-grey cloud in FP64; emission with L_pad <= 160
+// in reduced precision, <= 128 in FP64
+void launch_emis_adjoint(const Model& m, const Work& w, const AdjWork& aw, int B, bool fp64, hipStream_t st);
+void launch_layer_sums_emis(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, bool fp64,
+                            hipStream_t st);
 bool adjoint_supported(const Model& m, bool fp64);
 // default reverse-kernel shape, whether a shape serves this model, and switching shapes
 int adjoint_default_variant(const Model& m);

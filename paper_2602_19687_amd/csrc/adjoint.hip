@@ -877,7 +877,11 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
   auto layer_sum = [&](int l, int k) {
     double v = 0.0;
     if constexpr (sizeof(PbarT) == 8) {
-      for (int c = 0; c < Cn; ++c) v += aw.layer_sums[(((size_t)b * C + c) * Lp + l) * NS + k];
+      if (m.mode == kEmission) {
+        for (int c = 0; c < aw.lsum_chunks; ++c) v += aw.lsum64[(((size_t)b * aw.lsum_stride + c) * Lp + l) * NS + k];
+      } else {
+        for (int c = 0; c < Cn; ++c) v += aw.layer_sums[(((size_t)b * C + c) * Lp + l) * NS + k];
+      }
     } else {
       for (int c = 0; c < aw.lsum_chunks; ++c) v += (double)aw.lsum[(((size_t)b * aw.lsum_stride + c) * Lp + l) * NT + k];
     }
@@ -1119,7 +1123,11 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
     const double* tlev = w.t_lev + (size_t)b * (Lp + 1);
     for (int j = tid; j <= L; j += kBlock) {
       double tb = 0.0;
-      for (int t = 0; t < m.n_tiles64; ++t) tb += (double)aw.psum[((size_t)b * m.n_tiles64 + t) * (Lp + 1) + j];
+      for (int t = 0; t < m.n_tiles64; ++t) {
+        const size_t i = ((size_t)b * m.n_tiles64 + t) * (Lp + 1) + j;
+        if constexpr (sizeof(PbarT) == 8) tb += aw.psum64[i];
+        else tb += (double)aw.psum[i];
+      }
       tp_grad(logp_lev(j), tlev[j], tb);
     }
   }
@@ -1207,7 +1215,7 @@ int adjoint_chunks(const Model& m, const AdjWork& aw, int B, bool fp64) {
 }
 
 bool adjoint_supported(const Model& m, bool fp64) {
-  if (m.mode == kEmission) return !fp64 && m.L_pad <= 160;
+  if (m.mode == kEmission) return m.L_pad <= (fp64 ? 128 : 160);
   return m.L_pad <= (fp64 ? 128 : 160) && !(fp64 && m.cloud_ng);
 }
 
@@ -1239,6 +1247,15 @@ bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std:
   aw.ls_tiles = 8;
   aw.max_pairs = pairs;
   const size_t Lp = m.L_pad;
+  if (m.mode == kEmission && fp64) {
+    aw.lsum_stride = (m.n_tiles + kLsTileChoices[0] - 1) / kLsTileChoices[0];
+    aw.lsum_chunks = (m.n_tiles + aw.ls_tiles - 1) / aw.ls_tiles;
+    aw.dtb64 = (double*)alloc((size_t)B_max * m.L_pad * m.n_nu_pad * sizeof(double));
+    aw.dtau64 = (double*)alloc((size_t)B_max * m.L_pad * m.n_nu_pad * sizeof(double));
+    aw.lsum64 = (double*)alloc((size_t)B_max * aw.lsum_stride * Lp * n_lsums(m) * sizeof(double));
+    aw.psum64 = (double*)alloc((size_t)B_max * m.n_tiles64 * (Lp + 1) * sizeof(double));
+    return aw.dtb64 && aw.dtau64 && aw.lsum64 && aw.psum64;
+  }
   if (m.mode == kEmission) {
     aw.lsum_stride = (m.n_tiles + kLsTileChoices[0] - 1) / kLsTileChoices[0];
     aw.lsum_chunks = (m.n_tiles + aw.ls_tiles - 1) / aw.ls_tiles;
@@ -1360,9 +1377,10 @@ void launch_trans_adjoint(const Model& m, const Work& w, const Tables& tb, const
                   adj_lds_bytes(m, fp64, aw.variant), st);
 }
 
-void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, hipStream_t st) {
+void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, bool fp64,
+                       hipStream_t st) {
   if (m.mode == kEmission) {
-    launch_layer_sums_emis(m, w, tb, aw, B, st);
+    launch_layer_sums_emis(m, w, tb, aw, B, fp64, st);
     return;
   }
   const int NG = (m.L_max + kLsLayers - 1) / kLsLayers;

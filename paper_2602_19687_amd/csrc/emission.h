@@ -2,9 +2,10 @@
 #include "common.h"
 
 namespace exofwd {
-// dtau_out (reduced precision only, may be null): layer optical depths [B][L_pad][n_nu_pad] for the reverse pass
+// dtau_out (may be null): layer optical depths [B][L_pad][n_nu_pad] for the reverse pass, float in reduced
+// precision, double in FP64
 void launch_emission(const Model& m, const Work& w, const Tables& tb, int B, void* spec, bool fp64, hipStream_t st,
-                     float* dtau_out = nullptr);
+                     void* dtau_out = nullptr);
 hipError_t emission_configure(const Model& m, bool fp64);
 size_t emission_lds_bytes(const Model& m, bool fp64);
 

@@ -60,7 +60,8 @@ __device__ inline Real lin_source(Real x, Real e) {
 
 // plain FP64 path
 template <typename Real>
-__global__ __launch_bounds__(kBlock) void k_emission(Model m, Work w, Tables tb, int B, Real* __restrict__ spec) {
+__global__ __launch_bounds__(kBlock) void k_emission(Model m, Work w, Tables tb, int B, Real* __restrict__ spec,
+                                                     Real* __restrict__ dtau_out) {
   static_assert(sizeof(Real) == 8, "the reduced-precision path is k_emission_mixed");
   extern __shared__ __align__(16) unsigned char lds[];
   const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
@@ -83,7 +84,11 @@ __global__ __launch_bounds__(kBlock) void k_emission(Model m, Work w, Tables tb,
   const int nu = nu0 + lane;
   const double* t_lev = w.t_lev + (size_t)b * (Lp + 1);
   const Real nuv = Real(m.nu[nu]);
-  for (int l = wv; l < L; l += 4) s_dt[l * kTile64 + lane] = opacity_fp64_e(m, tb, cells[l], rec + (size_t)l * RL, nu);
+  for (int l = wv; l < L; l += 4) {
+    s_dt[l * kTile64 + lane] = opacity_fp64_e(m, tb, cells[l], rec + (size_t)l * RL, nu);
+    // the reverse pass reads the layer optical depths back
+    if (dtau_out) dtau_out[((size_t)b * Lp + l) * m.n_nu_pad + nu] = s_dt[l * kTile64 + lane];
+  }
   for (int j = wv; j <= L; j += 4) s_b[j * kTile64 + lane] = planck<Real>(Real(t_lev[j]), nuv);
   __syncthreads();
 
@@ -263,15 +268,16 @@ hipError_t emission_configure(const Model& m, bool fp64) {
 }
 
 void launch_emission(const Model& m, const Work& w, const Tables& tb, int B, void* spec, bool fp64, hipStream_t st,
-                     float* dtau_out) {
+                     void* dtau_out) {
   const size_t lds = emission_lds_bytes(m, fp64);
   if (fp64) {
     hipLaunchKernelGGL(k_emission<double>, dim3((unsigned)(m.n_tiles64 * B)), dim3(kBlock), lds, st, m, w, tb, B,
-                       (double*)spec);
+                       (double*)spec, (double*)dtau_out);
   } else {
     // four 64-wavenumber tiles (one per wave) of one sample per workgroup
     const dim3 grid((unsigned)((m.n_tiles64 + 3) / 4 * B));
-    void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec, (void*)&dtau_out};
+    float* dtau_f = (float*)dtau_out;
+    void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec, (void*)&dtau_f};
     hipLaunchKernel(emis_kernel_for(m.S, m.has_cia), grid, dim3(kBlock), args, lds, st);
   }
 }

@@ -228,6 +228,167 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_emis(Model m, Work w, Tab
   }
 }
 
+// ============================================================================
+// plain FP64 emission adjoint: the same two passes and sums in double, from the
+// FP64 forward's stored layer optical depths and the FP64 log10 sigma tables
+__global__ __launch_bounds__(kBlock) void k_emis_adj_fp64(Model m, Work w, AdjWork aw, int B) {
+  const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int b = logical % B;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tile = (logical / B) * 4 + wv;
+  if (tile >= m.n_tiles64 || w.status[b]) return;
+  const int nu = tile * kTile64 + lane;
+  const int L = w.nlay[b], Lp = m.L_pad;
+  const size_t npad = (size_t)m.n_nu_pad;
+  const double* dt = aw.dtau64 + (size_t)b * Lp * npad + nu;
+  double* dtb = aw.dtb64 + (size_t)b * Lp * npad + nu;
+  double* ps = aw.psum64 + ((size_t)b * m.n_tiles64 + tile) * (Lp + 1);
+  const double* t_lev = w.t_lev + (size_t)b * (Lp + 1);
+  const int kb = w.bin_of[nu];
+  const double nd = m.nu[nu];
+  double seed = 0.0;
+  if (kb >= 0) {
+    const double fstar = M_PI * 2.0 * kHpl * kC * kC * nd * nd * nd / expm1(kHpl * kC * nd / (kB * m.t_star));
+    seed = w.dm[(size_t)b * m.K + kb] * w.inv_cnt[kb] * m.dilution * w.core[b] / fstar;
+  }
+  const double c1n3 = 2.0 * kHpl * kC * kC * nd * nd * nd, c2n = kHpl * kC / kB * nd;
+  auto planck_at = [&](int j, double& dbdt) {
+    const double t = t_lev[j], y = c2n / t, em1 = expm1(y);
+    const double bv = c1n3 / em1;
+    dbdt = bv * y * (em1 + 1.0) / (em1 * t);
+    return bv;
+  };
+  // 1 - e^-x, (1 - e^-x)/x - e^-x and its derivative, by series for thin slabs
+  auto slab = [](double x, double& e, double& om, double& src, double& dsrc) {
+    e = exp(-x);
+    om = -expm1(-x);
+    if (x < 1.0e-4) src = x * (0.5 + x * (-1.0 / 3.0 + x * (0.125 + x * (-1.0 / 30.0))));
+    else src = om / x - e;
+    if (x < 1.0e-3) dsrc = 0.5 + x * (-2.0 / 3.0 + x * (0.375 + x * (-2.0 / 15.0 + x * (5.0 / 144.0))));
+    else dsrc = e * (1.0 + 1.0 / x) - om / (x * x);
+  };
+  const int n_mu = m.n_mu;
+  double inv_mu[kMaxMu], inten[kMaxMu], ibar_top[kMaxMu];
+  double above = 0.0;
+  for (int l = L - 1; l >= 0; --l) {
+    dtb[(size_t)l * npad] = above;
+    above += dt[(size_t)l * npad];
+  }
+  double dbdt_bot;
+  double b_bot = planck_at(0, dbdt_bot);
+  for (int k = 0; k < kMaxMu; ++k) {
+    inv_mu[k] = k < n_mu ? 1.0 / m.mu_nodes[k] : 0.0;
+    ibar_top[k] = k < n_mu ? seed * 2.0 * M_PI * m.mu_weights[k] * m.mu_nodes[k] : 0.0;
+    inten[k] = b_bot;
+  }
+  double bb_lev = 0.0;
+  for (int k = 0; k < n_mu; ++k) bb_lev += ibar_top[k] * exp(-above * inv_mu[k]);
+  for (int l = 0; l < L; ++l) {
+    const double d = dt[(size_t)l * npad];
+    const double x_above = dtb[(size_t)l * npad];
+    double dbdt_top;
+    const double b_top = planck_at(l + 1, dbdt_top);
+    const double db = b_bot - b_top;
+    double dsum = 0.0, bt_bar = 0.0;
+    for (int k = 0; k < n_mu; ++k) {
+      double e, om, src, dsrc;
+      slab(d * inv_mu[k], e, om, src, dsrc);
+      const double ib = ibar_top[k] * exp(-x_above * inv_mu[k]);
+      dsum += ib * ((b_top - inten[k]) * e + db * dsrc) * inv_mu[k];
+      bt_bar += ib * (om - src);
+      bb_lev += ib * src;
+      inten[k] += om * (b_top - inten[k]) + db * src;
+    }
+    dtb[(size_t)l * npad] = dsum;
+    double lev = bb_lev * dbdt_bot;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) lev += __shfl_xor(lev, off);
+    if (lane == 0) ps[l] = lev;
+    bb_lev = bt_bar;
+    b_bot = b_top;
+    dbdt_bot = dbdt_top;
+  }
+  double lev = bb_lev * dbdt_bot;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) lev += __shfl_xor(lev, off);
+  if (lane == 0) ps[L] = lev;
+}
+
+// FP64 per-layer opacity sums of the emission path (log10 sigma tables, one
+// wavenumber per lane, layers whose dtau_bar is zero across the tile skipped)
+__global__ __launch_bounds__(kBlock) void k_layer_sums_emis_fp64(Model m, Work w, Tables tb, AdjWork aw, int B) {
+  constexpr int kLayers = 5;
+  const int S = m.S, NS = n_sums(S);
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int NG = (m.L_max + kLayers - 1) / kLayers;
+  const int per_chunk = B * NG;
+  const int chunk = gw / per_chunk;
+  if (chunk >= aw.lsum_chunks) return;
+  const int rem = gw - chunk * per_chunk;
+  const int b = rem / NG, lg = rem - b * NG;
+  if (w.status[b]) return;
+  const int L = w.nlay[b];
+  const int l0 = lg * kLayers;
+  if (l0 >= L) return;
+  const int Lp = m.L_pad, RL = rec_len(S);
+  const size_t npad = (size_t)m.n_nu_pad;
+  const double* rec = reinterpret_cast<const double*>(w.rec) + (size_t)b * Lp * RL;
+  const int32_t* cells = w.cells + (size_t)b * Lp;
+  const double* dtb = aw.dtb64 + (size_t)b * Lp * npad;
+  double acc[kLayers][kMaxSpecies + kExtraSums];
+  for (int q = 0; q < kLayers; ++q)
+    for (int k = 0; k < NS; ++k) acc[q][k] = 0.0;
+  const int t0 = 2 * chunk * aw.ls_tiles, t1 = min(t0 + 2 * aw.ls_tiles, m.n_tiles64);
+  for (int tile = t0; tile < t1; ++tile) {
+    const int nu = tile * kTile64 + lane;
+    for (int q = 0; q < kLayers; ++q) {
+      const int l = l0 + q;
+      if (l >= L) continue;
+      const double db = dtb[(size_t)l * npad + nu];
+      if (__builtin_amdgcn_ballot_w64(db != 0.0) == 0) continue;
+      const int cl = cells[l];
+      const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
+      const double* rl = rec + (size_t)l * RL;
+      const double wt = rl[0], wp = rl[1];
+      double z = 0.0;
+      for (int s2 = 0; s2 < S; ++s2) {
+        const double* p = tb.t64 + (((size_t)s2 * m.n_t + it) * m.n_p + ip) * npad + nu;
+        const double t00 = p[0], t10 = p[(size_t)m.n_p * npad], t01 = p[npad], t11 = p[(size_t)(m.n_p + 1) * npad];
+        const double v = (1.0 - wt) * (1.0 - wp) * t00 + wt * (1.0 - wp) * t10 + (1.0 - wt) * wp * t01 + wt * wp * t11;
+        const double t = exp2(v * kLog2_10 + rl[kRecFixed + s2]);
+        const double dw = ((1.0 - wp) * (t10 - t00) + wp * (t11 - t01)) * kLog2_10;   // log2 units
+        acc[q][s2] += db * t;
+        z += t * dw;
+      }
+      acc[q][S] += db * z;
+      if (m.has_cia) {
+        const double wtc = rl[2];
+        double y = 0.0;
+        for (int c = 0; c < 2; ++c) {
+          const double* p = tb.tc64 + ((size_t)c * m.n_tc + itc) * npad + nu;
+          const double t = exp2(((1.0 - wtc) * p[0] + wtc * p[npad]) * kLog2_10 + rl[5 + c]);
+          acc[q][S + 1 + c] += db * t;
+          y += t * (p[npad] - p[0]) * kLog2_10;
+        }
+        acc[q][S + 3] += db * y;
+      }
+    }
+  }
+  double* out = aw.lsum64 + ((size_t)b * aw.lsum_stride + chunk) * Lp * NS;
+  for (int q = 0; q < kLayers; ++q) {
+    const int l = l0 + q;
+    if (l >= L) continue;
+    for (int k = 0; k < NS; ++k) {
+      double v = acc[q][k];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0) out[(size_t)l * NS + k] = v;
+    }
+  }
+}
+
 const void* ls_emis_kernel_for(int S, bool cia) {
 #define EXOFWD_CASE(n) \
   case n: return cia ? (const void*)k_layer_sums_emis<n, true> : (const void*)k_layer_sums_emis<n, false>;
@@ -239,16 +400,24 @@ const void* ls_emis_kernel_for(int S, bool cia) {
   return nullptr;
 }
 
-void launch_emis_adjoint(const Model& m, const Work& w, const AdjWork& aw, int B, hipStream_t st) {
+void launch_emis_adjoint(const Model& m, const Work& w, const AdjWork& aw, int B, bool fp64, hipStream_t st) {
   // four 64-wavenumber tiles (one per wave) of one sample per workgroup
-  hipLaunchKernelGGL(k_emis_adj_mixed, dim3((unsigned)((m.n_tiles64 + 3) / 4 * B)), dim3(kBlock), 0, st, m, w, aw, B);
+  const dim3 grid((unsigned)((m.n_tiles64 + 3) / 4 * B));
+  if (fp64) hipLaunchKernelGGL(k_emis_adj_fp64, grid, dim3(kBlock), 0, st, m, w, aw, B);
+  else hipLaunchKernelGGL(k_emis_adj_mixed, grid, dim3(kBlock), 0, st, m, w, aw, B);
 }
 
-void launch_layer_sums_emis(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, hipStream_t st) {
+void launch_layer_sums_emis(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, bool fp64,
+                            hipStream_t st) {
   const int NG = (m.L_max + 4) / 5;
   const long waves = (long)aw.lsum_chunks * B * NG;
+  const dim3 grid((unsigned)((waves + 3) / 4));
+  if (fp64) {
+    hipLaunchKernelGGL(k_layer_sums_emis_fp64, grid, dim3(kBlock), 0, st, m, w, tb, aw, B);
+    return;
+  }
   void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&aw, (void*)&B};
-  hipLaunchKernel(ls_emis_kernel_for(m.S, m.has_cia), dim3((unsigned)((waves + 3) / 4)), dim3(kBlock), args, 0, st);
+  hipLaunchKernel(ls_emis_kernel_for(m.S, m.has_cia), grid, dim3(kBlock), args, 0, st);
 }
 
 }  // namespace exofwd

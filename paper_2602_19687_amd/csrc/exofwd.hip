@@ -246,6 +246,9 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
       return EXOFWD_ERR_CONFIG;
   }
   if (g.has_fcld && (!g.has_cloud || g.mode != EXOFWD_TRANSMISSION)) return EXOFWD_ERR_CONFIG;
+  // the FP64 emission kernel stages a tile's layers in LDS: at most 128 padded layers
+  if (g.mode == EXOFWD_EMISSION && g.precision == EXOFWD_PREC_FP64 && (g.n_layers_max + 31) / 32 * 32 > 128)
+    return EXOFWD_ERR_UNSUPPORTED;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || g.device < 0 || g.device >= ndev) return EXOFWD_ERR_DEVICE;
 
@@ -484,7 +487,7 @@ static exofwd_status check_call(exofwd_ctx* c, int32_t B, const double* params) 
 }
 
 static exofwd_status run_forward(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers,
-                                 void* spectra, double* lnL, int32_t* status, void* hip_stream, float* dtau_out);
+                                 void* spectra, double* lnL, int32_t* status, void* hip_stream, void* dtau_out);
 static exofwd_status run_grad(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers,
                               void* spectra, double* lnL, double* grad, int32_t* status, void* hip_stream);
 
@@ -549,7 +552,7 @@ exofwd_status exofwd_forward(exofwd_ctx* c, int32_t B, const double* params, con
 }
 
 static exofwd_status run_forward(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers,
-                                 void* spectra, double* lnL, int32_t* status, void* hip_stream, float* dtau_out) {
+                                 void* spectra, double* lnL, int32_t* status, void* hip_stream, void* dtau_out) {
   exofwd_status s = EXOFWD_OK;
   hipStream_t st = (hipStream_t)hip_stream;
   const bool fp64 = c->precision == EXOFWD_PREC_FP64;
@@ -563,7 +566,7 @@ static exofwd_status run_forward(exofwd_ctx* c, int32_t B, const double* params,
   if ((s = check_hip(c, hipGetLastError(), "profile launch"))) return s;
   if (c->m.mode == kTransmission) {
     prof_begin(c, "trans_fwd", st);
-    launch_trans_fwd(c->m, c->w, c->tb, Bv, spec, fp64, st, dtau_out);
+    launch_trans_fwd(c->m, c->w, c->tb, Bv, spec, fp64, st, (float*)dtau_out);
   } else {
     prof_begin(c, "emis_fwd", st);
     launch_emission(c->m, c->w, c->tb, Bv, spec, fp64, st, dtau_out);
@@ -595,9 +598,10 @@ exofwd_status exofwd_grad(exofwd_ctx* c, int32_t B, const double* params, const 
 static exofwd_status run_grad(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers,
                               void* spectra, double* lnL, double* grad, int32_t* status, void* hip_stream) {
   exofwd_status s;
-  if ((s = run_forward(c, B, params, n_layers, spectra, lnL, status, hip_stream,
-                       c->precision == EXOFWD_PREC_MIXED ? c->aw.dtau : nullptr)))
-    return s;
+  // the reverse passes read the forward's layer optical depths (not the FP64 transmission one)
+  void* dtau_out = c->precision == EXOFWD_PREC_MIXED ? (void*)c->aw.dtau
+                                                     : (c->m.mode == kEmission ? (void*)c->aw.dtau64 : nullptr);
+  if ((s = run_forward(c, B, params, n_layers, spectra, lnL, status, hip_stream, dtau_out))) return s;
   hipStream_t st = (hipStream_t)hip_stream;
   const bool fp64 = c->precision == EXOFWD_PREC_FP64;
   const int Bv = c->m.has_fcld ? 2 * B : B;
@@ -606,13 +610,13 @@ static exofwd_status run_grad(exofwd_ctx* c, int32_t B, const double* params, co
     launch_trans_adjoint(c->m, c->w, c->tb, c->aw, Bv, fp64, st);
   } else {
     prof_begin(c, "emis_adj", st);
-    launch_emis_adjoint(c->m, c->w, c->aw, Bv, st);
+    launch_emis_adjoint(c->m, c->w, c->aw, Bv, fp64, st);
   }
   prof_end(c, st);
   if ((s = check_hip(c, hipGetLastError(), "adjoint launch"))) return s;
-  if (!fp64) {
+  if (!fp64 || c->m.mode == kEmission) {
     prof_begin(c, "layer_sums", st);
-    launch_layer_sums(c->m, c->w, c->tb, c->aw, Bv, st);
+    launch_layer_sums(c->m, c->w, c->tb, c->aw, Bv, fp64, st);
     prof_end(c, st);
     if ((s = check_hip(c, hipGetLastError(), "layer-sum launch"))) return s;
   }

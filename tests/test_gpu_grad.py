@@ -218,15 +218,28 @@ def test_emission_grad_ragged_layers():
         assert e < TOL["mixed"]
 
 
-def test_emission_fp64_grad_unsupported():
+def test_emission_fp64_grad_vs_complex_step():
+    """The plain FP64 emission adjoint against the oracle's complex step at the
+    FP64 tolerance: the reverse sweep, Planck sums and chain with no FP32 rounding."""
+    wl = reduced(2, n_nu=700, n_bins=25, batch=4, step=28)
+    lnl, g, st, lnl_f = _grad(wl, "fp64", wl["params"])
+    assert np.array_equal(lnl, lnl_f)
+    errs = []
+    for b in range(4):
+        gref = oracle.grad_complex_step(wl, wl["params"][b])
+        assert st[b] == 0
+        errs.append(grad_err(g[b], gref))
+    print(f"emission fp64: max grad err {max(errs):.3e}")
+    assert max(errs) < TOL["fp64"]
+
+
+def test_emission_fp64_beyond_128_layers_unsupported():
+    # the FP64 emission kernels stage a tile's layers in LDS: the context is refused
     from paper_2602_19687_amd import ForwardModel
     from paper_2602_19687_amd import _lib as L
-    wl = reduced(2, n_nu=200, n_bins=8, batch=2, step=90)
-    fm = ForwardModel(wl, precision="fp64", batch_max=2)
-    assert not fm.has_grad
-    with pytest.raises(L.ExoError):
-        fm.grad(torch.tensor(wl["params"], device="cuda"))
-    fm.close()
+    wl = reduced(2, n_nu=200, n_bins=8, batch=2, step=90, n_layers=130)
+    with pytest.raises(L.ExoError, match="unsupported"):
+        ForwardModel(wl, precision="fp64", batch_max=2)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -247,3 +260,35 @@ def test_pchip_transmission_grad(prec):
         errs.append(grad_err(g[b], gref))
     print(f"pchip transmission {prec}: max grad err {max(errs):.3e}")
     assert max(errs) < TOL[prec]
+
+
+def test_emission_grad_eight_angles_isothermal():
+    """Emission with 8 Gauss-Legendre angles (the largest count) and an isothermal
+    profile: the level and layer temperatures are one parameter."""
+    wl = reduced(2, n_nu=500, n_bins=20, batch=3, step=40)
+    cfg = {**synth.CONFIGS[2], "tp": synth.TP_ISOTHERMAL}
+    bounds = synth.param_bounds(cfg)
+    bounds[0] = (900.0, 2200.0)
+    u = np.random.default_rng(41).uniform(size=(3, len(bounds)))
+    wl.update(tp=synth.TP_ISOTHERMAL, n_mu=8, param_bounds=bounds, param_names=synth.param_names(cfg),
+              params=bounds[:, 0] + u * (bounds[:, 1] - bounds[:, 0]))
+    lnl, g, st, _ = _grad(wl, "mixed", wl["params"])
+    for b in range(3):
+        gref = oracle.grad_complex_step(wl, wl["params"][b])
+        assert st[b] == 0
+        e = grad_err(g[b], gref)
+        print(f"emission iso n_mu=8 sample {b}: grad err {e:.3e}")
+        assert e < TOL["mixed"]
+
+
+def test_emission_full_size_grad_sampled():
+    """The full emission workload (20000 wavenumbers, 8 absorbers, 100 layers) at
+    B = 64, one sample against the oracle's complex-step gradient."""
+    wl = synth.workload(2, batch=64)
+    lnl, g, st, _ = _grad(wl, "mixed", wl["params"])
+    b = 17
+    gref = oracle.grad_complex_step(wl, wl["params"][b])
+    e = grad_err(g[b], gref)
+    print(f"emission full size sample {b}: grad err {e:.3e}")
+    assert st[b] == 0 and e < TOL["mixed"]
+    assert np.all(np.isfinite(g[st == 0]))
