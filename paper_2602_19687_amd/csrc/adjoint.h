@@ -34,7 +34,8 @@ struct AdjWork {
   void* pbar;          // [pair][L_pad][L_pad] d lnL / d P_il (row i, column l), float (mixed) or double (FP64)
   double* abar;        // [pair][L_pad] d lnL / d area_i
   // reduced-precision path: the fused kernel stores dtau_bar, a second kernel forms the layer sums
-  float* dtau;         // [B_max][L_pad][n_nu_pad] layer optical depths stored by the forward kernel
+  float* dtau;         // [B_max][L_pad][n_nu_pad] layer optical depths stored by the forward kernel:
+                       //   transmission as packed bf16 pairs (hi | lo << 16), emission as FP32
   float* dtb;          // [B_max][L_pad][n_nu_pad] d lnL / d dtau_l(nu)
   float* lsum;         // [B_max][lsum_chunks][L_pad][n_lsums] partial layer sums
   float* hq;           // non-grey cloud: [B_max][lsum_stride][kCloudSpec] per-chunk sums over nu of

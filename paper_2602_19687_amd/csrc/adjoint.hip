@@ -162,7 +162,7 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
   // the stored optical depths of a tile are fetched into registers while the
   // previous tile's Pbar product runs, then written to LDS as packed hi/lo:
   // items (layer octet o, half of the tile), a lane takes one wavenumber of the half
-  float pf[kItemsA][8];
+  uint32_t pf[kItemsA][8];   // packed bf16 hi | lo << 16, as the forward stored them
   // row offsets go in the scalar offset (wave-uniform, recomputed per tile); rows
   // [L, 32 MBe) lie inside the sample's L_pad rows and are replaced by zero when staged
   const __amdgpu_buffer_rsrc_t rs_dt = make_rsrc(dtau_b, (size_t)Lp * npad * 4);
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
       const uint32_t soff = (uint32_t)((8 * o * npad + (size_t)tile * kTileA) * 4);
 #pragma unroll
       for (int j = 0; j < 8; ++j)
-        pf[q][j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs_dt, voff, soff + j * rowb, 0));
+        pf[q][j] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs_dt, voff, soff + j * rowb, 0);
     }
   };
   auto stage = [&]() {
@@ -190,12 +190,12 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
       const int it = wv + kWavesA * q;
       if (it >= 4 * kHalves * MBe) continue;   // 4 MBe layer octets per half
       const int o = it / kHalves, nu = 64 * (it % kHalves) + lane;
-      float d[8];
+      uint32_t d[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) d[j] = 8 * o + j < Lq ? pf[q][j] : 0.0f;
+      for (int j = 0; j < 8; ++j) d[j] = 8 * o + j < Lq ? pf[q][j] : 0u;
       uint32_t* dst = s_dt + nu * ld + 8 * o;
-      *reinterpret_cast<uint4*>(dst) = make_uint4(pack_hl(d[0]), pack_hl(d[1]), pack_hl(d[2]), pack_hl(d[3]));
-      *reinterpret_cast<uint4*>(dst + 4) = make_uint4(pack_hl(d[4]), pack_hl(d[5]), pack_hl(d[6]), pack_hl(d[7]));
+      *reinterpret_cast<uint4*>(dst) = make_uint4(d[0], d[1], d[2], d[3]);
+      *reinterpret_cast<uint4*>(dst + 4) = make_uint4(d[4], d[5], d[6], d[7]);
     }
   };
   // ---- phase A of the first tile

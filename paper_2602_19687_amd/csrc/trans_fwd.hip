@@ -95,9 +95,6 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
         layer_terms<S, CIA, NGC>(c, kc, g, rh, rhc, voff, d0, d1, q0, q1);
         d0 = fminf(d0, 16384.0f);
         d1 = fminf(d1, 16384.0f);
-        // the reverse pass reads the layer optical depths back instead of recomputing them
-        if (dtau_out)
-          *reinterpret_cast<float2*>(dtau_out + ((size_t)b * Lp + l) * npad + nu0 + 2 * lane) = make_float2(d0, d1);
       }
       e0[j] = d0;
       e1[j] = d1;
@@ -108,6 +105,20 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
     for (int j = 0; j < 4; ++j) {
       split_pair(e0[2 * j], e0[2 * j + 1], h0[j], l0[j]);
       split_pair(e1[2 * j], e1[2 * j + 1], h1[j], l1[j]);
+    }
+    // the reverse pass reads the layer optical depths back instead of recomputing
+    // them, already split: one dword (bf16 hi | bf16 lo << 16) per layer and wavenumber
+    if (dtau_out) {
+      uint32_t* dst = reinterpret_cast<uint32_t*>(dtau_out) + ((size_t)b * Lp + 8 * o) * npad + nu0 + 2 * lane;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (8 * o + 2 * j < L)
+          *reinterpret_cast<uint2*>(dst + (size_t)(2 * j) * npad) =
+              make_uint2(__builtin_amdgcn_perm(l0[j], h0[j], 0x05040100u), __builtin_amdgcn_perm(l1[j], h1[j], 0x05040100u));
+        if (8 * o + 2 * j + 1 < L)
+          *reinterpret_cast<uint2*>(dst + (size_t)(2 * j + 1) * npad) =
+              make_uint2(__builtin_amdgcn_perm(l0[j], h0[j], 0x07060302u), __builtin_amdgcn_perm(l1[j], h1[j], 0x07060302u));
+      }
     }
     const int r0 = (2 * lane) * stride + 8 * o, r1 = r0 + stride;
     *reinterpret_cast<uint4*>(s_bhi + r0) = make_uint4(h0[0], h0[1], h0[2], h0[3]);
