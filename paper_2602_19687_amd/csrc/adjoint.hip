@@ -167,12 +167,21 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
   // [L, 32 MBe) lie inside the sample's L_pad rows and are replaced by zero when staged
   const __amdgpu_buffer_rsrc_t rs_dt = make_rsrc(dtau_b, (size_t)Lp * npad * 4);
   const uint32_t rowb = (uint32_t)npad * 4u;
+  // layers below the tile's opaque frontier feed only chords whose seeds are zero
+  // (nothing below reads them): they are neither fetched nor staged
+  auto front_row = [&](int tile) { return 32 * w.front[(size_t)b * m.n_tiles + tile * kTileA / kTileNu]; };
   auto fetch = [&](int tile) {
+    const int lo_row = front_row(tile);
 #pragma unroll
     for (int q = 0; q < kItemsA; ++q) {
       const int it = wv + kWavesA * q;
       if (it >= 4 * kHalves * MBe) continue;   // 4 MBe layer octets per half
       const int o = it / kHalves;
+      if (8 * o + 8 <= lo_row) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) pf[q][j] = 0u;
+        continue;
+      }
       const uint32_t voff = (uint32_t)(64 * (it % kHalves) + lane) * 4u;
       const uint32_t soff = (uint32_t)((8 * o * npad + (size_t)tile * kTileA) * 4);
 #pragma unroll
@@ -180,11 +189,12 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
         pf[q][j] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs_dt, voff, soff + j * rowb, 0);
     }
   };
-  auto stage = [&]() {
+  auto stage = [&](int tile) {
     // L passed through an empty asm: the row tests below are then formed where
     // they are used, instead of being hoisted out of the tile loop as 32 masks
     int Lq = L;
     asm volatile("" : "+s"(Lq));
+    const int lo_row = front_row(tile);
 #pragma unroll
     for (int q = 0; q < kItemsA; ++q) {
       const int it = wv + kWavesA * q;
@@ -192,7 +202,7 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
       const int o = it / kHalves, nu = 64 * (it % kHalves) + lane;
       uint32_t d[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) d[j] = 8 * o + j < Lq ? pf[q][j] : 0u;
+      for (int j = 0; j < 8; ++j) d[j] = (8 * o + j < Lq && 8 * o + j >= lo_row) ? pf[q][j] : 0u;
       uint32_t* dst = s_dt + nu * ld + 8 * o;
       *reinterpret_cast<uint4*>(dst) = make_uint4(d[0], d[1], d[2], d[3]);
       *reinterpret_cast<uint4*>(dst + 4) = make_uint4(d[4], d[5], d[6], d[7]);
@@ -201,7 +211,7 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
   // ---- phase A of the first tile
   if (t0 < t1) {
     fetch(t0);
-    stage();
+    stage(t0);
   }
   __syncthreads();
 
@@ -300,7 +310,7 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
     // ---- phase A of the next tile, part 2: every wave is past phase E, the last
     // reader of this tile's dtau
     __syncthreads();
-    if (more) stage();
+    if (more) stage(tile + 1);
     // ---- phase D: dtau_bar = P^T tau_bar (rows l, this wave's column block) -> HBM
     {
       const __amdgpu_buffer_rsrc_t rs_db = make_rsrc(dtb_b + nu0, ((size_t)Lp * npad - nu0) * 4);
