@@ -317,7 +317,9 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
 #pragma unroll
       for (int q = 0; q < kSlots; ++q) {
         const int ml = d_ml[q];
-        if (ml < 0) continue;
+        // rows below the opaque frontier would be exact zeros: the readers of
+        // dtau_bar consult the frontier instead, so they are not stored
+        if (ml < mi0) continue;
         f32x16 acc = {};
         const int kend = min(2 * ml + 2, KBe);
         // the seed rows of blocks below mi0 are zero: the sum starts at row 32 mi0
@@ -452,13 +454,17 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
   for (int tile = t0; tile < t1; ++tile) {
     const int nu0 = tile * kTileNu;
     // every chord through the group's layers opaque across the tile: dtau_bar is
-    // exactly zero there and the tile adds nothing (the deep layers of most atmospheres)
+    // exactly zero there and the tile adds nothing (the deep layers of most
+    // atmospheres).  Rows below the reverse pass's opaque frontier are not stored.
+    const int lo_row = 32 * w.front[(size_t)b * m.n_tiles + tile];
+    if (l0 + kLsLayers <= lo_row) continue;
     float2 dbq[kLsLayers];
     bool live = false;
 #pragma unroll
     for (int q = 0; q < kLsLayers; ++q) {
-      dbq[q] = l0 + q < L ? *reinterpret_cast<const float2*>(dtb + (size_t)(l0 + q) * npad + nu0 + 2 * lane)
-                          : make_float2(0.0f, 0.0f);
+      dbq[q] = (l0 + q < L && l0 + q >= lo_row)
+                   ? *reinterpret_cast<const float2*>(dtb + (size_t)(l0 + q) * npad + nu0 + 2 * lane)
+                   : make_float2(0.0f, 0.0f);
       live |= dbq[q].x != 0.0f || dbq[q].y != 0.0f;
     }
     if (__builtin_amdgcn_ballot_w64(live) == 0) continue;
@@ -536,7 +542,8 @@ __global__ __launch_bounds__(kBlock) void k_cloud_spectral(Model m, Work w, AdjW
   for (int tile = t0; tile < t1; ++tile) {
     const int nu = tile * kTileNu + 2 * lane;
     float g0 = 0.0f, g1 = 0.0f;
-    for (int l = 0; l < L; ++l) {
+    // rows below the opaque frontier are zero (and not stored)
+    for (int l = 32 * w.front[(size_t)b * m.n_tiles + tile]; l < L; ++l) {
       const float dl = rec[(size_t)l * rec_len(m.S) + 4];
       const float2 d = *reinterpret_cast<const float2*>(dtb + (size_t)l * npad + nu);
       g0 = fmaf(dl, d.x, g0);
