@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
   uint16_t* s_blo = s_bhi + kTileNu * stride;
   float* s_area = reinterpret_cast<float*>(s_blo + kTileNu * stride);
   float* s_red = s_area + Lp;   // [8][32]
-  int* s_live = reinterpret_cast<int*>(s_red + 8 * 32);   // [8] row block holds a chord below kOpaqueTau
+  int* s_live = reinterpret_cast<int*>(s_red + 8 * 32);   // [0, MB): row block holds a chord below kOpaqueTau; [7]: frontier
   if (tid < 8) s_live[tid] = 0;
 
   const float* area = reinterpret_cast<const float*>(w.area) + (size_t)b * Lp;
@@ -105,20 +105,6 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
     for (int j = 0; j < 4; ++j) {
       split_pair(e0[2 * j], e0[2 * j + 1], h0[j], l0[j]);
       split_pair(e1[2 * j], e1[2 * j + 1], h1[j], l1[j]);
-    }
-    // the reverse pass reads the layer optical depths back instead of recomputing
-    // them, already split: one dword (bf16 hi | bf16 lo << 16) per layer and wavenumber
-    if (dtau_out) {
-      uint32_t* dst = reinterpret_cast<uint32_t*>(dtau_out) + ((size_t)b * Lp + 8 * o) * npad + nu0 + 2 * lane;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (8 * o + 2 * j < L)
-          *reinterpret_cast<uint2*>(dst + (size_t)(2 * j) * npad) =
-              make_uint2(__builtin_amdgcn_perm(l0[j], h0[j], 0x05040100u), __builtin_amdgcn_perm(l1[j], h1[j], 0x05040100u));
-        if (8 * o + 2 * j + 1 < L)
-          *reinterpret_cast<uint2*>(dst + (size_t)(2 * j + 1) * npad) =
-              make_uint2(__builtin_amdgcn_perm(l0[j], h0[j], 0x07060302u), __builtin_amdgcn_perm(l1[j], h1[j], 0x07060302u));
-      }
     }
     const int r0 = (2 * lane) * stride + 8 * o, r1 = r0 + stride;
     *reinterpret_cast<uint4*>(s_bhi + r0) = make_uint4(h0[0], h0[1], h0[2], h0[3]);
@@ -172,10 +158,29 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
     const float tot = s_red[h * 32 + c] + s_red[(h + 4) * 32 + c];
     if (nu0 + tid < m.n_nu) out[nu0 + tid] = (float)w.core[b] + tot;
   }
-  if (dtau_out && tid == 0) {
-    int f = 0;
-    while (f < MBe && !s_live[f]) ++f;
-    w.front[(size_t)b * m.n_tiles + tile] = f;
+  if (dtau_out) {
+    if (tid == 0) {
+      int f = 0;
+      while (f < MBe && !s_live[f]) ++f;
+      w.front[(size_t)b * m.n_tiles + tile] = f;
+      s_live[7] = f;
+    }
+    __syncthreads();
+    // the reverse pass reads the layer optical depths back instead of recomputing
+    // them, already split: one dword (bf16 hi | bf16 lo << 16) per layer and
+    // wavenumber, from the LDS planes, and only above the opaque frontier (the
+    // layers below feed only chords whose seeds are zero)
+    const int k0 = 16 * s_live[7], k1 = (L + 1) >> 1;   // layer pairs
+    const uint32_t* ph = reinterpret_cast<const uint32_t*>(s_bhi);
+    const uint32_t* pl = reinterpret_cast<const uint32_t*>(s_blo);
+    uint32_t* dt = reinterpret_cast<uint32_t*>(dtau_out) + (size_t)b * Lp * npad + nu0;
+    for (int e = tid; e < (k1 - k0) * kTileNu; e += kBlockT) {
+      const int nu = e & (kTileNu - 1), k = k0 + e / kTileNu;
+      const int a = nu * (stride >> 1) + k;
+      const uint32_t hp = ph[a], lp = pl[a];
+      dt[(size_t)(2 * k) * npad + nu] = __builtin_amdgcn_perm(lp, hp, 0x05040100u);
+      if (2 * k + 1 < L) dt[(size_t)(2 * k + 1) * npad + nu] = __builtin_amdgcn_perm(lp, hp, 0x07060302u);
+    }
   }
 }
 
