@@ -172,19 +172,39 @@ __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tabl
     inten[k] = b_bot;
   }
 
+  // table pairs of the current cell: a layer in the same cell as the one below reuses them
+  half2_t tp[4 * S + 4];
+  int cell_prev = -1;
   for (int l = 0; l < L; ++l) {
     // ---- optical depth of layer l
     const int cl = cells[l];
-    const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
     const float* rl = rec + (size_t)l * RL;
+    if (cl != cell_prev) {
+      const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2) {
+        const uint32_t row = (uint32_t)((s2 * m.n_t + it) * m.n_p + ip) * row_bytes + nu0_bytes;
+        tp[4 * s2] = load_h2(rh, voff, row);
+        tp[4 * s2 + 1] = load_h2(rh, voff, row + tstep);
+        tp[4 * s2 + 2] = load_h2(rh, voff, row + row_bytes);
+        tp[4 * s2 + 3] = load_h2(rh, voff, row + tstep + row_bytes);
+      }
+      if (CIA) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          const uint32_t row = (uint32_t)(p * m.n_tc + itc) * row_bytes + nu0_bytes;
+          tp[4 * S + 2 * p] = load_h2(rhc, voff, row);
+          tp[4 * S + 2 * p + 1] = load_h2(rhc, voff, row + row_bytes);
+        }
+      }
+      cell_prev = cl;
+    }
     const float wt = rl[0], wp = rl[1];
     const float w11 = wt * wp, w10 = wt - w11, w01 = wp - w11, w00 = 1.0f - wt - wp + w11;
     float d = 0.0f;
 #pragma unroll
     for (int s2 = 0; s2 < S; ++s2) {
-      const uint32_t row = (uint32_t)((s2 * m.n_t + it) * m.n_p + ip) * row_bytes + nu0_bytes;
-      const half2_t p00 = load_h2(rh, voff, row), p10 = load_h2(rh, voff, row + tstep);
-      const half2_t p01 = load_h2(rh, voff, row + row_bytes), p11 = load_h2(rh, voff, row + tstep + row_bytes);
+      const half2_t p00 = tp[4 * s2], p10 = tp[4 * s2 + 1], p01 = tp[4 * s2 + 2], p11 = tp[4 * s2 + 3];
       float v = cs[s2] + rl[kRecFixed + s2];
       v = fmaf(w00, (float)p00.x, v);
       v = fmaf(w10, (float)p10.x, v);
@@ -200,8 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tabl
       const float wtc = rl[2];
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
-        const uint32_t row = (uint32_t)(p * m.n_tc + itc) * row_bytes + nu0_bytes;
-        const half2_t a = load_h2(rhc, voff, row), c2 = load_h2(rhc, voff, row + row_bytes);
+        const half2_t a = tp[4 * S + 2 * p], c2 = tp[4 * S + 2 * p + 1];
         float v = ccs[p] + rl[5 + p];
         v = fmaf(1.0f - wtc, (float)a.x, v);
         v = fmaf(wtc, (float)c2.x, v);

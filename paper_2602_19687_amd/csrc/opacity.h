@@ -25,6 +25,7 @@ struct LayerCoef {
   float w00, w10, w01, w11, wtc, R, D;
   float lam[S], lamc[2];
   float wt, wp, omp;   // T and log p weights, 1 - wP (derivative form of the bilinear)
+  int cell;            // packed (iT, iP, iTc): equal cells read equal table pairs
 };
 
 struct TableGeom {
@@ -40,6 +41,7 @@ __device__ inline LayerCoef<S> load_layer(const Model& m, const int32_t* __restr
   LayerCoef<S> c;
   const int cl = cells[l];
   const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
+  c.cell = cl;
   const float* rl = rec + (size_t)l * rec_len(S);
   const float wt = rl[0], wp = rl[1];
   c.wt = wt;
@@ -100,15 +102,40 @@ __device__ inline half2_t load_h2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint3
   return __builtin_bit_cast(half2_t, (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 
-// Optical depth of one layer at two wavenumbers: Rayleigh + cloud, the
-// VMR-weighted line terms (bilinear in T and log p of the log2 tables) and the
-// CIA pair terms (linear in T).
+// Raw FP16 table pairs of one layer: four bilinear corners per line source,
+// two T rows per CIA pair.
+template <int S, bool CIA>
+struct LayerRaw {
+  half2_t h[4 * S + (CIA ? 4 : 0)];
+};
+
+template <int S, bool CIA>
+__device__ inline void fetch_terms(const LayerCoef<S>& c, const TableGeom& g, __amdgpu_buffer_rsrc_t rh,
+                                   __amdgpu_buffer_rsrc_t rhc, uint32_t voff, LayerRaw<S, CIA>& r) {
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    r.h[4 * s + 0] = load_h2(rh, voff, c.row[s]);
+    r.h[4 * s + 1] = load_h2(rh, voff, c.row[s] + g.tstep);
+    r.h[4 * s + 2] = load_h2(rh, voff, c.row[s] + g.pstep);
+    r.h[4 * s + 3] = load_h2(rh, voff, c.row[s] + g.tstep + g.pstep);
+  }
+  if constexpr (CIA) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      r.h[4 * S + 2 * p] = load_h2(rhc, voff, c.rowc[p]);
+      r.h[4 * S + 2 * p + 1] = load_h2(rhc, voff, c.rowc[p] + g.row_bytes);
+    }
+  }
+}
+
+// Optical depth of one layer at two wavenumbers from its fetched table pairs:
+// Rayleigh + cloud, the VMR-weighted line terms (bilinear in T and log p of the
+// log2 tables) and the CIA pair terms (linear in T).
 // With the non-grey cloud (NGC) D is the layer's cloud column and q0, q1 the
 // extinction efficiency Q_ext at the two wavenumbers.
 template <int S, bool CIA, bool NGC = false>
-__device__ inline void layer_terms(const LayerCoef<S>& c, const LaneConst<S>& k, const TableGeom& g,
-                                   __amdgpu_buffer_rsrc_t rh, __amdgpu_buffer_rsrc_t rhc, uint32_t voff,
-                                   float& d0, float& d1, float q0 = 1.0f, float q1 = 1.0f) {
+__device__ inline void eval_terms(const LayerCoef<S>& c, const LaneConst<S>& k, const LayerRaw<S, CIA>& r, float& d0,
+                                  float& d1, float q0 = 1.0f, float q1 = 1.0f) {
   if constexpr (NGC) {
     d0 = fmaf(c.D, q0, c.R * k.nu4_0);
     d1 = fmaf(c.D, q1, c.R * k.nu4_1);
@@ -118,10 +145,7 @@ __device__ inline void layer_terms(const LayerCoef<S>& c, const LaneConst<S>& k,
   }
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const half2_t h00 = load_h2(rh, voff, c.row[s]);
-    const half2_t h10 = load_h2(rh, voff, c.row[s] + g.tstep);
-    const half2_t h01 = load_h2(rh, voff, c.row[s] + g.pstep);
-    const half2_t h11 = load_h2(rh, voff, c.row[s] + g.tstep + g.pstep);
+    const half2_t h00 = r.h[4 * s], h10 = r.h[4 * s + 1], h01 = r.h[4 * s + 2], h11 = r.h[4 * s + 3];
     float v0 = k.c0[s] + c.lam[s];
     float v1 = k.c1[s] + c.lam[s];
     v0 = fmaf(c.w00, (float)h00.x, v0);
@@ -135,11 +159,10 @@ __device__ inline void layer_terms(const LayerCoef<S>& c, const LaneConst<S>& k,
     d0 += exp2_fast(v0);
     d1 += exp2_fast(v1);
   }
-  if (CIA) {
+  if constexpr (CIA) {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-      const half2_t a = load_h2(rhc, voff, c.rowc[p]);
-      const half2_t b = load_h2(rhc, voff, c.rowc[p] + g.row_bytes);
+      const half2_t a = r.h[4 * S + 2 * p], b = r.h[4 * S + 2 * p + 1];
       float v0 = k.cc0[p] + c.lamc[p];
       float v1 = k.cc1[p] + c.lamc[p];
       v0 = fmaf(1.0f - c.wtc, (float)a.x, v0);
@@ -152,20 +175,26 @@ __device__ inline void layer_terms(const LayerCoef<S>& c, const LaneConst<S>& k,
   }
 }
 
+// Fetch and evaluate in one step.
+template <int S, bool CIA, bool NGC = false>
+__device__ inline void layer_terms(const LayerCoef<S>& c, const LaneConst<S>& k, const TableGeom& g,
+                                   __amdgpu_buffer_rsrc_t rh, __amdgpu_buffer_rsrc_t rhc, uint32_t voff,
+                                   float& d0, float& d1, float q0 = 1.0f, float q1 = 1.0f) {
+  LayerRaw<S, CIA> r;
+  fetch_terms<S, CIA>(c, g, rh, rhc, voff, r);
+  eval_terms<S, CIA, NGC>(c, k, r, d0, d1, q0, q1);
+}
+
 // Line and CIA terms of one layer for two wavenumbers together with the
 // derivative of each exponent with respect to the T weight, from the two
 // log p-interpolated rows u0 (at iT) and u1 (at iT+1), both offset by c + lam:
 //   exponent = u0 + wT (u1 - u0),  d exponent / d wT = u1 - u0.
 template <int S, bool CIA>
-__device__ inline void layer_terms_deriv(const LayerCoef<S>& c, const LaneConst<S>& k, const TableGeom& g,
-                                         __amdgpu_buffer_rsrc_t rh, __amdgpu_buffer_rsrc_t rhc, uint32_t voff,
-                                         float* t0, float* t1, float* dw0, float* dw1) {
+__device__ inline void eval_terms_deriv(const LayerCoef<S>& c, const LaneConst<S>& k, const LayerRaw<S, CIA>& r,
+                                        float* t0, float* t1, float* dw0, float* dw1) {
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const half2_t h00 = load_h2(rh, voff, c.row[s]);
-    const half2_t h10 = load_h2(rh, voff, c.row[s] + g.tstep);
-    const half2_t h01 = load_h2(rh, voff, c.row[s] + g.pstep);
-    const half2_t h11 = load_h2(rh, voff, c.row[s] + g.tstep + g.pstep);
+    const half2_t h00 = r.h[4 * s], h10 = r.h[4 * s + 1], h01 = r.h[4 * s + 2], h11 = r.h[4 * s + 3];
     const float cl0 = k.c0[s] + c.lam[s], cl1 = k.c1[s] + c.lam[s];
     const float u00 = fmaf(c.omp, (float)h00.x, fmaf(c.wp, (float)h01.x, cl0));
     const float u10 = fmaf(c.omp, (float)h10.x, fmaf(c.wp, (float)h11.x, cl0));
@@ -176,11 +205,10 @@ __device__ inline void layer_terms_deriv(const LayerCoef<S>& c, const LaneConst<
     t0[s] = exp2_fast(fmaf(c.wt, dw0[s], u00));
     t1[s] = exp2_fast(fmaf(c.wt, dw1[s], u01));
   }
-  if (CIA) {
+  if constexpr (CIA) {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-      const half2_t a = load_h2(rhc, voff, c.rowc[p]);
-      const half2_t b = load_h2(rhc, voff, c.rowc[p] + g.row_bytes);
+      const half2_t a = r.h[4 * S + 2 * p], b = r.h[4 * S + 2 * p + 1];
       const float u0 = (float)a.x + (k.cc0[p] + c.lamc[p]);
       const float u1 = (float)a.y + (k.cc1[p] + c.lamc[p]);
       dw0[S + p] = (float)b.x - (float)a.x;
@@ -189,6 +217,15 @@ __device__ inline void layer_terms_deriv(const LayerCoef<S>& c, const LaneConst<
       t1[S + p] = exp2_fast(fmaf(c.wtc, dw1[S + p], u1));
     }
   }
+}
+
+template <int S, bool CIA>
+__device__ inline void layer_terms_deriv(const LayerCoef<S>& c, const LaneConst<S>& k, const TableGeom& g,
+                                         __amdgpu_buffer_rsrc_t rh, __amdgpu_buffer_rsrc_t rhc, uint32_t voff,
+                                         float* t0, float* t1, float* dw0, float* dw1) {
+  LayerRaw<S, CIA> r;
+  fetch_terms<S, CIA>(c, g, rh, rhc, voff, r);
+  eval_terms_deriv<S, CIA>(c, k, r, t0, t1, dw0, dw1);
 }
 
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, size_t bytes) {

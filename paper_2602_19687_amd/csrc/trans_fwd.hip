@@ -84,6 +84,9 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
     q1 = q.y;
   }
   const int KBe = (L + 15) >> 4;
+  // a layer in the same table cell as the wave's previous one reuses its pairs
+  LayerRaw<S, CIA> raw;
+  int cell_prev = -1;
   for (int o = wv; o < 2 * KBe; o += kBlockT / 64) {
     float e0[8], e1[8];
 #pragma unroll
@@ -92,7 +95,11 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
       float d0 = 0.0f, d1 = 0.0f;
       if (l < L) {
         const LayerCoef<S> c = load_layer<S>(m, cells, rec, l, (uint32_t)nu0 * 2u, g);
-        layer_terms<S, CIA, NGC>(c, kc, g, rh, rhc, voff, d0, d1, q0, q1);
+        if (c.cell != cell_prev) {
+          fetch_terms<S, CIA>(c, g, rh, rhc, voff, raw);
+          cell_prev = c.cell;
+        }
+        eval_terms<S, CIA, NGC>(c, kc, raw, d0, d1, q0, q1);
         d0 = fminf(d0, 16384.0f);
         d1 = fminf(d1, 16384.0f);
       }
