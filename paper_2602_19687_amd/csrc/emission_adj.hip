@@ -130,20 +130,22 @@ __global__ __launch_bounds__(kBlock) void k_emis_adj_mixed(Model m, Work w, AdjW
 template <int S, bool CIA>
 __global__ __launch_bounds__(kBlock) void k_layer_sums_emis(Model m, Work w, Tables tb, AdjWork aw, int B) {
   constexpr int NS = n_sums(S);
-  constexpr int kLayers = 5;
+  constexpr int kLayers = kLsGroup;
   const int lane = threadIdx.x & 63;
   const int gw = blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int NG = (m.L_max + kLayers - 1) / kLayers;
+  const int NG = m.L_max;   // groups per sample: at most one per layer
   const int per_chunk = B * NG;
   const int chunk = gw / per_chunk;
   if (chunk >= aw.lsum_chunks) return;
   const int rem = gw - chunk * per_chunk;
   const int b = rem / NG, lg = rem - b * NG;
   if (w.status[b]) return;
-  const int L = w.nlay[b];
-  const int l0 = lg * kLayers;
-  if (l0 >= L) return;
   const int Lp = m.L_pad;
+  // a run of up to kLayers consecutive layers in one table cell: the table pairs
+  // are fetched once per tile for all of them
+  const int32_t* grp = w.lsg + (size_t)b * (Lp + 1);
+  if (lg >= grp[0]) return;
+  const int l0 = grp[1 + lg] & 0xffff, cnt = grp[1 + lg] >> 16;
   const size_t npad = (size_t)m.n_nu_pad;
   const uint32_t row_bytes = (uint32_t)npad * 4u, tstep = (uint32_t)m.n_p * row_bytes;
   const __amdgpu_buffer_rsrc_t rh = make_rsrc(tb.h, (size_t)S * m.n_t * m.n_p * npad * 4);
@@ -152,8 +154,9 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_emis(Model m, Work w, Tab
   const uint32_t voff = (uint32_t)lane * 4u;
   constexpr int RL = rec_len(S);
   const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * RL;
-  const int32_t* cells = w.cells + (size_t)b * Lp;
   const float* dtb = aw.dtb + (size_t)b * Lp * npad;
+  const int cl = w.cells[(size_t)b * Lp + l0];
+  const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
 
   float acc[kLayers][NS];
 #pragma unroll
@@ -166,29 +169,49 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_emis(Model m, Work w, Tab
   for (int tile = t0; tile < t1; ++tile) {
     const int nu0 = tile * kTile64, nu = nu0 + lane;
     const uint32_t nu0_bytes = (uint32_t)nu0 * 4u;
+    // a layer seen through no transmission at any wavenumber of the tile adds
+    // nothing (the skip is per layer: the opaque depth varies across a tile)
+    float dbv[kLayers];
+    bool live = false;
+#pragma unroll
+    for (int q = 0; q < kLayers; ++q) {
+      dbv[q] = q < cnt ? dtb[(size_t)(l0 + q) * npad + nu] : 0.0f;
+      live |= dbv[q] != 0.0f;
+    }
+    if (__builtin_amdgcn_ballot_w64(live) == 0) continue;
     float cs[S], ccs[2];
 #pragma unroll
     for (int s = 0; s < S; ++s) cs[s] = tb.c[(size_t)s * npad + nu];
 #pragma unroll
     for (int p = 0; p < 2; ++p) ccs[p] = CIA ? tb.cc[(size_t)p * npad + nu] : 0.0f;
+    half2_t tp[4 * S + 4];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t row = (uint32_t)((s * m.n_t + it) * m.n_p + ip) * row_bytes + nu0_bytes;
+      tp[4 * s] = load_h2(rh, voff, row);
+      tp[4 * s + 1] = load_h2(rh, voff, row + tstep);
+      tp[4 * s + 2] = load_h2(rh, voff, row + row_bytes);
+      tp[4 * s + 3] = load_h2(rh, voff, row + tstep + row_bytes);
+    }
+    if (CIA) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const uint32_t row = (uint32_t)(p * m.n_tc + itc) * row_bytes + nu0_bytes;
+        tp[4 * S + 2 * p] = load_h2(rhc, voff, row);
+        tp[4 * S + 2 * p + 1] = load_h2(rhc, voff, row + row_bytes);
+      }
+    }
 #pragma unroll
     for (int q = 0; q < kLayers; ++q) {
-      const int l = l0 + q;
-      if (l >= L) continue;
-      const float db = dtb[(size_t)l * npad + nu];
-      // a layer seen through no transmission at any wavenumber of the tile adds
-      // nothing (the skip is per layer: the opaque depth varies across a tile)
+      if (q >= cnt) continue;
+      const float db = dbv[q];
       if (__builtin_amdgcn_ballot_w64(db != 0.0f) == 0) continue;
-      const int cl = cells[l];
-      const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
-      const float* rl = rec + (size_t)l * RL;
+      const float* rl = rec + (size_t)(l0 + q) * RL;
       const float wt = rl[0], wp = rl[1], omp = 1.0f - wp;
       float z = 0.0f;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        const uint32_t row = (uint32_t)((s * m.n_t + it) * m.n_p + ip) * row_bytes + nu0_bytes;
-        const half2_t p00 = load_h2(rh, voff, row), p10 = load_h2(rh, voff, row + tstep);
-        const half2_t p01 = load_h2(rh, voff, row + row_bytes), p11 = load_h2(rh, voff, row + tstep + row_bytes);
+        const half2_t p00 = tp[4 * s], p10 = tp[4 * s + 1], p01 = tp[4 * s + 2], p11 = tp[4 * s + 3];
         const float base = cs[s] + rl[kRecFixed + s];
         const float u0 = fmaf(omp, (float)p00.x + (float)p00.y, fmaf(wp, (float)p01.x + (float)p01.y, base));
         const float u1 = fmaf(omp, (float)p10.x + (float)p10.y, fmaf(wp, (float)p11.x + (float)p11.y, base));
@@ -203,8 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_emis(Model m, Work w, Tab
         float y = 0.0f;
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
-          const uint32_t row = (uint32_t)(p * m.n_tc + itc) * row_bytes + nu0_bytes;
-          const half2_t a = load_h2(rhc, voff, row), c2 = load_h2(rhc, voff, row + row_bytes);
+          const half2_t a = tp[4 * S + 2 * p], c2 = tp[4 * S + 2 * p + 1];
           const float va = (float)a.x + (float)a.y + (ccs[p] + rl[5 + p]);
           const float dw = ((float)c2.x + (float)c2.y) - ((float)a.x + (float)a.y);
           const float t = exp2_fast(fmaf(wtc, dw, va));
@@ -218,12 +240,11 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_emis(Model m, Work w, Tab
   float* out = aw.lsum + ((size_t)b * aw.lsum_stride + chunk) * Lp * NS;
 #pragma unroll
   for (int q = 0; q < kLayers; ++q) {
-    const int l = l0 + q;
-    if (l >= L) continue;
+    if (q >= cnt) continue;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const float tot = wave_sum_f(acc[q][k]);
-      if (lane == 0) out[(size_t)l * NS + k] = tot;
+      if (lane == 0) out[(size_t)(l0 + q) * NS + k] = tot;
     }
   }
 }
@@ -409,8 +430,8 @@ void launch_emis_adjoint(const Model& m, const Work& w, const AdjWork& aw, int B
 
 void launch_layer_sums_emis(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, bool fp64,
                             hipStream_t st) {
-  const int NG = (m.L_max + 4) / 5;
-  const long waves = (long)aw.lsum_chunks * B * NG;
+  // FP64: fixed groups of 5 layers; reduced precision: one wave per (chunk, sample, layer group)
+  const long waves = (long)aw.lsum_chunks * B * (fp64 ? (m.L_max + 4) / 5 : m.L_max);
   const dim3 grid((unsigned)((waves + 3) / 4));
   if (fp64) {
     hipLaunchKernelGGL(k_layer_sums_emis_fp64, grid, dim3(kBlock), 0, st, m, w, tb, aw, B);

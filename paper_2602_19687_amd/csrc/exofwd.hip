@@ -423,6 +423,7 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   if (m.cloud_ng && g.precision == EXOFWD_PREC_MIXED)
     w.cloud_q = A(dalloc<float>(c, (size_t)B * (1 + kCloudSpec) * m.n_nu_pad));
   w.cells = A(dalloc<int32_t>(c, (size_t)B * Lp));
+  if (!fp64 && m.mode == kEmission) w.lsg = A(dalloc<int32_t>(c, (size_t)B * (Lp + 1)));
   if (m.mode == kTransmission && !fp64) w.front = A(dalloc<int32_t>(c, (size_t)B * m.n_tiles));
   w.rec = A(dalloc<unsigned char>(c, (size_t)B * Lp * RL * rs));
   w.area = A(dalloc<unsigned char>(c, (size_t)B * Lp * rs));

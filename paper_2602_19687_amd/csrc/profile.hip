@@ -105,6 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
   __shared__ double s_knot_x[kMaxKnots], s_knot_y[kMaxKnots], s_knot_d[kMaxKnots];
   __shared__ int s_status;
   __shared__ int s_badt;
+  __shared__ int s_cell[kMaxLayers];
 
   // virtual sample b of real sample bs; a clear one (cloudy/clear mixing) has no cloud
   const int bs = real_sample(m, b);
@@ -267,6 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
     cell_index(m.logp_grid, m.n_p, lp_bar, ip, wp);
     if (m.has_cia) cell_index(m.tc_grid, m.n_tc, t, itc, wtc);
     w.cells[(size_t)b * Lp + l] = pack_cells(it, ip, itc);
+    s_cell[l] = pack_cells(it, ip, itc);
     rl[0] = Real(wt);
     rl[1] = Real(wp);
     rl[2] = Real(wtc);
@@ -287,6 +289,22 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
     rl[6] = Real(m.has_cia ? log2(n * n * xh2 * xhe * dr) : -1000.0);
     for (int s = 0; s < m.S; ++s) rl[kRecFixed + s] = Real(log2(n * x[s] * dr));
     area[l] = Real(dr * (s_r[l] + s_r[l + 1]) / (m.r_s * m.r_s));
+  }
+  if (w.lsg) {
+    // layer-sum groups: a run of layers in one table cell reads one set of table
+    // rows, so the layer sums fetch them once per tile for the whole group
+    __syncthreads();
+    if (tid == 0) {
+      int32_t* grp = w.lsg + (size_t)b * (Lp + 1);
+      int n = 0;
+      for (int l = 0; l < L;) {
+        int e = l + 1;
+        while (e < L && e - l < kLsGroup && s_cell[e] == s_cell[l]) ++e;
+        grp[1 + n++] = l | ((e - l) << 16);
+        l = e;
+      }
+      grp[0] = n;
+    }
   }
 
   if (m.mode != kTransmission) return;
