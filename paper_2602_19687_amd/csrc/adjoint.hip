@@ -241,14 +241,18 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
           continue;
         }
         f32x16 acc = {};
-        // path-matrix fragments are loaded one k-step ahead
+        // path-matrix fragments are loaded two k-steps ahead (a fragment past the
+        // sample's blocks reads the next row block's or zeros and is never used)
         bf16x8 nh = frag(rs_p, mi * KB + 2 * mi, 0), nl_ = frag(rs_p, mi * KB + 2 * mi, lo_plane);
+        bf16x8 mh = frag(rs_p, mi * KB + 2 * mi + 1, 0), ml_ = frag(rs_p, mi * KB + 2 * mi + 1, lo_plane);
 #pragma unroll 1
         for (int kb = 2 * mi; kb < KBe; ++kb) {
           const bf16x8 ah = nh, al = nl_;
-          if (kb + 1 < KBe) {
-            nh = frag(rs_p, mi * KB + kb + 1, 0);
-            nl_ = frag(rs_p, mi * KB + kb + 1, lo_plane);
+          nh = mh;
+          nl_ = ml_;
+          if (kb + 2 < KBe) {
+            mh = frag(rs_p, mi * KB + kb + 2, 0);
+            ml_ = frag(rs_p, mi * KB + kb + 2, lo_plane);
           }
           bf16x8 bh, bl;
           {
@@ -325,12 +329,15 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
         // the seed rows of blocks below mi0 are zero: the sum starts at row 32 mi0
         const int kbeg = min(2 * mi0, kend);
         bf16x8 nh = frag(rs_pt, ml * KB + kbeg, 0), nl_ = frag(rs_pt, ml * KB + kbeg, lo_plane);
+        bf16x8 mh = frag(rs_pt, ml * KB + kbeg + 1, 0), ml_ = frag(rs_pt, ml * KB + kbeg + 1, lo_plane);
 #pragma unroll 1
         for (int ki = kbeg; ki < kend; ++ki) {
           const bf16x8 ah = nh, al = nl_;
-          if (ki + 1 < kend) {
-            nh = frag(rs_pt, ml * KB + ki + 1, 0);
-            nl_ = frag(rs_pt, ml * KB + ki + 1, lo_plane);
+          nh = mh;
+          nl_ = ml_;
+          if (ki + 2 < kend) {
+            mh = frag(rs_pt, ml * KB + ki + 2, 0);
+            ml_ = frag(rs_pt, ml * KB + ki + 2, lo_plane);
           }
           bf16x8 bh, bl;
           {
