@@ -416,7 +416,7 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
 // reduced-precision per-layer sums: one wave per (sample, kLsLayers layers, ls_tiles tiles);
 // lanes hold two wavenumbers, partial sums stay in registers across the tiles
 // and are reduced over the wave once
-constexpr int kLsLayers = 5;
+constexpr int kLsLayers = 3;   // three layers' accumulators keep the kernel under 128 VGPRs: four waves per SIMD
 
 template <int S, bool CIA, bool NGC>
 __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Tables tb, AdjWork aw, int B) {

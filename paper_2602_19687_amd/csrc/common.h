@@ -19,7 +19,7 @@ constexpr double kInvalidLnL = -1.0e300;
 
 constexpr int kMaxSpecies = 8;
 constexpr int kMaxLayers = 160;   // L_max; padded layer count is a multiple of 32
-constexpr int kLsGroup = 5;       // most layers in one reduced-precision emission layer-sum group
+constexpr int kLsGroup = 3;       // most layers in one reduced-precision emission layer-sum group
 constexpr int kMaxKnots = 8;
 constexpr int kMaxMu = 8;
 constexpr int kTileNu = 128;      // wavenumbers per tile of the reduced-precision transmission kernels
