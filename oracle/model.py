@@ -32,7 +32,10 @@ S_BAD_T = 8
 S_BAD_LAYERS = 16
 INVALID_LNL = -1.0e300      # log-likelihood of an invalid forward output (Section "Likelihood")
 
-TP_ISOTHERMAL, TP_GUILLOT3, TP_PCHIP = 0, 1, 2
+TP_ISOTHERMAL, TP_GUILLOT3, TP_PCHIP, TP_BARSTOW, TP_MILNE, TP_GUILLOT7 = 0, 1, 2, 3, 4, 5
+TP_NPARAM = {TP_ISOTHERMAL: 1, TP_GUILLOT3: 3, TP_BARSTOW: 1, TP_MILNE: 5, TP_GUILLOT7: 7}
+KAPPA_AD = 2.0 / 7.0        # adiabatic exponent of the Barstow profile (Eq. 8)
+Q_HOPF_INF = 0.710446       # Hopf function at large optical depth (Milne q_inf)
 
 
 def _re(x):
@@ -74,6 +77,58 @@ def tp_guillot3(t_int, t_eq, log10_gamma, p, kappa_ir, g_ref, f_hem):
     t4 = (0.75 * t_int ** 4 * (q + tau)
           + 0.75 * t_eq ** 4 * 4.0 * f_hem
           * (q + 1.0 / (gam * s3) + (gam / s3 - 1.0 / (gam * s3)) * np.exp(-gam * tau * s3)))
+    return t4 ** 0.25
+
+
+def tp_barstow(t_strat, p):
+    """Barstow 2020 profile, Eq. 8: T_strat up to 0.1 bar, an adiabat
+    T_strat (p / 0.1 bar)^kappa between 0.1 and 1 bar, and its 1-bar value
+    below.  kappa = 2/7.  p in dyn cm^-2; one parameter, T_strat."""
+    pb = np.asarray(p, dtype=np.float64) / BAR
+    f = np.where(pb <= 0.1, 1.0, np.where(pb < 1.0, (pb / 0.1) ** KAPPA_AD, 10.0 ** KAPPA_AD))
+    return t_strat * f
+
+
+def hopf_stretched(q0, q_inf, p, p_t, beta):
+    """Stretched-exponential Hopf-like function in pressure, Eq. 12:
+    q(p) = q_inf + (q0 - q_inf) exp[-(p/p_t)^beta]."""
+    return q_inf + (q0 - q_inf) * np.exp(-(p / p_t) ** beta)
+
+
+def tp_milne(t_int, log10_kappa, t_ratio, log10_pt_bar, beta, p, g_ref):
+    """Modified Milne profile, Eqs. 9-14: T^4 = 3/4 T_int^4 [tau + q(tau)] with
+    tau = kappa_ir p / g (Eq. 10) and q the stretched exponential of Eq. 12,
+    q0 = 4/3 (T_skin/T_int)^4 = 4/3 T_ratio^4 (Eqs. 13-14).
+
+    Readings: q_inf is held at the classic large-depth Hopf value 0.710446
+    (the paper names five retrieved parameters, q_inf not among them);
+    kappa_ir and p_t are retrieved as log10 (cgs and bar).  Parameters:
+    T_int, log10 kappa_ir, T_ratio, log10 p_t [bar], beta."""
+    tau = 10.0 ** log10_kappa * p / g_ref
+    q0 = 4.0 / 3.0 * t_ratio ** 4
+    q = hopf_stretched(q0, Q_HOPF_INF, p, 10.0 ** log10_pt_bar * BAR, beta)
+    return (0.75 * t_int ** 4 * (tau + q)) ** 0.25
+
+
+def tp_guillot7(t_int, t_eq, log10_kappa, log10_gamma, q_irr0, log10_pt_bar, beta, p, g_ref, f_hem):
+    """Modified Guillot profile, Eq. 16, in its seven-parameter form.
+
+    T^4 = 3/4 T_int^4 [q_int + tau]
+        + 3/4 T_eq^4 4 f_hem [q_irr(tau) + 1/(gamma sqrt 3) + (gamma/sqrt 3 - 1/(gamma sqrt 3)) e^(-gamma tau sqrt 3)]
+    with mu_* = 1/sqrt 3, q_int = 2/3 (Eddington, as the paper recommends for
+    hot Jupiters), q_irr the stretched exponential of Eq. 12 from q_irr,0 to
+    q_irr,inf = 2/3, tau = kappa_ir p / g (Eq. 10) and f_hem a fixed workload
+    constant.  Readings: kappa_ir, gamma_v and p_t are retrieved as log10 (cgs,
+    -, bar).  Parameters: T_int, T_eq, log10 kappa_ir, log10 gamma_v, q_irr,0,
+    log10 p_t [bar], beta.  With q_irr,0 = 2/3 this is the three-parameter form
+    at kappa_ir = 10^log10_kappa."""
+    gam = 10.0 ** log10_gamma
+    tau = 10.0 ** log10_kappa * p / g_ref
+    s3 = np.sqrt(3.0)
+    q_irr = hopf_stretched(q_irr0, 2.0 / 3.0, p, 10.0 ** log10_pt_bar * BAR, beta)
+    t4 = (0.75 * t_int ** 4 * (2.0 / 3.0 + tau)
+          + 0.75 * t_eq ** 4 * 4.0 * f_hem
+          * (q_irr + 1.0 / (gam * s3) + (gam / s3 - 1.0 / (gam * s3)) * np.exp(-gam * tau * s3)))
     return t4 ** 0.25
 
 
@@ -132,6 +187,12 @@ def tp_profile(wl, tp_theta, p):
     if kind == TP_GUILLOT3:
         return tp_guillot3(tp_theta[0], tp_theta[1], tp_theta[2], p,
                            wl["kappa_ir"], wl["g_ref"], wl["f_hem"])
+    if kind == TP_BARSTOW:
+        return tp_barstow(tp_theta[0], p)
+    if kind == TP_MILNE:
+        return tp_milne(*tp_theta, p, wl["g_ref"])
+    if kind == TP_GUILLOT7:
+        return tp_guillot7(*tp_theta, p, wl["g_ref"], wl["f_hem"])
     # knots equally spaced in log10 p from p_top (knot 0) to p_bot (last knot)
     nk = len(tp_theta)
     xk = np.linspace(np.log10(wl["p_top"]), np.log10(wl["p_bot"]), nk)
@@ -505,7 +566,7 @@ def log_likelihood(y_obs, model, sigma, err_c=-99.0):
 def split_params(wl, theta):
     """Split a parameter vector by the workload's layout."""
     k = 0
-    ntp = {TP_ISOTHERMAL: 1, TP_GUILLOT3: 3, TP_PCHIP: wl.get("n_knots", 5)}[wl["tp"]]
+    ntp = wl.get("n_knots", 5) if wl["tp"] == TP_PCHIP else TP_NPARAM[wl["tp"]]
     out = {"tp": theta[k:k + ntp]}
     k += ntp
     out["logx"] = theta[k:k + wl["n_species"]]

@@ -46,6 +46,9 @@ SPECIES_MASS = (18.015, 44.009, 28.010, 16.043, 17.031, 34.081, 64.066, 22.990)
 TP_ISOTHERMAL = 0
 TP_GUILLOT3 = 1
 TP_PCHIP = 2
+TP_BARSTOW = 3
+TP_MILNE = 4
+TP_GUILLOT7 = 5
 
 MODE_TRANSMISSION = 0
 MODE_EMISSION = 1
@@ -220,6 +223,12 @@ def param_names(cfg) -> list:
         names = ["T_iso"]
     elif cfg["tp"] == TP_GUILLOT3:
         names = ["T_int", "T_eq", "log10_gamma_v"]
+    elif cfg["tp"] == TP_BARSTOW:
+        names = ["T_strat"]
+    elif cfg["tp"] == TP_MILNE:
+        names = ["T_int", "log10_kappa_ir", "T_ratio", "log10_p_t_bar", "beta"]
+    elif cfg["tp"] == TP_GUILLOT7:
+        names = ["T_int", "T_eq", "log10_kappa_ir", "log10_gamma_v", "q_irr0", "log10_p_t_bar", "beta"]
     else:
         names = [f"T_knot{k}" for k in range(cfg["n_knots"])]
     names += [f"log10_X_{SPECIES[i]}" for i in range(s)]
@@ -247,6 +256,12 @@ def param_bounds(cfg):
         b = [(1200.0, 1200.0)]
     elif cfg["tp"] == TP_GUILLOT3:
         b = [(100.0, 1500.0), (500.0, 2000.0), (-3.0, 2.0)]
+    elif cfg["tp"] == TP_BARSTOW:
+        b = [(600.0, 2000.0)]
+    elif cfg["tp"] == TP_MILNE:
+        b = [(600.0, 1500.0), (-3.0, -1.0), (0.4, 0.9), (-3.0, 1.0), (0.5, 2.0)]
+    elif cfg["tp"] == TP_GUILLOT7:
+        b = [(100.0, 500.0), (800.0, 1800.0), (-3.0, -1.0), (-2.0, 1.0), (0.1, 0.65), (-4.0, 0.0), (0.5, 2.0)]
     else:
         b = [(800.0, 2500.0)] * cfg["n_knots"]
     b += [(-8.0, -2.0)] * s if cfg["tp"] != TP_ISOTHERMAL else [(-3.0, -3.0)] * s

@@ -635,3 +635,108 @@ def test_cloud_fraction_complex_step_matches_central_differences():
     gf = oracle.grad_central_fd(wl, th)
     scale = np.maximum(np.abs(gc), 1e-3 * np.max(np.abs(gc)))
     assert np.max(np.abs(gc - gf) / scale) < 1e-5, (gc, gf)
+
+
+# --------------------------------------------------------------------------- f3: T-p family
+def test_barstow_isotherms_and_adiabat():
+    """Eq. 8: flat at T_strat above 0.1 bar, d ln T / d ln p = kappa = 2/7 between 0.1 and
+    1 bar (the dry adiabat of a diatomic gas, R/c_p = 2/7), flat below, continuous at both joins."""
+    t = 1234.0
+    assert oracle.KAPPA_AD == pytest.approx(8.314462618 / (3.5 * 8.314462618))
+    hi = oracle.tp_barstow(t, np.logspace(-7, -1, 9) * BAR)
+    np.testing.assert_array_equal(hi, t)
+    pm = np.logspace(-0.95, -0.05, 7) * BAR
+    h = 1e-6
+    slope = (np.log(oracle.tp_barstow(t, pm * (1 + h))) - np.log(oracle.tp_barstow(t, pm * (1 - h)))) / (
+        np.log1p(h) - np.log1p(-h))
+    np.testing.assert_allclose(slope, 2.0 / 7.0, rtol=1e-8)
+    for pj in (0.1, 1.0):
+        a, b = oracle.tp_barstow(t, np.array([pj * (1 - 1e-12), pj * (1 + 1e-12)]) * BAR)
+        assert a == pytest.approx(b, rel=1e-10)
+    deep = oracle.tp_barstow(t, np.logspace(0.01, 2, 5) * BAR)
+    np.testing.assert_allclose(deep, oracle.tp_barstow(t, np.array([1.0 * BAR]))[0], rtol=1e-15)
+    assert deep[0] / t == pytest.approx(10.0 ** (2.0 / 7.0), rel=1e-14)
+
+
+def test_milne_limits_and_constant_hopf():
+    """Eqs. 9-14: with q0 = q_inf the stretched Hopf function is constant and T^4 = 3/4 T_int^4
+    (tau + q_inf) whatever p_t and beta (the classic Milne solution); at tau -> 0 the profile
+    tends to the skin temperature T_ratio T_int (the definition of q0); deep down it is
+    the q_inf solution; a steep beta switches q from q0 to q_inf at p_t."""
+    g = 1000.0
+    p = np.logspace(-8, 3, 40) * BAR
+    t_int, lk = 900.0, -2.0
+    t_ratio_eq = (0.75 * oracle.Q_HOPF_INF) ** 0.25
+    for lpt, beta in ((-2.0, 0.7), (0.5, 1.8)):
+        t = oracle.tp_milne(t_int, lk, t_ratio_eq, lpt, beta, p, g)
+        np.testing.assert_allclose(t ** 4, 0.75 * t_int ** 4 * (10 ** lk * p / g + oracle.Q_HOPF_INF), rtol=1e-13)
+    t_ratio = 0.55
+    top = oracle.tp_milne(t_int, lk, t_ratio, -1.0, 1.0, np.array([1e-12 * BAR]), g)[0]
+    assert top == pytest.approx(t_ratio * t_int, rel=1e-9)
+    deep_p = np.array([1e3 * BAR])
+    deep = oracle.tp_milne(t_int, lk, t_ratio, -3.0, 1.0, deep_p, g)[0]
+    assert deep ** 4 == pytest.approx(0.75 * t_int ** 4 * (10 ** lk * deep_p[0] / g + oracle.Q_HOPF_INF), rel=1e-13)
+    q0 = 4.0 / 3.0 * t_ratio ** 4
+    pt = 10.0 ** -1.0 * BAR
+    pp = np.array([0.5 * pt, 2.0 * pt])
+    steep = oracle.tp_milne(t_int, lk, t_ratio, -1.0, 60.0, pp, g)
+    np.testing.assert_allclose(steep ** 4, 0.75 * t_int ** 4 * (10 ** lk * pp / g + np.array([q0, oracle.Q_HOPF_INF])),
+                               rtol=1e-13)
+    # the Hopf function itself at its ends and at p_t (value e^-1 of the way)
+    assert oracle.hopf_stretched(0.3, 0.7, pt, pt, 1.3) == pytest.approx(0.7 - 0.4 * math.exp(-1.0), rel=1e-15)
+
+
+def test_guillot7_reduces_to_three_parameter_form():
+    """Eq. 16 with q_irr,0 = q_irr,inf = 2/3 is the three-parameter profile (an independent
+    code path) at kappa_ir = 10^log10_kappa, for any p_t and beta; at tau -> 0 the
+    irradiation bracket is q_irr,0 + gamma/sqrt 3 and the internal one 2/3."""
+    p = np.logspace(-7, 2, 50) * BAR
+    g, fh = 1000.0, 0.25
+    t_int, t_eq, lk, lg = 250.0, 1300.0, -2.3, -0.4
+    for lpt, beta in ((-3.0, 0.6), (-0.5, 1.9)):
+        a = oracle.tp_guillot7(t_int, t_eq, lk, lg, 2.0 / 3.0, lpt, beta, p, g, fh)
+        b = oracle.tp_guillot3(t_int, t_eq, lg, p, 10 ** lk, g, fh)
+        np.testing.assert_allclose(a, b, rtol=1e-14)
+    q0 = 0.2
+    gam = 10 ** lg
+    top = oracle.tp_guillot7(t_int, t_eq, lk, lg, q0, -1.0, 1.0, np.array([1e-14 * BAR]), g, fh)[0]
+    assert top ** 4 == pytest.approx(0.5 * t_int ** 4 + 3 * fh * t_eq ** 4 * (q0 + gam / math.sqrt(3)), rel=1e-10)
+    # a lower q_irr,0 cools the upper atmosphere and leaves the deep one
+    cool = oracle.tp_guillot7(t_int, t_eq, lk, lg, q0, -2.0, 1.0, p, g, fh)
+    ref = oracle.tp_guillot7(t_int, t_eq, lk, lg, 2.0 / 3.0, -2.0, 1.0, p, g, fh)
+    assert np.all(cool <= ref) and cool[0] < ref[0] and cool[-1] == pytest.approx(ref[-1], rel=1e-12)
+
+
+def _tp_slice(tp, cid=1, n_nu=1500, batch=3, seed=7):
+    wl = dict(synth.workload(cid, batch=batch, require_obs=False))
+    sl = slice(0, n_nu)
+    wl["nu"] = wl["nu"][sl]
+    wl["log10_xsec"] = wl["log10_xsec"][..., sl]
+    if wl["log10_cia"] is not None:
+        wl["log10_cia"] = wl["log10_cia"][..., sl]
+    wl["bin_lo"] = np.arange(0, n_nu, 100, dtype=np.int32)
+    wl["bin_hi"] = wl["bin_lo"] + 100
+    k = len(wl["bin_lo"])
+    lvl = 0.0125 if wl["mode"] == 0 else 1e-4
+    wl["y_obs"] = np.full(k, lvl)
+    wl["y_err"] = np.full(k, 5e-5 if wl["mode"] == 0 else 1e-5)
+    wl["offset_mask"] = (np.arange(k) % 2).astype(np.uint8)
+    cfg = {**synth.CONFIGS[cid], "tp": tp}
+    bounds = synth.param_bounds(cfg)
+    u = np.random.default_rng(seed).uniform(size=(batch, len(bounds)))
+    wl.update(tp=tp, param_names=synth.param_names(cfg), param_bounds=bounds,
+              params=bounds[:, 0] + u * (bounds[:, 1] - bounds[:, 0]))
+    return wl
+
+
+@pytest.mark.parametrize("tp,cid", [(oracle.TP_BARSTOW, 1), (oracle.TP_MILNE, 2), (oracle.TP_GUILLOT7, 1),
+                                    (oracle.TP_GUILLOT7, 2)])
+def test_tp_family_complex_step_matches_central_differences(tp, cid):
+    wl = _tp_slice(tp, cid)
+    wl["n_layers"] = 40
+    th = wl["params"][0]
+    assert oracle.forward(wl, th)["status"] == 0
+    gc = oracle.grad_complex_step(wl, th)
+    gf = oracle.grad_central_fd(wl, th)
+    scale = np.maximum(np.abs(gc), 1e-3 * np.max(np.abs(gc)))
+    assert np.max(np.abs(gc - gf) / scale) < 1e-5, (gc, gf)
