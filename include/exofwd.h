@@ -62,7 +62,11 @@ enum { EXOFWD_TRANSMISSION = 0, EXOFWD_EMISSION = 1 };
  *        profile, hydrostatics and likelihood sums stay FP64.           */
 enum { EXOFWD_PREC_FP64 = 0, EXOFWD_PREC_MIXED = 1 };
 
-enum { EXOFWD_TP_ISOTHERMAL = 0, EXOFWD_TP_GUILLOT3 = 1, EXOFWD_TP_PCHIP = 2 };
+/* T-p profiles (Section "T-p profile parameterisation"): isothermal (Eq. 7), the
+ * modified Guillot profile (Eq. 16) in three- and seven-parameter forms, PCHIP
+ * knots, Barstow 2020 (Eq. 8) and the modified Milne profile (Eqs. 9-14). */
+enum { EXOFWD_TP_ISOTHERMAL = 0, EXOFWD_TP_GUILLOT3 = 1, EXOFWD_TP_PCHIP = 2, EXOFWD_TP_BARSTOW = 3,
+       EXOFWD_TP_MILNE = 4, EXOFWD_TP_GUILLOT7 = 5 };
 
 /* Cloud models (transmission).  GREY_DECK: a slab from P_cloud down with a
  * fixed grey opacity kappa_cloud.  NONGREY: a condensate profile q_c(p)
@@ -89,6 +93,14 @@ enum {
  *         guillot3    -> [T_int, T_eq, log10 gamma_v]          (Eq. 16, q = 2/3)
  *         pchip       -> [T_0 .. T_{n_knots-1}], knot k at log10 p equally
  *                        spaced from p_top (k = 0) to p_bot
+ *         barstow     -> [T_strat]   (Eq. 8: isotherm to 0.1 bar, adiabat with kappa = 2/7
+ *                        to 1 bar, isotherm below)
+ *         milne       -> [T_int, log10 kappa_ir, T_ratio, log10 p_t/bar, beta]
+ *                        (Eqs. 9-14: T^4 = 3/4 T_int^4 (tau + q), tau = kappa_ir p / g_ref,
+ *                        q stretched from q0 = 4/3 T_ratio^4 to q_inf = 0.710446)
+ *         guillot7    -> [T_int, T_eq, log10 kappa_ir, log10 gamma_v, q_irr0, log10 p_t/bar, beta]
+ *                        (Eq. 16, q_int = 2/3, q_irr stretched from q_irr0 to 2/3;
+ *                        kappa_ir here replaces the config's kappa_ir)
  *   then  log10 X_s for s = 0..n_species-1                       (Eq. 35)
  *   then  cloud parameters      if has_cloud:
  *           GREY_DECK: [log10 P_cloud/bar]
@@ -122,7 +134,7 @@ typedef struct exofwd_config {
   double mu_fixed;           /* > 0: fixed mean molecular weight [amu]; else from composition */
   double p_bot_bar, p_top_bar, p_ref_bar;   /* grid bottom/top, reference pressure [bar] */
   double r_p, r_s, g_ref;    /* reference radius [cm], stellar radius [cm], gravity at r_p [cm s^-2] */
-  double kappa_ir, f_hem;    /* Guillot infrared opacity [cm^2 g^-1], redistribution factor */
+  double kappa_ir, f_hem;    /* guillot3 infrared opacity [cm^2 g^-1]; redistribution factor (guillot3/7) */
   double kappa_cloud;        /* grey deck mass opacity [cm^2 g^-1] */
   double t_star, dilution;   /* emission: stellar blackbody T [K], dilution s */
   double err_c;              /* error inflation exponent c (Eq. 3); -99 = off */

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(_HERE, "libexofwd.so")
 OK, ERR_ARG, ERR_SHAPE, ERR_CONFIG, ERR_NOMEM, ERR_DEVICE, ERR_UNSUPPORTED = range(7)
 TRANSMISSION, EMISSION = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
-TP_ISOTHERMAL, TP_GUILLOT3, TP_PCHIP = 0, 1, 2
+TP_ISOTHERMAL, TP_GUILLOT3, TP_PCHIP, TP_BARSTOW, TP_MILNE, TP_GUILLOT7 = 0, 1, 2, 3, 4, 5
 S_BAD_VMR, S_UNBOUND, S_NONFINITE, S_BAD_T, S_BAD_LAYERS = 1, 2, 4, 8, 16
 
 _D = C.POINTER(C.c_double)

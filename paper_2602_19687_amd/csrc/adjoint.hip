@@ -18,6 +18,7 @@
 #include "kernels.h"
 #include "cloud.h"
 #include "opacity.h"
+#include "tp.h"
 
 namespace exofwd {
 
@@ -1125,6 +1126,14 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
       s_red[tid] += tbar * 3.0 * ti * ti * ti * (2.0 / 3.0 + tau) / (4.0 * t3);
       s_red[kBlock + tid] += tbar * 12.0 * m.f_hem * te * te * te * bk / (4.0 * t3);
       s_red[2 * kBlock + tid] += tbar * 3.0 * m.f_hem * te * te * te * te * dbk * gam * ln10 / (4.0 * t3);
+    } else if (m.tp_kind == kTpBarstow) {
+      s_red[tid] += tbar * barstow_factor(lp);
+    } else if (m.tp_kind == kTpMilne || m.tp_kind == kTpGuillot7) {
+      double d4[7];
+      if (m.tp_kind == kTpMilne) milne_t4(th, lp, m.g_ref, d4);
+      else guillot7_t4(th, lp, m.g_ref, m.f_hem, d4);
+      const double inv = tbar / (4.0 * t * t * t);
+      for (int k = 0; k < m.n_tp; ++k) s_red[k * kBlock + tid] += d4[k] * inv;
     } else {
       // T = h00 y_k + h10 h d_k + h01 y_k+1 + h11 h d_k+1 on the knot interval holding lp
       const int n = m.n_knots;

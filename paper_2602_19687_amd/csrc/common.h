@@ -44,7 +44,9 @@ __host__ __device__ inline int pack_cells(int it, int ip, int itc) { return it |
 
 enum : int { kTransmission = 0, kEmission = 1 };
 enum : int { kFP64 = 0, kMixed = 1 };
-enum : int { kTpIso = 0, kTpGuillot3 = 1, kTpPchip = 2 };
+enum : int { kTpIso = 0, kTpGuillot3 = 1, kTpPchip = 2, kTpBarstow = 3, kTpMilne = 4, kTpGuillot7 = 5 };
+constexpr double kKappaAd = 2.0 / 7.0;    // adiabatic exponent of the Barstow profile (Eq. 8)
+constexpr double kQHopfInf = 0.710446;    // large-depth Hopf value, q_inf of the modified Milne profile
 enum : int { kQprofUniform = 0, kQprofSlab = 1, kQprofPower = 2 };
 enum : int { kQextFit = 0, kQextFeature = 1, kQextGrey = 2 };
 constexpr int kCloudSpec = 7;   // spectral cloud parameters: log10 r, a, log10 Q0, A, lambda0, log10 omega, xi

@@ -216,7 +216,7 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   const auto& g = *cfg;
   if (g.mode != EXOFWD_TRANSMISSION && g.mode != EXOFWD_EMISSION) return EXOFWD_ERR_CONFIG;
   if (g.precision != EXOFWD_PREC_FP64 && g.precision != EXOFWD_PREC_MIXED) return EXOFWD_ERR_CONFIG;
-  if (g.tp_kind < 0 || g.tp_kind > 2) return EXOFWD_ERR_CONFIG;
+  if (g.tp_kind < EXOFWD_TP_ISOTHERMAL || g.tp_kind > EXOFWD_TP_GUILLOT7) return EXOFWD_ERR_CONFIG;
   if (g.tp_kind == EXOFWD_TP_PCHIP && (g.n_knots < 2 || g.n_knots > kMaxKnots)) return EXOFWD_ERR_CONFIG;
   if (g.n_species < 1 || g.n_species > kMaxSpecies) return EXOFWD_ERR_CONFIG;
   if (g.n_layers_max < 1 || g.n_layers_max > kMaxLayers) return EXOFWD_ERR_CONFIG;
@@ -289,7 +289,14 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   m.n_p = g.n_p;
   m.n_tc = g.has_cia ? g.n_tc : 2;
   m.K = g.n_bins;
-  m.n_tp = g.tp_kind == EXOFWD_TP_ISOTHERMAL ? 1 : (g.tp_kind == EXOFWD_TP_GUILLOT3 ? 3 : g.n_knots);
+  switch (g.tp_kind) {
+    case EXOFWD_TP_ISOTHERMAL: m.n_tp = 1; break;
+    case EXOFWD_TP_GUILLOT3: m.n_tp = 3; break;
+    case EXOFWD_TP_PCHIP: m.n_tp = g.n_knots; break;
+    case EXOFWD_TP_BARSTOW: m.n_tp = 1; break;
+    case EXOFWD_TP_MILNE: m.n_tp = 5; break;
+    default: m.n_tp = 7; break;   // EXOFWD_TP_GUILLOT7
+  }
   int k = m.n_tp + m.S;
   m.idx_cloud = m.has_cloud ? k : -1;
   k += m.n_cloud;
@@ -700,7 +707,11 @@ std::vector<double> neutral_params(const Model& m) {
   std::vector<double> th(m.P, 0.0);
   if (m.tp_kind == kTpIso) th[0] = 1200.0;
   else if (m.tp_kind == kTpGuillot3) { th[0] = 500.0; th[1] = 1200.0; th[2] = 0.0; }
-  else for (int k = 0; k < m.n_tp; ++k) th[k] = 1200.0;
+  else if (m.tp_kind == kTpBarstow) th[0] = 1000.0;
+  else if (m.tp_kind == kTpMilne) { th[0] = 1000.0; th[1] = -2.0; th[2] = 0.6; th[3] = -1.0; th[4] = 1.0; }
+  else if (m.tp_kind == kTpGuillot7) {
+    th[0] = 300.0; th[1] = 1200.0; th[2] = -2.0; th[3] = 0.0; th[4] = 0.4; th[5] = -2.0; th[6] = 1.0;
+  } else for (int k = 0; k < m.n_tp; ++k) th[k] = 1200.0;
   for (int s2 = 0; s2 < m.S; ++s2) th[m.n_tp + s2] = -6.0;
   if (m.has_cloud && !m.cloud_ng) th[m.idx_cloud] = m.log10_pbot + 1.0;
   if (m.cloud_ng) {

@@ -3,6 +3,7 @@
 // areas.  One workgroup of 256 threads per sample.
 #include "cloud.h"
 #include "kernels.h"
+#include "tp.h"
 
 namespace exofwd {
 
@@ -159,6 +160,9 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
       double tau = m.kappa_ir * exp10(log10p_bar) * kBar / m.g_ref;
       return guillot3(th[0], th[1], exp10(th[2]), tau, m.f_hem);
     }
+    if (m.tp_kind == kTpBarstow) return th[0] * barstow_factor(log10p_bar);
+    if (m.tp_kind == kTpMilne) return sqrt(sqrt(milne_t4(th, log10p_bar, m.g_ref)));
+    if (m.tp_kind == kTpGuillot7) return sqrt(sqrt(guillot7_t4(th, log10p_bar, m.g_ref, m.f_hem)));
     return pchip_eval(s_knot_x, s_knot_y, s_knot_d, m.n_knots, log10p_bar);
   };
 

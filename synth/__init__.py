@@ -259,9 +259,9 @@ def param_bounds(cfg):
     elif cfg["tp"] == TP_BARSTOW:
         b = [(600.0, 2000.0)]
     elif cfg["tp"] == TP_MILNE:
-        b = [(600.0, 1500.0), (-3.0, -1.0), (0.4, 0.9), (-3.0, 1.0), (0.5, 2.0)]
+        b = [(400.0, 1000.0), (-4.0, -2.5), (0.4, 0.9), (-3.0, 1.0), (0.5, 2.0)]
     elif cfg["tp"] == TP_GUILLOT7:
-        b = [(100.0, 500.0), (800.0, 1800.0), (-3.0, -1.0), (-2.0, 1.0), (0.1, 0.65), (-4.0, 0.0), (0.5, 2.0)]
+        b = [(100.0, 500.0), (800.0, 1800.0), (-3.0, -2.0), (-2.0, 1.0), (0.1, 0.65), (-4.0, 0.0), (0.5, 2.0)]
     else:
         b = [(800.0, 2500.0)] * cfg["n_knots"]
     b += [(-8.0, -2.0)] * s if cfg["tp"] != TP_ISOTHERMAL else [(-3.0, -3.0)] * s

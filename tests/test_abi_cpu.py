@@ -95,3 +95,25 @@ def test_cloud_options_validated_before_device(change, ok):
     else:
         assert rc == L.ERR_CONFIG
         assert ctx.value is None
+
+
+@pytest.mark.parametrize("tp,ok", [(3, True), (4, True), (5, True), (6, False), (-1, False)])
+def test_tp_kinds_validated_before_device(tp, ok):
+    """Barstow, modified Milne and seven-parameter Guillot are accepted; unknown kinds
+    are refused before any device call."""
+    import synth
+    from paper_2602_19687_amd.model import build_config
+    lib = pkg.load()
+    wl = dict(synth.workload(1, batch=2))
+    wl["tp"] = tp
+    cfg, keep = build_config(wl, L.PREC_MIXED, 2)
+    ctx = C.c_void_p()
+    rc = lib.exofwd_create(C.byref(cfg), C.byref(ctx))
+    if ok:
+        assert rc in (L.OK, L.ERR_DEVICE)
+        if rc == L.OK:
+            assert lib.exofwd_num_params(ctx) == len(synth.param_names({**synth.CONFIGS[1], "tp": tp}))
+            lib.exofwd_destroy(ctx)
+    else:
+        assert rc == L.ERR_CONFIG
+        assert ctx.value is None

@@ -1,0 +1,90 @@
+"""GPU parity of the Barstow (Eq. 8), modified Milne (Eqs. 9-14) and
+seven-parameter modified Guillot (Eq. 16) T-p profiles against the FP64
+oracle: spectra and lnL of every sample in both precisions, and the gradient
+against the oracle's complex step (the chain rule through each profile's
+parameter derivatives).
+
+Workloads: the grey-deck transmission setup (every 30th of 30000 wavenumbers,
+30 bins) and the emission setup (every 40th of 20000, 20 bins), 100 layers,
+4 samples drawn from the prior bounds.  Tolerances: spectra and lnL 1e-5
+(FP64) / 1e-3 (mixed); gradients per component relative to
+max(|g*_j|, 1e-3 max|g*|): 1e-5 (FP64), 1e-3 (mixed transmission), 2e-3
+(mixed emission).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity_util import reduced, rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+CASES = [(synth.TP_BARSTOW, 3), (synth.TP_MILNE, 3), (synth.TP_MILNE, 2), (synth.TP_GUILLOT7, 3),
+         (synth.TP_GUILLOT7, 2)]
+IDS = ["barstow-trans", "milne-trans", "milne-emis", "guillot7-trans", "guillot7-emis"]
+SPEC_TOL = {"fp64": 1e-5, "mixed": 1e-3}
+BATCH = 4
+
+
+def tp_wl(tp, cid):
+    if cid == 2:
+        wl = reduced(2, n_nu=500, n_bins=20, batch=BATCH, step=40)
+    else:
+        wl = reduced(cid, n_nu=1000, n_bins=30, batch=BATCH, step=30)
+    cfg = {**synth.CONFIGS[cid], "tp": tp}
+    bounds = synth.param_bounds(cfg)
+    u = np.random.default_rng(500 + 10 * tp + cid).uniform(size=(BATCH, len(bounds)))
+    wl.update(tp=tp, param_bounds=bounds, param_names=synth.param_names(cfg),
+              params=bounds[:, 0] + u * (bounds[:, 1] - bounds[:, 0]))
+    return wl
+
+
+_REF = {}
+
+
+def oracle_refs(tp, cid, wl):
+    if (tp, cid) not in _REF:
+        fwd = [oracle.forward(wl, th) for th in wl["params"]]
+        grads = [oracle.grad_complex_step(wl, th) if r["status"] == 0 else None for th, r in zip(wl["params"], fwd)]
+        _REF[(tp, cid)] = (fwd, grads)
+    return _REF[(tp, cid)]
+
+
+def grad_err(g, gref):
+    scale = np.maximum(np.abs(gref), 1e-3 * np.max(np.abs(gref)))
+    return np.max(np.abs(g - gref) / scale)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("tp,cid", CASES, ids=IDS)
+def test_tp_profile_forward_and_grad(tp, cid, prec):
+    from paper_2602_19687_amd import ForwardModel
+    wl = tp_wl(tp, cid)
+    print(f"[gpu] T-p kind {tp} config {cid} {prec}", flush=True)
+    fwd, grads = oracle_refs(tp, cid, wl)
+    fm = ForwardModel(wl, precision=prec, batch_max=BATCH)
+    assert fm.n_params == len(wl["param_names"])
+    th = torch.tensor(wl["params"], device="cuda")
+    spec, lnl, st = fm.forward(th)
+    spec, lnl, st = spec.double().cpu().numpy(), lnl.cpu().numpy(), st.cpu().numpy()
+    assert fm.has_grad
+    lnl2, g, st2, _ = fm.grad(th)
+    lnl2, g, st2 = lnl2.cpu().numpy(), g.cpu().numpy(), st2.cpu().numpy()
+    fm.close()
+    gtol = 1e-5 if prec == "fp64" else (2e-3 if cid == 2 else 1e-3)
+    n_ok, worst_s, worst_g = 0, 0.0, 0.0
+    for b, ref in enumerate(fwd):
+        assert st[b] == ref["status"] and st2[b] == ref["status"]
+        if ref["status"]:
+            continue
+        n_ok += 1
+        worst_s = max(worst_s, rel_err(spec[b], ref["spectrum"]))
+        assert abs(lnl[b] - ref["lnL"]) <= SPEC_TOL[prec] * abs(ref["lnL"]), (b, lnl[b], ref["lnL"])
+        assert lnl2[b] == lnl[b]
+        worst_g = max(worst_g, grad_err(g[b], grads[b]))
+    print(f"T-p kind {tp} config {cid} {prec}: spectrum {worst_s:.3e}, gradient {worst_g:.3e}")
+    assert n_ok >= 3
+    assert worst_s < SPEC_TOL[prec]
+    assert worst_g < gtol
