@@ -103,11 +103,35 @@ def measured_traffic(kernel, workload_tag="transmission_ns_b1024"):
 
 _WL = {}
 
+TP_KINDS = {"barstow": 3, "milne": 4, "guillot7": 5}
 
-def _oracle_init(cid, batch):
+
+def with_tp(wl, cid, tp_name):
+    """The workload with its T-p profile replaced (Barstow, modified Milne or the
+    seven-parameter modified Guillot form): the T-p parameters are drawn from that
+    profile's prior bounds, every other parameter keeps the workload's own draw."""
+    if not tp_name:
+        return wl
+    import numpy as np
+    import synth
+    tp = TP_KINDS[tp_name]
+    cfg = {**synth.CONFIGS[cid], "tp": tp}
+    names, bounds = synth.param_names(cfg), synth.param_bounds(cfg)
+    n_new = next(i for i, n in enumerate(names) if n.startswith("log10_X_"))
+    n_old = next(i for i, n in enumerate(wl["param_names"]) if n.startswith("log10_X_"))
+    B = wl["params"].shape[0]
+    u = np.random.default_rng([19687, cid, 7, tp]).uniform(size=(B, n_new))
+    tp_par = bounds[:n_new, 0] + u * (bounds[:n_new, 1] - bounds[:n_new, 0])
+    out = dict(wl)
+    out.update(tp=tp, param_names=names, param_bounds=bounds,
+               params=np.concatenate([tp_par, wl["params"][:, n_old:]], axis=1))
+    return out
+
+
+def _oracle_init(cid, batch, tp_name=None):
     os.environ["OMP_NUM_THREADS"] = "1"
     import synth
-    _WL["wl"] = synth.workload(cid, batch=batch)
+    _WL["wl"] = with_tp(synth.workload(cid, batch=batch), cid, tp_name)
 
 
 def _oracle_worker(args):
@@ -121,7 +145,7 @@ def _oracle_worker(args):
     return idx, out["spectrum"], out["lnL"], g, time.perf_counter() - t0
 
 
-def cpu_baseline(cid, batch, n_samples, do_grad):
+def cpu_baseline(cid, batch, n_samples, do_grad, tp_name=None):
     """Time the FP64 oracle, as it stands, on a bounded sample of the workload on
     the host cores: one sample per task, one BLAS thread per worker process;
     throughput = samples / (summed per-sample seconds / workers)."""
@@ -129,7 +153,7 @@ def cpu_baseline(cid, batch, n_samples, do_grad):
     idx = list(range(0, batch, max(1, batch // n_samples)))[:n_samples]
     workers = min(cores, len(idx))
     ctx = mp.get_context("spawn")
-    with ctx.Pool(workers, initializer=_oracle_init, initargs=(cid, batch)) as pool:
+    with ctx.Pool(workers, initializer=_oracle_init, initargs=(cid, batch, tp_name)) as pool:
         res = pool.map(_oracle_worker, [(i, do_grad) for i in idx], chunksize=1)
     busy = sum(r[4] for r in res)
     return [r[:4] for r in res], busy / workers, workers
@@ -149,6 +173,8 @@ def main():
     ap.add_argument("--tuning", type=str, default=None,
                     help="launch choices a,b,c,d to use instead of autotuning (see exofwd_set_tuning)")
     ap.add_argument("--no-graphs", action="store_true")
+    ap.add_argument("--tp", choices=sorted(TP_KINDS), default=None,
+                    help="replace the workload's T-p profile (Barstow, modified Milne, 7-parameter modified Guillot)")
     ap.add_argument("--cpu-samples", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -178,7 +204,7 @@ def main():
     cid = args.config
     B = args.batch or (64 if cid == 4 else 1024)
     t_setup = time.perf_counter()
-    wl = synth.workload(cid, batch=B)
+    wl = with_tp(synth.workload(cid, batch=B), cid, args.tp)
     L_, S, n_nu = wl["n_layers"], wl["n_species"], len(wl["nu"])
     th = torch.tensor(wl["params"], dtype=torch.float64, device="cuda")
     nl_np = wl["n_layers_per_sample"]
@@ -293,6 +319,9 @@ def main():
     else:
         workload = (f"high-resolution transmission, 4 absorbers, 8x8x400000 FP16 tables, {int(Ls.min())}-{int(Ls.max())} "
                     f"layers per sample, 400 bins, {th.shape[1]} params")
+    if args.tp:
+        names = {"barstow": "Barstow 2020", "milne": "modified Milne", "guillot7": "7-parameter modified Guillot"}
+        workload += f"; T-p profile replaced by the {names[args.tp]} profile ({th.shape[1]} params)"
     out = {
         "metric": ("forward+grad spectra/sec at B=1024 (FP32/FP16 vs FP64 plain), max rel err"
                    if mixed["has_grad"] else "forward spectra/sec at B=1024 (FP32/FP16 vs FP64 plain), max rel err")
@@ -335,7 +364,7 @@ def main():
         out["max_rel_err_vs_fp64_gpu"] = float(np.max(np.abs(mixed["spec"][ok] - fp64["spec"][ok])
                                                       / np.abs(fp64["spec"][ok])))
     if not args.no_cpu_baseline and cid == 1:
-        res, dt, cores = cpu_baseline(cid, B, args.cpu_samples, mixed["has_grad"])
+        res, dt, cores = cpu_baseline(cid, B, args.cpu_samples, mixed["has_grad"], args.tp)
         n = len(res)
         errs, lerrs, gerrs = [], [], []
         for idx, spec, lnl, g in res:
