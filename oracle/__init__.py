@@ -16,7 +16,9 @@ from .model import (  # noqa: F401
     BAR, K_B, M_U, H_PL, C_LIGHT, HE_H2, M_H2, M_HE,
     S_BAD_VMR, S_UNBOUND, S_NONFINITE, S_BAD_T, S_BAD_LAYERS, INVALID_LNL,
     level_pressures, tp_isothermal, tp_guillot3, pchip, tp_profile, chemistry,
-    TP_BARSTOW, TP_MILNE, TP_GUILLOT7, KAPPA_AD, Q_HOPF_INF, tp_barstow, hopf_stretched, tp_milne, tp_guillot7,
+    TP_ISOTHERMAL, TP_GUILLOT3, TP_PCHIP, TP_BARSTOW, TP_MILNE, TP_GUILLOT7, KAPPA_AD, Q_HOPF_INF, tp_barstow,
+    hopf_stretched, tp_milne, tp_guillot7,
+    G_GRAV, M_JUP, toa_flux, brown_dwarf_radius, brown_dwarf_flux,
     altitudes, interp_index, bilinear_log_table, cia_log, cloud_fraction,
     layer_optical_depth, path_matrix, transit_depth, planck, gauss_legendre_01,
     emission_intensity, emission_ratio, bin_means, log_likelihood,

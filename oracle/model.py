@@ -20,6 +20,8 @@ H_PL = 6.62607015e-27       # erg s
 C_LIGHT = 2.99792458e10     # cm s^-1
 M_U = 1.66053906660e-24     # g
 BAR = 1.0e6                 # dyn cm^-2
+G_GRAV = 6.67430e-8         # cm^3 g^-1 s^-2
+M_JUP = 1.89813e30          # g (nominal G M_J / G)
 HE_H2 = 0.164               # He/H2 number ratio (free-chemistry filling, Eq. 36)
 M_H2 = 2.01588              # amu
 M_HE = 4.002602             # amu
@@ -179,20 +181,23 @@ def pchip(xk, yk, x):
     return h00 * yk[k] + h10 * h[k] * d[k] + h01 * yk[k + 1] + h11 * h[k] * d[k + 1]
 
 
-def tp_profile(wl, tp_theta, p):
-    """T at pressures p [dyn cm^-2] for the workload's profile kind."""
+def tp_profile(wl, tp_theta, p, g=None):
+    """T at pressures p [dyn cm^-2] for the workload's profile kind; g is the
+    gravity in the infrared optical depth tau = kappa_ir p / g (default: the
+    workload's g_ref)."""
     kind = wl["tp"]
+    g = wl["g_ref"] if g is None else g
     if kind == TP_ISOTHERMAL:
         return tp_isothermal(tp_theta[0], p)
     if kind == TP_GUILLOT3:
         return tp_guillot3(tp_theta[0], tp_theta[1], tp_theta[2], p,
-                           wl["kappa_ir"], wl["g_ref"], wl["f_hem"])
+                           wl["kappa_ir"], g, wl["f_hem"])
     if kind == TP_BARSTOW:
         return tp_barstow(tp_theta[0], p)
     if kind == TP_MILNE:
-        return tp_milne(*tp_theta, p, wl["g_ref"])
+        return tp_milne(*tp_theta, p, g)
     if kind == TP_GUILLOT7:
-        return tp_guillot7(*tp_theta, p, wl["g_ref"], wl["f_hem"])
+        return tp_guillot7(*tp_theta, p, g, wl["f_hem"])
     # knots equally spaced in log10 p from p_top (knot 0) to p_bot (last knot)
     nk = len(tp_theta)
     xk = np.linspace(np.log10(wl["p_top"]), np.log10(wl["p_bot"]), nk)
@@ -534,15 +539,30 @@ def emission_intensity(dtau, b_lev, mu):
     return i_nu
 
 
-def emission_ratio(dtau, t_lev, nu, r_p, r_s, t_star, n_mu, dilution):
-    """F_p / F_* = s F_toa / F_* (R_p/R_*)^2 (Eq. 45), F_toa = 2 pi sum_k w_k mu_k I_k,
-    F_* = pi B(T_*)."""
+def toa_flux(dtau, t_lev, nu, n_mu):
+    """Outgoing flux at the top of the atmosphere, F_toa = 2 pi sum_k w_k mu_k I_k."""
     b_lev = np.stack([planck(t, nu) for t in t_lev])
     mus, ws = gauss_legendre_01(n_mu)
     flux = 0.0
     for mu_k, w_k in zip(mus, ws):
         flux = flux + 2.0 * np.pi * w_k * mu_k * emission_intensity(dtau, b_lev, mu_k)
-    return dilution * flux / (np.pi * planck(t_star, nu)) * (r_p / r_s) ** 2
+    return flux
+
+
+def emission_ratio(dtau, t_lev, nu, r_p, r_s, t_star, n_mu, dilution):
+    """F_p / F_* = s F_toa / F_* (R_p/R_*)^2 (Eq. 45), F_* = pi B(T_*)."""
+    return dilution * toa_flux(dtau, t_lev, nu, n_mu) / (np.pi * planck(t_star, nu)) * (r_p / r_s) ** 2
+
+
+def brown_dwarf_radius(m_bd_mjup, g):
+    """R_bd = sqrt(G M_bd / g) (Eq. 47), M_bd in Jupiter masses, g in cm s^-2."""
+    return np.sqrt(G_GRAV * m_bd_mjup * M_JUP / g)
+
+
+def brown_dwarf_flux(dtau, t_lev, nu, r_bd, distance, n_mu, dilution):
+    """Flux of an isolated object at the observer, F_bd = s F_toa (R_bd/D)^2 (Eq. 46)
+    [erg s^-1 cm^-2 (cm^-1)^-1]."""
+    return dilution * toa_flux(dtau, t_lev, nu, n_mu) * (r_bd / distance) ** 2
 
 
 # ---------------------------------------------------------------------------
@@ -596,6 +616,9 @@ def split_params(wl, theta):
     fc = bool(wl.get("fcld", False))
     out["fcld"] = theta[k] if fc else 1.0
     k += int(fc)
+    bd = bool(wl.get("bd", False))
+    out["log10_g"], out["m_bd"] = (theta[k], theta[k + 1]) if bd else (None, None)
+    k += 2 * int(bd)
     out["scale"] = theta[k] if wl["scale"] else 1.0
     k += int(wl["scale"])
     out["offset"] = theta[k] if wl["offset"] else 0.0
@@ -648,9 +671,12 @@ def forward(wl, theta, n_layers=None, tables=None, want_internals=False):
     if not np.all(np.isfinite(_re(theta))):
         return dict(bad, status=S_NONFINITE)
     ps = split_params(wl, theta)
+    # an isolated object (Eqs. 46-47) retrieves its gravity and mass
+    bd = bool(wl.get("bd", False))
+    g_ref = 10.0 ** ps["log10_g"] if bd else wl["g_ref"]
     p_lev, p_lay = level_pressures(wl["p_bot"], wl["p_top"], n_lay)
-    t_lay = tp_profile(wl, ps["tp"], p_lay)
-    t_lev = tp_profile(wl, ps["tp"], p_lev) if wl["mode"] == 1 else None
+    t_lay = tp_profile(wl, ps["tp"], p_lay, g_ref)
+    t_lev = tp_profile(wl, ps["tp"], p_lev, g_ref) if wl["mode"] == 1 else None
     status = 0
     tt = _re(t_lay) if t_lev is None else np.concatenate([_re(t_lay), _re(t_lev)])
     if not np.all(np.isfinite(tt)) or np.any(tt <= 0.0):
@@ -660,8 +686,8 @@ def forward(wl, theta, n_layers=None, tables=None, want_internals=False):
         status |= S_BAD_VMR
     if status:
         return dict(bad, status=status)
-    r_ref = wl["r_p"] * ps["scale"]
-    r_lev, ok = altitudes(t_lay, p_lev, mu, wl["g_ref"], r_ref, wl["p_ref_bar"] * BAR,
+    r_ref = brown_dwarf_radius(ps["m_bd"], g_ref) if bd else wl["r_p"] * ps["scale"]
+    r_lev, ok = altitudes(t_lay, p_lev, mu, g_ref, r_ref, wl["p_ref_bar"] * BAR,
                           constant_g=wl.get("constant_g", False))
     if not ok:
         return dict(bad, status=S_UNBOUND)
@@ -676,6 +702,8 @@ def forward(wl, theta, n_layers=None, tables=None, want_internals=False):
                                           None, tables=tables)
             spec_cf = transit_depth(pm, dtau_cf, r_lev, wl["r_s"])
             spec = ps["fcld"] * spec + (1.0 - ps["fcld"]) * spec_cf
+    elif bd:
+        spec = brown_dwarf_flux(dtau, t_lev, wl["nu"], r_ref, wl["bd_distance"], wl["n_mu"], wl["dilution"])
     else:
         spec = emission_ratio(dtau, t_lev, wl["nu"], r_ref, wl["r_s"], wl["t_star"],
                               wl["n_mu"], wl["dilution"])

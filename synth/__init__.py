@@ -169,6 +169,8 @@ _BASE = dict(
     cloud_profile=0,         # non-grey q_c(p): 0 uniform, 1 slab, 2 base + power law
     cloud_qext=0,            # non-grey Q_ext: 0 fit, 1 fit + mid-IR feature, 2 grey Q = 2
     fcld=False,              # cloudy fraction f_cld of the limb (Eq. 26) as a parameter
+    bd=False,                # isolated object (emission): log10 g and M_bd retrieved, flux at distance bd_distance
+    bd_distance=10.0 * 3.0856775814913673e18,   # [cm], 10 pc
     sigma_ppm=50.0,          # observational error per bin [ppm]
 )
 
@@ -242,6 +244,8 @@ def param_names(cfg) -> list:
         names.append("log10_P_cloud_bar")
     if cfg.get("fcld", False):
         names.append("f_cld")
+    if cfg.get("bd", False):
+        names += ["log10_g_cgs", "M_bd_MJup"]
     if cfg["scale"]:
         names.append("R_p_scale")
     if cfg["offset"]:
@@ -278,6 +282,8 @@ def param_bounds(cfg):
         b.append((-6.0, 2.0))
     if cfg.get("fcld", False):
         b.append((0.0, 1.0))
+    if cfg.get("bd", False):
+        b += [(4.5, 5.5), (20.0, 80.0)]
     if cfg["scale"]:
         b.append((0.95, 1.05))
     if cfg["offset"]:

@@ -740,3 +740,72 @@ def test_tp_family_complex_step_matches_central_differences(tp, cid):
     gf = oracle.grad_central_fd(wl, th)
     scale = np.maximum(np.abs(gc), 1e-3 * np.max(np.abs(gc)))
     assert np.max(np.abs(gc - gf) / scale) < 1e-5, (gc, gf)
+
+
+# --------------------------------------------------------------------------- f3: isolated objects
+def _bd_slice(tp=oracle.TP_ISOTHERMAL, n_nu=800, batch=3, seed=11):
+    wl = _tp_slice(tp, cid=2, n_nu=n_nu, batch=batch, seed=seed)
+    cfg = {**synth.CONFIGS[2], "tp": tp, "bd": True}
+    bounds = synth.param_bounds(cfg)
+    if tp == oracle.TP_ISOTHERMAL:
+        bounds[0] = (900.0, 1500.0)
+    u = np.random.default_rng(seed).uniform(size=(batch, len(bounds)))
+    wl.update(bd=True, param_names=synth.param_names(cfg), param_bounds=bounds,
+              params=bounds[:, 0] + u * (bounds[:, 1] - bounds[:, 0]))
+    return wl
+
+
+def test_brown_dwarf_isothermal_flux_is_blackbody():
+    """Eqs. 46-47 with an isothermal atmosphere: F_bd = s pi B(T) (R_bd/D)^2 with
+    R_bd = sqrt(G M/g) the radius at the reference pressure."""
+    wl = _bd_slice()
+    names = wl["param_names"]
+    for th in wl["params"]:
+        out = oracle.forward(wl, th, want_internals=True)
+        assert out["status"] == 0
+        t, lg, m = th[0], th[names.index("log10_g_cgs")], th[names.index("M_bd_MJup")]
+        r_bd = math.sqrt(oracle.G_GRAV * m * oracle.M_JUP / 10 ** lg)
+        bb = wl["dilution"] * math.pi * oracle.planck(t, wl["nu"]) * (r_bd / wl["bd_distance"]) ** 2
+        np.testing.assert_allclose(out["spectrum"], bb, rtol=1e-12)
+        # the reference level sits at R_bd
+        r = out["internals"]["r_lev"]
+        lp = np.log10(out["internals"]["p_lev"] / BAR)
+        assert np.interp(-np.log10(wl["p_ref_bar"]), -lp, 1.0 / r) == pytest.approx(1.0 / r_bd, rel=1e-12)
+
+
+def test_brown_dwarf_hydrostatics_depend_on_mass_only():
+    """With g(r) = G M / r^2 the hydrostatic step in 1/r, k T d ln p / (mu m_u G M), does not
+    depend on g: two gravities at one mass shift 1/r by the same amount everywhere."""
+    wl = _bd_slice()
+    names = wl["param_names"]
+    th = wl["params"][0].copy()
+    radii = []
+    for lg in (4.6, 5.4):
+        th[names.index("log10_g_cgs")] = lg
+        radii.append(oracle.forward(wl, th, want_internals=True)["internals"]["r_lev"])
+    du = 1.0 / radii[0] - 1.0 / radii[1]
+    np.testing.assert_allclose(du, du[0], rtol=1e-10)
+
+
+def test_brown_dwarf_flux_and_ratio_are_one_flux():
+    """Eq. 46 at R_bd = R_p and D = R_* is Eq. 45 times the stellar surface flux pi B(T_*)."""
+    wl = _bd_slice(n_nu=200)
+    t_lev = np.linspace(900.0, 1600.0, 31)
+    dtau = np.abs(np.random.default_rng(3).normal(0.2, 0.1, size=(30, len(wl["nu"]))))
+    a = oracle.brown_dwarf_flux(dtau, t_lev, wl["nu"], 7e9, 7e10, 4, 0.9)
+    b = oracle.emission_ratio(dtau, t_lev, wl["nu"], 7e9, 7e10, 5500.0, 4, 0.9) * math.pi * oracle.planck(5500.0, wl["nu"])
+    np.testing.assert_allclose(a, b, rtol=1e-13)
+
+
+@pytest.mark.parametrize("tp", [oracle.TP_MILNE, oracle.TP_GUILLOT3])
+def test_brown_dwarf_complex_step_matches_central_differences(tp):
+    wl = _bd_slice(tp, n_nu=600)
+    wl["n_layers"] = 40
+    wl["y_obs"] = np.full(len(wl["bin_lo"]), 1e-17)
+    wl["y_err"] = np.full(len(wl["bin_lo"]), 1e-18)
+    th = wl["params"][0]
+    assert oracle.forward(wl, th)["status"] == 0
+    gc = oracle.grad_complex_step(wl, th)
+    gf = oracle.grad_central_fd(wl, th)
+    scale = np.maximum(np.abs(gc), 1e-3 * np.max(np.abs(gc)))
+    assert np.max(np.abs(gc - gf) / scale) < 1e-5, (gc, gf)
