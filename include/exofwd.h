@@ -113,6 +113,10 @@ enum {
  *                        (Eqs. 27-29; the window's x0 is 0.5 and Q_max is 2)
  *   then  f_cld                 if has_fcld: cloudy fraction of the limb in [0, 1] (Eq. 26);
  *                               the spectrum is f_cld x (cloudy) + (1 - f_cld) x (cloud-free)
+ *   then  [log10 g/cgs, M/M_Jup] if has_bd (emission, isolated object, Eqs. 46-47): the gravity
+ *                               replaces g_ref (hydrostatics, T-p optical depth), the radius at
+ *                               p_ref is sqrt(G M / g), and the spectrum is the flux at the
+ *                               observer s F_toa (R/bd_distance)^2 [erg s^-1 cm^-2 (cm^-1)^-1]
  *   then  R_p scale factor      if has_scale  (R_ref = scale * r_p)
  *   then  offset [ppm]          if has_offset (added to bins with offset_mask)
  */
@@ -156,6 +160,8 @@ typedef struct exofwd_config {
   const double* y_err;       /* host [K] 1-sigma errors */
   const uint8_t* offset_mask;/* host [K] or NULL: bins that receive the offset */
   int32_t device;            /* HIP device ordinal */
+  int32_t has_bd;            /* emission of an isolated object (Eqs. 46-47); excludes has_scale */
+  double bd_distance;        /* its distance [cm] (has_bd) */
 } exofwd_config;
 
 /* Validate the configuration, upload and encode the tables, allocate the

@@ -38,6 +38,7 @@ class Config(C.Structure):
         ("n_bins", C.c_int32), ("bin_lo", _I), ("bin_hi", _I), ("y_obs", _D), ("y_err", _D),
         ("offset_mask", _U8),
         ("device", C.c_int32),
+        ("has_bd", C.c_int32), ("bd_distance", C.c_double),
     ]
 
 

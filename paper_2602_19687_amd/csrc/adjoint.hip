@@ -888,8 +888,9 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
     for (int s = 0; s < m.S; ++s) mu += x[s] * m.mass[s];
   }
   const double scale = m.has_scale ? th[m.idx_scale] : 1.0;
-  const double r_ref = m.r_p * scale;
-  const double kk = kB / (mu * kMu * m.g_ref * r_ref * r_ref);
+  const double g_ref = m.has_bd ? exp10(th[m.idx_bd]) : m.g_ref;
+  const double r_ref = m.has_bd ? sqrt(kGrav * th[m.idx_bd + 1] * kMJup / g_ref) : m.r_p * scale;
+  const double kk = kB / (mu * kMu * g_ref * r_ref * r_ref);
   const double step = (m.log10_ptop - m.log10_pbot) / L;
   const double ln10 = 2.302585092994045684017991454684;
   const double dlnp = -step * ln10;
@@ -1108,13 +1109,15 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
     s_kx[m.n_knots - 1] = m.log10_pbot;
     pchip_slopes_jac(s_kx, s_ky, m.n_knots, s_kd, s_kj);
   }
-  for (int k = 0; k < m.n_tp; ++k) s_red[k * kBlock + tid] = 0.0;
+  // slot n_tp: the profile's share of d lnL / d log10 g (tau = kappa_ir p / g) for an isolated object
+  const int n_red = m.n_tp + m.has_bd;
+  for (int k = 0; k < n_red; ++k) s_red[k * kBlock + tid] = 0.0;
   __syncthreads();
   auto tp_grad = [&](double lp, double t, double tbar) {
     if (m.tp_kind == kTpIso) {
       s_red[tid] += tbar;
     } else if (m.tp_kind == kTpGuillot3) {
-      const double tau = m.kappa_ir * exp10(lp) * kBar / m.g_ref;
+      const double tau = m.kappa_ir * exp10(lp) * kBar / g_ref;
       const double t3 = t * t * t;
       const double s3 = 1.7320508075688772935274463415059;
       const double gam = exp10(th[2]);
@@ -1126,14 +1129,21 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
       s_red[tid] += tbar * 3.0 * ti * ti * ti * (2.0 / 3.0 + tau) / (4.0 * t3);
       s_red[kBlock + tid] += tbar * 12.0 * m.f_hem * te * te * te * bk / (4.0 * t3);
       s_red[2 * kBlock + tid] += tbar * 3.0 * m.f_hem * te * te * te * te * dbk * gam * ln10 / (4.0 * t3);
+      if (m.has_bd) {
+        // d T^4 / d tau times d tau / d log10 g = -tau ln 10
+        const double dt4 = 0.75 * ti * ti * ti * ti - 3.0 * m.f_hem * te * te * te * te * (gam / s3 - 1.0 / (gam * s3)) * e * gam * s3;
+        s_red[3 * kBlock + tid] -= tbar * dt4 * tau * ln10 / (4.0 * t3);
+      }
     } else if (m.tp_kind == kTpBarstow) {
       s_red[tid] += tbar * barstow_factor(lp);
     } else if (m.tp_kind == kTpMilne || m.tp_kind == kTpGuillot7) {
       double d4[7];
-      if (m.tp_kind == kTpMilne) milne_t4(th, lp, m.g_ref, d4);
-      else guillot7_t4(th, lp, m.g_ref, m.f_hem, d4);
+      if (m.tp_kind == kTpMilne) milne_t4(th, lp, g_ref, d4);
+      else guillot7_t4(th, lp, g_ref, m.f_hem, d4);
       const double inv = tbar / (4.0 * t * t * t);
       for (int k = 0; k < m.n_tp; ++k) s_red[k * kBlock + tid] += d4[k] * inv;
+      // tau depends on kappa_ir / g: d/d log10 g = -d/d log10 kappa_ir
+      if (m.has_bd) s_red[m.n_tp * kBlock + tid] -= d4[m.tp_kind == kTpMilne ? 1 : 2] * inv;
     } else {
       // T = h00 y_k + h10 h d_k + h01 y_k+1 + h11 h d_k+1 on the knot interval holding lp
       const int n = m.n_knots;
@@ -1164,9 +1174,15 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
       tp_grad(logp_lev(j), tlev[j], tb);
     }
   }
-  block_sum(s_red, tid, m.n_tp);
+  block_sum(s_red, tid, n_red);
   if (tid == 0) {
     for (int k = 0; k < m.n_tp; ++k) gout[k] = s_red[k * kBlock];
+    if (m.has_bd) {
+      // g R_ref^2 = G M fixes the hydrostatic constant: ln g enters at fixed R_ref like ln mu
+      // (s_scal[1]) and through R_ref = sqrt(G M / g) (s_scal[0] = d lnL / d R_ref)
+      gout[m.idx_bd] = (s_scal[1] - 0.5 * r_ref * s_scal[0]) * ln10 + s_red[m.n_tp * kBlock];
+      gout[m.idx_bd + 1] = 0.5 * r_ref * s_scal[0] / th[m.idx_bd + 1];
+    }
     // chemistry: X_H2 = (1 - sum X)/1.164, X_He = 0.164 X_H2, mu = sum X m
     const double lnmu_bar = chem[m.S + 4] + s_scal[1];
     const double mu_bar = mu_free ? lnmu_bar / mu : 0.0;

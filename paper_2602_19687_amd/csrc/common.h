@@ -12,6 +12,8 @@ constexpr double kHpl = 6.62607015e-27;    // erg s
 constexpr double kC = 2.99792458e10;       // cm s^-1
 constexpr double kMu = 1.66053906660e-24;  // g
 constexpr double kBar = 1.0e6;             // dyn cm^-2
+constexpr double kGrav = 6.67430e-8;       // cm^3 g^-1 s^-2
+constexpr double kMJup = 1.89813e30;       // g (nominal G M_J / G)
 constexpr double kHeH2 = 0.164;            // He/H2 filling ratio (Eq. 36)
 constexpr double kMH2 = 2.01588, kMHe = 4.002602;
 constexpr double kLog2_10 = 3.321928094887362347870319429489;
@@ -62,6 +64,8 @@ struct Model {
   int cloud_ng;             // 1: non-grey cloud (q_c profile x Q_ext(nu)); 0: grey deck or none
   int cloud_profile, cloud_qext, n_cloud;   // kQprof*, kQext*, cloud parameters in theta
   int has_fcld, idx_fcld;   // cloudy/clear mixing: sample b runs as virtual samples 2b (cloudy) and 2b+1 (clear)
+  int has_bd, idx_bd;       // isolated object: theta[idx_bd] = log10 g, theta[idx_bd + 1] = M / M_Jup
+  double bd_dist;           // its distance [cm]
   double mu_fixed, log10_pbot, log10_ptop, p_ref, r_p, r_s, g_ref;
   double kappa_ir, f_hem, kappa_cloud, t_star, dilution, err_c, ray_h2, ray_he;
   double mass[kMaxSpecies];

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_emission(Model m, Work w, Tables tb,
   __syncthreads();
   if (tid < kTile64 && nu0 + tid < m.n_nu) {
     const Real f = (s_f[tid] + s_f[kTile64 + tid]) + (s_f[2 * kTile64 + tid] + s_f[3 * kTile64 + tid]);
-    const Real fstar = Real(M_PI) * planck<Real>(Real(m.t_star), Real(m.nu[nu0 + tid]));
+    const Real fstar = m.has_bd ? Real(1) : Real(M_PI) * planck<Real>(Real(m.t_star), Real(m.nu[nu0 + tid]));
     out[nu0 + tid] = Real(m.dilution) * f / fstar * Real(w.core[b]);
   }
 }
@@ -252,7 +252,8 @@ __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tabl
     if (k < n_mu) flux = fmaf((float)(2.0 * M_PI * m.mu_weights[k] * m.mu_nodes[k]), inten[k], flux);
   if (nu < m.n_nu) {
     const double nd = m.nu[nu];
-    const double fstar = M_PI * 2.0 * kHpl * kC * kC * nd * nd * nd / expm1(kHpl * kC * nd / (kB * m.t_star));
+    const double fstar =
+        m.has_bd ? 1.0 : M_PI * 2.0 * kHpl * kC * kC * nd * nd * nd / expm1(kHpl * kC * nd / (kB * m.t_star));
     out[nu] = (float)(m.dilution * (double)flux / fstar * w.core[b]);
   }
 }

@@ -56,7 +56,8 @@ __global__ __launch_bounds__(kBlock) void k_emis_adj_mixed(Model m, Work w, AdjW
   float seed = 0.0f;
   if (kb >= 0) {
     const double nd = m.nu[nu];
-    const double fstar = M_PI * 2.0 * kHpl * kC * kC * nd * nd * nd / expm1(kHpl * kC * nd / (kB * m.t_star));
+    const double fstar =
+        m.has_bd ? 1.0 : M_PI * 2.0 * kHpl * kC * kC * nd * nd * nd / expm1(kHpl * kC * nd / (kB * m.t_star));
     seed = (float)(w.dm[(size_t)b * m.K + kb] * w.inv_cnt[kb] * m.dilution * w.core[b] / fstar);
   }
   const float nuv = (float)m.nu[nu];
@@ -270,7 +271,8 @@ __global__ __launch_bounds__(kBlock) void k_emis_adj_fp64(Model m, Work w, AdjWo
   const double nd = m.nu[nu];
   double seed = 0.0;
   if (kb >= 0) {
-    const double fstar = M_PI * 2.0 * kHpl * kC * kC * nd * nd * nd / expm1(kHpl * kC * nd / (kB * m.t_star));
+    const double fstar =
+        m.has_bd ? 1.0 : M_PI * 2.0 * kHpl * kC * kC * nd * nd * nd / expm1(kHpl * kC * nd / (kB * m.t_star));
     seed = w.dm[(size_t)b * m.K + kb] * w.inv_cnt[kb] * m.dilution * w.core[b] / fstar;
   }
   const double c1n3 = 2.0 * kHpl * kC * kC * nd * nd * nd, c2n = kHpl * kC / kB * nd;

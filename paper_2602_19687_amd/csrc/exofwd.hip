@@ -246,6 +246,7 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
       return EXOFWD_ERR_CONFIG;
   }
   if (g.has_fcld && (!g.has_cloud || g.mode != EXOFWD_TRANSMISSION)) return EXOFWD_ERR_CONFIG;
+  if (g.has_bd && (g.mode != EXOFWD_EMISSION || g.has_scale || !(g.bd_distance > 0.0))) return EXOFWD_ERR_CONFIG;
   // the FP64 emission kernel stages a tile's layers in LDS: at most 128 padded layers
   if (g.mode == EXOFWD_EMISSION && g.precision == EXOFWD_PREC_FP64 && (g.n_layers_max + 31) / 32 * 32 > 128)
     return EXOFWD_ERR_UNSUPPORTED;
@@ -302,6 +303,10 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   k += m.n_cloud;
   m.has_fcld = g.has_fcld ? 1 : 0;
   m.idx_fcld = m.has_fcld ? k++ : -1;
+  m.has_bd = g.has_bd ? 1 : 0;
+  m.idx_bd = m.has_bd ? k : -1;
+  k += 2 * m.has_bd;
+  m.bd_dist = g.has_bd ? g.bd_distance : 0.0;
   m.idx_scale = m.has_scale ? k++ : -1;
   m.idx_offset = m.has_offset ? k++ : -1;
   m.P = k;
@@ -725,6 +730,7 @@ std::vector<double> neutral_params(const Model& m) {
     if (m.cloud_qext == kQextFeature) { th[k++] = 0.5; th[k++] = 10.0; th[k++] = 0.0; th[k++] = 0.0; }
   }
   if (m.has_fcld) th[m.idx_fcld] = 0.5;
+  if (m.has_bd) { th[m.idx_bd] = 5.0; th[m.idx_bd + 1] = 50.0; }
   if (m.has_scale) th[m.idx_scale] = 1.0;
   if (m.has_offset) th[m.idx_offset] = 0.0;
   return th;

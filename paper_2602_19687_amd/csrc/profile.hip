@@ -134,7 +134,9 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
     for (int s = 0; s < m.S; ++s) mu += x[s] * m.mass[s];
   }
   const double scale = m.has_scale ? th[m.idx_scale] : 1.0;
-  const double r_ref = m.r_p * scale;
+  // an isolated object retrieves its gravity; its radius at p_ref is sqrt(G M / g) (Eq. 47)
+  const double g_ref = m.has_bd ? exp10(th[m.idx_bd]) : m.g_ref;
+  const double r_ref = m.has_bd ? sqrt(kGrav * th[m.idx_bd + 1] * kMJup / g_ref) : m.r_p * scale;
 
   const double step = (m.log10_ptop - m.log10_pbot) / L;   // log10 p per layer (negative)
   const double dlnp = -step * 2.302585092994045684017991454684;  // ln(p_l / p_{l+1})
@@ -157,12 +159,12 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
   auto temperature = [&](double log10p_bar) {
     if (m.tp_kind == kTpIso) return th[0];
     if (m.tp_kind == kTpGuillot3) {
-      double tau = m.kappa_ir * exp10(log10p_bar) * kBar / m.g_ref;
+      double tau = m.kappa_ir * exp10(log10p_bar) * kBar / g_ref;
       return guillot3(th[0], th[1], exp10(th[2]), tau, m.f_hem);
     }
     if (m.tp_kind == kTpBarstow) return th[0] * barstow_factor(log10p_bar);
-    if (m.tp_kind == kTpMilne) return sqrt(sqrt(milne_t4(th, log10p_bar, m.g_ref)));
-    if (m.tp_kind == kTpGuillot7) return sqrt(sqrt(guillot7_t4(th, log10p_bar, m.g_ref, m.f_hem)));
+    if (m.tp_kind == kTpMilne) return sqrt(sqrt(milne_t4(th, log10p_bar, g_ref)));
+    if (m.tp_kind == kTpGuillot7) return sqrt(sqrt(guillot7_t4(th, log10p_bar, g_ref, m.f_hem)));
     return pchip_eval(s_knot_x, s_knot_y, s_knot_d, m.n_knots, log10p_bar);
   };
 
@@ -187,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
   }
 
   // hydrostatics (1/r linear in ln p inside each isothermal layer)
-  const double kk = kB / (mu * kMu * m.g_ref * r_ref * r_ref);
+  const double kk = kB / (mu * kMu * g_ref * r_ref * r_ref);
   for (int l = tid; l < L; l += kBlock) s_inc[l] = kk * s_t[l] * dlnp;
   __syncthreads();
   if (tid == 0 && !status) {
@@ -230,7 +232,8 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
   }
   // transmission: opaque-core depth (r_0/R_s)^2; emission: (R_ref/R_s)^2 of Eq. 45
   if (tid == 0)
-    w.core[b] = m.mode == kTransmission ? s_r[0] * s_r[0] / (m.r_s * m.r_s) : r_ref * r_ref / (m.r_s * m.r_s);
+    w.core[b] = m.mode == kTransmission ? s_r[0] * s_r[0] / (m.r_s * m.r_s)
+                                        : r_ref * r_ref / (m.has_bd ? m.bd_dist * m.bd_dist : m.r_s * m.r_s);
 
   // per-layer opacity records
   const int RL = rec_len(m.S);

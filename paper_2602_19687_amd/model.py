@@ -48,6 +48,8 @@ def build_config(wl, precision: int, batch_max: int, device: int = 0, n_layers_m
     cfg.cloud_profile = int(wl.get("cloud_profile", 0))
     cfg.cloud_qext = int(wl.get("cloud_qext", 0))
     cfg.has_fcld = int(bool(wl.get("fcld", False)))
+    cfg.has_bd = int(bool(wl.get("bd", False)))
+    cfg.bd_distance = float(wl.get("bd_distance", 0.0))
     for k in ("mu_fixed", "r_p", "r_s", "g_ref", "kappa_ir", "f_hem", "kappa_cloud", "t_star", "dilution",
               "err_c", "ray_h2", "ray_he"):
         setattr(cfg, k, float(wl[k]))

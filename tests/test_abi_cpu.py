@@ -117,3 +117,28 @@ def test_tp_kinds_validated_before_device(tp, ok):
     else:
         assert rc == L.ERR_CONFIG
         assert ctx.value is None
+
+
+@pytest.mark.parametrize("change,ok", [
+    ({"bd": True}, True),
+    ({"bd": True, "bd_distance": 0.0}, False),
+    ({"bd": True, "scale": True}, False),        # the radius comes from the mass and gravity
+    ({"bd": True, "mode": 0, "n_mu": 4}, False),  # an emission option
+])
+def test_isolated_object_options_validated_before_device(change, ok):
+    import synth
+    from paper_2602_19687_amd.model import build_config
+    lib = pkg.load()
+    wl = dict(synth.workload(2, batch=2))
+    wl.update(change)
+    cfg, keep = build_config(wl, L.PREC_MIXED, 2)
+    ctx = C.c_void_p()
+    rc = lib.exofwd_create(C.byref(cfg), C.byref(ctx))
+    if ok:
+        assert rc in (L.OK, L.ERR_DEVICE)
+        if rc == L.OK:
+            assert lib.exofwd_num_params(ctx) == len(synth.param_names({**synth.CONFIGS[2], **change}))
+            lib.exofwd_destroy(ctx)
+    else:
+        assert rc == L.ERR_CONFIG
+        assert ctx.value is None

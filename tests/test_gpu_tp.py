@@ -88,3 +88,61 @@ def test_tp_profile_forward_and_grad(tp, cid, prec):
     assert n_ok >= 3
     assert worst_s < SPEC_TOL[prec]
     assert worst_g < gtol
+
+
+# ---------------------------------------------------------------------------
+# isolated objects (Eqs. 46-47): retrieved gravity and mass, flux at the observer
+
+BD_CASES = [synth.TP_ISOTHERMAL, synth.TP_GUILLOT3, synth.TP_MILNE]
+
+
+def bd_wl(tp):
+    wl = reduced(2, n_nu=500, n_bins=20, batch=BATCH, step=40)
+    cfg = {**synth.CONFIGS[2], "tp": tp, "bd": True}
+    bounds = synth.param_bounds(cfg)
+    if tp == synth.TP_ISOTHERMAL:
+        bounds[0] = (900.0, 1500.0)
+    u = np.random.default_rng(700 + tp).uniform(size=(BATCH, len(bounds)))
+    wl.update(tp=tp, bd=True, param_bounds=bounds, param_names=synth.param_names(cfg),
+              params=bounds[:, 0] + u * (bounds[:, 1] - bounds[:, 0]))
+    # observations at the flux level of the first sample, 2 % errors
+    ref = oracle.forward(dict(wl, y_obs=np.ones(20), y_err=np.ones(20)), wl["params"][0])
+    y = ref["binned"] * (1.0 + 0.05 * np.sin(np.arange(20)))
+    wl.update(y_obs=y, y_err=0.02 * np.abs(y))
+    return wl
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("tp", BD_CASES, ids=["iso", "guillot3", "milne"])
+def test_isolated_object_forward_and_grad(tp, prec):
+    from paper_2602_19687_amd import ForwardModel
+    wl = bd_wl(tp)
+    print(f"[gpu] isolated object, T-p kind {tp} {prec}", flush=True)
+    key = ("bd", tp)
+    if key not in _REF:
+        fwd = [oracle.forward(wl, th) for th in wl["params"]]
+        _REF[key] = (fwd, [oracle.grad_complex_step(wl, th) if r["status"] == 0 else None
+                           for th, r in zip(wl["params"], fwd)])
+    fwd, grads = _REF[key]
+    fm = ForwardModel(wl, precision=prec, batch_max=BATCH)
+    assert fm.n_params == len(wl["param_names"])
+    th = torch.tensor(wl["params"], device="cuda")
+    spec, lnl, st = fm.forward(th)
+    spec, lnl, st = spec.double().cpu().numpy(), lnl.cpu().numpy(), st.cpu().numpy()
+    lnl2, g, st2, _ = fm.grad(th)
+    g, st2 = g.cpu().numpy(), st2.cpu().numpy()
+    fm.close()
+    gtol = 1e-5 if prec == "fp64" else 2e-3
+    n_ok, worst_s, worst_g = 0, 0.0, 0.0
+    for b, ref in enumerate(fwd):
+        assert st[b] == ref["status"] and st2[b] == ref["status"]
+        if ref["status"]:
+            continue
+        n_ok += 1
+        worst_s = max(worst_s, rel_err(spec[b], ref["spectrum"]))
+        assert abs(lnl[b] - ref["lnL"]) <= SPEC_TOL[prec] * max(abs(ref["lnL"]), 1.0), (b, lnl[b], ref["lnL"])
+        worst_g = max(worst_g, grad_err(g[b], grads[b]))
+    print(f"isolated object, T-p kind {tp} {prec}: spectrum {worst_s:.3e}, gradient {worst_g:.3e}")
+    assert n_ok >= 3
+    assert worst_s < SPEC_TOL[prec]
+    assert worst_g < gtol
