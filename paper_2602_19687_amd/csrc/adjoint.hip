@@ -414,17 +414,20 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
 }
 
 // ============================================================================
-// reduced-precision per-layer sums: one wave per (sample, kLsLayers layers, ls_tiles tiles);
+// reduced-precision per-layer sums: one wave per (sample, ls_layers layers, ls_tiles tiles);
 // lanes hold two wavenumbers, partial sums stay in registers across the tiles
 // and are reduced over the wave once
-constexpr int kLsLayers = 3;   // three layers' accumulators keep the kernel under 128 VGPRs: four waves per SIMD
+// layers per wave: three layers' accumulators keep the kernel under 128 VGPRs (four waves per
+// SIMD); the non-grey cloud's extra sum needs two
+__host__ __device__ constexpr int ls_layers(bool ngc) { return ngc ? 2 : 3; }
 
 template <int S, bool CIA, bool NGC>
 __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Tables tb, AdjWork aw, int B) {
   constexpr int NS = n_sums(S);
+  constexpr int kLs = ls_layers(NGC);
   const int lane = threadIdx.x & 63;
   const int gw = blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int NG = (m.L_max + kLsLayers - 1) / kLsLayers;
+  const int NG = (m.L_max + kLs - 1) / kLs;
   const int per_chunk = B * NG;
   const int chunk = gw / per_chunk;
   if (chunk >= aw.lsum_chunks) return;
@@ -432,7 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
   const int b = rem / NG, lg = rem - b * NG;
   if (w.status[b]) return;
   const int L = w.nlay[b];
-  const int l0 = lg * kLsLayers;
+  const int l0 = lg * kLs;
   if (l0 >= L) return;
   const int Lp = m.L_pad;
   const size_t npad = (size_t)m.n_nu_pad;
@@ -448,9 +451,9 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
   const int32_t* cells = w.cells + (size_t)b * Lp;
   const float* dtb = aw.dtb + (size_t)b * Lp * npad;
 
-  float acc[kLsLayers][NS];
+  float acc[kLs][NS];
 #pragma unroll
-  for (int q = 0; q < kLsLayers; ++q)
+  for (int q = 0; q < kLs; ++q)
 #pragma unroll
     for (int k = 0; k < NS; ++k) acc[q][k] = 0.0f;
   // non-grey cloud: Q_ext at the lane's two wavenumbers weights the cloud sum (its
@@ -465,11 +468,11 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
     // exactly zero there and the tile adds nothing (the deep layers of most
     // atmospheres).  Rows below the reverse pass's opaque frontier are not stored.
     const int lo_row = 32 * w.front[(size_t)b * m.n_tiles + tile];
-    if (l0 + kLsLayers <= lo_row) continue;
-    float2 dbq[kLsLayers];
+    if (l0 + kLs <= lo_row) continue;
+    float2 dbq[kLs];
     bool live = false;
 #pragma unroll
-    for (int q = 0; q < kLsLayers; ++q) {
+    for (int q = 0; q < kLs; ++q) {
       dbq[q] = (l0 + q < L && l0 + q >= lo_row)
                    ? *reinterpret_cast<const float2*>(dtb + (size_t)(l0 + q) * npad + nu0 + 2 * lane)
                    : make_float2(0.0f, 0.0f);
@@ -484,7 +487,7 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
       q1 = q.y;
     }
 #pragma unroll
-    for (int q = 0; q < kLsLayers; ++q) {
+    for (int q = 0; q < kLs; ++q) {
       const int l = l0 + q;
       if (l >= L) continue;
       const float2 db = dbq[q];
@@ -521,7 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
   }
   float* out = aw.lsum + ((size_t)b * aw.lsum_stride + chunk) * Lp * NS;
 #pragma unroll
-  for (int q = 0; q < kLsLayers; ++q) {
+  for (int q = 0; q < kLs; ++q) {
     const int l = l0 + q;
     if (l >= L) continue;
 #pragma unroll
@@ -1432,7 +1435,7 @@ void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const Ad
     launch_layer_sums_emis(m, w, tb, aw, B, fp64, st);
     return;
   }
-  const int NG = (m.L_max + kLsLayers - 1) / kLsLayers;
+  const int nl = ls_layers(m.cloud_ng), NG = (m.L_max + nl - 1) / nl;
   const long waves = (long)aw.lsum_chunks * B * NG;
   void* args2[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&aw, (void*)&B};
   hipLaunchKernel(ls_kernel_for(m.S, m.has_cia, m.cloud_ng), dim3((unsigned)((waves + 3) / 4)), dim3(kBlock), args2, 0, st);
