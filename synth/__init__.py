@@ -12,7 +12,7 @@ HST/JWST spectra (Section "Gas phase opacities" and Table 2), which are not
 available; their shapes follow those workloads: 100 layers, tens of thousands
 of wavenumbers, 4-8 absorbers, 10-13 parameters.
 
-Configurations (ids 0-4) and the spec batch:
+Configurations (ids 0-6); config 1 at B = 1024 is the headline transmission batch:
 
 * 0 -- plain transmission, one sample, isothermal, one absorber, 2000 nu.
 * 1 -- JWST-like transmission, 6 absorbers x 20 T x 20 log p x 30000 nu,
@@ -21,6 +21,9 @@ Configurations (ids 0-4) and the spec batch:
 * 3 -- transmission setup of 1, used for gradients (B=128).
 * 4 -- high-resolution transmission, 4 absorbers x 8 x 8 x 400000 nu,
        per-sample layer counts 60-150.
+* 5 -- the setup of 1 with a non-grey cloud (power-law condensate, fitted Q_ext
+       with the mid-infrared feature).
+* 6 -- the setup of 1 with a partly cloudy limb (non-grey slab cloud, cloudy fraction).
 
 Every random stream is ``numpy.random.default_rng([19687, cid, stream])``.
 """
@@ -215,7 +218,7 @@ CONFIGS = {
             mu_fixed=0.0, n_bins=400, batch=128, cloud_model=1, cloud_profile=1, cloud_qext=0, fcld=True),
 }
 
-# configs 1 and 3 share tables (same seeds) so the spec batch reuses them
+# configs 1, 3, 5 and 6 share tables (same seeds) with the headline batch
 _TABLE_CID = {0: 0, 1: 1, 2: 2, 3: 1, 4: 4, 5: 1, 6: 1}
 
 
