@@ -46,6 +46,7 @@ struct AdjWork {
   double* dtb64;
   double* psum64;
   double* lsum64;      // [B_max][lsum_chunks][L_pad][n_sums]
+  double* hq64;        // FP64 transmission, non-grey cloud: [pair][kCloudSpec] the sums of hq
   int lsum_chunks;     // wavenumber chunks of the layer-sum kernel (n_tiles / ls_tiles, rounded up)
   int lsum_stride;     // allocated chunks per sample (the bound over the ls_tiles choices)
 };

@@ -578,11 +578,11 @@ __global__ __launch_bounds__(kBlock) void k_cloud_spectral(Model m, Work w, AdjW
 // FP64 MFMA (16x16x4) for Pbar
 template <int S, bool CIA>
 __device__ inline void opacity_fp64_terms(const Model& m, const Tables& tb, int cl, const double* __restrict__ rl,
-                                          int nu, double nu4, double& dtau, double* t, double* dw) {
+                                          int nu, double nu4, double& dtau, double* t, double* dw, double qext = 1.0) {
   const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
   const double wt = rl[0], wp = rl[1];
   const size_t npad = (size_t)m.n_nu_pad;
-  double acc = rl[3] * nu4 + rl[4];
+  double acc = rl[3] * nu4 + rl[4] * qext;   // the non-grey cloud's column times Q_ext(nu)
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const double* p = tb.t64 + (((size_t)s * m.n_t + it) * m.n_p + ip) * npad + nu;
@@ -656,13 +656,20 @@ __global__ __launch_bounds__(kBlockT) void k_trans_adj_fp64(Model m, Work w, Tab
 #pragma unroll
   for (int q = 0; q < kPSlots64; ++q) pacc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
 
+  // non-grey cloud: Q_ext(nu) and its spectral derivatives, and (wave 0) the sums over
+  // nu of G(nu) dQ/dp_k with G = sum_l D_l dtau_bar_l
+  double hq[kCloudSpec] = {};
+  CloudCoef<double> cc{};
+  if (m.cloud_ng) cc = load_cloud<double>(w.cloud + (size_t)b * kCloudSpec);
   const int t0 = chunk * m.n_tiles64 / C, t1 = (chunk + 1) * m.n_tiles64 / C;
   for (int tile = t0; tile < t1; ++tile) {
     const int nu = tile * kTile64 + lane;
     const double nu4 = tb.nu4d[nu];
+    double dqx[kCloudSpec];
+    const double qx = m.cloud_ng ? cloud_q<double>(m.cloud_qext, cc, m.nu[nu], dqx) : 1.0;
     for (int l = wv; l < Lp; l += 8) {
       double d = 0.0;
-      if (l < L) opacity_fp64_terms<S, CIA>(m, tb, cells[l], rec + (size_t)l * rec_len(S), nu, nu4, d, nullptr, nullptr);
+      if (l < L) opacity_fp64_terms<S, CIA>(m, tb, cells[l], rec + (size_t)l * rec_len(S), nu, nu4, d, nullptr, nullptr, qx);
       s_dt[lane * ld + l] = d;
     }
     const int bin = w.bin_of[nu];
@@ -714,10 +721,16 @@ __global__ __launch_bounds__(kBlockT) void k_trans_adj_fp64(Model m, Work w, Tab
       if (l < Lp) s_tb[lane * ld + l] = dtb[k];
     }
     __syncthreads();
+    if (m.cloud_ng && wv == 0) {
+      double g = 0.0;
+      for (int l = 0; l < L; ++l) g = fma(rec[(size_t)l * rec_len(S) + 4], s_tb[lane * ld + l], g);
+#pragma unroll
+      for (int k = 0; k < kCloudSpec; ++k) hq[k] = fma(g, dqx[k], hq[k]);
+    }
     // per-layer sums
     for (int l = wv; l < L; l += 8) {
       double d, t[S + 2], dw[S + 2];
-      opacity_fp64_terms<S, CIA>(m, tb, cells[l], rec + (size_t)l * rec_len(S), nu, nu4, d, t, dw);
+      opacity_fp64_terms<S, CIA>(m, tb, cells[l], rec + (size_t)l * rec_len(S), nu, nu4, d, t, dw, qx);
       const double db = s_tb[lane * ld + l];
       double sums[NS];
       double ht = 0.0, htc = 0.0;
@@ -738,7 +751,7 @@ __global__ __launch_bounds__(kBlockT) void k_trans_adj_fp64(Model m, Work w, Tab
       }
       sums[S + 3] = htc;
       sums[S + 4] = db * nu4;
-      sums[S + 5] = db;
+      sums[S + 5] = db * qx;   // the cloud column: Q_ext weights the non-grey cloud (1 for the grey deck)
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
         const double tot = wave_sum(sums[k]);
@@ -751,6 +764,13 @@ __global__ __launch_bounds__(kBlockT) void k_trans_adj_fp64(Model m, Work w, Tab
   const size_t pair = (size_t)b * C + chunk;
   double* ls = aw.layer_sums + pair * Lp * NS;
   for (int i = tid; i < Lp * NS; i += kBlockT) ls[i] = s_sums[i];
+  if (m.cloud_ng && wv == 0) {
+#pragma unroll
+    for (int k = 0; k < kCloudSpec; ++k) {
+      const double tot = wave_sum(hq[k]);
+      if (lane == 0) aw.hq64[pair * kCloudSpec + k] = tot;
+    }
+  }
   double* pb = reinterpret_cast<double*>(aw.pbar) + pair * Lp * Lp;
 #pragma unroll
   for (int q = 0; q < kPSlots64; ++q) {
@@ -998,8 +1018,13 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
       for (int k = 0; k < 3; ++k) s_red[(kCloudSpec + k) * kBlock + tid] += gd * col * dq[k];
     }
     // spectral parameters: the per-chunk sums of k_cloud_spectral
-    for (int i = tid; i < (ng ? aw.lsum_chunks * kCloudSpec : 0); i += kBlock)
-      s_red[(i % kCloudSpec) * kBlock + tid] += (double)aw.hq[((size_t)b * aw.lsum_stride) * kCloudSpec + i];
+    if constexpr (sizeof(PbarT) == 8) {
+      for (int i = tid; i < (ng ? C * kCloudSpec : 0); i += kBlock)
+        s_red[(i % kCloudSpec) * kBlock + tid] += aw.hq64[(size_t)b * C * kCloudSpec + i];
+    } else {
+      for (int i = tid; i < (ng ? aw.lsum_chunks * kCloudSpec : 0); i += kBlock)
+        s_red[(i % kCloudSpec) * kBlock + tid] += (double)aw.hq[((size_t)b * aw.lsum_stride) * kCloudSpec + i];
+    }
     block_sum(s_red, tid, NC);
     if (tid < NC) s_cloud[tid] = s_red[tid * kBlock];
     __syncthreads();
@@ -1268,7 +1293,7 @@ int adjoint_chunks(const Model& m, const AdjWork& aw, int B, bool fp64) {
 
 bool adjoint_supported(const Model& m, bool fp64) {
   if (m.mode == kEmission) return m.L_pad <= (fp64 ? 128 : 160);
-  return m.L_pad <= (fp64 ? 128 : 160) && !(fp64 && m.cloud_ng);
+  return m.L_pad <= (fp64 ? 128 : 160);
 }
 
 int adjoint_default_variant(const Model& m) { return m.L_pad <= 128 ? kAdjT128M4 : kAdjT64M5; }
@@ -1322,7 +1347,8 @@ bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std:
   if (!aw.pbar || !aw.abar) return false;
   if (fp64) {
     aw.layer_sums = (double*)alloc((size_t)pairs * Lp * n_sums(m.S) * sizeof(double));
-    return aw.layer_sums != nullptr;
+    if (m.cloud_ng) aw.hq64 = (double*)alloc((size_t)pairs * kCloudSpec * sizeof(double));
+    return aw.layer_sums != nullptr && (!m.cloud_ng || aw.hq64 != nullptr);
   }
   aw.lsum_stride = (m.n_tiles + kLsTileChoices[0] - 1) / kLsTileChoices[0];   // bound over the choices
   aw.lsum_chunks = (m.n_tiles + aw.ls_tiles - 1) / aw.ls_tiles;
