@@ -174,8 +174,9 @@ def _oracle_worker(args):
     th = wl["params"][idx]
     t0 = time.perf_counter()
     out = oracle.forward(wl, th)
+    t_fwd = time.perf_counter() - t0
     g = oracle.grad_complex_step(wl, th) if do_grad else None
-    return idx, out["spectrum"], out["lnL"], g, time.perf_counter() - t0
+    return idx, out["spectrum"], out["lnL"], g, time.perf_counter() - t0, t_fwd
 
 
 def cpu_baseline(cid, batch, n_samples, do_grad, tp_name=None, bd=False):
@@ -189,7 +190,21 @@ def cpu_baseline(cid, batch, n_samples, do_grad, tp_name=None, bd=False):
     with ctx.Pool(workers, initializer=_oracle_init, initargs=(cid, batch, tp_name, bd)) as pool:
         res = pool.map(_oracle_worker, [(i, do_grad) for i in idx], chunksize=1)
     busy = sum(r[4] for r in res)
-    return [r[:4] for r in res], busy / workers, workers
+    busy_fwd = sum(r[5] for r in res)
+    return [r[:4] for r in res], busy / workers, workers, busy, busy_fwd
+
+
+def cpu_model():
+    """The host CPU's model name (Linux), or the platform's processor string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def main():
@@ -275,21 +290,29 @@ def main():
         kern = {k: fm.kernel_time(k) for k in ("profile", "trans_fwd", "emis_fwd", "loglike", "trans_adj", "emis_adj",
                                                "layer_sums", "chain")}
         fm.set_profiling(False)
-        graph_ms = None
+        graph_ms = graph_pct = None
         if not args.no_graphs:
-            # the same step captured once into a hipGraph and replayed
+            # the same step captured once into a hipGraph and replayed; the replays run
+            # on a side stream ordered with torch's current stream, so events recorded
+            # on the current stream bracket each replay
             fm.set_graphs(True)
             step()
             torch.cuda.synchronize()
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
             t0 = time.perf_counter()
-            for _ in range(steps):
+            for e0, e1 in evs:
+                e0.record()
                 step()
+                e1.record()
             torch.cuda.synchronize()
             graph_ms = (time.perf_counter() - t0) / steps * 1e3
+            per_step = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+            graph_pct = [float(np.percentile(per_step, q)) for q in (50, 10, 90)]
             fm.set_graphs(False)
         spec, lnl, status = fm.forward(th, n_layers=nl)
         torch.cuda.synchronize()
-        res = dict(ms_per_step=dt / steps * 1e3, has_grad=has_grad, kernels=kern, graph_ms=graph_ms, tuning=tuning,
+        res = dict(ms_per_step=dt / steps * 1e3, has_grad=has_grad, kernels=kern, graph_ms=graph_ms, graph_pct=graph_pct,
+                   tuning=tuning,
                    spec=spec.double().cpu().numpy(), lnl=lnl.cpu().numpy(), status=status.cpu().numpy(),
                    grad=out[1].cpu().numpy() if has_grad else None, bytes=fm.device_bytes())
         fm.close()
@@ -393,7 +416,8 @@ def main():
             out["forward_grad"]["max_grad_err_vs_fp64_gpu"] = float(np.max(np.abs(gm - g64) / scale))
     if mixed["graph_ms"] is not None:
         out["graph_replay"] = {"ms_per_step": round(mixed["graph_ms"], 4),
-                               "spectra_per_s": round(B / (mixed["graph_ms"] / 1e3), 1)}
+                               "spectra_per_s": round(B / (mixed["graph_ms"] / 1e3), 1),
+                               "event_ms_median_p10_p90": [round(x, 4) for x in mixed["graph_pct"]]}
     if fp64 is not None:
         out["fp64_plain"] = {"spectra_per_s": round(B / (fp64["ms_per_step"] / 1e3), 1),
                              "ms_per_step": round(fp64["ms_per_step"], 3),
@@ -403,7 +427,7 @@ def main():
         ok = (mixed["status"] == 0) & (fp64["status"] == 0)
         out["max_rel_err_vs_fp64_gpu"] = spec_err(mixed["spec"][ok], fp64["spec"][ok])
     if not args.no_cpu_baseline and cid == 1:
-        res, dt, cores = cpu_baseline(cid, B, args.cpu_samples, mixed["has_grad"], args.tp, args.bd)
+        res, dt, cores, busy, busy_fwd = cpu_baseline(cid, B, args.cpu_samples, mixed["has_grad"], args.tp, args.bd)
         n = len(res)
         errs, lerrs, gerrs = [], [], []
         for idx, spec, lnl, g in res:
@@ -418,7 +442,9 @@ def main():
         out["cpu_baseline"] = {"value": round(n / dt, 4), "unit": "spectra/s", "cores": cores, "kind": "oracle",
                                "sample": f"{n} of the {B} samples (every {B // n}th), FP64 oracle forward"
                                          + (" + complex-step gradient" if mixed["has_grad"] else "")
-                                         + f", {cores} worker processes, {dt:.1f} s per worker"}
+                                         + f", {cores} worker processes, {dt:.1f} s per worker",
+                               "cpu": cpu_model(), "per_core_value": round(n / busy, 4),
+                               "forward_only_value": round(n / (busy_fwd / cores), 4)}
         out["max_rel_err"] = {"spectrum": max(errs) if errs else None, "lnL": float(max(lerrs)) if lerrs else None,
                               "grad": max(gerrs) if gerrs else None, "samples": len(errs)}
     print(json.dumps(out))
