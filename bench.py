@@ -265,6 +265,21 @@ def main():
     Ls = nl_np if nl_np is not None else np.full(B, L_)
     print(f"[bench] workload ready in {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
 
+    # measured HBM copy peak: a 1 GiB device-to-device copy (read + write) timed with events
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 4 / (c0.elapsed_time(c1) / 5 / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+
     def run(prec, steps, warmup, want_grad=True):
         fm = ForwardModel(wl, precision=prec, batch_max=B)
         has_grad = fm.has_grad and want_grad
@@ -354,16 +369,18 @@ def main():
         if k in per:
             bk, ak, pk, _ = kernel_model(k, Ls, S, n_nu)
             a = ak / (per[k] / 1e3) / 1e12
+            tr = measured_traffic(k, tag)
             roofline.setdefault("kernels", {})[k] = {"bound": bk, "ms": round(per[k], 4), "achieved": round(a, 2),
-                                                     "peak": pk, "frac": round(a / pk, 4),
-                                                     "traffic": measured_traffic(k, tag)}
+                                                     "peak": pk, "frac": round(a / pk, 4), "traffic": tr,
+                                                     "traffic_gbs": round(tr / (per[k] / 1e3) / 1e9, 1) if tr else None}
     # table-gather bytes the method needs (the forward pass), against the HBM peak
     fwd_kernel = "emis_fwd" if cid == 2 else "trans_fwd"
     if cid == 2:
         alg_bytes = sum((4 * int(l) * S * n_nu + 4 * int(l) * n_nu) * 2 + n_nu * 4 for l in Ls)
     hbm_gbs = alg_bytes / (per[fwd_kernel] / 1e3) / 1e9
     roofline["table_gather"] = {"bytes_per_launch": alg_bytes, "kernel": fwd_kernel,
-                                "achieved_gbs": round(hbm_gbs, 1), "frac_of_8000_gbs": round(hbm_gbs / HBM_PEAK_GBS, 4)}
+                                "achieved_gbs": round(hbm_gbs, 1), "frac_of_8000_gbs": round(hbm_gbs / HBM_PEAK_GBS, 4),
+                                "copy_peak_gbs": round(copy_gbs, 1), "frac_of_copy_peak": round(hbm_gbs / copy_gbs, 4)}
 
     if cid == 1:
         workload = ("jwst-like transmission, 6 absorbers, 20x20x30000 FP16 tables, 100 layers, 400 bins, 12 params")
