@@ -220,3 +220,33 @@ def test_emission_full_batch_mixed_vs_fp64():
     ref = oracle.forward(wl, wl["params"][worst])
     assert rel_err(b[worst], ref["spectrum"]) < 1e-10
     assert rel_err(a[worst], ref["spectrum"]) < 1e-4
+
+
+def test_call_errors_through_the_c_abi():
+    """Misuse caught on the host before any launch: B outside [1, batch_max]
+    (ERR_SHAPE), NULL params (ERR_ARG), a gradient call without lnL or grad
+    buffers (ERR_ARG); the context stays usable and its last error names the cause."""
+    import ctypes as C
+    from paper_2602_19687_amd import ForwardModel, _lib as L
+    wl = reduced(1, n_nu=256, n_bins=4, batch=4)
+    fm = ForwardModel(wl, precision="mixed", batch_max=4)
+    lib, ctx = fm.lib, fm.ctx
+    th = torch.tensor(wl["params"], device="cuda")
+    lnl = torch.empty(4, dtype=torch.float64, device="cuda")
+    grad = torch.empty_like(th)
+    st = torch.empty(4, dtype=torch.int32, device="cuda")
+    p = C.c_void_p(th.data_ptr())
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for B in (0, 5, -1):
+        assert lib.exofwd_forward(ctx, B, p, None, None, C.c_void_p(lnl.data_ptr()), C.c_void_p(st.data_ptr()),
+                                  stream) == L.ERR_SHAPE
+    assert b"batch_max" in lib.exofwd_last_error(ctx)
+    assert lib.exofwd_forward(ctx, 4, None, None, None, C.c_void_p(lnl.data_ptr()), C.c_void_p(st.data_ptr()),
+                              stream) == L.ERR_ARG
+    assert lib.exofwd_grad(ctx, 4, p, None, None, None, C.c_void_p(grad.data_ptr()), C.c_void_p(st.data_ptr()),
+                           stream) == L.ERR_ARG
+    # still usable
+    spec, lnl2, st2 = fm.forward(th)
+    torch.cuda.synchronize()
+    assert torch.all(st2 == 0) and torch.all(torch.isfinite(lnl2))
+    fm.close()
