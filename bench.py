@@ -345,10 +345,14 @@ def main():
             emis_grad64 = run("fp64", 2, 1, want_grad=True)
             print(f"[bench] fp64 forward+grad {emis_grad64['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     fp64 = None
-    # the FP64 adjoint stops at 128 padded layers, so the high-resolution batch has no FP64 comparison
     if not args.no_fp64 and cid in (1, 2):
         fp64 = run("fp64", max(2, args.steps // 4), 1, want_grad=cid != 2)
         print(f"[bench] fp64 {fp64['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+    elif not args.no_fp64 and cid == 4:
+        # the FP64 adjoint stops at 128 padded layers: the high-resolution batch is compared
+        # with the FP64 path on its forward model (spectra) only
+        fp64 = run("fp64", 2, 1, want_grad=False)
+        print(f"[bench] fp64 forward {fp64['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
 
     value = B / (mixed["ms_per_step"] / 1e3)
     # dominant kernel of the step by time
@@ -440,7 +444,10 @@ def main():
                              "ms_per_step": round(fp64["ms_per_step"], 3),
                              "kernel_ms_per_step": {k: round(v[0] / max(1, v[1]), 4)
                                                     for k, v in fp64["kernels"].items() if v[1]}}
-        out["speedup_vs_fp64"] = round(fp64["ms_per_step"] / mixed["ms_per_step"], 3)
+        if fp64["has_grad"] == mixed["has_grad"]:
+            out["speedup_vs_fp64"] = round(fp64["ms_per_step"] / mixed["ms_per_step"], 3)
+        else:
+            out["fp64_plain"]["step"] = "forward only (no FP64 adjoint beyond 128 padded layers)"
         ok = (mixed["status"] == 0) & (fp64["status"] == 0)
         out["max_rel_err_vs_fp64_gpu"] = spec_err(mixed["spec"][ok], fp64["spec"][ok])
     if not args.no_cpu_baseline and cid == 1:
