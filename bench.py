@@ -337,7 +337,11 @@ def main():
     # reduced-precision forward+gradient step is timed beside it
     mixed = run("mixed", args.steps, args.warmup, want_grad=cid != 2)
     print(f"[bench] mixed {mixed['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
-    emis_grad = emis_grad64 = None
+    emis_grad = emis_grad64 = fwd_only = None
+    if cid in (1, 4, 5, 6):
+        # the forward model alone beside the forward+gradient step
+        fwd_only = run("mixed", max(2, args.steps // 2), 1, want_grad=False)
+        print(f"[bench] mixed forward {fwd_only['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     if cid == 2:
         emis_grad = run("mixed", max(2, args.steps // 2), 1, want_grad=True)
         print(f"[bench] mixed forward+grad {emis_grad['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
@@ -423,6 +427,12 @@ def main():
         "roofline": roofline,
         "kernel_ms_per_step": {k: round(v[0] / max(1, v[1]), 4) for k, v in mixed["kernels"].items() if v[1]},
     }
+    if fwd_only is not None:
+        out["forward_only"] = {"spectra_per_s": round(B / (fwd_only["ms_per_step"] / 1e3), 1),
+                               "ms_per_step": round(fwd_only["ms_per_step"], 4),
+                               "launch_choices": fwd_only["tuning"],
+                               "kernel_ms_per_step": {k: round(v[0] / max(1, v[1]), 4)
+                                                      for k, v in fwd_only["kernels"].items() if v[1]}}
     if emis_grad is not None and emis_grad["has_grad"]:
         out["forward_grad"] = {"spectra_per_s": round(B / (emis_grad["ms_per_step"] / 1e3), 1),
                                "ms_per_step": round(emis_grad["ms_per_step"], 4),
