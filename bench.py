@@ -393,7 +393,7 @@ def main():
     if cid == 1:
         workload = ("jwst-like transmission, 6 absorbers, 20x20x30000 FP16 tables, 100 layers, 400 bins, 12 params")
     elif cid == 2:
-        workload = ("emission, 8 absorbers, 20x20x20000 FP16 tables, 100 layers, 4 Gauss-Legendre angles, "
+        workload = ("emission, 8 absorbers, 20x20x20000 FP32 tables, 100 layers, 4 Gauss-Legendre angles, "
                     "5-knot PCHIP profile, 400 bins")
     elif cid == 5:
         workload = ("jwst-like transmission with a non-grey cloud (power-law condensate profile, fitted Q_ext with "
@@ -413,7 +413,7 @@ def main():
     out = {
         "metric": ("forward+grad spectra/sec at B=1024 (FP32/FP16 vs FP64 plain), max rel err"
                    if mixed["has_grad"] else "forward spectra/sec at B=1024 (FP32/FP16 vs FP64 plain), max rel err")
-        if cid == 1 else (f"emission forward spectra/sec at B={B} (FP32/FP16 vs FP64 plain)" if cid == 2 else
+        if cid == 1 else (f"emission forward spectra/sec at B={B} (FP32 vs FP64 plain)" if cid == 2 else
                           f"forward+grad spectra/sec, non-grey cloud transmission batch B={B} (FP32/FP16)" if cid == 5
                           else f"forward+grad spectra/sec, partly cloudy transmission batch B={B} (FP32/FP16)"
                           if cid == 6 else f"forward+grad spectra/sec, high-resolution ragged batch B={B} (FP32/FP16)"),
@@ -422,7 +422,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": workload, "batch": B, "n_nu": n_nu, "n_layers": L_ if nl_np is None else
                    f"{int(Ls.min())}-{int(Ls.max())} (mean {float(Ls.mean()):.1f})", "n_species": S,
-                   "precision": "fp16 tables / fp32 opacity / bf16x3 mfma chord / fp64 profile+lnL",
+                   "precision": ("fp32 tables / fp32 opacity / fp32 sweep / fp64 profile+lnL" if cid == 2 else
+                                 "fp16 tables / fp32 opacity / bf16x3 mfma chord / fp64 profile+lnL"),
                    "launch_choices": mixed["tuning"]},
         "roofline": roofline,
         "kernel_ms_per_step": {k: round(v[0] / max(1, v[1]), 4) for k, v in mixed["kernels"].items() if v[1]},

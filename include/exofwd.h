@@ -57,9 +57,11 @@ typedef enum {
 enum { EXOFWD_TRANSMISSION = 0, EXOFWD_EMISSION = 1 };
 
 /* FP64: FP64 tables and arithmetic throughout ("plain FP64").
- * MIXED: FP16 log-sigma tables (per-(species, nu) FP32 offsets), FP32 opacity,
- *        bf16x3 split-precision MFMA chord products with FP32 accumulation;
- *        profile, hydrostatics and likelihood sums stay FP64.           */
+ * MIXED: log-sigma tables stored relative to per-(species, nu) FP32 offsets,
+ *        as FP16 entries in transmission and FP32 entries in emission; FP32
+ *        opacity; transmission chords as bf16x3 split-precision MFMA products
+ *        with FP32 accumulation, the emission sweep in FP32; profile,
+ *        hydrostatics and likelihood sums stay FP64.                   */
 enum { EXOFWD_PREC_FP64 = 0, EXOFWD_PREC_MIXED = 1 };
 
 /* T-p profiles (Section "T-p profile parameterisation"): isothermal (Eq. 7), the

@@ -22,7 +22,7 @@ from .model import (  # noqa: F401
     altitudes, interp_index, bilinear_log_table, cia_log, cloud_fraction,
     layer_optical_depth, path_matrix, transit_depth, planck, gauss_legendre_01,
     emission_intensity, emission_ratio, bin_means, log_likelihood,
-    forward, decode_fp16_tables, split_params,
+    forward, decode_tables, split_params,
     CLOUD_GREY_DECK, CLOUD_NONGREY, QPROF_UNIFORM, QPROF_SLAB, QPROF_POWER, QEXT_FIT, QEXT_FIT_FEATURE,
     QEXT_GREY, X0_FEATURE, Q_MAX, nongrey_param_count, layer_coverage, condensate_profile,
     feature_efficiency, extinction_efficiency, nongrey_cloud_dtau,

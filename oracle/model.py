@@ -628,27 +628,25 @@ def split_params(wl, theta):
     return out
 
 
-def decode_fp16_tables(wl, pairs=None):
+def decode_tables(wl, wide=None):
     """The tables as the reduced-precision path stores them, decoded to FP64.
 
     Storage rule of the reduced-precision path: per species (or CIA pair) and
     wavenumber, c = float32((min + max)/2) of log2 sigma over the (T, p) grid;
-    each entry is float16(log2 sigma - c).  Emission stores each entry as the
-    pair hi = float16(v), lo = float16(v - hi) of v = log2 sigma - c (``pairs``,
-    by default for emission workloads).  The decoded value is (c + h [+ lo]) /
-    log2(10) in log10 units, so forward(..., tables=...) isolates the storage
-    error from the arithmetic error.
+    each entry is float16(log2 sigma - c).  Emission stores each entry as
+    float32(log2 sigma - c) instead (``wide``, by default for emission
+    workloads).  The decoded value is (c + entry) / log2(10) in log10 units, so
+    forward(..., tables=...) isolates the storage error from the arithmetic error.
     """
-    if pairs is None:
-        pairs = wl["mode"] == 1
+    if wide is None:
+        wide = wl["mode"] == 1
+    store = np.float32 if wide else np.float16
 
     def dec(tab, axes):
         l2 = tab * np.log2(10.0)
         c = (0.5 * (l2.min(axis=axes, keepdims=True) + l2.max(axis=axes, keepdims=True))).astype(np.float32)
         v = l2 - c.astype(np.float64)
-        h = v.astype(np.float16).astype(np.float64)
-        if pairs:
-            h = h + (v - h).astype(np.float16).astype(np.float64)
+        h = v.astype(store).astype(np.float64)
         return (c.astype(np.float64) + h) / np.log2(10.0)
     xs = dec(wl["log10_xsec"], (1, 2))
     cia = dec(wl["log10_cia"], (1,)) if wl["log10_cia"] is not None else None

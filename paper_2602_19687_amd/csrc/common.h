@@ -115,9 +115,9 @@ struct Work {
 
 // Tables on the device.
 struct Tables {
-  const uint16_t* h;     // mixed: [S][n_t][n_p][n_nu_pad] fp16 (log2 sigma - c); emission: (hi, lo) fp16 pairs
+  const uint16_t* h;     // mixed: [S][n_t][n_p][n_nu_pad] fp16 (log2 sigma - c); emission: fp32 entries (two halves each)
   const float* c;        // mixed: [S][n_nu_pad] per-(species, nu) offsets, log2 units
-  const uint16_t* hc;    // mixed: [2][n_tc][n_nu_pad] (pairs for emission)
+  const uint16_t* hc;    // mixed: [2][n_tc][n_nu_pad] (fp32 entries for emission)
   const float* cc;       // mixed: [2][n_nu_pad]
   const float* nu4f;     // mixed: [n_nu_pad] (nu/1e4)^4
   const double* t64;     // fp64: [S][n_t][n_p][n_nu_pad] log10 sigma

@@ -4,10 +4,9 @@
 // for each Gauss-Legendre angle and the planet/star flux ratio (Eq. 45).
 // One thread owns one (wavenumber, angle) pair during the sweep.
 //
-// Reduced precision: the tables are stored as FP16 (hi, lo) pairs of
-// log2 sigma - c (hi = fp16(v), lo = fp16(v - hi)), one 4-byte word per entry,
-// so the stored value keeps about 22 significant bits: emitted flux is far
-// more sensitive to opacity errors than the transit depth.
+// Reduced precision: the tables store log2 sigma - c as FP32, one 4-byte word
+// per entry (24 significant bits, against 11 for the FP16 transmission tables):
+// emitted flux is far more sensitive to opacity errors than the transit depth.
 #include "emission.h"
 #include "kernels.h"
 #include "opacity.h"
@@ -144,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tabl
   const int32_t* cells = w.cells + (size_t)b * Lp;
   const double* t_lev = w.t_lev + (size_t)b * (Lp + 1);
   const size_t npad = (size_t)m.n_nu_pad;
-  // pair tables: 4 bytes per (row, wavenumber)
+  // FP32 tables: 4 bytes per (row, wavenumber)
   const uint32_t row_bytes = (uint32_t)npad * 4u, tstep = (uint32_t)m.n_p * row_bytes;
   const __amdgpu_buffer_rsrc_t rh = make_rsrc(tb.h, (size_t)S * m.n_t * m.n_p * npad * 4);
   const __amdgpu_buffer_rsrc_t rhc = make_rsrc(CIA ? (const void*)tb.hc : (const void*)tb.h,
@@ -172,8 +171,8 @@ __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tabl
     inten[k] = b_bot;
   }
 
-  // table pairs of the current cell: a layer in the same cell as the one below reuses them
-  half2_t tp[4 * S + 4];
+  // table entries of the current cell: a layer in the same cell as the one below reuses them
+  float tp[4 * S + 4];
   int cell_prev = -1;
   for (int l = 0; l < L; ++l) {
     // ---- optical depth of layer l
@@ -184,17 +183,17 @@ __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tabl
 #pragma unroll
       for (int s2 = 0; s2 < S; ++s2) {
         const uint32_t row = (uint32_t)((s2 * m.n_t + it) * m.n_p + ip) * row_bytes + nu0_bytes;
-        tp[4 * s2] = load_h2(rh, voff, row);
-        tp[4 * s2 + 1] = load_h2(rh, voff, row + tstep);
-        tp[4 * s2 + 2] = load_h2(rh, voff, row + row_bytes);
-        tp[4 * s2 + 3] = load_h2(rh, voff, row + tstep + row_bytes);
+        tp[4 * s2] = load_f32(rh, voff, row);
+        tp[4 * s2 + 1] = load_f32(rh, voff, row + tstep);
+        tp[4 * s2 + 2] = load_f32(rh, voff, row + row_bytes);
+        tp[4 * s2 + 3] = load_f32(rh, voff, row + tstep + row_bytes);
       }
       if (CIA) {
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
           const uint32_t row = (uint32_t)(p * m.n_tc + itc) * row_bytes + nu0_bytes;
-          tp[4 * S + 2 * p] = load_h2(rhc, voff, row);
-          tp[4 * S + 2 * p + 1] = load_h2(rhc, voff, row + row_bytes);
+          tp[4 * S + 2 * p] = load_f32(rhc, voff, row);
+          tp[4 * S + 2 * p + 1] = load_f32(rhc, voff, row + row_bytes);
         }
       }
       cell_prev = cl;
@@ -204,28 +203,22 @@ __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tabl
     float d = 0.0f;
 #pragma unroll
     for (int s2 = 0; s2 < S; ++s2) {
-      const half2_t p00 = tp[4 * s2], p10 = tp[4 * s2 + 1], p01 = tp[4 * s2 + 2], p11 = tp[4 * s2 + 3];
+      const float p00 = tp[4 * s2], p10 = tp[4 * s2 + 1], p01 = tp[4 * s2 + 2], p11 = tp[4 * s2 + 3];
       float v = cs[s2] + rl[kRecFixed + s2];
-      v = fmaf(w00, (float)p00.x, v);
-      v = fmaf(w10, (float)p10.x, v);
-      v = fmaf(w01, (float)p01.x, v);
-      v = fmaf(w11, (float)p11.x, v);
-      v = fmaf(w00, (float)p00.y, v);
-      v = fmaf(w10, (float)p10.y, v);
-      v = fmaf(w01, (float)p01.y, v);
-      v = fmaf(w11, (float)p11.y, v);
+      v = fmaf(w00, p00, v);
+      v = fmaf(w10, p10, v);
+      v = fmaf(w01, p01, v);
+      v = fmaf(w11, p11, v);
       d += exp2_fast(v);
     }
     if (CIA) {
       const float wtc = rl[2];
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
-        const half2_t a = tp[4 * S + 2 * p], c2 = tp[4 * S + 2 * p + 1];
+        const float a = tp[4 * S + 2 * p], c2 = tp[4 * S + 2 * p + 1];
         float v = ccs[p] + rl[5 + p];
-        v = fmaf(1.0f - wtc, (float)a.x, v);
-        v = fmaf(wtc, (float)c2.x, v);
-        v = fmaf(1.0f - wtc, (float)a.y, v);
-        v = fmaf(wtc, (float)c2.y, v);
+        v = fmaf(1.0f - wtc, a, v);
+        v = fmaf(wtc, c2, v);
         d += exp2_fast(v);
       }
     }

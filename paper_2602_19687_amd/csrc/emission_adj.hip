@@ -1,7 +1,7 @@
 // Adjoint of the reduced-precision emission path (Eq. 45 with the
 // linear-in-tau sweep): d lnL / d dtau_l(nu) for every layer and wavenumber,
 // the per-level sums over wavenumber of d lnL / d B_j times dB/dT_j, and the
-// per-layer opacity sums of the pair tables.  The chain kernel of the
+// per-layer opacity sums of the FP32 tables.  The chain kernel of the
 // transmission adjoint then carries both to the parameters.
 //
 // One wave per (sample, 64-wavenumber tile), one wavenumber per lane.  The
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_emis_adj_mixed(Model m, Work w, AdjW
   if (lane == 0) ps[L] = lev_top;
 }
 
-// Per-layer opacity sums of the emission tables (FP16 (hi, lo) pairs, one
+// Per-layer opacity sums of the emission tables (FP32 entries, one
 // wavenumber per lane, 64-wavenumber tiles): the same sums, in the same order,
 // as the transmission layer sums, with no Rayleigh or cloud term.
 template <int S, bool CIA>
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_emis(Model m, Work w, Tab
   const int b = rem / NG, lg = rem - b * NG;
   if (w.status[b]) return;
   const int Lp = m.L_pad;
-  // a run of up to kLayers consecutive layers in one table cell: the table pairs
+  // a run of up to kLayers consecutive layers in one table cell: the table entries
   // are fetched once per tile for all of them
   const int32_t* grp = w.lsg + (size_t)b * (Lp + 1);
   if (lg >= grp[0]) return;
@@ -185,21 +185,21 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_emis(Model m, Work w, Tab
     for (int s = 0; s < S; ++s) cs[s] = tb.c[(size_t)s * npad + nu];
 #pragma unroll
     for (int p = 0; p < 2; ++p) ccs[p] = CIA ? tb.cc[(size_t)p * npad + nu] : 0.0f;
-    half2_t tp[4 * S + 4];
+    float tp[4 * S + 4];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const uint32_t row = (uint32_t)((s * m.n_t + it) * m.n_p + ip) * row_bytes + nu0_bytes;
-      tp[4 * s] = load_h2(rh, voff, row);
-      tp[4 * s + 1] = load_h2(rh, voff, row + tstep);
-      tp[4 * s + 2] = load_h2(rh, voff, row + row_bytes);
-      tp[4 * s + 3] = load_h2(rh, voff, row + tstep + row_bytes);
+      tp[4 * s] = load_f32(rh, voff, row);
+      tp[4 * s + 1] = load_f32(rh, voff, row + tstep);
+      tp[4 * s + 2] = load_f32(rh, voff, row + row_bytes);
+      tp[4 * s + 3] = load_f32(rh, voff, row + tstep + row_bytes);
     }
     if (CIA) {
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
         const uint32_t row = (uint32_t)(p * m.n_tc + itc) * row_bytes + nu0_bytes;
-        tp[4 * S + 2 * p] = load_h2(rhc, voff, row);
-        tp[4 * S + 2 * p + 1] = load_h2(rhc, voff, row + row_bytes);
+        tp[4 * S + 2 * p] = load_f32(rhc, voff, row);
+        tp[4 * S + 2 * p + 1] = load_f32(rhc, voff, row + row_bytes);
       }
     }
 #pragma unroll
@@ -212,10 +212,10 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_emis(Model m, Work w, Tab
       float z = 0.0f;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        const half2_t p00 = tp[4 * s], p10 = tp[4 * s + 1], p01 = tp[4 * s + 2], p11 = tp[4 * s + 3];
+        const float p00 = tp[4 * s], p10 = tp[4 * s + 1], p01 = tp[4 * s + 2], p11 = tp[4 * s + 3];
         const float base = cs[s] + rl[kRecFixed + s];
-        const float u0 = fmaf(omp, (float)p00.x + (float)p00.y, fmaf(wp, (float)p01.x + (float)p01.y, base));
-        const float u1 = fmaf(omp, (float)p10.x + (float)p10.y, fmaf(wp, (float)p11.x + (float)p11.y, base));
+        const float u0 = fmaf(omp, p00, fmaf(wp, p01, base));
+        const float u1 = fmaf(omp, p10, fmaf(wp, p11, base));
         const float dw = u1 - u0;
         const float t = exp2_fast(fmaf(wt, dw, u0));
         acc[q][s] = fmaf(db, t, acc[q][s]);
@@ -227,9 +227,9 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_emis(Model m, Work w, Tab
         float y = 0.0f;
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
-          const half2_t a = tp[4 * S + 2 * p], c2 = tp[4 * S + 2 * p + 1];
-          const float va = (float)a.x + (float)a.y + (ccs[p] + rl[5 + p]);
-          const float dw = ((float)c2.x + (float)c2.y) - ((float)a.x + (float)a.y);
+          const float a = tp[4 * S + 2 * p], c2 = tp[4 * S + 2 * p + 1];
+          const float va = a + (ccs[p] + rl[5 + p]);
+          const float dw = c2 - a;
           const float t = exp2_fast(fmaf(wtc, dw, va));
           acc[q][S + 1 + p] = fmaf(db, t, acc[q][S + 1 + p]);
           y = fmaf(t, dw, y);

@@ -106,11 +106,11 @@ void gauss_legendre(int n, double* x, double* wgt) {
 
 // Reduced-precision table storage: per (source, nu) offset c = float((min+max)/2)
 // of log2 sigma over the interpolation axes, entries float16(log2 sigma - c);
-// with `pairs` each entry is the (hi, lo) pair hi = fp16(v), lo = fp16(v - hi),
-// stored next to each other (emission, whose flux is sensitive to opacity error).
-void encode_fp16(const double* log10_tab, int n_src, int n_rows, int n_nu, int n_nu_pad, std::vector<_Float16>& h,
-                 std::vector<float>& c, bool pairs = false) {
-  const int k = pairs ? 2 : 1;
+// with `wide` each entry is float32(log2 sigma - c) in the space of two halves
+// (emission, whose flux is sensitive to opacity error).
+void encode_tables(const double* log10_tab, int n_src, int n_rows, int n_nu, int n_nu_pad, std::vector<_Float16>& h,
+                   std::vector<float>& c, bool wide = false) {
+  const int k = wide ? 2 : 1;
   h.assign((size_t)n_src * n_rows * n_nu_pad * k, (_Float16)0.0f);
   c.assign((size_t)n_src * n_nu_pad, -1000.0f);
   for (int s = 0; s < n_src; ++s) {
@@ -127,10 +127,9 @@ void encode_fp16(const double* log10_tab, int n_src, int n_rows, int n_nu, int n
       for (int r = 0; r < n_rows; ++r) {
         double v = t[(size_t)r * n_nu + i] * kLog2_10 - (double)cf;
         const size_t e = ((size_t)s * n_rows + r) * n_nu_pad + i;
-        if (pairs) {
-          const _Float16 hi = (_Float16)v;
-          h[2 * e] = hi;
-          h[2 * e + 1] = (_Float16)(v - (double)hi);
+        if (wide) {
+          const float f = (float)v;
+          std::memcpy(&h[2 * e], &f, sizeof f);
           continue;
         }
         h[e] = (_Float16)v;
@@ -386,8 +385,8 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   } else {
     std::vector<_Float16> h;
     std::vector<float> off;
-    const bool pairs = m.mode == kEmission;
-    encode_fp16(g.log10_xsec, m.S, rows, g.n_nu, (int)np, h, off, pairs);
+    const bool wide = m.mode == kEmission;
+    encode_tables(g.log10_xsec, m.S, rows, g.n_nu, (int)np, h, off, wide);
     uint16_t* dh = A(dalloc<uint16_t>(c, h.size()));
     float* dc = A(dalloc<float>(c, off.size()));
     float* dn4 = A(dalloc<float>(c, np));
@@ -400,7 +399,7 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
     c->tb.c = dc;
     c->tb.nu4f = dn4;
     if (m.has_cia) {
-      encode_fp16(g.log10_cia, 2, m.n_tc, g.n_nu, (int)np, h, off, pairs);
+      encode_tables(g.log10_cia, 2, m.n_tc, g.n_nu, (int)np, h, off, wide);
       uint16_t* dhc = A(dalloc<uint16_t>(c, h.size()));
       float* dcc = A(dalloc<float>(c, off.size()));
       if (ok) ok = upload(dhc, reinterpret_cast<const uint16_t*>(h.data()), h.size()) && upload(dcc, off.data(), off.size());

@@ -98,6 +98,9 @@ __device__ inline LaneConst<S> load_lane(const Model& m, const Tables& tb, int n
   return k;
 }
 
+__device__ inline float load_f32(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
 __device__ inline half2_t load_h2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   return __builtin_bit_cast(half2_t, (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }

@@ -81,7 +81,8 @@ class ForwardModel:
 
     ``wl`` is a mapping with the keys produced by ``synth.workload`` (grids,
     tables, bins, observed data and scalar settings).  ``precision`` is
-    "mixed" (FP16 tables, FP32 opacity, bf16x3 MFMA chord) or "fp64".
+    "mixed" (FP16 tables in transmission, FP32 in emission; FP32 opacity; bf16x3
+    MFMA chord) or "fp64".
     """
 
     def __init__(self, wl, precision: str = "mixed", batch_max: int | None = None, device: int = 0,

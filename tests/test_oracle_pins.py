@@ -469,26 +469,25 @@ def test_complex_step_matches_central_differences():
 
 def test_fp16_decoded_tables_within_half_ulp():
     wl = synth.workload(0)
-    xs, _ = oracle.decode_fp16_tables(wl)
+    xs, _ = oracle.decode_tables(wl)
     l2 = wl["log10_xsec"] * np.log2(10.0)
     c = 0.5 * (l2.min(axis=(1, 2), keepdims=True) + l2.max(axis=(1, 2), keepdims=True))
     half_ulp = np.abs(l2 - c) * 2.0 ** -11 + 2.0 ** -25
     assert np.all(np.abs(xs * np.log2(10.0) - l2) <= half_ulp + 1e-6)
 
 
-def test_fp16_pair_decoded_tables_within_pair_bound():
-    """(hi, lo) storage: hi = fp16(v) is within 2^-11 |v| of v, and lo = fp16(v - hi)
-    leaves at most 2^-11 of that (plus the fp16 subnormal step 2^-25), so the
-    pair is within ~2^-22 |v| + 2^-25; a single fp16 would not be."""
+def test_fp32_decoded_tables_within_single_ulp():
+    """Emission storage: float32(v) is within 2^-24 |v| of v (round to nearest),
+    so the decoded table is ~2^13 times closer than a single fp16 entry."""
     wl = synth.workload(0)
-    xs, _ = oracle.decode_fp16_tables(wl, pairs=True)
+    xs, _ = oracle.decode_tables(wl, wide=True)
     l2 = wl["log10_xsec"] * np.log2(10.0)
     c = (0.5 * (l2.min(axis=(1, 2), keepdims=True) + l2.max(axis=(1, 2), keepdims=True))).astype(np.float32)
     v = l2 - c.astype(np.float64)
     err = np.abs(xs * np.log2(10.0) - l2)
-    assert np.all(err <= np.abs(v) * 2.0 ** -21 + 2.0 ** -24 + 1e-12)
-    single, _ = oracle.decode_fp16_tables(wl, pairs=False)
-    assert np.max(err) < 0.01 * np.max(np.abs(single * np.log2(10.0) - l2))
+    assert np.all(err <= np.abs(v) * 2.0 ** -24 + 1e-12)
+    single, _ = oracle.decode_tables(wl, wide=False)
+    assert np.max(err) < 1e-3 * np.max(np.abs(single * np.log2(10.0) - l2))
 
 
 # ---------------------------------------------------------------------------
