@@ -426,7 +426,9 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
   constexpr int NS = n_sums(S);
   constexpr int kLs = ls_layers(NGC);
   const int lane = threadIdx.x & 63;
-  const int gw = blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // consecutive waves (one wavenumber chunk) on one XCD: its L2 holds that chunk's table columns
+  const int gw = xcd_logical_block(blockIdx.x, gridDim.x) * (kBlock / 64) +
+                 __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int NG = (m.L_max + kLs - 1) / kLs;
   const int per_chunk = B * NG;
   const int chunk = gw / per_chunk;
@@ -1030,40 +1032,58 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
     __syncthreads();
   }
 
-  // path-matrix adjoint: column pass (r_l, r_{l+1}) and row pass (b_i)
-  const PbarT* pbar = reinterpret_cast<const PbarT*>(aw.pbar);
-  auto pb = [&](int i, int l) {
-    double v = 0.0;
-    for (int c = 0; c < Cn; ++c) v += (double)pbar[(((size_t)b * C + c) * Lp + i) * Lp + l];
-    return v;
-  };
+  // path-matrix adjoint: column pass (r_l, r_{l+1}) and row pass (b_i); four entries'
+  // loads are issued together, each entry summed over the chunks in chunk order
+  const PbarT* pbar = reinterpret_cast<const PbarT*>(aw.pbar) + (size_t)b * C * Lp * Lp;
+  const size_t pst = (size_t)Lp * Lp;
   const bool trans = m.mode == kTransmission;
   for (int l = tid; l < (trans ? L : 0); l += kBlock) {
     double clo = 0.0, cup = 0.0;
-    for (int i = 0; i <= l; ++i) {
-      double dlo, dup, db;
-      path_derivs(s_r, i, l, dlo, dup, db);
-      const double p = pb(i, l);
-      clo += p * dlo;
-      cup += p * dup;
+    for (int i0 = 0; i0 <= l; i0 += 4) {
+      double p[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int c = 0; c < Cn; ++c)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i0 + u <= l) p[u] += (double)pbar[c * pst + (size_t)(i0 + u) * Lp + l];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (i0 + u > l) break;
+        double dlo, dup, db;
+        path_derivs(s_r, i0 + u, l, dlo, dup, db);
+        clo += p[u] * dlo;
+        cup += p[u] * dup;
+      }
     }
     s_clo[l] = clo;
     s_cup[l] = cup;
   }
   for (int i = tid; i < (trans ? L : 0); i += kBlock) {
     double acc = 0.0;
-    for (int l = i + 1; l < L; ++l) {
-      double dlo, dup, db;
-      path_derivs(s_r, i, l, dlo, dup, db);
-      acc += pb(i, l) * db;
+    for (int l0 = i + 1; l0 < L; l0 += 4) {
+      double p[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int c = 0; c < Cn; ++c)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (l0 + u < L) p[u] += (double)pbar[c * pst + (size_t)i * Lp + l0 + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (l0 + u >= L) break;
+        double dlo, dup, db;
+        path_derivs(s_r, i, l0 + u, dlo, dup, db);
+        acc += p[u] * db;
+      }
     }
     s_bb[i] = acc;
   }
   // emission: no chord; the levels move the optical depths only through dr
   for (int l = tid; l < (trans ? 0 : L); l += kBlock) s_clo[l] = s_cup[l] = s_bb[l] = 0.0;
-  double core_bar = 0.0;
-  for (int k = 0; k < m.K; ++k) core_bar += w.dm[(size_t)b * m.K + k];
-  __syncthreads();
+  // seed of the core term: the bins' d lnL / d depth summed over the block
+  // (s_red is free between the cloud sums and the T-p sums)
+  double cb = 0.0;
+  for (int k = tid; k < m.K; k += kBlock) cb += w.dm[(size_t)b * m.K + k];
+  s_red[tid] = cb;
+  block_sum(s_red, tid, 1);
+  const double core_bar = s_red[0];
   for (int j = tid; j <= L; j += kBlock) {
     double rb = 0.0;
     double ab_j = 0.0, ab_jm = 0.0;
@@ -1194,10 +1214,19 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
     const double* tlev = w.t_lev + (size_t)b * (Lp + 1);
     for (int j = tid; j <= L; j += kBlock) {
       double tb = 0.0;
-      for (int t = 0; t < m.n_tiles64; ++t) {
-        const size_t i = ((size_t)b * m.n_tiles64 + t) * (Lp + 1) + j;
-        if constexpr (sizeof(PbarT) == 8) tb += aw.psum64[i];
-        else tb += (double)aw.psum[i];
+      const size_t i0 = (size_t)b * m.n_tiles64 * (Lp + 1) + j;
+      for (int t0 = 0; t0 < m.n_tiles64; t0 += 4) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const size_t i = i0 + (size_t)(t0 + u) * (Lp + 1);
+          if (t0 + u >= m.n_tiles64) v[u] = 0.0;
+          else if constexpr (sizeof(PbarT) == 8) v[u] = aw.psum64[i];
+          else v[u] = (double)aw.psum[i];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (t0 + u < m.n_tiles64) tb += v[u];
       }
       tp_grad(logp_lev(j), tlev[j], tb);
     }
@@ -1464,7 +1493,9 @@ void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const Ad
   const int nl = ls_layers(m.cloud_ng), NG = (m.L_max + nl - 1) / nl;
   const long waves = (long)aw.lsum_chunks * B * NG;
   void* args2[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&aw, (void*)&B};
-  hipLaunchKernel(ls_kernel_for(m.S, m.has_cia, m.cloud_ng), dim3((unsigned)((waves + 3) / 4)), dim3(kBlock), args2, 0, st);
+  // a whole number of blocks per XCD; the waves past the last chunk return at once
+  const long blocks = ((waves + 3) / 4 + 7) / 8 * 8;
+  hipLaunchKernel(ls_kernel_for(m.S, m.has_cia, m.cloud_ng), dim3((unsigned)blocks), dim3(kBlock), args2, 0, st);
   if (m.cloud_ng) {
     const long cw = (long)B * aw.lsum_chunks;
     hipLaunchKernelGGL(k_cloud_spectral, dim3((unsigned)((cw + 3) / 4)), dim3(kBlock), 0, st, m, w, aw, B);

@@ -133,7 +133,9 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_emis(Model m, Work w, Tab
   constexpr int NS = n_sums(S);
   constexpr int kLayers = kLsGroup;
   const int lane = threadIdx.x & 63;
-  const int gw = blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // consecutive waves (one wavenumber chunk) on one XCD: its L2 holds that chunk's table columns
+  const int gw = xcd_logical_block(blockIdx.x, gridDim.x) * (kBlock / 64) +
+                 __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int NG = m.L_max;   // groups per sample: at most one per layer
   const int per_chunk = B * NG;
   const int chunk = gw / per_chunk;
@@ -434,7 +436,8 @@ void launch_layer_sums_emis(const Model& m, const Work& w, const Tables& tb, con
                             hipStream_t st) {
   // FP64: fixed groups of 5 layers; reduced precision: one wave per (chunk, sample, layer group)
   const long waves = (long)aw.lsum_chunks * B * (fp64 ? (m.L_max + 4) / 5 : m.L_max);
-  const dim3 grid((unsigned)((waves + 3) / 4));
+  // a whole number of blocks per XCD; the waves past the last chunk return at once
+  const dim3 grid((unsigned)(((waves + 3) / 4 + 7) / 8 * 8));
   if (fp64) {
     hipLaunchKernelGGL(k_layer_sums_emis_fp64, grid, dim3(kBlock), 0, st, m, w, tb, aw, B);
     return;
