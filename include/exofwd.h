@@ -219,7 +219,7 @@ exofwd_status exofwd_grad(exofwd_ctx* ctx, int32_t B, const double* params,
  *       layers <= 128), 1 = 64 x 4 (<= 128), 2 = 64 x 5 (<= 160)
  *   [2] reverse work items per call, one of 512, 1024, 2048, 4096 (each sample's
  *       wavenumbers are split into ceil(items / B) chunks)
- *   [3] 128-wavenumber tiles per wave of the layer-sum kernel: 4, 8, 16 or 32
+ *   [3] 128-wavenumber tiles per wave of the layer-sum kernel: 4, 8, 16, 32 or 64
  * Every choice gives the same results up to FP32 summation order.
  * exofwd_set_tuning returns EXOFWD_ERR_ARG, changing nothing, for a choice that
  * does not serve the context (entries [1..3] are ignored when the context has no

@@ -23,7 +23,7 @@ enum : int { kAdjT128M4 = 0, kAdjT64M4 = 1, kAdjT64M5 = 2, kAdjVariants = 3 };
 
 // launch choices the autotuner may change (every value is valid for any workload)
 constexpr int kChunkTargets[] = {512, 1024, 2048, 4096};   // (sample, chunk) work items per reverse launch
-constexpr int kLsTileChoices[] = {4, 8, 16, 32};             // 128-wavenumber tiles per layer-sum wave
+constexpr int kLsTileChoices[] = {4, 8, 16, 32, 64};           // 128-wavenumber tiles per layer-sum wave
 
 struct AdjWork {
   int variant;         // reduced-precision reverse kernel shape (kAdj*)

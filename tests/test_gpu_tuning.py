@@ -37,6 +37,7 @@ def _model(wl, **kw):
 CHOICES = [
     [0, 0, 1024, 8], [1, 0, 1024, 8], [0, 1, 1024, 8], [0, 2, 1024, 8],
     [0, 0, 512, 4], [0, 0, 4096, 16], [1, 1, 2048, 16], [0, 1, 4096, 4], [1, 0, 4096, 32], [0, 2, 1024, 32],
+    [1, 2, 4096, 64],
 ]
 
 
