@@ -947,8 +947,24 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
   const int NR = m.S + 6;
   for (int k = 0; k < NR; ++k) s_red[k * kBlock + tid] = 0.0;
   for (int l = tid; l < L; l += kBlock) {
-    double sm[kMaxSpecies + kExtraSums];
-    for (int k = 0; k < NS; ++k) sm[k] = layer_sum(l, k);
+    constexpr int kMaxNS = kMaxSpecies + kExtraSums;
+    double sm[kMaxNS];
+    if constexpr (sizeof(PbarT) == 8) {
+      for (int k = 0; k < NS; ++k) sm[k] = layer_sum(l, k);
+    } else {
+      // chunk by chunk with a chunk's sums loaded together; each sum still adds
+      // its chunks in chunk order
+      for (int k = 0; k < NS; ++k) sm[k] = 0.0;
+      for (int c = 0; c < aw.lsum_chunks; ++c) {
+        const float* src = aw.lsum + (((size_t)b * aw.lsum_stride + c) * Lp + l) * NT;
+        float v[kMaxNS];
+#pragma unroll
+        for (int k = 0; k < kMaxNS; ++k) v[k] = k < NS ? src[k] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < kMaxNS; ++k)
+          if (k < NS) sm[k] += (double)v[k];
+      }
+    }
     const double t = s_t[l];
     const double lp_bar = 0.5 * (logp_lev(l) + logp_lev(l + 1));
     const double n = exp10(lp_bar) * kBar / (kB * t);
