@@ -14,7 +14,7 @@ from scipy import integrate, interpolate, special, stats
 
 import oracle
 import synth
-from wl_helpers import constant_sigma_workload
+from wl_helpers import constant_sigma_workload, continuum_workload
 
 K_B, M_U, BAR = oracle.K_B, oracle.M_U, oracle.BAR
 
@@ -304,6 +304,92 @@ def test_layer_optical_depth_sums_sources():
     dr = it["r_lev"][l + 1] - it["r_lev"][l]
     np.testing.assert_allclose(parts[1][l], n_l ** 2 * (it["x_h2"] ** 2 * k1 + it["x_h2"] * it["x_he"] * k2) * dr,
                                rtol=1e-13)
+
+
+# --------------------------------------------------------------------------- continuum sources
+def _continuum_radius_error(wl):
+    """Discrete oracle transit radius minus the scale-height radius of the same
+    isothermal constant-g atmosphere, in units of the opacity's scale height,
+    at each wavenumber of a one-source workload (``continuum_workload``).
+
+    CIA scales as n^2, so its opacity falls with scale height H/2 and the
+    chord-depth closed form holds with H -> H/2 and sigma n0 -> w k n0^2, where
+    the pair weight w is X_H2^2 (H2-H2) or X_H2 X_He (H2-He).  Rayleigh scales
+    as n with sigma = X_H2 sigma_H2 + X_He sigma_He, both times (nu/1e4)^4."""
+    t, mu = wl["theta"][0], wl["mu_fixed"]
+    h = K_B * t / (mu * M_U * wl["g_ref"])
+    n0 = wl["p_ref_bar"] * BAR / (K_B * t)
+    x_h2 = (1.0 - 10.0 ** wl["theta"][1]) / (1.0 + oracle.HE_H2)
+    x_he = oracle.HE_H2 * x_h2
+    out = oracle.forward(wl, wl["theta"])
+    assert out["status"] == 0
+    errs = []
+    for i, nu in enumerate(wl["nu"]):
+        if wl["cia"]:
+            w = x_h2 * x_h2 if wl["log10_cia"][0, 0, i] > -200 else x_h2 * x_he
+            k = 10.0 ** max(wl["log10_cia"][0, 0, i], wl["log10_cia"][1, 0, i])
+            sig_n0, h_eff = w * k * n0 * n0, 0.5 * h
+        else:
+            sig_n0 = (x_h2 * wl["ray_h2"] + x_he * wl["ray_he"]) * (nu / 1.0e4) ** 4 * n0
+            h_eff = h
+        _, area = _gumbel_radius(sig_n0 / n0, n0, wl["r_p"], h_eff)
+        r_disc = math.sqrt(out["spectrum"][i] * wl["r_s"] ** 2)
+        errs.append((r_disc - math.sqrt(area)) / h_eff)
+    return np.array(errs), h
+
+
+@pytest.mark.parametrize("kind", ["cia1", "cia2"])
+def test_cia_density_power_and_pair_weight(kind):
+    """CIA alone in an isothermal exponential atmosphere lands on the scale-height
+    transit radius of an n^2 opacity (scale height H/2) with the pair weights
+    X_H2^2 (H2-H2) and X_H2 X_He (H2-He)."""
+    wl = continuum_workload(kind, nu=(1.0e4,), k_pair=(1e-45, 1e-44))
+    errs, _ = _continuum_radius_error(wl)
+    assert np.all(np.abs(errs) < 2e-3), errs
+
+
+def test_rayleigh_nu4_shift_and_weights():
+    """Rayleigh alone: each radius lands on the scale-height radius of sigma =
+    (X_H2 sigma_H2 + X_He sigma_He)(nu/1e4)^4, and doubling nu moves the radius
+    up by H [ln 2^4 + 1/2 ln(R_e2/R_e1)] (the second term is the chord length's
+    sqrt(R_e) in the scale-height radius, 0.008 H here)."""
+    wl = continuum_workload("rayleigh", nu=(1.0e4, 2.0e4))
+    errs, h = _continuum_radius_error(wl)
+    assert np.all(np.abs(errs) < 1e-3), errs
+    out = oracle.forward(wl, wl["theta"])
+    r = np.sqrt(out["spectrum"] * wl["r_s"] ** 2)
+    shift = math.log(16.0) + 0.5 * math.log(r[1] / r[0])
+    assert (r[1] - r[0]) / h == pytest.approx(shift, abs=2e-3)
+
+
+def _plant(monkeypatch, scale):
+    """Replace the oracle's layer optical depth by the true one times scale(l, nu)
+    (a planted mistake, CPU only) for the pins above to catch."""
+    real = oracle.model.layer_optical_depth
+
+    def mutant(wl, t_lay, p_lev, p_lay, *a, **k):
+        return real(wl, t_lay, p_lev, p_lay, *a, **k) * scale(wl, t_lay, p_lay)
+    monkeypatch.setattr(oracle.model, "layer_optical_depth", mutant)
+
+
+def test_continuum_pins_catch_planted_mistakes(monkeypatch):
+    """Each pin fails for the mistake it guards: CIA with n instead of n^2, the
+    H2-He pair weighted by X_H2^2, Rayleigh with nu^2 instead of nu^4, and the
+    He Rayleigh term weighted by X_H2."""
+    n_ref = lambda wl, t: wl["p_ref_bar"] * BAR / (K_B * t[0])
+    cases = [
+        ("cia1", lambda wl, t, p: (n_ref(wl, t) * K_B * t / p)[:, None]),            # n^2 -> n (same n at p_ref)
+        ("cia2", lambda wl, t, p: np.full((len(t), 1), 1.0 / oracle.HE_H2)),          # X_H2 X_He -> X_H2^2
+        ("rayleigh", lambda wl, t, p: (wl["nu"] / 1.0e4)[None, :] ** -2),             # nu^4 -> nu^2
+        ("rayleigh", lambda wl, t, p: np.full((len(t), 1), 1.0 + 0.836 * 6e-30 / (8e-29 + 0.164 * 6e-30))),
+    ]
+    for kind, scale in cases:
+        wl = continuum_workload(kind, nu=(1.0e4, 2.0e4) if kind == "rayleigh" else (1.0e4,),
+                                k_pair=(1e-45, 1e-44))
+        with monkeypatch.context() as mp:
+            _plant(mp, scale)
+            errs, _ = _continuum_radius_error(wl)
+        assert np.max(np.abs(errs)) > 2e-2, (kind, errs)
 
 
 # --------------------------------------------------------------------------- a1/a2

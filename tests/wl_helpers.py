@@ -21,3 +21,27 @@ def constant_sigma_workload(sigma=1.0e-26, t_iso=1200.0, n_layers=50, n_nu=4, mu
               constant_g=constant_g, params=np.array([[t_iso, -3.0]]), n_knots=0)
     wl["theta"] = np.array([t_iso, -3.0])
     return wl
+
+
+def continuum_workload(kind, n_layers=1000, t_iso=1200.0, mu=2.3, nu=(1.0e4, 2.0e4), k_pair=(1e-45, 1e-45),
+                       ray=(8.0e-29, 6.0e-30)):
+    """Isothermal, constant g, only one continuum source: ``kind`` is "cia1"
+    (H2-H2 alone, wavelength-independent k_pair[0]), "cia2" (H2-He alone,
+    k_pair[1]) or "rayleigh" (H2 and He Rayleigh scattering, sigma_R =
+    ray * (nu/1e4)^4).  The one absorber is present with a negligible cross
+    section so that the composition (X_H2, X_He) is that of a pure H2/He gas."""
+    n_nu = len(nu)
+    wl = constant_sigma_workload(sigma=1e-300, t_iso=t_iso, n_layers=n_layers, n_nu=n_nu, mu=mu)
+    wl["nu"] = np.asarray(nu, dtype=np.float64)
+    tc = np.linspace(300.0, 3500.0, 3)
+    if kind in ("cia1", "cia2"):
+        tab = np.full((2, len(tc), n_nu), -300.0)
+        j = 0 if kind == "cia1" else 1
+        tab[j] = np.log10(k_pair[j])
+        wl.update(cia=True, log10_cia=tab, tc_grid=tc, rayleigh=False)
+    else:
+        wl.update(cia=False, log10_cia=None, rayleigh=True, ray_h2=ray[0], ray_he=ray[1])
+    # theta = [T_iso, log10 X]: the absorber's X is negligible, the gas is H2 + He
+    wl["theta"] = np.array([t_iso, -12.0])
+    wl["params"] = wl["theta"][None, :].copy()
+    return wl
