@@ -168,9 +168,19 @@ typedef struct exofwd_config {
 
 /* Validate the configuration, upload and encode the tables, allocate the
  * workspace for batch_max samples of n_layers_max layers.  Synchronous.
- * On success *out owns all device memory of the context.  EXOFWD_ERR_CONFIG for
- * an invalid description, EXOFWD_ERR_UNSUPPORTED for FP64 emission with more than
- * 128 padded layers, EXOFWD_ERR_DEVICE / EXOFWD_ERR_NOMEM for device failures. */
+ * On success *out owns all device memory of the context.  Every check below runs
+ * on the host before any device call:
+ *   EXOFWD_ERR_CONFIG       an invalid description, including a non-finite entry in
+ *                           log10_xsec or log10_cia (give a zero cross-section as a
+ *                           finite floor);
+ *   EXOFWD_ERR_UNSUPPORTED  FP64 emission with more than 128 padded layers; in MIXED
+ *                           precision, a line or CIA table of 2^31 bytes or more once
+ *                           encoded (2 bytes per entry in transmission, 4 in emission,
+ *                           n_nu padded to a multiple of 128), or padded layers x padded
+ *                           n_nu x 4 bytes of 2^31 or more (the reduced-precision
+ *                           kernels address these buffers with 32-bit offsets).
+ * EXOFWD_ERR_DEVICE / EXOFWD_ERR_NOMEM for device failures.  On failure
+ * exofwd_last_error(NULL) gives the reason (per thread). */
 exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out);
 
 /* Free everything the context owns (synchronises its device). NULL is a no-op. */
@@ -268,7 +278,8 @@ exofwd_status exofwd_kernel_time(exofwd_ctx* ctx, const char* name, double* tota
 int64_t exofwd_device_bytes(const exofwd_ctx* ctx);
 
 const char* exofwd_strerror(exofwd_status s);
-/* Text of the last error raised on this context (empty if none). */
+/* Text of the last error raised on this context (empty if none); with a NULL
+ * context, the text of this thread's last failed exofwd_create. */
 const char* exofwd_last_error(const exofwd_ctx* ctx);
 
 #ifdef __cplusplus

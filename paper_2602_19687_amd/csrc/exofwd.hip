@@ -163,6 +163,9 @@ void prof_end(exofwd_ctx* c, hipStream_t st) {
 }
 }  // namespace exofwd
 
+// Text of the last exofwd_create failure on this thread (exofwd_last_error(NULL)).
+static thread_local std::string g_create_err;
+
 extern "C" {
 
 const char* exofwd_strerror(exofwd_status s) {
@@ -178,7 +181,10 @@ const char* exofwd_strerror(exofwd_status s) {
   return "unknown status";
 }
 
-const char* exofwd_last_error(const exofwd_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* exofwd_last_error(const exofwd_ctx* c) {
+  if (c) return c->err.c_str();
+  return g_create_err.empty() ? "null context" : g_create_err.c_str();
+}
 int32_t exofwd_num_params(const exofwd_ctx* c) { return c ? c->m.P : -1; }
 int32_t exofwd_num_nu(const exofwd_ctx* c) { return c ? c->m.n_nu : -1; }
 int32_t exofwd_num_bins(const exofwd_ctx* c) { return c ? c->m.K : -1; }
@@ -207,50 +213,95 @@ exofwd_status exofwd_destroy(exofwd_ctx* c) {
   return EXOFWD_OK;
 }
 
+static exofwd_status create_fail(exofwd_status s, const std::string& msg) {
+  g_create_err = "exofwd_create: " + msg;
+  return s;
+}
+
+static bool all_finite(const double* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
 exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
-  if (!out) return EXOFWD_ERR_ARG;
+  if (!out) return create_fail(EXOFWD_ERR_ARG, "out is NULL");
   *out = nullptr;
-  if (!cfg) return EXOFWD_ERR_ARG;
+  if (!cfg) return create_fail(EXOFWD_ERR_ARG, "cfg is NULL");
+  g_create_err.clear();
   // ---- validation (nothing touches the device before this passes)
   const auto& g = *cfg;
-  if (g.mode != EXOFWD_TRANSMISSION && g.mode != EXOFWD_EMISSION) return EXOFWD_ERR_CONFIG;
-  if (g.precision != EXOFWD_PREC_FP64 && g.precision != EXOFWD_PREC_MIXED) return EXOFWD_ERR_CONFIG;
-  if (g.tp_kind < EXOFWD_TP_ISOTHERMAL || g.tp_kind > EXOFWD_TP_GUILLOT7) return EXOFWD_ERR_CONFIG;
-  if (g.tp_kind == EXOFWD_TP_PCHIP && (g.n_knots < 2 || g.n_knots > kMaxKnots)) return EXOFWD_ERR_CONFIG;
-  if (g.n_species < 1 || g.n_species > kMaxSpecies) return EXOFWD_ERR_CONFIG;
-  if (g.n_layers_max < 1 || g.n_layers_max > kMaxLayers) return EXOFWD_ERR_CONFIG;
-  if (g.batch_max < 1) return EXOFWD_ERR_CONFIG;
-  if (g.n_nu < 1 || !g.nu || !ascending(g.nu, g.n_nu) || !(g.nu[0] > 0.0)) return EXOFWD_ERR_CONFIG;
+  const exofwd_status E = EXOFWD_ERR_CONFIG;
+  if (g.mode != EXOFWD_TRANSMISSION && g.mode != EXOFWD_EMISSION) return create_fail(E, "unknown mode");
+  if (g.precision != EXOFWD_PREC_FP64 && g.precision != EXOFWD_PREC_MIXED) return create_fail(E, "unknown precision");
+  if (g.tp_kind < EXOFWD_TP_ISOTHERMAL || g.tp_kind > EXOFWD_TP_GUILLOT7) return create_fail(E, "unknown T-p profile");
+  if (g.tp_kind == EXOFWD_TP_PCHIP && (g.n_knots < 2 || g.n_knots > kMaxKnots))
+    return create_fail(E, "n_knots outside [2, 8]");
+  if (g.n_species < 1 || g.n_species > kMaxSpecies) return create_fail(E, "n_species outside [1, 8]");
+  if (g.n_layers_max < 1 || g.n_layers_max > kMaxLayers) return create_fail(E, "n_layers_max outside [1, 160]");
+  if (g.batch_max < 1) return create_fail(E, "batch_max < 1");
+  if (g.n_nu < 1 || !g.nu || !ascending(g.nu, g.n_nu) || !(g.nu[0] > 0.0))
+    return create_fail(E, "nu must hold n_nu >= 1 positive ascending wavenumbers");
   if (g.n_t < 2 || g.n_t > 255 || g.n_p < 2 || g.n_p > 255 || !g.t_grid || !g.logp_grid || !g.log10_xsec)
-    return EXOFWD_ERR_CONFIG;
-  if (!ascending(g.t_grid, g.n_t) || !ascending(g.logp_grid, g.n_p)) return EXOFWD_ERR_CONFIG;
+    return create_fail(E, "table axes need 2..255 points each and the table pointers");
+  if (!ascending(g.t_grid, g.n_t) || !ascending(g.logp_grid, g.n_p)) return create_fail(E, "table axes not ascending");
   if (g.has_cia && (g.n_tc < 2 || g.n_tc > 255 || !g.tc_grid || !g.log10_cia || !ascending(g.tc_grid, g.n_tc)))
-    return EXOFWD_ERR_CONFIG;
-  if (!(g.mu_fixed > 0.0) && !g.species_mass) return EXOFWD_ERR_CONFIG;
-  if (g.n_bins < 1 || !g.bin_lo || !g.bin_hi || !g.y_obs || !g.y_err) return EXOFWD_ERR_CONFIG;
+    return create_fail(E, "CIA axis needs 2..255 ascending temperatures and the CIA table");
+  if (!(g.mu_fixed > 0.0) && !g.species_mass) return create_fail(E, "species_mass is NULL and mu_fixed <= 0");
+  if (g.n_bins < 1 || !g.bin_lo || !g.bin_hi || !g.y_obs || !g.y_err) return create_fail(E, "bins or data missing");
   for (int k = 0; k < g.n_bins; ++k) {
     if (g.bin_lo[k] < 0 || g.bin_hi[k] > g.n_nu || g.bin_lo[k] >= g.bin_hi[k] || !(g.y_err[k] > 0.0))
-      return EXOFWD_ERR_CONFIG;
+      return create_fail(E, "bin " + std::to_string(k) + " empty, outside [0, n_nu) or with y_err <= 0");
     // bins are ordered and disjoint, so every wavenumber feeds at most one bin
-    if (k > 0 && g.bin_lo[k] < g.bin_hi[k - 1]) return EXOFWD_ERR_CONFIG;
+    if (k > 0 && g.bin_lo[k] < g.bin_hi[k - 1]) return create_fail(E, "bins not ordered and disjoint");
   }
-  if (!(g.p_bot_bar > g.p_top_bar) || !(g.p_top_bar > 0.0) || !(g.p_ref_bar > 0.0)) return EXOFWD_ERR_CONFIG;
-  if (!(g.r_p > 0.0) || !(g.r_s > 0.0) || !(g.g_ref > 0.0)) return EXOFWD_ERR_CONFIG;
-  if (g.mode == EXOFWD_EMISSION && (g.n_mu < 1 || g.n_mu > kMaxMu || !(g.t_star > 0.0))) return EXOFWD_ERR_CONFIG;
+  if (!(g.p_bot_bar > g.p_top_bar) || !(g.p_top_bar > 0.0) || !(g.p_ref_bar > 0.0))
+    return create_fail(E, "pressures need p_bot > p_top > 0 and p_ref > 0");
+  if (!(g.r_p > 0.0) || !(g.r_s > 0.0) || !(g.g_ref > 0.0)) return create_fail(E, "r_p, r_s and g_ref must be > 0");
+  if (g.mode == EXOFWD_EMISSION && (g.n_mu < 1 || g.n_mu > kMaxMu || !(g.t_star > 0.0)))
+    return create_fail(E, "emission needs n_mu in [1, 8] and t_star > 0");
   if (g.has_cloud) {
-    if (g.cloud_model != EXOFWD_CLOUD_GREY_DECK && g.cloud_model != EXOFWD_CLOUD_NONGREY) return EXOFWD_ERR_CONFIG;
+    if (g.cloud_model != EXOFWD_CLOUD_GREY_DECK && g.cloud_model != EXOFWD_CLOUD_NONGREY)
+      return create_fail(E, "unknown cloud model");
     if (g.cloud_model == EXOFWD_CLOUD_NONGREY &&
         (g.mode != EXOFWD_TRANSMISSION || g.cloud_profile < EXOFWD_QPROF_UNIFORM || g.cloud_profile > EXOFWD_QPROF_POWER ||
          g.cloud_qext < EXOFWD_QEXT_FIT || g.cloud_qext > EXOFWD_QEXT_GREY))
-      return EXOFWD_ERR_CONFIG;
+      return create_fail(E, "the non-grey cloud is a transmission model with a known profile and Q_ext form");
   }
-  if (g.has_fcld && (!g.has_cloud || g.mode != EXOFWD_TRANSMISSION)) return EXOFWD_ERR_CONFIG;
-  if (g.has_bd && (g.mode != EXOFWD_EMISSION || g.has_scale || !(g.bd_distance > 0.0))) return EXOFWD_ERR_CONFIG;
+  if (g.has_fcld && (!g.has_cloud || g.mode != EXOFWD_TRANSMISSION))
+    return create_fail(E, "cloudy/clear mixing needs a transmission model with a cloud");
+  if (g.has_bd && (g.mode != EXOFWD_EMISSION || g.has_scale || !(g.bd_distance > 0.0)))
+    return create_fail(E, "an isolated object is an emission model without R_p scaling and with a distance > 0");
   // the FP64 emission kernel stages a tile's layers in LDS: at most 128 padded layers
   if (g.mode == EXOFWD_EMISSION && g.precision == EXOFWD_PREC_FP64 && (g.n_layers_max + 31) / 32 * 32 > 128)
-    return EXOFWD_ERR_UNSUPPORTED;
+    return create_fail(EXOFWD_ERR_UNSUPPORTED, "FP64 emission takes at most 128 padded layers");
+  // The reduced-precision kernels read the encoded tables, and the gradient's stored
+  // optical depths of a sample, through buffer resources whose range and offsets are
+  // 32-bit: each of these buffers must stay below 2^31 bytes (checked before any
+  // table is read).
+  if (g.precision == EXOFWD_PREC_MIXED) {
+    const uint64_t lim = 0x7fffffffull;
+    const uint64_t npad = ((uint64_t)g.n_nu + kTileNu - 1) / kTileNu * kTileNu;
+    const uint64_t eb = g.mode == EXOFWD_EMISSION ? 4 : 2;
+    const uint64_t lpad = ((uint64_t)g.n_layers_max + 31) / 32 * 32;
+    const uint64_t tab = (uint64_t)g.n_species * g.n_t * g.n_p * npad * eb;
+    const uint64_t cia = g.has_cia ? 2ull * g.n_tc * npad * eb : 0;
+    if (tab > lim || cia > lim || lpad * npad * 4 > lim)
+      return create_fail(EXOFWD_ERR_UNSUPPORTED,
+                         "reduced precision addresses each table, and a sample's stored optical depths, with "
+                         "32-bit offsets: line table " + std::to_string(tab) + " B, CIA table " +
+                             std::to_string(cia) + " B, optical depths " + std::to_string(lpad * npad * 4) +
+                             " B; each must be below 2^31 B");
+  }
+  // log10 tables must be finite: a zero cross-section is given as a finite floor
+  // (the reduced-precision encoding keeps each wavenumber's range over the grid)
+  if (!all_finite(g.log10_xsec, (size_t)g.n_species * g.n_t * g.n_p * g.n_nu))
+    return create_fail(E, "log10_xsec holds a non-finite entry");
+  if (g.has_cia && !all_finite(g.log10_cia, (size_t)2 * g.n_tc * g.n_nu))
+    return create_fail(E, "log10_cia holds a non-finite entry");
   int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || g.device < 0 || g.device >= ndev) return EXOFWD_ERR_DEVICE;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || g.device < 0 || g.device >= ndev)
+    return create_fail(EXOFWD_ERR_DEVICE, "no HIP device with ordinal " + std::to_string(g.device));
 
   auto* c = new exofwd_ctx();
   c->precision = g.precision;
@@ -258,7 +309,7 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   c->batch_max = g.batch_max;
   if (hipSetDevice(g.device) != hipSuccess) {
     delete c;
-    return EXOFWD_ERR_DEVICE;
+    return create_fail(EXOFWD_ERR_DEVICE, "hipSetDevice failed");
   }
   Model& m = c->m;
   m.mode = g.mode;
@@ -346,7 +397,7 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   double* d_p = A(dalloc<double>(c, m.n_p));
   double* d_tc = A(dalloc<double>(c, m.n_tc));
   double* d_nu = A(dalloc<double>(c, np));
-  if (!ok) { exofwd_destroy(c); return EXOFWD_ERR_NOMEM; }
+  if (!ok) { exofwd_destroy(c); return create_fail(EXOFWD_ERR_NOMEM, "device allocation failed"); }
   std::vector<double> nu_pad(np, g.nu[g.n_nu - 1]);
   std::memcpy(nu_pad.data(), g.nu, sizeof(double) * g.n_nu);
   std::vector<double> tc(m.n_tc, 0.0);
@@ -473,17 +524,17 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   });
   if (!ok) {
     exofwd_destroy(c);
-    return EXOFWD_ERR_NOMEM;
+    return create_fail(EXOFWD_ERR_NOMEM, "device allocation or upload failed");
   }
   hipError_t e = m.mode == kTransmission ? trans_fwd_configure(m, fp64) : emission_configure(m, fp64);
   if (e == hipSuccess) e = adjoint_configure(m, fp64);
   if (e != hipSuccess) {
     exofwd_destroy(c);
-    return EXOFWD_ERR_DEVICE;
+    return create_fail(EXOFWD_ERR_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(e));
   }
   if (hipDeviceSynchronize() != hipSuccess) {
     exofwd_destroy(c);
-    return EXOFWD_ERR_DEVICE;
+    return create_fail(EXOFWD_ERR_DEVICE, "device synchronisation failed");
   }
   *out = c;
   return EXOFWD_OK;

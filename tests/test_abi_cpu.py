@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_2602_19687_amd as pkg
@@ -142,3 +143,62 @@ def test_isolated_object_options_validated_before_device(change, ok):
     else:
         assert rc == L.ERR_CONFIG
         assert ctx.value is None
+
+
+def _cfg_with_table_shape(wl, precision, n_nu, n_species, n_t, n_p, n_layers=100):
+    """A config of workload ``wl`` whose table shape is overridden; its table
+    pointer holds a single entry, so validation must refuse the shape without
+    reading the table."""
+    from paper_2602_19687_amd.model import build_config
+    cfg, keep = build_config(wl, precision, 2)
+    nu = np.linspace(2000.0, 12000.0, n_nu)
+    tg = np.linspace(300.0, 3500.0, n_t)
+    pg = np.linspace(-7.0, 2.0, n_p)
+    one = np.zeros(1)
+    keep += [nu, tg, pg, one]
+    cfg.n_nu, cfg.nu = n_nu, nu.ctypes.data_as(C.POINTER(C.c_double))
+    cfg.n_species, cfg.n_t, cfg.n_p = n_species, n_t, n_p
+    cfg.t_grid = tg.ctypes.data_as(C.POINTER(C.c_double))
+    cfg.logp_grid = pg.ctypes.data_as(C.POINTER(C.c_double))
+    cfg.log10_xsec = one.ctypes.data_as(C.POINTER(C.c_double))
+    cfg.has_cia = 0
+    cfg.n_layers_max = n_layers
+    return cfg, keep
+
+
+@pytest.mark.parametrize("cid,n_nu,n_species,n_t,n_p,n_layers", [
+    (1, 400000, 8, 20, 20, 100),     # FP16 line table of 2.56 GB
+    (2, 200000, 8, 20, 20, 100),     # FP32 emission entries, 2.56 GB
+    (1, 3400000, 1, 2, 2, 160),      # a sample's stored optical depths, 2.18 GB
+])
+def test_create_refuses_buffers_beyond_32bit_offsets(cid, n_nu, n_species, n_t, n_p, n_layers):
+    import synth
+    lib = pkg.load()
+    wl = dict(synth.workload(cid, batch=2))
+    cfg, keep = _cfg_with_table_shape(wl, L.PREC_MIXED, n_nu, n_species, n_t, n_p, n_layers)
+    ctx = C.c_void_p()
+    assert lib.exofwd_create(C.byref(cfg), C.byref(ctx)) == L.ERR_UNSUPPORTED
+    assert ctx.value is None
+    msg = lib.exofwd_last_error(None).decode()
+    assert "2^31" in msg, msg
+
+
+@pytest.mark.parametrize("what,value", [("xsec", -np.inf), ("xsec", np.nan), ("cia", np.inf)])
+def test_create_refuses_non_finite_tables(what, value):
+    """A log10 table entry of -inf (a zero cross-section), +inf or NaN would turn
+    the reduced-precision encoding's per-wavenumber offset non-finite; both
+    precisions refuse it before any device call."""
+    import synth
+    from paper_2602_19687_amd.model import build_config
+    lib = pkg.load()
+    wl = dict(synth.workload(1, batch=2))
+    key = "log10_xsec" if what == "xsec" else "log10_cia"
+    tab = np.array(wl[key], copy=True)
+    tab.flat[tab.size // 3] = value
+    wl[key] = tab
+    for prec in (L.PREC_MIXED, L.PREC_FP64):
+        cfg, keep = build_config(wl, prec, 2)
+        ctx = C.c_void_p()
+        assert lib.exofwd_create(C.byref(cfg), C.byref(ctx)) == L.ERR_CONFIG
+        assert ctx.value is None
+        assert "non-finite" in lib.exofwd_last_error(None).decode()
