@@ -209,6 +209,33 @@ exofwd_status exofwd_forward(exofwd_ctx* ctx, int32_t B, const double* params,
                              const int32_t* n_layers, void* spectra, double* lnL,
                              int32_t* status, void* hip_stream);
 
+/* Size in bytes of the static device array that exofwd_forward_noalloc takes its
+ * scratch from; every device the library runs on holds one until the process ends. */
+#define EXOFWD_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/*
+ * exofwd_forward for callers that cannot allocate device memory: code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * kernels and results (bit for bit) as exofwd_forward, but the per-call workspace
+ * (profile records, path-matrix fragments, likelihood partials, and the spectra
+ * when spectra is NULL or with the cloudy/clear mixing) lives in a static device
+ * array of EXOFWD_NOALLOC_SCRATCH_BYTES on the context's device, not in the
+ * context's own workspace.  The call allocates and frees nothing, creates no
+ * events (per-kernel timing is skipped) and never captures or replays graphs (a
+ * caller that is capturing its stream gets the kernels in its own graph).
+ *   EXOFWD_ERR_SHAPE   the batch's workspace exceeds the array (last_error gives
+ *                      the bytes needed); about 80 KB per sample of a 128-layer
+ *                      reduced-precision transmission model, plus the spectra
+ *   EXOFWD_ERR_DEVICE  the array's device address could not be looked up (done
+ *                      once per device when the first context is created there)
+ * Every call on a device shares that device's array and overwrites it: calls that
+ * overlap in time on one device, from any context or stream, race and give wrong
+ * results.  Nothing in the array needs to start at zero.
+ */
+exofwd_status exofwd_forward_noalloc(exofwd_ctx* ctx, int32_t B, const double* params,
+                                     const int32_t* n_layers, void* spectra, double* lnL,
+                                     int32_t* status, void* hip_stream);
+
 /*
  * lnL and its gradient with respect to every parameter for B samples, by the
  * hand-written adjoint.  Workloads outside exofwd_grad_supported return

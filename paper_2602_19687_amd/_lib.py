@@ -52,6 +52,8 @@ EXPORTS = {
     "exofwd_grad_supported": (C.c_int32, [C.c_void_p]),
     "exofwd_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p]),
+    "exofwd_forward_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_void_p]),
     "exofwd_grad": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p]),
     "exofwd_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_char_p]),
@@ -64,6 +66,8 @@ EXPORTS = {
     "exofwd_strerror": (C.c_char_p, [C.c_int]),
     "exofwd_last_error": (C.c_char_p, [C.c_void_p]),
 }
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # EXOFWD_NOALLOC_SCRATCH_BYTES
 
 _lib = None
 

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -141,6 +142,29 @@ void encode_tables(const double* log10_tab, int n_src, int n_rows, int n_nu, int
 exofwd_status check_hip(exofwd_ctx* c, hipError_t e, const char* what) {
   if (e == hipSuccess) return EXOFWD_OK;
   return fail(c, EXOFWD_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---- scratch of the allocation-free forward call (exofwd_forward_noalloc)
+// Every device the library runs on holds one copy of this array until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it is only
+// a stand-in for the symbol): it uses the device address looked up below.
+static __device__ __align__(256) unsigned char scratch[EXOFWD_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices];      // device address of `scratch` on each device, once looked up
+bool g_scratch_tried[kMaxDevices];
+
+// Looks up the array's address on `dev`, which must be the current device
+// (once per device; later calls return the stored address, nullptr if the lookup failed).
+void* scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_tried[dev]) {
+    g_scratch_tried[dev] = true;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch_addr[dev] = p;
+  }
+  return g_scratch_addr[dev];
 }
 
 }  // namespace
@@ -311,6 +335,9 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
     delete c;
     return create_fail(EXOFWD_ERR_DEVICE, "hipSetDevice failed");
   }
+  // the allocation-free call's scratch address on this device (its failure only
+  // disables that call, which then reports it)
+  scratch_address(g.device);
   Model& m = c->m;
   m.mode = g.mode;
   m.tp_kind = g.tp_kind;
@@ -549,8 +576,9 @@ static exofwd_status check_call(exofwd_ctx* c, int32_t B, const double* params) 
   return EXOFWD_OK;
 }
 
-static exofwd_status run_forward(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers,
-                                 void* spectra, double* lnL, int32_t* status, void* hip_stream, void* dtau_out);
+static exofwd_status run_forward(exofwd_ctx* c, const Work& w, int32_t B, const double* params,
+                                 const int32_t* n_layers, void* spectra, double* lnL, int32_t* status,
+                                 void* hip_stream, void* dtau_out);
 static exofwd_status run_grad(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers,
                               void* spectra, double* lnL, double* grad, int32_t* status, void* hip_stream);
 
@@ -608,39 +636,103 @@ exofwd_status exofwd_forward(exofwd_ctx* c, int32_t B, const double* params, con
                              double* lnL, int32_t* status, void* hip_stream) {
   exofwd_status s = check_call(c, B, params);
   if (s) return s;
-  auto enqueue = [&]() { return run_forward(c, B, params, n_layers, spectra, lnL, status, hip_stream, nullptr); };
+  auto enqueue = [&]() { return run_forward(c, c->w, B, params, n_layers, spectra, lnL, status, hip_stream, nullptr); };
   if (!c->use_graphs) return enqueue();
   return graph_call(c, 0, B, {params, n_layers, spectra, lnL, status, nullptr, nullptr}, (hipStream_t)hip_stream,
                     enqueue);
 }
 
-static exofwd_status run_forward(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers,
-                                 void* spectra, double* lnL, int32_t* status, void* hip_stream, void* dtau_out) {
+static exofwd_status run_forward(exofwd_ctx* c, const Work& w, int32_t B, const double* params,
+                                 const int32_t* n_layers, void* spectra, double* lnL, int32_t* status,
+                                 void* hip_stream, void* dtau_out) {
   exofwd_status s = EXOFWD_OK;
   hipStream_t st = (hipStream_t)hip_stream;
   const bool fp64 = c->precision == EXOFWD_PREC_FP64;
   // with the cloudy/clear mixing the kernels run 2B virtual samples into the internal
   // spectra; the likelihood kernel mixes each pair into the caller's spectrum
   const int Bv = c->m.has_fcld ? 2 * B : B;
-  void* spec = (spectra && !c->m.has_fcld) ? spectra : c->w.spec;
+  void* spec = (spectra && !c->m.has_fcld) ? spectra : w.spec;
   prof_begin(c, "profile", st);
-  launch_profile(c->m, c->w, Bv, params, n_layers, fp64, st);
+  launch_profile(c->m, w, Bv, params, n_layers, fp64, st);
   prof_end(c, st);
   if ((s = check_hip(c, hipGetLastError(), "profile launch"))) return s;
   if (c->m.mode == kTransmission) {
     prof_begin(c, "trans_fwd", st);
-    launch_trans_fwd(c->m, c->w, c->tb, Bv, spec, fp64, st, (float*)dtau_out);
+    launch_trans_fwd(c->m, w, c->tb, Bv, spec, fp64, st, (float*)dtau_out);
   } else {
     prof_begin(c, "emis_fwd", st);
-    launch_emission(c->m, c->w, c->tb, Bv, spec, fp64, st, dtau_out);
+    launch_emission(c->m, w, c->tb, Bv, spec, fp64, st, dtau_out);
   }
   prof_end(c, st);
   if ((s = check_hip(c, hipGetLastError(), "spectrum launch"))) return s;
   prof_begin(c, "loglike", st);
-  launch_loglike(c->m, c->w, B, params, spec, c->m.has_fcld ? spectra : nullptr, fp64, c->d_lo, c->d_hi, c->d_y,
+  launch_loglike(c->m, w, B, params, spec, c->m.has_fcld ? spectra : nullptr, fp64, c->d_lo, c->d_hi, c->d_y,
                  c->d_yerr, c->m.has_offset ? c->d_mask : nullptr, lnL, status, st);
   prof_end(c, st);
   return check_hip(c, hipGetLastError(), "loglike launch");
+}
+
+extern "C++" {
+// Per-call workspace of a forward call for B samples laid out from `base` in
+// 256-byte aligned pieces; returns its size in bytes.  With base == nullptr it only
+// sizes the layout.  The tables and the bin map stay the context's own.
+static size_t carve_forward_work(const exofwd_ctx* c, int B, bool internal_spec, unsigned char* base, Work& w) {
+  const Model& m = c->m;
+  const bool fp64 = c->precision == EXOFWD_PREC_FP64, trans = m.mode == kTransmission;
+  const size_t Bv = (size_t)(m.has_fcld ? 2 * B : B), Lp = (size_t)m.L_pad, rs = fp64 ? 8 : 4;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> unsigned char* {
+    unsigned char* p = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  w = Work{};
+  w.status = (int32_t*)take(4 * Bv);
+  w.nlay = (int32_t*)take(4 * Bv);
+  w.t_lay = (double*)take(8 * Bv * Lp);
+  w.t_lev = (double*)take(8 * Bv * (Lp + 1));
+  w.r_lev = (double*)take(8 * Bv * (Lp + 1));
+  w.core = (double*)take(8 * Bv);
+  w.cloud = (double*)take(8 * Bv * kCloudSpec);
+  if (m.cloud_ng && !fp64) w.cloud_q = (float*)take(4 * Bv * (1 + kCloudSpec) * (size_t)m.n_nu_pad);
+  w.cells = (int32_t*)take(4 * Bv * Lp);
+  if (!fp64 && !trans) w.lsg = (int32_t*)take(4 * Bv * (Lp + 1));
+  if (trans && !fp64) w.front = (int32_t*)take(4 * Bv * (size_t)m.n_tiles);
+  w.rec = take(rs * Bv * Lp * (size_t)rec_len(m.S));
+  w.area = take(rs * Bv * Lp);
+  if (trans && fp64) w.pm64 = (double*)take(8 * Bv * Lp * Lp);
+  if (trans && !fp64) w.pfrag = (uint16_t*)take(2 * Bv * 2 * (Lp / 32) * (Lp / 16) * 512);
+  if (internal_spec) w.spec = take(rs * Bv * (size_t)m.n_nu);
+  w.dm = (double*)take(8 * Bv * (size_t)m.K);
+  w.lnl_tmp = (double*)take(8 * Bv);
+  w.mdot = (double*)take(8 * Bv);
+  if (m.has_fcld) w.fbar = (double*)take(8 * Bv);
+  w.bin_of = c->w.bin_of;
+  w.inv_cnt = c->w.inv_cnt;
+  return off;
+}
+}  // extern "C++"
+
+exofwd_status exofwd_forward_noalloc(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers,
+                                     void* spectra, double* lnL, int32_t* status, void* hip_stream) {
+  exofwd_status s = check_call(c, B, params);
+  if (s) return s;
+  unsigned char* base = static_cast<unsigned char*>(scratch_address(c->device));
+  if (!base) return fail(c, EXOFWD_ERR_DEVICE, "the static scratch array has no device address on this device");
+  const bool internal_spec = !spectra || c->m.has_fcld;
+  Work w;
+  const size_t need = carve_forward_work(c, B, internal_spec, nullptr, w);
+  if (need > (size_t)EXOFWD_NOALLOC_SCRATCH_BYTES)
+    return fail(c, EXOFWD_ERR_SHAPE, "exofwd_forward_noalloc: " + std::to_string(B) + " samples need " +
+                                         std::to_string(need) + " bytes of scratch, more than the static array's " +
+                                         std::to_string((size_t)EXOFWD_NOALLOC_SCRATCH_BYTES));
+  carve_forward_work(c, B, internal_spec, base, w);
+  // no timing events either (creating them may allocate)
+  const bool prof = c->profiling;
+  c->profiling = false;
+  s = run_forward(c, w, B, params, n_layers, spectra, lnL, status, hip_stream, nullptr);
+  c->profiling = prof;
+  return s;
 }
 
 exofwd_status exofwd_grad(exofwd_ctx* c, int32_t B, const double* params, const int32_t* n_layers, void* spectra,
@@ -663,7 +755,7 @@ static exofwd_status run_grad(exofwd_ctx* c, int32_t B, const double* params, co
   // the reverse passes read the forward's layer optical depths (not the FP64 transmission one)
   void* dtau_out = c->precision == EXOFWD_PREC_MIXED ? (void*)c->aw.dtau
                                                      : (c->m.mode == kEmission ? (void*)c->aw.dtau64 : nullptr);
-  if ((s = run_forward(c, B, params, n_layers, spectra, lnL, status, hip_stream, dtau_out))) return s;
+  if ((s = run_forward(c, c->w, B, params, n_layers, spectra, lnL, status, hip_stream, dtau_out))) return s;
   hipStream_t st = (hipStream_t)hip_stream;
   const bool fp64 = c->precision == EXOFWD_PREC_FP64;
   const int Bv = c->m.has_fcld ? 2 * B : B;
@@ -853,7 +945,7 @@ exofwd_status exofwd_autotune(exofwd_ctx* c, int32_t B, const double* params, co
   c->use_graphs = false;
   auto step = [&]() {
     return grad ? run_grad(c, B, th, n_layers, nullptr, d_lnl, d_g, d_st, st)
-                : run_forward(c, B, th, n_layers, nullptr, d_lnl, d_st, st, nullptr);
+                : run_forward(c, c->w, B, th, n_layers, nullptr, d_lnl, d_st, st, nullptr);
   };
   auto time_once = [&](const int32_t* t) -> double {
     if (exofwd_set_tuning(c, t) != EXOFWD_OK) return 1e30;

@@ -328,8 +328,9 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
     const size_t plane = (size_t)MB * KB * 512;
     uint16_t* fh = w.pfrag + (size_t)b * 2 * plane;
     uint16_t* fl = fh + plane;
-    uint16_t* th_ = w.ptfrag + (size_t)b * 2 * plane;
-    uint16_t* tl_ = th_ + plane;
+    // the transposed fragments serve only the adjoint; a forward-only workspace has none
+    uint16_t* th_ = w.ptfrag ? w.ptfrag + (size_t)b * 2 * plane : nullptr;
+    uint16_t* tl_ = th_ ? th_ + plane : nullptr;
     for (int e = tid; e < MB * KB * 64; e += kBlock) {
       const int lane = e & 63, kb = (e >> 6) % KB, mi = (e >> 6) / KB;
       const int row = 32 * mi + (lane & 31);
@@ -349,9 +350,12 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
       for (int j = 0; j < 8; ++j) {
         fh[off + j] = hv[j];
         fl[off + j] = lv[j];
-        th_[off + j] = thv[j];
-        tl_[off + j] = tlv[j];
       }
+      if (th_)
+        for (int j = 0; j < 8; ++j) {
+          th_[off + j] = thv[j];
+          tl_[off + j] = tlv[j];
+        }
     }
   }
 }
