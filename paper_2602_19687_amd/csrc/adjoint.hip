@@ -274,7 +274,7 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
             const int j = 4 * qd + r;
             const int row = 32 * mi + 8 * qd + 4 * h + r;
             const float e = exp2_fast(-1.4426950408889634f * acc[j]);
-            abar_acc[q][j] = fmaf(dbar, 1.0f - e, abar_acc[q][j]);
+            abar_acc[q][j] = fmaf(dbar, one_minus_exp(acc[j], e), abar_acc[q][j]);
             tv[r] = dbar * s_area[row] * e;
           }
           *reinterpret_cast<uint4*>(s_tt + col * ld + 32 * mi + 8 * qd + 4 * h) =

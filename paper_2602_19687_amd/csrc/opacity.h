@@ -17,6 +17,13 @@ typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
 __device__ inline float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
+// 1 - e^-tau given e = e^-tau: below tau = 1/64, where 1 - e keeps too few digits
+// of a thin chord's absorption in FP32, the series tau (1 - tau/2 + tau^2/6)
+// (truncation tau^3/24 relative, under 2e-7)
+__device__ inline float one_minus_exp(float tau, float e) {
+  return tau < 0.015625f ? tau * (1.0f - tau * (0.5f - tau * (1.0f / 6.0f))) : 1.0f - e;
+}
+
 // Wave-uniform data of one (sample, layer).
 template <int S>
 struct LayerCoef {

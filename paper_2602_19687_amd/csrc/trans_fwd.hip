@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int row = 32 * mi + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
-      dsum = fmaf(s_area[row], 1.0f - exp2_fast(-1.4426950408889634f * acc[j]), dsum);
+      dsum = fmaf(s_area[row], one_minus_exp(acc[j], exp2_fast(-1.4426950408889634f * acc[j])), dsum);
       live |= !(acc[j] > kOpaqueTau);
     }
     // the reverse pass skips row blocks whose chords are all opaque across the tile

@@ -217,3 +217,68 @@ def test_fcld_one_is_the_cloudy_model():
     assert torch.equal(spa, spb) and torch.equal(la, lb) and torch.equal(sa, sb)
     ga, gb = ga.cpu().numpy(), gb.cpu().numpy()
     np.testing.assert_allclose(np.delete(ga, k, axis=1), gb, rtol=1e-12, atol=0.0)
+
+
+def cap_wl(batch, n_nu, step, n_bins=30):
+    """The fitted Q_ext with the mid-infrared feature, its amplitude drawn in
+    [2, 3.5] and small particles (r_eff 0.03-0.1 um, where the feature's window
+    is open), so that fit + window x feature exceeds Q_max = 2 around lambda0."""
+    wl = cloud_wl(0, 1, batch=batch, n_nu=n_nu, step=step, n_bins=n_bins)
+    names = wl["param_names"]
+    rng = np.random.default_rng(4242)
+    p = wl["params"].copy()
+    p[:, names.index("feature_A")] = rng.uniform(2.0, 3.5, batch)
+    p[:, names.index("log10_r_eff_um")] = rng.uniform(-1.5, -1.0, batch)
+    p[:, names.index("log10_feature_width_um")] = rng.uniform(-0.7, -0.3, batch)
+    p[:, names.index("log10_q")] = rng.uniform(-5.0, -4.0, batch)
+    wl["params"] = p
+    return wl
+
+
+def _capped_points(wl, th):
+    """Wavenumbers where the uncapped efficiency, fit + window x feature, is at or above Q_max."""
+    cp = oracle.split_params(wl, th)["log10_pc"]
+    q, r = oracle.extinction_efficiency(dict(wl, cloud_qext=oracle.QEXT_FIT), cp, wl["nu"])
+    x = 2.0 * np.pi * r * wl["nu"]
+    q = q + np.exp(-x / oracle.X0_FEATURE) * oracle.feature_efficiency(cp["feat"], 1.0e4 / wl["nu"])
+    return int(np.sum(q >= oracle.Q_MAX))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_cloud_q_max_cap_forward(prec):
+    """Eq. 27's cap is reached: spectra and lnL of both precisions against the oracle
+    at samples where some wavenumbers are capped."""
+    wl = cap_wl(batch=6, n_nu=1000, step=30)
+    capped = [_capped_points(wl, th) for th in wl["params"]]
+    print(f"[gpu] cloud cap forward {prec}: capped points per sample {capped}", flush=True)
+    assert sum(c > 0 for c in capped) >= 4
+    fm = _model(wl, prec, 6)
+    spec, lnl, st = fm.forward(torch.tensor(wl["params"], device="cuda"))
+    spec, lnl, st = spec.double().cpu().numpy(), lnl.cpu().numpy(), st.cpu().numpy()
+    fm.close()
+    for b, ref in enumerate(oracle_forward("cap", wl)):
+        assert st[b] == ref["status"] == 0
+        err = rel_err(spec[b], ref["spectrum"])
+        assert err < SPEC_TOL[prec], (b, err)
+        assert abs(lnl[b] - ref["lnL"]) <= SPEC_TOL[prec] * abs(ref["lnL"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_cloud_q_max_cap_grad(prec):
+    """Gradients where the cap is active (every Q_ext derivative is zero at capped
+    wavenumbers) against the oracle's complex step."""
+    wl = cap_wl(batch=3, n_nu=600, step=50)
+    capped = [_capped_points(wl, th) for th in wl["params"]]
+    print(f"[gpu] cloud cap grad {prec}: capped points per sample {capped}", flush=True)
+    assert all(c > 0 for c in capped)
+    fm = _model(wl, prec, 3)
+    lnl, g, st, _ = fm.grad(torch.tensor(wl["params"], device="cuda"))
+    g, st = g.cpu().numpy(), st.cpu().numpy()
+    fm.close()
+    tol = 1e-5 if prec == "fp64" else GRAD_TOL
+    worst = 0.0
+    for b in range(3):
+        assert st[b] == 0
+        worst = max(worst, grad_err(g[b], oracle.grad_complex_step(wl, wl["params"][b])))
+    print(f"cloud cap grad {prec}: max err {worst:.3e}")
+    assert worst < tol

@@ -292,3 +292,32 @@ def test_emission_full_size_grad_sampled():
     print(f"emission full size sample {b}: grad err {e:.3e}")
     assert st[b] == 0 and e < TOL["mixed"]
     assert np.all(np.isfinite(g[st == 0]))
+
+
+def test_ns_size_grad_sampled():
+    """The headline batch as the benchmark times it: the JWST-like transmission
+    workload at B = 1024 (30000 wavenumbers, 100 layers, 12 parameters) with the
+    launch choices [tiles fastest, 128 x 4 reverse shape, 4096 reverse items,
+    16 layer-sum tiles] (4 wavenumber chunks per sample).  Four samples spread
+    over the batch against the oracle: spectra, lnL and the gradient within 1e-3."""
+    from paper_2602_19687_amd import ForwardModel
+    wl = synth.workload(1, batch=1024)
+    print("[gpu] NS-size gradient B=1024", flush=True)
+    fm = ForwardModel(wl, precision="mixed", batch_max=1024)
+    fm.set_tuning([1, 0, 4096, 16])
+    th = torch.tensor(wl["params"], dtype=torch.float64, device="cuda")
+    lnl, g, st, spec = fm.grad(th, want_spectra=True)
+    torch.cuda.synchronize()
+    lnl, g, st, spec = lnl.cpu().numpy(), g.cpu().numpy(), st.cpu().numpy(), spec.double().cpu().numpy()
+    fm.close()
+    worst = [0.0, 0.0, 0.0]
+    for b in (0, 341, 682, 1023):
+        ref = oracle.forward(wl, wl["params"][b])
+        assert st[b] == ref["status"] == 0
+        gref = oracle.grad_complex_step(wl, wl["params"][b])
+        es = float(np.max(np.abs(spec[b] - ref["spectrum"]) / np.abs(ref["spectrum"])))
+        el = abs(lnl[b] - ref["lnL"]) / abs(ref["lnL"])
+        eg = grad_err(g[b], gref)
+        print(f"NS b={b}: spectrum {es:.2e} lnL {el:.2e} grad {eg:.2e}", flush=True)
+        worst = [max(worst[0], es), max(worst[1], el), max(worst[2], eg)]
+    assert worst[0] < 1e-3 and worst[1] < 1e-3 and worst[2] < 1e-3, worst

@@ -88,25 +88,31 @@ def test_autotune_and_cache(case, tmp_path):
     fm2.close()
 
 
+@pytest.mark.parametrize("ragged", [False, True], ids=["uniform", "ragged"])
 @pytest.mark.parametrize("kind", ["forward", "grad"])
-def test_graph_replays_match_eager(case, kind):
+def test_graph_replays_match_eager(case, kind, ragged):
+    """Replays equal eager calls bit for bit; with ragged layer counts each replay
+    reads new per-sample counts (2-100) from the same buffer, so the captured
+    launches serve any mix of layer grids."""
     wl, _ = case
     rng = np.random.default_rng(7)
     thetas = [wl["params"] * (1.0 + 1e-3 * rng.standard_normal(wl["params"].shape)) for _ in range(3)]
     thetas = [np.where(np.abs(t) > 0, t, 0.0) for t in thetas]
+    layers = [rng.integers(2, wl["n_layers"] + 1, size=len(wl["params"])).astype(np.int32) if ragged else None
+              for _ in range(3)]
     eager = _model(wl)
     graph = _model(wl)
     graph.set_graphs(True)
-    print(f"[gpu] graph replay {kind}", flush=True)
+    print(f"[gpu] graph replay {kind} ragged={ragged}", flush=True)
     for rep in range(3):
-        for th_np in thetas:
+        for th_np, nl in zip(thetas, layers):
             th = torch.tensor(th_np, device="cuda")
             if kind == "forward":
-                a = eager.forward(th)
-                b = graph.forward(th)
+                a = eager.forward(th, n_layers=nl)
+                b = graph.forward(th, n_layers=nl)
             else:
-                a = eager.grad(th, want_spectra=True)
-                b = graph.grad(th, want_spectra=True)
+                a = eager.grad(th, n_layers=nl, want_spectra=True)
+                b = graph.grad(th, n_layers=nl, want_spectra=True)
             # eager work and a synchronisation between replays
             junk = torch.randn(1 << 20, device="cuda").sum()
             torch.cuda.synchronize()
