@@ -28,3 +28,4 @@ from .model import (  # noqa: F401
     feature_efficiency, extinction_efficiency, nongrey_cloud_dtau,
 )
 from .grad import grad_complex_step, grad_central_fd  # noqa: F401
+from . import ck  # noqa: F401

@@ -689,9 +689,19 @@ def forward(wl, theta, n_layers=None, tables=None, want_internals=False):
                           constant_g=wl.get("constant_g", False))
     if not ok:
         return dict(bad, status=S_UNBOUND)
-    dtau = layer_optical_depth(wl, t_lay, p_lev, p_lay, r_lev, x, x_h2, x_he, mu,
-                               ps["log10_pc"], tables=tables)
-    if wl["mode"] == 0:
+    if wl.get("ck", False):
+        # correlated-k tables: the spectrum is per bin, the native points of the binning
+        from . import ck
+        internals = dict(t_lay=t_lay, t_lev=t_lev, r_lev=r_lev, x=x, x_h2=x_h2, x_he=x_he, mu=mu,
+                         p_lev=p_lev, p_lay=p_lay, r_ref=r_ref)
+        spec = ck.spectrum(wl, internals, ps["log10_pc"])
+        dtau = None
+    else:
+        dtau = layer_optical_depth(wl, t_lay, p_lev, p_lay, r_lev, x, x_h2, x_he, mu,
+                                   ps["log10_pc"], tables=tables)
+    if wl.get("ck", False):
+        pass
+    elif wl["mode"] == 0:
         pm = path_matrix(r_lev)
         spec = transit_depth(pm, dtau, r_lev, wl["r_s"])
         if wl.get("fcld", False):

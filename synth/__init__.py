@@ -24,6 +24,11 @@ Configurations (ids 0-6); config 1 at B = 1024 is the headline transmission batc
 * 5 -- the setup of 1 with a non-grey cloud (power-law condensate, fitted Q_ext
        with the mid-infrared feature).
 * 6 -- the setup of 1 with a partly cloudy limb (non-grey slab cloud, cloudy fraction).
+* 7 -- correlated-k transmission: the species of 1 as k-tables on R = 1000 bins
+       (0.6-5.3 um, 2178 bins) with 8 g-points, mixed by random overlap.
+* 8 -- correlated-k emission: the species of 2 as k-tables on R = 1000 bins
+       (1-12 um, 2485 bins) with 8 g-points, mixed by random overlap with
+       resorting and rebinning.
 
 Every random stream is ``numpy.random.default_rng([19687, cid, stream])``.
 """
@@ -153,6 +158,72 @@ def ln_lambda_bins(nu, n_bins):
 
 
 # ----------------------------------------------------------------------------
+# correlated-k tables (the same line lists, summarised per spectral bin)
+def ck_bin_edges(nu_min: float, nu_max: float, resolution: float) -> np.ndarray:
+    """Bin edges uniform in ln(nu) with nu/dnu = resolution: [n_bins + 1] ascending."""
+    n = int(round(np.log(nu_max / nu_min) * resolution))
+    return np.exp(np.linspace(np.log(nu_min), np.log(nu_max), n + 1))
+
+
+def ck_g_quadrature(n_lo: int = 4, n_hi: int = 4, g_split: float = 0.9):
+    """g-points and weights on [0, 1]: Gauss-Legendre rules of n_lo points on
+    [0, g_split] and n_hi points on [g_split, 1] (the strong-absorption tail
+    gets its own points).  Weights sum to 1; nodes ascend."""
+    x1, w1 = np.polynomial.legendre.leggauss(n_lo)
+    x2, w2 = np.polynomial.legendre.leggauss(n_hi)
+    g = np.concatenate([0.5 * g_split * (x1 + 1.0), g_split + 0.5 * (1.0 - g_split) * (x2 + 1.0)])
+    w = np.concatenate([0.5 * g_split * w1, 0.5 * (1.0 - g_split) * w2])
+    return g, w
+
+
+def ck_sub_grid(edges: np.ndarray, n_sub: int) -> np.ndarray:
+    """n_sub midpoints of equal sub-intervals in every bin: [n_bins, n_sub]."""
+    lo, hi = edges[:-1], edges[1:]
+    f = (np.arange(n_sub) + 0.5) / n_sub
+    return lo[:, None] + (hi - lo)[:, None] * f[None, :]
+
+
+def lorentz_sigma_nonuniform(nu, gamma, centres, strengths, cutoff=25.0, continuum=1.0e-24):
+    """sigma(nu) [cm^2] at arbitrary ascending nu for one Lorentz half width
+    gamma (the line shape of ``lorentz_log10_xsec``, same cutoff and continuum)."""
+    lo = np.searchsorted(nu, centres - cutoff, side="left")
+    hi = np.searchsorted(nu, centres + cutoff, side="right")
+    cnt = hi - lo
+    tot = int(cnt.sum())
+    start = np.repeat(lo, cnt)
+    offs = np.arange(tot) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+    idx = start + offs
+    line = np.repeat(np.arange(len(centres)), cnt)
+    d2 = (nu[idx] - centres[line]) ** 2
+    prof = strengths[line] * (gamma / np.pi) / (d2 + gamma * gamma)
+    return continuum + np.bincount(idx, weights=prof, minlength=len(nu))
+
+
+def ck_log10_table(sub_nu, g_nodes, t_grid, logp_grid, centres, strengths, gamma0=0.07):
+    """log10 k(g) [cm^2] per (T, log10 p[bar], bin, g-point) from the sub-grid
+    cross sections: within each bin the n_sub values are sorted ascending (the
+    k-distribution as a function of g, each value standing for a sub-interval of
+    width 1/n_sub centred at (i + 1/2)/n_sub) and read at the g-nodes by linear
+    interpolation (held constant outside the first and last centres)."""
+    n_bins, n_sub = sub_nu.shape
+    flat = sub_nu.ravel()
+    gc = (np.arange(n_sub) + 0.5) / n_sub
+    out = np.empty((len(t_grid), len(logp_grid), n_bins, len(g_nodes)))
+    for it, t in enumerate(t_grid):
+        for ip, lp in enumerate(logp_grid):
+            gam = gamma0 * (10.0 ** lp) * (t / 296.0) ** -0.5
+            sig = np.sort(lorentz_sigma_nonuniform(flat, gam, centres, strengths).reshape(n_bins, n_sub), axis=1)
+            k = np.empty((n_bins, len(g_nodes)))
+            for n, gn in enumerate(g_nodes):
+                pos = np.clip(gn * n_sub - 0.5, 0.0, n_sub - 1.0)
+                i0 = np.minimum(np.floor(pos).astype(int), n_sub - 2)
+                fr = pos - i0
+                k[:, n] = (1.0 - fr) * sig[:, i0] + fr * sig[:, i0 + 1]
+            out[it, ip] = np.log10(k)
+    return out
+
+
+# ----------------------------------------------------------------------------
 # configuration descriptions
 _BASE = dict(
     p_ref_bar=10.0,          # reference pressure of the altitude grid
@@ -216,10 +287,29 @@ CONFIGS = {
             t_grid=np.linspace(300.0, 3500.0, 20), logp_grid=np.linspace(-7.0, 2.0, 20),
             n_lines=2000, cia=True, rayleigh=True, cloud=True, scale=True, offset=True,
             mu_fixed=0.0, n_bins=400, batch=128, cloud_model=1, cloud_profile=1, cloud_qext=0, fcld=True),
+    # correlated-k transmission: the six species of 1 (same line lists) as k-tables on
+    # R = 1000 bins of 16 sub-points, 8 g-points; random overlap of the species
+    # (ck_mix 1: product of the species' transmission functions; 0: RORR)
+    7: dict(mode=MODE_TRANSMISSION, tp=TP_GUILLOT3, n_layers=100, p_bot=100.0, p_top=1.0e-7,
+            n_species=6, nu_min=1.0e4 / 5.3, nu_max=1.0e4 / 0.6, ck_resolution=1000.0, ck_sub=16,
+            t_grid=np.linspace(300.0, 3500.0, 20), logp_grid=np.linspace(-7.0, 2.0, 20),
+            n_lines=2000, cia=True, rayleigh=True, cloud=True, scale=True, offset=True,
+            mu_fixed=0.0, n_bins=400, batch=256, ck=True, ck_mix=1),
+    # correlated-k emission: the eight species of 2 on R = 1000 bins, mixed by random
+    # overlap with resorting and rebinning
+    8: dict(mode=MODE_EMISSION, tp=TP_PCHIP, n_layers=100, p_bot=100.0, p_top=1.0e-7,
+            n_species=8, nu_min=1.0e4 / 12.0, nu_max=1.0e4 / 1.0, ck_resolution=1000.0, ck_sub=16,
+            t_grid=np.linspace(300.0, 3500.0, 20), logp_grid=np.linspace(-7.0, 2.0, 20),
+            n_lines=2000, cia=True, rayleigh=False, cloud=False, scale=False, offset=False,
+            mu_fixed=0.0, n_bins=400, batch=256, n_knots=5, ck=True, ck_mix=0),
 }
 
-# configs 1, 3, 5 and 6 share tables (same seeds) with the headline batch
-_TABLE_CID = {0: 0, 1: 1, 2: 2, 3: 1, 4: 4, 5: 1, 6: 1}
+CK_MIX_RORR = 0       # random overlap with resorting and rebinning, layer by layer
+CK_MIX_PRODUCT = 1    # transmission: product of the species' chord transmission functions
+
+# configs 1, 3, 5 and 6 share tables (same seeds) with the headline batch; the
+# correlated-k configs summarise the line lists of 1 and 2
+_TABLE_CID = {0: 0, 1: 1, 2: 2, 3: 1, 4: 4, 5: 1, 6: 1, 7: 1, 8: 2}
 
 
 def param_names(cfg) -> list:
@@ -310,6 +400,27 @@ def draw_layers(cid: int, batch: int) -> np.ndarray | None:
     return _rng(cid, STREAM_LAYERS).integers(lo, hi + 1, size=batch).astype(np.int32)
 
 
+@functools.lru_cache(maxsize=2)
+def _ck_tables(cid: int):
+    """Bin centres, k-tables [S][nT][nP][n_bins][G] (log10), g-nodes and weights, CIA at the centres."""
+    cfg = CONFIGS[cid]
+    tcid = _TABLE_CID[cid]
+    lcfg = CONFIGS[tcid]
+    edges = ck_bin_edges(cfg["nu_min"], cfg["nu_max"], cfg["ck_resolution"])
+    centres = np.sqrt(edges[:-1] * edges[1:])
+    sub = ck_sub_grid(edges, cfg["ck_sub"])
+    g_nodes, g_w = ck_g_quadrature()
+    xs = np.empty((cfg["n_species"], len(cfg["t_grid"]), len(cfg["logp_grid"]), len(centres), len(g_nodes)))
+    for s in range(cfg["n_species"]):
+        c, st = line_list(tcid, s, lcfg["n_lines"], lcfg["nu_min"], lcfg["nu_max"])
+        xs[s] = ck_log10_table(sub, g_nodes, cfg["t_grid"], cfg["logp_grid"], c, st)
+    tc = np.linspace(300.0, 3500.0, 20)
+    cia = np.stack([cia_log10(tcid, p, centres, tc) for p in range(2)]) if cfg["cia"] else None
+    for a in (centres, xs, tc, g_nodes, g_w, edges) + ((cia,) if cia is not None else ()):
+        a.setflags(write=False)
+    return centres, xs, tc, cia, g_nodes, g_w, edges
+
+
 @functools.lru_cache(maxsize=4)
 def _tables(tcid: int):
     cfg = CONFIGS[tcid]
@@ -358,7 +469,12 @@ def workload(cid: int, batch: int | None = None, require_obs: bool = True) -> di
     Units are cgs except where a key says otherwise (pressures in bar).
     """
     cfg = CONFIGS[cid]
-    nu, xs, tc, cia = _tables(_TABLE_CID[cid])
+    ck = {}
+    if cfg.get("ck", False):
+        nu, xs, tc, cia, g_nodes, g_w, edges = _ck_tables(cid)
+        ck = dict(ck_g=g_nodes, ck_w=g_w, ck_edges=edges, n_nu=len(nu))
+    else:
+        nu, xs, tc, cia = _tables(_TABLE_CID[cid])
     lo, hi = ln_lambda_bins(nu, cfg["n_bins"]) if cid != 0 else _uniform_bins(len(nu), cfg["n_bins"])
     b = cfg["batch"] if batch is None else int(batch)
     wl = dict(_BASE)
@@ -373,8 +489,9 @@ def workload(cid: int, batch: int | None = None, require_obs: bool = True) -> di
         else np.zeros(cfg["n_bins"], np.uint8),
         params=draw_params(cid, b), n_layers_per_sample=draw_layers(cid, b),
         param_names=param_names(cfg), param_bounds=param_bounds(cfg),
-        n_knots=cfg.get("n_knots", 0),
+        n_knots=cfg.get("n_knots", 0), ck=bool(cfg.get("ck", False)), ck_mix=int(cfg.get("ck_mix", 0)),
     )
+    wl.update(ck)
     y = load_obs(cid, cfg["n_bins"])
     if y is None:
         if require_obs:
