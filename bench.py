@@ -38,7 +38,7 @@ def algorithmic_bytes_per_sample(L, S, n_nu, b_tab, b_out):
     return (4 * L * S * n_nu + 4 * L * n_nu) * b_tab + 2 * n_nu * 4 + n_nu * b_out
 
 
-def kernel_model(kernel, Ls, S, n_nu, n_mu=4):
+def kernel_model(kernel, Ls, S, n_nu, n_mu=4, ck_mix=0):
     """Roofline model of one launch of a hot kernel over samples with layer
     counts Ls, S sources and n_nu wavenumbers: (bound, algorithmic amount, peak, unit).
 
@@ -65,6 +65,21 @@ def kernel_model(kernel, Ls, S, n_nu, n_mu=4):
         return "alu", (11 * S + 14 + 5 + 12 * n_mu) * elems, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
     if kernel == "trans_adj":
         return "mfma", 3 * 3 * int((Ls * (Ls + 1) // 2).sum()) * 2 * n_nu, BF16_MFMA_PEAK_TFLOPS, "TFLOP/s"
+    if kernel == "ck_mix":
+        # per (sample, layer, bin): S x 8 interpolations (4 FMA + add + exp2 = 10), then S - 1
+        # random-overlap merges of 64 pairs: pair sum (1), the 64-key bitonic network
+        # (672 compare-exchanges, min + max), two 64-long running sums (128) and the rebinning
+        # (7 edges x FMA + 8 differences x multiply = 22), and the continuum (11)
+        per_merge = 64 + 672 * 2 + 128 + 22
+        return "alu", int(Ls.sum()) * n_nu * (S * 8 * 10 + (S - 1) * per_merge + 11), FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
+    if kernel == "ck_spectrum":
+        # the chord over the (bin, g-point) columns: L(L+1)/2 FMA per column as three bf16 MFMA products
+        # (RORR: 8 columns per bin; product of transmissions: 64, one per absorber slot and g-point)
+        cols = n_nu * (8 if ck_mix == 0 else 64)
+        return "mfma", 3 * int((Ls * (Ls + 1) // 2).sum()) * 2 * cols, BF16_MFMA_PEAK_TFLOPS, "TFLOP/s"
+    if kernel == "ck_spectrum_emis":
+        # per (layer, bin, g-point): Planck at the level (10) and per angle the sweep step (12)
+        return "alu", int(Ls.sum()) * n_nu * 8 * (10 + 12 * n_mu), FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
     raise ValueError(kernel)
 
 
@@ -161,10 +176,12 @@ def with_bd(wl, cid, on):
     return out
 
 
-def _oracle_init(cid, batch, tp_name=None, bd=False):
+def _oracle_init(cid, batch, tp_name=None, bd=False, ck_mix=None):
     os.environ["OMP_NUM_THREADS"] = "1"
     import synth
     _WL["wl"] = with_bd(with_tp(synth.workload(cid, batch=batch), cid, tp_name), cid, bd)
+    if ck_mix is not None:
+        _WL["wl"] = dict(_WL["wl"], ck_mix=ck_mix)
 
 
 def _oracle_worker(args):
@@ -179,7 +196,7 @@ def _oracle_worker(args):
     return idx, out["spectrum"], out["lnL"], g, time.perf_counter() - t0, t_fwd
 
 
-def cpu_baseline(cid, batch, n_samples, do_grad, tp_name=None, bd=False):
+def cpu_baseline(cid, batch, n_samples, do_grad, tp_name=None, bd=False, ck_mix=None):
     """Time the FP64 oracle, as it stands, on a bounded sample of the workload on
     the host cores: one sample per task, one BLAS thread per worker process;
     throughput = samples / (summed per-sample seconds / workers)."""
@@ -187,7 +204,7 @@ def cpu_baseline(cid, batch, n_samples, do_grad, tp_name=None, bd=False):
     idx = list(range(0, batch, max(1, batch // n_samples)))[:n_samples]
     workers = min(cores, len(idx))
     ctx = mp.get_context("spawn")
-    with ctx.Pool(workers, initializer=_oracle_init, initargs=(cid, batch, tp_name, bd)) as pool:
+    with ctx.Pool(workers, initializer=_oracle_init, initargs=(cid, batch, tp_name, bd, ck_mix)) as pool:
         res = pool.map(_oracle_worker, [(i, do_grad) for i in idx], chunksize=1)
     busy = sum(r[4] for r in res)
     busy_fwd = sum(r[5] for r in res)
@@ -212,11 +229,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=1, choices=(1, 2, 4, 5, 6),
+    ap.add_argument("--config", type=int, default=1, choices=(1, 2, 4, 5, 6, 7, 8),
                     help="1: the JWST-like transmission batch (default); 2: the emission batch (forward); "
                          "4: the high-resolution ragged batch; 5: the transmission batch with a non-grey cloud; "
-                         "6: as 5 with a partly cloudy limb (two spectra per sample)")
-    ap.add_argument("--batch", type=int, default=None, help="default 1024 (configs 1, 2, 5) or 64 (config 4)")
+                         "6: as 5 with a partly cloudy limb (two spectra per sample); 7: correlated-k transmission "
+                         "(forward); 8: correlated-k emission (forward)")
+    ap.add_argument("--batch", type=int, default=None,
+                    help="default 1024 (configs 1, 2, 5, 6), 64 (config 4) or 256 (configs 7, 8)")
+    ap.add_argument("--ck-mix", type=int, default=None, choices=(0, 1),
+                    help="correlated-k transmission mixing: 0 random overlap with resorting and rebinning, "
+                         "1 product of transmission functions (config 7's default)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", type=str, default=None,
                     help="launch choices a,b,c,d to use instead of autotuning (see exofwd_set_tuning)")
@@ -252,12 +274,15 @@ def main():
     from paper_2602_19687_amd import ForwardModel
 
     cid = args.config
-    B = args.batch or (64 if cid == 4 else 1024)
+    B = args.batch or (64 if cid == 4 else 256 if cid in (7, 8) else 1024)
+    ck = cid in (7, 8)
     t_setup = time.perf_counter()
     if args.bd and cid != 2:
         print("--bd applies to the emission batch (--config 2)", file=sys.stderr)
         sys.exit(2)
     wl = with_bd(with_tp(synth.workload(cid, batch=B), cid, args.tp), cid, args.bd)
+    if ck and args.ck_mix is not None:
+        wl = dict(wl, ck_mix=args.ck_mix)
     L_, S, n_nu = wl["n_layers"], wl["n_species"], len(wl["nu"])
     th = torch.tensor(wl["params"], dtype=torch.float64, device="cuda")
     nl_np = wl["n_layers_per_sample"]
@@ -302,8 +327,8 @@ def main():
             out = step()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        kern = {k: fm.kernel_time(k) for k in ("profile", "trans_fwd", "emis_fwd", "loglike", "trans_adj", "emis_adj",
-                                               "layer_sums", "chain")}
+        kern = {k: fm.kernel_time(k) for k in ("profile", "trans_fwd", "emis_fwd", "ck_mix", "ck_spectrum", "loglike",
+                                               "trans_adj", "emis_adj", "layer_sums", "chain")}
         fm.set_profiling(False)
         graph_ms = graph_pct = None
         if not args.no_graphs:
@@ -335,7 +360,7 @@ def main():
 
     # the emission batch is quoted as a forward rate (its FP64 path has no adjoint); its
     # reduced-precision forward+gradient step is timed beside it
-    mixed = run("mixed", args.steps, args.warmup, want_grad=cid != 2)
+    mixed = run("mixed", args.steps, args.warmup, want_grad=cid not in (2, 7, 8))
     print(f"[bench] mixed {mixed['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     emis_grad = emis_grad64 = fwd_only = None
     if cid in (1, 4, 5, 6):
@@ -348,10 +373,24 @@ def main():
         if not args.no_fp64:
             emis_grad64 = run("fp64", 2, 1, want_grad=True)
             print(f"[bench] fp64 forward+grad {emis_grad64['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
-    fp64 = None
+    fp64 = fp64_fwd = None
     if not args.no_fp64 and cid in (1, 2):
         fp64 = run("fp64", max(2, args.steps // 4), 1, want_grad=cid != 2)
         print(f"[bench] fp64 {fp64['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+    if not args.no_fp64 and cid == 1:
+        # the plain FP64 forward model alone, beside the reduced-precision forward alone
+        fp64_fwd = run("fp64", 2, 1, want_grad=False)
+        print(f"[bench] fp64 forward {fp64_fwd['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+    ck_other = None
+    if cid == 7:
+        # the other mixing of the absorbers, timed beside the configured one
+        other = 1 - int(wl["ck_mix"])
+        wl_main = wl
+        wl = dict(wl, ck_mix=other)
+        ck_other = run("mixed", max(2, args.steps // 2), 1, want_grad=False)
+        ck_other["ck_mix"] = other
+        wl = wl_main
+        print(f"[bench] ck mix {other}: {ck_other['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     elif not args.no_fp64 and cid == 4:
         # the FP64 adjoint stops at 128 padded layers: the high-resolution batch is compared
         # with the FP64 path on its forward model (spectra) only
@@ -361,12 +400,18 @@ def main():
     value = B / (mixed["ms_per_step"] / 1e3)
     # dominant kernel of the step by time
     per = {k: v[0] / max(1, v[1]) for k, v in mixed["kernels"].items() if v[1]}
-    hot = ("emis_fwd",) if cid == 2 else ("trans_fwd", "trans_adj", "layer_sums")
+    hot = ("emis_fwd",) if cid == 2 else ("ck_mix", "ck_spectrum") if ck else ("trans_fwd", "trans_adj", "layer_sums")
     dom = max(hot, key=lambda k: per.get(k, 0.0))
     dom_ms = per[dom]
     tag = ("transmission_ns_b1024" if (cid == 1 and B == 1024) else
-           f"emission_c2_b{B}" if cid == 2 else f"transmission_c{cid}_b{B}")
-    bound, amount, peak, unit = kernel_model(dom, Ls, S, n_nu)
+           f"emission_c2_b{B}" if cid == 2 else f"ck_c{cid}_b{B}" if ck else f"transmission_c{cid}_b{B}")
+    ck_mix = int(wl.get("ck_mix", 0))
+
+    def model_of(k):
+        if k == "ck_spectrum" and wl["mode"] == 1:
+            return kernel_model("ck_spectrum_emis", Ls, S, n_nu)
+        return kernel_model(k, Ls, S, n_nu, ck_mix=ck_mix)
+    bound, amount, peak, unit = model_of(dom)
     achieved = amount / (dom_ms / 1e3) / 1e12
     traffic = measured_traffic(dom, tag)
     alg_bytes = sum(algorithmic_bytes_per_sample(int(l), S, n_nu, 2, 4) for l in Ls)
@@ -375,20 +420,27 @@ def main():
                 "kernel": dom, "kernel_ms": round(dom_ms, 4), "flops_per_launch": amount}
     for k in hot:
         if k in per:
-            bk, ak, pk, _ = kernel_model(k, Ls, S, n_nu)
+            bk, ak, pk, _ = model_of(k)
             a = ak / (per[k] / 1e3) / 1e12
             tr = measured_traffic(k, tag)
             roofline.setdefault("kernels", {})[k] = {"bound": bk, "ms": round(per[k], 4), "achieved": round(a, 2),
                                                      "peak": pk, "frac": round(a / pk, 4), "traffic": tr,
                                                      "traffic_gbs": round(tr / (per[k] / 1e3) / 1e9, 1) if tr else None}
-    # table-gather bytes the method needs (the forward pass), against the HBM peak
-    fwd_kernel = "emis_fwd" if cid == 2 else "trans_fwd"
-    if cid == 2:
-        alg_bytes = sum((4 * int(l) * S * n_nu + 4 * int(l) * n_nu) * 2 + n_nu * 4 for l in Ls)
-    hbm_gbs = alg_bytes / (per[fwd_kernel] / 1e3) / 1e9
+    # table-gather bytes the method needs (the forward pass) per launch time: an algorithmic
+    # rate, not HBM traffic (the tables stay in the 256 MB MALL across samples; rocprof's
+    # counters give the HBM bytes, `traffic` above)
+    fwd_kernel = "emis_fwd" if cid == 2 else ("ck_mix" if ck_mix == 0 else "ck_spectrum") if ck else "trans_fwd"
+    if cid == 2:   # FP32 table entries
+        alg_bytes = sum((4 * int(l) * S * n_nu + 4 * int(l) * n_nu) * 4 + n_nu * 4 for l in Ls)
+    elif ck:       # FP32 k-table entries at 8 g-points, CIA at the bin centres
+        alg_bytes = sum((4 * int(l) * S * n_nu * 8 + 4 * int(l) * n_nu) * 4 + n_nu * 4 for l in Ls)
+    gather_gbs = alg_bytes / (per[fwd_kernel] / 1e3) / 1e9
     roofline["table_gather"] = {"bytes_per_launch": alg_bytes, "kernel": fwd_kernel,
-                                "achieved_gbs": round(hbm_gbs, 1), "frac_of_8000_gbs": round(hbm_gbs / HBM_PEAK_GBS, 4),
-                                "copy_peak_gbs": round(copy_gbs, 1), "frac_of_copy_peak": round(hbm_gbs / copy_gbs, 4)}
+                                "algorithmic_gbs": round(gather_gbs, 1),
+                                "algorithmic_over_hbm_peak": round(gather_gbs / HBM_PEAK_GBS, 4),
+                                "copy_peak_gbs": round(copy_gbs, 1),
+                                "note": "table reuse across samples is served from the MALL and L2, so a ratio "
+                                        "above 1 is no HBM figure; the opacity kernels are bound by the VALU"}
 
     if cid == 1:
         workload = ("jwst-like transmission, 6 absorbers, 20x20x30000 FP16 tables, 100 layers, 400 bins, 12 params")
@@ -402,6 +454,15 @@ def main():
         workload = ("jwst-like transmission with a partly cloudy limb (cloudy and clear spectra mixed by f_cld; "
                     "non-grey slab cloud, fitted Q_ext), 6 absorbers, 20x20x30000 FP16 tables, 100 layers, 400 bins, "
                     f"{th.shape[1]} params")
+    elif cid == 7:
+        workload = (f"correlated-k transmission, 6 absorbers, 20x20 k-tables on {n_nu} R=1000 bins x 8 g-points, "
+                    f"100 layers, 400 bins, {th.shape[1]} params, "
+                    + ("random overlap with resorting and rebinning" if ck_mix == 0 else
+                       "product of the absorbers' transmission functions"))
+    elif cid == 8:
+        workload = (f"correlated-k emission, 8 absorbers, 20x20 k-tables on {n_nu} R=1000 bins x 8 g-points, "
+                    f"100 layers, 4 Gauss-Legendre angles, 5-knot PCHIP profile, 400 bins, random overlap with "
+                    f"resorting and rebinning")
     else:
         workload = (f"high-resolution transmission, 4 absorbers, 8x8x400000 FP16 tables, {int(Ls.min())}-{int(Ls.max())} "
                     f"layers per sample, 400 bins, {th.shape[1]} params")
@@ -414,6 +475,7 @@ def main():
         "metric": ("forward+grad spectra/sec at B=1024 (FP32/FP16 vs FP64 plain), max rel err"
                    if mixed["has_grad"] else "forward spectra/sec at B=1024 (FP32/FP16 vs FP64 plain), max rel err")
         if cid == 1 else (f"emission forward spectra/sec at B={B} (FP32 vs FP64 plain)" if cid == 2 else
+                          f"correlated-k forward spectra/sec at B={B} (FP32)" if ck else
                           f"forward+grad spectra/sec, non-grey cloud transmission batch B={B} (FP32/FP16)" if cid == 5
                           else f"forward+grad spectra/sec, partly cloudy transmission batch B={B} (FP32/FP16)"
                           if cid == 6 else f"forward+grad spectra/sec, high-resolution ragged batch B={B} (FP32/FP16)"),
@@ -422,8 +484,11 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": workload, "batch": B, "n_nu": n_nu, "n_layers": L_ if nl_np is None else
                    f"{int(Ls.min())}-{int(Ls.max())} (mean {float(Ls.mean()):.1f})", "n_species": S,
-                   "precision": ("fp32 tables / fp32 opacity / fp32 sweep / fp64 profile+lnL" if cid == 2 else
-                                 "fp16 tables / fp32 opacity / bf16x3 mfma chord / fp64 profile+lnL"),
+                   "precision": ("fp32 tables / fp32 opacity / fp32 sweep, fp64 intensities / fp64 profile+lnL"
+                                 if cid == 2 else
+                                 "fp32 k-tables / fp32 mixing / " + ("fp32 sweep, fp64 intensities" if cid == 8 else
+                                                                     "bf16x3 mfma chord") + " / fp64 profile+lnL"
+                                 if ck else "fp16 tables / fp32 opacity / bf16x3 mfma chord / fp64 profile+lnL"),
                    "launch_choices": mixed["tuning"]},
         "roofline": roofline,
         "kernel_ms_per_step": {k: round(v[0] / max(1, v[1]), 4) for k, v in mixed["kernels"].items() if v[1]},
@@ -450,6 +515,12 @@ def main():
         out["graph_replay"] = {"ms_per_step": round(mixed["graph_ms"], 4),
                                "spectra_per_s": round(B / (mixed["graph_ms"] / 1e3), 1),
                                "event_ms_median_p10_p90": [round(x, 4) for x in mixed["graph_pct"]]}
+    if ck_other is not None:
+        out["ck_other_mixing"] = {"ck_mix": ck_other["ck_mix"],
+                                  "spectra_per_s": round(B / (ck_other["ms_per_step"] / 1e3), 1),
+                                  "ms_per_step": round(ck_other["ms_per_step"], 4),
+                                  "kernel_ms_per_step": {k: round(v[0] / max(1, v[1]), 4)
+                                                         for k, v in ck_other["kernels"].items() if v[1]}}
     if fp64 is not None:
         out["fp64_plain"] = {"spectra_per_s": round(B / (fp64["ms_per_step"] / 1e3), 1),
                              "ms_per_step": round(fp64["ms_per_step"], 3),
@@ -461,8 +532,13 @@ def main():
             out["fp64_plain"]["step"] = "forward only (no FP64 adjoint beyond 128 padded layers)"
         ok = (mixed["status"] == 0) & (fp64["status"] == 0)
         out["max_rel_err_vs_fp64_gpu"] = spec_err(mixed["spec"][ok], fp64["spec"][ok])
-    if not args.no_cpu_baseline and cid == 1:
-        res, dt, cores, busy, busy_fwd = cpu_baseline(cid, B, args.cpu_samples, mixed["has_grad"], args.tp, args.bd)
+    if fp64_fwd is not None and fwd_only is not None:
+        out["fp64_plain"]["forward_only"] = {"spectra_per_s": round(B / (fp64_fwd["ms_per_step"] / 1e3), 1),
+                                             "ms_per_step": round(fp64_fwd["ms_per_step"], 3)}
+        out["speedup_vs_fp64_forward_only"] = round(fp64_fwd["ms_per_step"] / fwd_only["ms_per_step"], 3)
+    if not args.no_cpu_baseline and cid in (1, 7, 8):
+        res, dt, cores, busy, busy_fwd = cpu_baseline(cid, B, args.cpu_samples, mixed["has_grad"], args.tp, args.bd,
+                                                      int(wl["ck_mix"]) if ck else None)
         n = len(res)
         errs, lerrs, gerrs = [], [], []
         for idx, spec, lnl, g in res:

@@ -164,7 +164,26 @@ typedef struct exofwd_config {
   int32_t device;            /* HIP device ordinal */
   int32_t has_bd;            /* emission of an isolated object (Eqs. 46-47); excludes has_scale */
   double bd_distance;        /* its distance [cm] (has_bd) */
+  /* Correlated-k tables (Section "Gas phase opacities"): with ck_g > 0, nu holds the
+   * n_nu spectral bin centres (ascending) and log10_xsec is [n_species][n_t][n_p][n_nu][ck_g]:
+   * log10 k at ck_g g-points of each bin's cross-section distribution (ascending in g),
+   * with weights ck_weights[ck_g] (each > 0, summing to 1).  log10_cia is given at the
+   * bin centres.  The spectrum has one value per bin and the bins (bin_lo/bin_hi) group
+   * spectral bins.  ck_g must be 8; MIXED precision only (FP32 table entries); no
+   * gradient (exofwd_grad_supported gives 0), no cloudy/clear mixing, isolated object or
+   * non-grey cloud; the absorbers are mixed by ck_mix. */
+  int32_t ck_g;              /* g-points per bin, 8; 0 = cross-section (opacity-sampling) tables */
+  int32_t ck_mix;            /* EXOFWD_CK_RORR or EXOFWD_CK_PRODUCT */
+  const double* ck_weights;  /* host [ck_g] */
 } exofwd_config;
+
+/* Mixing of the absorbers' k-distributions in a layer: random overlap with resorting
+ * and rebinning (Amundsen et al. 2017; the rebinned k is the mean of the sorted pair
+ * distribution over each g-interval, the absorbers mixed in table order, the grey
+ * continuum added to every g-point).  EXOFWD_CK_PRODUCT (transmission only): random
+ * overlap along each chord, the product of the absorbers' transmission functions, each
+ * absorber keeping its own g-points (the grey continuum a further factor). */
+enum { EXOFWD_CK_RORR = 0, EXOFWD_CK_PRODUCT = 1 };
 
 /* Validate the configuration, upload and encode the tables, allocate the
  * workspace for batch_max samples of n_layers_max layers.  Synchronous.

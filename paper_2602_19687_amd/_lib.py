@@ -12,6 +12,7 @@ TRANSMISSION, EMISSION = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 TP_ISOTHERMAL, TP_GUILLOT3, TP_PCHIP, TP_BARSTOW, TP_MILNE, TP_GUILLOT7 = 0, 1, 2, 3, 4, 5
 S_BAD_VMR, S_UNBOUND, S_NONFINITE, S_BAD_T, S_BAD_LAYERS = 1, 2, 4, 8, 16
+CK_RORR, CK_PRODUCT = 0, 1
 
 _D = C.POINTER(C.c_double)
 _I = C.POINTER(C.c_int32)
@@ -39,6 +40,7 @@ class Config(C.Structure):
         ("offset_mask", _U8),
         ("device", C.c_int32),
         ("has_bd", C.c_int32), ("bd_distance", C.c_double),
+        ("ck_g", C.c_int32), ("ck_mix", C.c_int32), ("ck_weights", _D),
     ]
 
 

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "libexofwd.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["exofwd.hip", "profile.hip", "trans_fwd.hip", "loglike.hip", "emission.hip", "emission_adj.hip",
-           "adjoint.hip"]
+           "adjoint.hip", "ck.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1,0 +1,569 @@
+// Correlated-k path (Section "Gas phase opacities"): per spectral bin, each
+// absorber's k-table holds the cross section at kCkG g-points of the bin's
+// cumulative distribution with quadrature weights w_g (sum 1).  The species are
+// mixed layer by layer by random overlap with resorting and rebinning (RORR,
+// Amundsen et al. 2017): two k-distributions, as layer optical depths, combine on
+// all g-point pairs (sum of the depths, product of the weights); the pairs are
+// sorted and the sorted distribution is averaged over each original g-interval
+// [E_{n-1}, E_n], E_n = w_1 + ... + w_n.  The next absorber is then mixed into the
+// result, in table order.  The grey continuum (CIA, Rayleigh, grey deck at the bin
+// centre) is added to every g-point.  Each g-point's column then goes through the
+// transmission chord (Eq. 44) or the emission sweep (Eq. 45), and the bin's
+// spectrum is the g-weighted sum.
+//
+// k_ck_mix: one wave per (sample, layer) and a run of bins, one bin at a time:
+//   lane s*8 + g interpolates absorber s at g-point g (FP32 table entries relative
+//   to per-(absorber, column) offsets, bilinear in (T, log p), exp2 with the layer
+//   prefactor); a merge puts pair (a, b) on lane 8a + b, sorts the 64 pair sums
+//   across the wave (bitonic, keys = the value's bits above the low six, the pair
+//   index in the low six), forms the running weight and weight x value sums by a
+//   wave prefix scan and reads the rebinned means at the interval edges with a
+//   ballot.  Output: the mixed layer optical depths [B][L_pad][n_bins_pad x 8]
+//   (FP32), read by k_ck_trans (bf16x3 MFMA chord, as the cross-section path) or
+//   k_ck_emis (one lane per (bin, g-point) column sweeping up the layers).
+#include "ck.h"
+#include "emission.h"
+#include "kernels.h"
+#include "opacity.h"
+
+namespace exofwd {
+
+// ascending bitonic sort of one 32-bit key per lane across the wave
+__device__ inline uint32_t wave_sort_u32(uint32_t key, int lane) {
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t other = (uint32_t)__shfl_xor((int)key, j);
+      const bool up = (lane & k) == 0, low = (lane & j) == 0;
+      key = (low == up) ? min(key, other) : max(key, other);
+    }
+  }
+  return key;
+}
+
+template <int S, bool CIA>
+__global__ __launch_bounds__(kBlock) void k_ck_mix(Model m, Work w, Tables tb, int B) {
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int b = blockIdx.z, l = blockIdx.y;
+  const int j0 = (blockIdx.x * (kBlock / 64) + wv) * kCkBinsPerWave;
+  if (j0 >= m.n_nu || w.status[b] || l >= w.nlay[b]) return;
+  const int Lp = m.L_pad;
+  constexpr int RL = rec_len(S);
+  const float* rl = reinterpret_cast<const float*>(w.rec) + ((size_t)b * Lp + l) * RL;
+  const int cl = w.cells[(size_t)b * Lp + l];
+  const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
+  const float wt = rl[0], wp = rl[1], wtc = rl[2], ray = rl[3], deck = rl[4];
+  const float w11 = wt * wp, w10 = wt - w11, w01 = wp - w11, w00 = 1.0f - wt - wp + w11;
+  const size_t npad = (size_t)m.n_nu_pad, ncol = npad * kCkG;
+  const uint32_t row_bytes = (uint32_t)ncol * 4u, tstep = (uint32_t)m.n_p * row_bytes;
+  const __amdgpu_buffer_rsrc_t rh = make_rsrc(tb.h, (size_t)S * m.n_t * m.n_p * ncol * 4);
+  const __amdgpu_buffer_rsrc_t rhc = make_rsrc(CIA ? (const void*)tb.hc : (const void*)tb.h,
+                                               CIA ? (size_t)2 * m.n_tc * npad * 4 : 0);
+  // this lane's absorber and g-point, and its table row
+  const int sl = lane >> 3, gl = lane & 7;
+  const bool live = sl < S;
+  const float lam = live ? rl[kRecFixed + sl] : 0.0f;
+  const uint32_t row = live ? (uint32_t)((sl * m.n_t + it) * m.n_p + ip) * row_bytes : 0u;
+  const float* coff = tb.c + (size_t)(live ? sl : 0) * ncol;
+  // weight of g-point (lane & 7), its reciprocal, and the interval edges E_0..E_6
+  const float wg = tb.ckw[gl], inv_wg = 1.0f / wg;
+  float edge[kCkG - 1];
+#pragma unroll
+  for (int n = 0; n < kCkG - 1; ++n) edge[n] = tb.cke[n];
+  float* out = w.ckmix + ((size_t)b * Lp + l) * ncol;
+
+  for (int t = 0; t < kCkBinsPerWave; ++t) {
+    const int j = j0 + t;
+    if (j >= m.n_nu) break;
+    const uint32_t col = (uint32_t)(j * kCkG + gl);
+    float sp = 0.0f;
+    if (live) {
+      const uint32_t voff = col * 4u;
+      float v = coff[col] + lam;
+      v = fmaf(w00, load_f32(rh, voff, row), v);
+      v = fmaf(w10, load_f32(rh, voff, row + tstep), v);
+      v = fmaf(w01, load_f32(rh, voff, row + row_bytes), v);
+      v = fmaf(w11, load_f32(rh, voff, row + tstep + row_bytes), v);
+      sp = exp2_fast(v);
+    }
+    // the running mixture, g-point (lane & 7) on every lane: absorber 0 to start
+    float mix = __shfl(sp, gl);
+#pragma unroll
+    for (int s = 1; s < S; ++s) {
+      // pair (a, c) = (lane >> 3, lane & 7): mixture point a with absorber s point c
+      const float v = __shfl(mix, sl) + __shfl(sp, 8 * s + gl);
+      // optical depths are >= 0, so the bit patterns order like the values; the low
+      // six bits carry the pair index (pairs within 64 ulp may swap: <4e-6 relative)
+      const uint32_t key = wave_sort_u32((__float_as_uint(v) & ~63u) | (uint32_t)lane, lane);
+      const int idx = (int)(key & 63u);
+      const float vv = __shfl(mix, idx >> 3) + __shfl(sp, 8 * s + (idx & 7));
+      const float ww = __shfl(wg, idx >> 3) * __shfl(wg, idx & 7);
+      // running sums along the sorted order: weight (g at the element's upper end) and weight x value
+      float c = ww, p = ww * vv;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const float c2 = __shfl_up(c, off), p2 = __shfl_up(p, off);
+        if (lane >= off) {
+          c += c2;
+          p += p2;
+        }
+      }
+      const float c_up = __shfl_up(c, 1), p_up = __shfl_up(p, 1);
+      const float c_lo = lane ? c_up : 0.0f;
+      const float p_lo = lane ? p_up : 0.0f;
+      // integral of the sorted distribution up to each interior edge, from the one
+      // element whose g-interval [c_lo, c) holds it
+      float I[kCkG];
+#pragma unroll
+      for (int n = 0; n < kCkG - 1; ++n) {
+        const uint64_t own = __builtin_amdgcn_ballot_w64(c_lo <= edge[n] && edge[n] < c);
+        const int owner = own ? (int)__builtin_ctzll(own) : 63;
+        I[n] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fmaf(edge[n] - c_lo, vv, p_lo)), owner));
+      }
+      I[kCkG - 1] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p), 63));
+      float hi = I[0], lo = 0.0f;
+#pragma unroll
+      for (int n = 1; n < kCkG; ++n)
+        if (gl == n) {
+          hi = I[n];
+          lo = I[n - 1];
+        }
+      mix = (hi - lo) * inv_wg;
+    }
+    // grey continuum at the bin centre: deck, Rayleigh and the two CIA pairs
+    float dc = fmaf(ray, tb.nu4f[j], deck);
+    if (CIA) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const uint32_t rowc = (uint32_t)(p * m.n_tc + itc) * (uint32_t)npad * 4u;
+        const uint32_t vo = (uint32_t)j * 4u;
+        float v = tb.cc[(size_t)p * npad + j] + rl[5 + p];
+        v = fmaf(1.0f - wtc, load_f32(rhc, vo, rowc), v);
+        v = fmaf(wtc, load_f32(rhc, vo, rowc + (uint32_t)npad * 4u), v);
+        dc += exp2_fast(v);
+      }
+    }
+    if (lane < kCkG) out[col] = mix + dc;
+  }
+}
+
+// Transmission: per (sample, 128-column tile) the chord tau = P dtau on MFMA
+// (bf16 hi/lo split of both operands, as the cross-section kernel), the transit
+// depth of every (bin, g-point) column and the g-weighted sum per bin.
+__global__ __launch_bounds__(kBlockT) void k_ck_trans(Model m, Work w, Tables tb, int B, float* __restrict__ spec) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int n_ct = m.n_tiles * kCkG;   // 128-column tiles per sample
+  const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int b = logical / n_ct, tile = logical % n_ct;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int Lp = m.L_pad;
+  const int c0 = tile * kTileNu;          // first column; bins c0/8 .. c0/8 + 15
+  const int j0 = c0 / kCkG;
+  float* out = spec + (size_t)b * m.n_nu;
+  if (w.status[b]) {
+    if (tid < kTileNu / kCkG && j0 + tid < m.n_nu) out[j0 + tid] = __builtin_nanf("");
+    return;
+  }
+  const int L = w.nlay[b];
+  const size_t ncol = (size_t)m.n_nu_pad * kCkG;
+  const int stride = Lp + 8;
+  uint16_t* s_bhi = reinterpret_cast<uint16_t*>(lds);
+  uint16_t* s_blo = s_bhi + kTileNu * stride;
+  float* s_area = reinterpret_cast<float*>(s_blo + kTileNu * stride);
+  float* s_red = s_area + Lp;   // [8][32]
+  const float* area = reinterpret_cast<const float*>(w.area) + (size_t)b * Lp;
+  for (int i = tid; i < Lp; i += kBlockT) s_area[i] = area[i];
+
+  // phase A: the mixed layer optical depths of the tile -> bf16 hi/lo B operand in LDS
+  const float* src = w.ckmix + (size_t)b * Lp * ncol + c0 + 2 * lane;
+  const bool real = (c0 + 2 * lane) / kCkG < m.n_nu;   // columns of padding bins hold nothing
+  const int KBe = (L + 15) >> 4;
+  for (int o = wv; o < 2 * KBe; o += kBlockT / 64) {
+    float e0[8], e1[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int l = 8 * o + q;
+      float2 d = make_float2(0.0f, 0.0f);
+      if (l < L && real) d = *reinterpret_cast<const float2*>(src + (size_t)l * ncol);
+      e0[q] = fminf(d.x, 16384.0f);
+      e1[q] = fminf(d.y, 16384.0f);
+    }
+    uint32_t h0[4], l0[4], h1[4], l1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      split_pair(e0[2 * q], e0[2 * q + 1], h0[q], l0[q]);
+      split_pair(e1[2 * q], e1[2 * q + 1], h1[q], l1[q]);
+    }
+    const int r0 = (2 * lane) * stride + 8 * o, r1 = r0 + stride;
+    *reinterpret_cast<uint4*>(s_bhi + r0) = make_uint4(h0[0], h0[1], h0[2], h0[3]);
+    *reinterpret_cast<uint4*>(s_blo + r0) = make_uint4(l0[0], l0[1], l0[2], l0[3]);
+    *reinterpret_cast<uint4*>(s_bhi + r1) = make_uint4(h1[0], h1[1], h1[2], h1[3]);
+    *reinterpret_cast<uint4*>(s_blo + r1) = make_uint4(l1[0], l1[1], l1[2], l1[3]);
+  }
+  __syncthreads();
+
+  // phase B: tau = P dtau; wave wv owns 32-column block (wv & 3) and half (wv >> 2) of the row blocks
+  const int MBe = (L + 31) >> 5;
+  const int KB = Lp >> 4;
+  const int nb = wv & 3;
+  const size_t plane = (size_t)(Lp >> 5) * KB * 512;
+  const uint16_t* fh = w.pfrag + (size_t)b * 2 * plane;
+  const uint16_t* fl = fh + plane;
+  const int col = 32 * nb + (lane & 31);
+  const int khalf = 8 * (lane >> 5);
+  float dsum = 0.0f;
+  for (int mi = (wv >> 2); mi < MBe; mi += 2) {
+    f32x16 acc = {};
+    for (int kb = 2 * mi; kb < KBe; ++kb) {
+      const size_t fo = ((size_t)(mi * KB + kb) * 64 + lane) * 8;
+      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(fh + fo);
+      const bf16x8 al = *reinterpret_cast<const bf16x8*>(fl + fo);
+      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(s_bhi + col * stride + 16 * kb + khalf);
+      const bf16x8 bl = *reinterpret_cast<const bf16x8*>(s_blo + col * stride + 16 * kb + khalf);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+    }
+    // phase C: annulus-weighted absorption of each column's chords
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int r = 32 * mi + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+      dsum = fmaf(s_area[r], one_minus_exp(acc[q], exp2_fast(-1.4426950408889634f * acc[q])), dsum);
+    }
+  }
+  dsum += __shfl_xor(dsum, 32);
+  if (lane < 32) s_red[wv * 32 + lane] = dsum;
+  __syncthreads();
+  if (tid < kTileNu) {
+    // column tid = bin tid/8, g-point tid%8: weighted, then summed over the bin's eight columns
+    const int h = tid >> 5, c = tid & 31;
+    float v = (float)w.core[b] + s_red[h * 32 + c] + s_red[(h + 4) * 32 + c];
+    v *= tb.ckw[tid & (kCkG - 1)];
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    const int j = j0 + (tid >> 3);
+    if ((tid & (kCkG - 1)) == 0 && j < m.n_nu) out[j] = v;
+  }
+}
+
+// Transmission with random overlap along each chord (the product of the absorbers'
+// transmission functions): columns (bin, absorber slot s < 8, g-point), 64 per bin
+// and two bins per 128-column tile; absorber 0's columns also carry the grey
+// continuum (exact: the chord is linear, so its factor e^-tau_c multiplies absorber
+// 0's g-sum).  Per chord row the absorption of absorber s is
+// A_s = sum_g w_g (1 - e^-tau_s,g), and the absorbers combine as
+// A (+) B = A + B - A B (= 1 - (1 - A)(1 - B), without the cancellation of a thin
+// chord's 1 - product of transmissions); slots s >= S have zero depth (A = 0).
+template <int S, bool CIA>
+__global__ __launch_bounds__(kBlockT) void k_ck_trans_prod(Model m, Work w, Tables tb, int B,
+                                                           float* __restrict__ spec) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int n_ct = (m.n_nu + 1) / 2;   // two bins per tile
+  const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int b = logical / n_ct, tile = logical % n_ct;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int Lp = m.L_pad;
+  const int j0 = 2 * tile;
+  float* out = spec + (size_t)b * m.n_nu;
+  if (w.status[b]) {
+    if (tid < 2 && j0 + tid < m.n_nu) out[j0 + tid] = __builtin_nanf("");
+    return;
+  }
+  const int L = w.nlay[b];
+  const int stride = Lp + 8;
+  uint16_t* s_bhi = reinterpret_cast<uint16_t*>(lds);
+  uint16_t* s_blo = s_bhi + kTileNu * stride;
+  float* s_area = reinterpret_cast<float*>(s_blo + kTileNu * stride);
+  float* s_abs = s_area + Lp;          // [4 column blocks][Lp] absorption of four absorbers per row
+  float* s_red = s_abs + 4 * Lp;       // [8] wave partial sums
+  const float* area = reinterpret_cast<const float*>(w.area) + (size_t)b * Lp;
+  for (int i = tid; i < Lp; i += kBlockT) s_area[i] = area[i];
+  for (int i = tid; i < 4 * Lp; i += kBlockT) s_abs[i] = 0.0f;
+
+  // this lane's two columns: bin jj, absorber slot sl, g-points gl and gl + 1
+  const int c2 = 2 * lane, jj = c2 >> 6, sl = (c2 >> 3) & 7, gl = c2 & 7;
+  const int j = min(j0 + jj, m.n_nu - 1);
+  const bool live = sl < S && j0 + jj < m.n_nu;
+  const size_t npad = (size_t)m.n_nu_pad, ncol = npad * kCkG;
+  const uint32_t row_bytes = (uint32_t)ncol * 4u, tstep = (uint32_t)m.n_p * row_bytes;
+  const __amdgpu_buffer_rsrc_t rh = make_rsrc(tb.h, (size_t)S * m.n_t * m.n_p * ncol * 4);
+  const __amdgpu_buffer_rsrc_t rhc = make_rsrc(CIA ? (const void*)tb.hc : (const void*)tb.h,
+                                               CIA ? (size_t)2 * m.n_tc * npad * 4 : 0);
+  const uint32_t col = (uint32_t)(j * kCkG + gl);
+  const float* coff = tb.c + (size_t)(live ? sl : 0) * ncol + col;
+  const float cof0 = live ? coff[0] : 0.0f, cof1 = live ? coff[1] : 0.0f;
+  const float nu4 = tb.nu4f[j];
+  float cc[2] = {0.0f, 0.0f};
+  if (CIA) {
+    cc[0] = tb.cc[j];
+    cc[1] = tb.cc[npad + j];
+  }
+  constexpr int RL = rec_len(S);
+  const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * RL;
+  const int32_t* cells = w.cells + (size_t)b * Lp;
+
+  // phase A: every layer's optical depth of the tile's columns -> bf16 hi/lo B operand in LDS
+  const int KBe = (L + 15) >> 4;
+  for (int o = wv; o < 2 * KBe; o += kBlockT / 64) {
+    float e0[8], e1[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int l = 8 * o + q;
+      float d0 = 0.0f, d1 = 0.0f;
+      if (l < L && live) {
+        const float* rl = rec + (size_t)l * RL;
+        const int cl = cells[l];
+        const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
+        const float wt = rl[0], wp = rl[1];
+        const float w11 = wt * wp, w10 = wt - w11, w01 = wp - w11, w00 = 1.0f - wt - wp + w11;
+        const uint32_t row = (uint32_t)((sl * m.n_t + it) * m.n_p + ip) * row_bytes;
+        const uint32_t vo = col * 4u;
+        const float lam = rl[kRecFixed + sl];
+        float v0 = cof0 + lam, v1 = cof1 + lam;
+        v0 = fmaf(w00, load_f32(rh, vo, row), v0);
+        v1 = fmaf(w00, load_f32(rh, vo + 4u, row), v1);
+        v0 = fmaf(w10, load_f32(rh, vo, row + tstep), v0);
+        v1 = fmaf(w10, load_f32(rh, vo + 4u, row + tstep), v1);
+        v0 = fmaf(w01, load_f32(rh, vo, row + row_bytes), v0);
+        v1 = fmaf(w01, load_f32(rh, vo + 4u, row + row_bytes), v1);
+        v0 = fmaf(w11, load_f32(rh, vo, row + tstep + row_bytes), v0);
+        v1 = fmaf(w11, load_f32(rh, vo + 4u, row + tstep + row_bytes), v1);
+        d0 = exp2_fast(v0);
+        d1 = exp2_fast(v1);
+        if (sl == 0) {
+          // the grey continuum at the bin centre rides on absorber 0
+          float dc = fmaf(rl[3], nu4, rl[4]);
+          if (CIA) {
+            const float wtc = rl[2];
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+              const uint32_t rowc = (uint32_t)(p * m.n_tc + itc) * (uint32_t)npad * 4u;
+              const uint32_t vj = (uint32_t)j * 4u;
+              float v = cc[p] + rl[5 + p];
+              v = fmaf(1.0f - wtc, load_f32(rhc, vj, rowc), v);
+              v = fmaf(wtc, load_f32(rhc, vj, rowc + (uint32_t)npad * 4u), v);
+              dc += exp2_fast(v);
+            }
+          }
+          d0 += dc;
+          d1 += dc;
+        }
+      }
+      e0[q] = fminf(d0, 16384.0f);
+      e1[q] = fminf(d1, 16384.0f);
+    }
+    uint32_t h0[4], l0[4], h1[4], l1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      split_pair(e0[2 * q], e0[2 * q + 1], h0[q], l0[q]);
+      split_pair(e1[2 * q], e1[2 * q + 1], h1[q], l1[q]);
+    }
+    const int r0 = c2 * stride + 8 * o, r1 = r0 + stride;
+    *reinterpret_cast<uint4*>(s_bhi + r0) = make_uint4(h0[0], h0[1], h0[2], h0[3]);
+    *reinterpret_cast<uint4*>(s_blo + r0) = make_uint4(l0[0], l0[1], l0[2], l0[3]);
+    *reinterpret_cast<uint4*>(s_bhi + r1) = make_uint4(h1[0], h1[1], h1[2], h1[3]);
+    *reinterpret_cast<uint4*>(s_blo + r1) = make_uint4(l1[0], l1[1], l1[2], l1[3]);
+  }
+  __syncthreads();
+
+  // phase B: tau = P dtau; wave wv owns 32-column block (wv & 3) and half (wv >> 2) of the row blocks
+  const int MBe = (L + 31) >> 5;
+  const int KB = Lp >> 4;
+  const int nb = wv & 3;
+  const size_t plane = (size_t)(Lp >> 5) * KB * 512;
+  const uint16_t* fh = w.pfrag + (size_t)b * 2 * plane;
+  const uint16_t* fl = fh + plane;
+  const int ccol = 32 * nb + (lane & 31);
+  const int khalf = 8 * (lane >> 5);
+  const float wg = tb.ckw[lane & 7];
+  for (int mi = (wv >> 2); mi < MBe; mi += 2) {
+    f32x16 acc = {};
+    for (int kb = 2 * mi; kb < KBe; ++kb) {
+      const size_t fo = ((size_t)(mi * KB + kb) * 64 + lane) * 8;
+      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(fh + fo);
+      const bf16x8 al = *reinterpret_cast<const bf16x8*>(fl + fo);
+      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(s_bhi + ccol * stride + 16 * kb + khalf);
+      const bf16x8 bl = *reinterpret_cast<const bf16x8*>(s_blo + ccol * stride + 16 * kb + khalf);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+    }
+    // phase C: per row, the g-weighted absorption of each absorber (8 lanes), then the
+    // four absorbers of this column block combined
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      float a = wg * one_minus_exp(acc[q], exp2_fast(-1.4426950408889634f * acc[q]));
+      a += __shfl_xor(a, 1);
+      a += __shfl_xor(a, 2);
+      a += __shfl_xor(a, 4);
+      float o2 = __shfl_xor(a, 8);
+      a = a + o2 - a * o2;
+      o2 = __shfl_xor(a, 16);
+      a = a + o2 - a * o2;
+      const int r = 32 * mi + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+      if ((lane & 31) == 0) s_abs[nb * Lp + r] = a;
+    }
+  }
+  __syncthreads();
+  // the two column blocks of each bin, annulus-weighted and summed over the rows
+  const int bj = tid >> 8, i = tid & 255;
+  float v = 0.0f;
+  if (i < Lp) {
+    const float a = s_abs[(2 * bj) * Lp + i], c = s_abs[(2 * bj + 1) * Lp + i];
+    v = s_area[i] * (a + c - a * c);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (lane == 0) s_red[wv] = v;
+  __syncthreads();
+  if (tid < 2 && j0 + tid < m.n_nu)
+    out[j0 + tid] = (float)w.core[b] + s_red[4 * tid] + s_red[4 * tid + 1] + s_red[4 * tid + 2] + s_red[4 * tid + 3];
+}
+
+// Emission: one lane per (bin, g-point) column, sweeping up the layers with the
+// linear-in-tau source at the bin centre's Planck intensity (FP64 intensities, as
+// the cross-section kernel), then the g-weighted flux per bin and F_p / F_*.
+__global__ __launch_bounds__(kBlock) void k_ck_emis(Model m, Work w, Tables tb, int B, float* __restrict__ spec) {
+  const int n_ct = m.n_tiles64 * kCkG;   // 64-column tiles per sample
+  const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gw = logical * (kBlock / 64) + wv;
+  const int b = gw / n_ct, tile = gw % n_ct;
+  if (b >= B) return;
+  const int colx = tile * kTile64 + lane, j = colx / kCkG;
+  float* out = spec + (size_t)b * m.n_nu;
+  if (w.status[b]) {
+    if ((lane & (kCkG - 1)) == 0 && j < m.n_nu) out[j] = __builtin_nanf("");
+    return;
+  }
+  const int L = w.nlay[b], Lp = m.L_pad;
+  const size_t ncol = (size_t)m.n_nu_pad * kCkG;
+  const float* dt = w.ckmix + (size_t)b * Lp * ncol + colx;
+  const double* t_lev = w.t_lev + (size_t)b * (Lp + 1);
+  const double* inv_t = w.inv_tlev + (size_t)b * (Lp + 1);
+  const double nud = m.nu[j];
+  const float c1n3 = (float)(2.0 * kHpl * kC * kC * nud * nud * nud);
+  const double c2n_log2e = kHpl * kC / kB * 1.4426950408889634074 * nud;
+  auto planck_at = [&](int lv) {
+    float y, em1;
+    return planck_split(c1n3, c2n_log2e, inv_t[lv], y, em1);
+  };
+  const int n_mu = m.n_mu;
+  float inv_mu[kMaxMu];
+  double inten[kMaxMu];
+  float b_bot = planck_at(0);
+#pragma unroll
+  for (int k = 0; k < kMaxMu; ++k) {
+    inv_mu[k] = k < n_mu ? (float)(1.0 / m.mu_nodes[k]) : 0.0f;
+    inten[k] = b_bot;
+  }
+  const bool real = j < m.n_nu;   // columns of padding bins hold nothing
+  for (int l = 0; l < L; ++l) {
+    const float d = real ? dt[(size_t)l * ncol] : 0.0f;
+    const float b_top = planck_at(l + 1);
+    const float db = b_bot - b_top;
+#pragma unroll
+    for (int k = 0; k < kMaxMu; ++k) {
+      if (k >= n_mu) break;
+      const float x = d * inv_mu[k];
+      const float e = exp2_fast(-1.4426950408889634f * x);
+      float om, src;
+      slab_terms(x, e, om, src);
+      inten[k] = fma((double)om, (double)b_top - inten[k], fma((double)db, (double)src, inten[k]));
+    }
+    b_bot = b_top;
+  }
+  double flux = 0.0;
+#pragma unroll
+  for (int k = 0; k < kMaxMu; ++k)
+    if (k < n_mu) flux = fma(2.0 * M_PI * m.mu_weights[k] * m.mu_nodes[k], inten[k], flux);
+  flux *= (double)tb.ckw[lane & (kCkG - 1)];
+  flux += __shfl_xor(flux, 1);
+  flux += __shfl_xor(flux, 2);
+  flux += __shfl_xor(flux, 4);
+  if ((lane & (kCkG - 1)) == 0 && j < m.n_nu) {
+    const double fstar = M_PI * 2.0 * kHpl * kC * kC * nud * nud * nud / expm1(kHpl * kC * nud / (kB * m.t_star));
+    out[j] = (float)(m.dilution * flux / fstar * w.core[b]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <int S, bool CIA>
+const void* ck_mix_kernel() { return (const void*)k_ck_mix<S, CIA>; }
+
+static const void* ck_mix_kernel_for(int S, bool cia) {
+#define EXOFWD_CASE(n) \
+  case n: return cia ? ck_mix_kernel<n, true>() : ck_mix_kernel<n, false>();
+  switch (S) {
+    EXOFWD_CASE(1) EXOFWD_CASE(2) EXOFWD_CASE(3) EXOFWD_CASE(4)
+    EXOFWD_CASE(5) EXOFWD_CASE(6) EXOFWD_CASE(7) EXOFWD_CASE(8)
+  }
+#undef EXOFWD_CASE
+  return nullptr;
+}
+
+template <int S, bool CIA>
+const void* ck_prod_kernel() { return (const void*)k_ck_trans_prod<S, CIA>; }
+
+static const void* ck_prod_kernel_for(int S, bool cia) {
+#define EXOFWD_CASE(n) \
+  case n: return cia ? ck_prod_kernel<n, true>() : ck_prod_kernel<n, false>();
+  switch (S) {
+    EXOFWD_CASE(1) EXOFWD_CASE(2) EXOFWD_CASE(3) EXOFWD_CASE(4)
+    EXOFWD_CASE(5) EXOFWD_CASE(6) EXOFWD_CASE(7) EXOFWD_CASE(8)
+  }
+#undef EXOFWD_CASE
+  return nullptr;
+}
+
+static size_t ck_trans_lds_bytes(const Model& m) {
+  return (size_t)2 * kTileNu * (m.L_pad + 8) * 2 + (size_t)m.L_pad * 4 + 8 * 32 * 4;
+}
+static size_t ck_prod_lds_bytes(const Model& m) {
+  return (size_t)2 * kTileNu * (m.L_pad + 8) * 2 + (size_t)m.L_pad * 4 * 5 + 8 * 4;
+}
+
+hipError_t ck_configure(const Model& m) {
+  if (m.mode != kTransmission) return ck_mix_kernel_for(m.S, m.has_cia) ? hipSuccess : hipErrorInvalidValue;
+  if (m.ck_mix == kCkProduct) {
+    const void* k = ck_prod_kernel_for(m.S, m.has_cia);
+    if (!k) return hipErrorInvalidValue;
+    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ck_prod_lds_bytes(m));
+  }
+  if (!ck_mix_kernel_for(m.S, m.has_cia)) return hipErrorInvalidValue;
+  return hipFuncSetAttribute((const void*)k_ck_trans, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)ck_trans_lds_bytes(m));
+}
+
+void launch_ck_mix(const Model& m, const Work& w, const Tables& tb, int B, hipStream_t st) {
+  if (m.ck_mix != kCkRorr) return;   // the product of transmissions mixes inside its chord kernel
+  const unsigned gx = (unsigned)((m.n_nu + kCkBinsPerWave * (kBlock / 64) - 1) / (kCkBinsPerWave * (kBlock / 64)));
+  void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B};
+  hipLaunchKernel(ck_mix_kernel_for(m.S, m.has_cia), dim3(gx, (unsigned)m.L_max, (unsigned)B), dim3(kBlock), args, 0,
+                  st);
+}
+
+void launch_ck_spectrum(const Model& m, const Work& w, const Tables& tb, int B, void* spec, hipStream_t st) {
+  if (m.ck_mix == kCkProduct) {
+    void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec};
+    hipLaunchKernel(ck_prod_kernel_for(m.S, m.has_cia), dim3((unsigned)(B * ((m.n_nu + 1) / 2))), dim3(kBlockT), args,
+                    ck_prod_lds_bytes(m), st);
+    return;
+  }
+  if (m.mode == kTransmission) {
+    hipLaunchKernelGGL(k_ck_trans, dim3((unsigned)(B * m.n_tiles * kCkG)), dim3(kBlockT), ck_trans_lds_bytes(m), st, m,
+                       w, tb, B, (float*)spec);
+  } else {
+    const int waves = B * m.n_tiles64 * kCkG;
+    hipLaunchKernelGGL(k_ck_emis, dim3((unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0, st, m,
+                       w, tb, B, (float*)spec);
+  }
+}
+
+}  // namespace exofwd

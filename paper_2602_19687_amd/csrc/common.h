@@ -28,6 +28,8 @@ constexpr int kTileNu = 128;      // wavenumbers per tile of the reduced-precisi
 constexpr int kTile64 = 64;       // wavenumbers per tile of the FP64 and emission kernels
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kBlockT = 512;      // threads per workgroup of the reduced-precision transmission kernels
+constexpr int kCkG = 8;           // g-points per bin of a correlated-k table
+constexpr int kCkBinsPerWave = 16;  // bins one wave of the k-distribution mixing kernel walks through
 // a chord optical depth beyond which e^-tau is zero in FP32 with a wide margin
 // (e^-103.3 is already below the smallest denormal): its adjoint seed is exactly 0
 constexpr float kOpaqueTau = 110.0f;
@@ -45,6 +47,7 @@ __host__ __device__ constexpr int rec_len(int s) { return kRecFixed + s; }
 __host__ __device__ inline int pack_cells(int it, int ip, int itc) { return it | (ip << 8) | (itc << 16); }
 
 enum : int { kTransmission = 0, kEmission = 1 };
+enum : int { kCkRorr = 0, kCkProduct = 1 };
 enum : int { kFP64 = 0, kMixed = 1 };
 enum : int { kTpIso = 0, kTpGuillot3 = 1, kTpPchip = 2, kTpBarstow = 3, kTpMilne = 4, kTpGuillot7 = 5 };
 constexpr double kKappaAd = 2.0 / 7.0;    // adiabatic exponent of the Barstow profile (Eq. 8)
@@ -66,6 +69,8 @@ struct Model {
   int has_fcld, idx_fcld;   // cloudy/clear mixing: sample b runs as virtual samples 2b (cloudy) and 2b+1 (clear)
   int has_bd, idx_bd;       // isolated object: theta[idx_bd] = log10 g, theta[idx_bd + 1] = M / M_Jup
   double bd_dist;           // its distance [cm]
+  int ck;                   // correlated-k tables: n_nu spectral bins of kCkG g-points (reduced precision)
+  int ck_mix;               // their mixing (kCkRorr)
   double mu_fixed, log10_pbot, log10_ptop, p_ref, r_p, r_s, g_ref;
   double kappa_ir, f_hem, kappa_cloud, t_star, dilution, err_c, ray_h2, ray_he;
   double mass[kMaxSpecies];
@@ -87,6 +92,7 @@ struct Work {
   int32_t* nlay;        // [B] layers used per sample
   double* t_lay;        // [B][L_pad]
   double* t_lev;        // [B][L_pad+1]
+  double* inv_tlev;     // reduced-precision emission: [B][L_pad+1] 1 / T at the levels (the Planck exponents)
   double* r_lev;        // [B][L_pad+1]
   double* core;         // [B] r_0^2 / R_s^2
   double* cloud;        // [B][kCloudSpec] non-grey cloud: r_eff [cm], a, Q0, A, lambda0 [um], omega [um], xi
@@ -109,6 +115,7 @@ struct Work {
   double* gv;           // cloudy/clear mixing: [2B][P] gradients of the virtual samples
   double* fbar;         // cloudy/clear mixing: [B] d lnL / d f_cld
   double* mdot;         // [B] sum_k d lnL/dm_k (m_k - offset_k): d lnL / d ln(spectrum scale)
+  float* ckmix;         // correlated-k: [B][L_pad][n_nu_pad * kCkG] mixed layer optical depths per (bin, g-point)
   const int32_t* bin_of;  // [n_nu_pad] bin holding each wavenumber, -1 if none
   const double* inv_cnt;  // [K] 1 / (hi_k - lo_k)
 };
@@ -123,6 +130,8 @@ struct Tables {
   const double* t64;     // fp64: [S][n_t][n_p][n_nu_pad] log10 sigma
   const double* tc64;    // fp64: [2][n_tc][n_nu_pad] log10 k
   const double* nu4d;    // fp64: [n_nu_pad]
+  const float* ckw;      // correlated-k: [kCkG] g-point weights
+  const float* cke;      // correlated-k: [kCkG] upper edges of the g-intervals (running sums of the weights)
 };
 
 }  // namespace exofwd

@@ -9,13 +9,24 @@ void launch_emission(const Model& m, const Work& w, const Tables& tb, int B, voi
 hipError_t emission_configure(const Model& m, bool fp64);
 size_t emission_lds_bytes(const Model& m, bool fp64);
 
-// Planck intensity per unit wavenumber at temperature t, 2 h c^2 nu^3 / (exp(y) - 1)
-// with y = h c nu / k t, from c1n3 = 2 h c^2 nu^3 and c2n = h c nu / k; below
-// y = 0.01, exp(y) - 1 is taken from its series.  em1 returns exp(y) - 1.
-__device__ inline float planck_f32(float c1n3, float c2n, float t, float& y, float& em1) {
-  y = c2n * __builtin_amdgcn_rcpf(t);
-  em1 = y < 0.01f ? y * (1.0f + y * (0.5f + y * (1.0f / 6.0f)))
-                  : __builtin_amdgcn_exp2f(1.4426950408889634f * y) - 1.0f;
+// Planck intensity per unit wavenumber, 2 h c^2 nu^3 / (e^y - 1) with y = h c nu / k T,
+// from c1n3 = 2 h c^2 nu^3, c2n_log2e = log2(e) h c nu / k and inv_t = 1/T; em1
+// returns e^y - 1.  FP32 holds y only to about 1e-6 absolute at y ~ 20, and e^y
+// inherits that as a relative error in B, which the emitted flux, and through the
+// likelihood residuals near the best fit the gradient, would carry.  So the exponent
+// a = log2(e) y is formed in FP64 and split as a = a_hi + a_lo with a_hi exactly a
+// float: e^y = 2^a_hi (1 + a_lo ln 2) (a_lo < 2^-24 a_hi, so the first-order term is
+// exact to FP32).  Below y = 0.1, e^y - 1 comes from its series (through y^5).
+__device__ inline float planck_split(float c1n3, double c2n_log2e, double inv_t, float& y, float& em1) {
+  const double a = c2n_log2e * inv_t;
+  y = (float)(a * 0.69314718055994530942);
+  if (y < 0.1f) {
+    em1 = y * (1.0f + y * (0.5f + y * (1.0f / 6.0f + y * (1.0f / 24.0f + y * (1.0f / 120.0f)))));
+  } else {
+    const float ah = (float)a;
+    const float al = (float)(a - (double)ah);
+    em1 = fmaf(__builtin_amdgcn_exp2f(ah), fmaf(al, 0.69314718055994530942f, 1.0f), -1.0f);
+  }
   return c1n3 * __builtin_amdgcn_rcpf(em1);
 }
 

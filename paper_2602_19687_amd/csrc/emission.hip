@@ -142,6 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tabl
   const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * RL;
   const int32_t* cells = w.cells + (size_t)b * Lp;
   const double* t_lev = w.t_lev + (size_t)b * (Lp + 1);
+  const double* inv_t = w.inv_tlev + (size_t)b * (Lp + 1);
   const size_t npad = (size_t)m.n_nu_pad;
   // FP32 tables: 4 bytes per (row, wavenumber)
   const uint32_t row_bytes = (uint32_t)npad * 4u, tstep = (uint32_t)m.n_p * row_bytes;
@@ -155,15 +156,18 @@ __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tabl
 #pragma unroll
   for (int p = 0; p < 2; ++p) ccs[p] = CIA ? tb.cc[(size_t)p * npad + nu] : 0.0f;
 
-  const float nuv = (float)m.nu[nu];
-  const float c1n3 = (float)(2.0 * kHpl * kC * kC) * nuv * nuv * nuv;
-  const float c2n = (float)(kHpl * kC / kB) * nuv;
+  const double nud = m.nu[nu];
+  const float c1n3 = (float)(2.0 * kHpl * kC * kC * nud * nud * nud);
+  const double c2n_log2e = kHpl * kC / kB * 1.4426950408889634074 * nud;
   auto planck_at = [&](int j) {
     float y, em1;
-    return planck_f32(c1n3, c2n, (float)t_lev[j], y, em1);
+    return planck_split(c1n3, c2n_log2e, inv_t[j], y, em1);
   };
   const int n_mu = m.n_mu;
-  float inv_mu[kMaxMu], inten[kMaxMu];
+  // the intensities accumulate in FP64: a hundred FP32 updates would leave ~1e-6 of
+  // rounding in the flux, which the likelihood residuals near the best fit amplify
+  float inv_mu[kMaxMu];
+  double inten[kMaxMu];
   float b_bot = planck_at(0);
 #pragma unroll
   for (int k = 0; k < kMaxMu; ++k) {
@@ -235,19 +239,18 @@ __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tabl
       float om, src;
       slab_terms(x, e, om, src);
       // I e^-x + B_top (1 - e^-x) + (B_bot - B_top) src, as an increment of I
-      inten[k] = fmaf(om, b_top - inten[k], fmaf(db, src, inten[k]));
+      inten[k] = fma((double)om, (double)b_top - inten[k], fma((double)db, (double)src, inten[k]));
     }
     b_bot = b_top;
   }
-  float flux = 0.0f;
+  double flux = 0.0;
 #pragma unroll
   for (int k = 0; k < kMaxMu; ++k)
-    if (k < n_mu) flux = fmaf((float)(2.0 * M_PI * m.mu_weights[k] * m.mu_nodes[k]), inten[k], flux);
+    if (k < n_mu) flux = fma(2.0 * M_PI * m.mu_weights[k] * m.mu_nodes[k], inten[k], flux);
   if (nu < m.n_nu) {
-    const double nd = m.nu[nu];
     const double fstar =
-        m.has_bd ? 1.0 : M_PI * 2.0 * kHpl * kC * kC * nd * nd * nd / expm1(kHpl * kC * nd / (kB * m.t_star));
-    out[nu] = (float)(m.dilution * (double)flux / fstar * w.core[b]);
+        m.has_bd ? 1.0 : M_PI * 2.0 * kHpl * kC * kC * nud * nud * nud / expm1(kHpl * kC * nud / (kB * m.t_star));
+    out[nu] = (float)(m.dilution * flux / fstar * w.core[b]);
   }
 }
 

@@ -49,6 +49,7 @@ __global__ __launch_bounds__(kBlock) void k_emis_adj_mixed(Model m, Work w, AdjW
   float* dtb = aw.dtb + (size_t)b * Lp * npad + nu;
   float* ps = aw.psum + ((size_t)b * m.n_tiles64 + tile) * (Lp + 1);
   const double* t_lev = w.t_lev + (size_t)b * (Lp + 1);
+  const double* inv_t = w.inv_tlev + (size_t)b * (Lp + 1);
 
   // seed: d lnL / d spectrum(nu) = dm_k / n_k for the bin holding nu, times the
   // flux-to-ratio factor s (R/R_s)^2 / (pi B_*) and each angle's 2 pi w mu
@@ -60,14 +61,15 @@ __global__ __launch_bounds__(kBlock) void k_emis_adj_mixed(Model m, Work w, AdjW
         m.has_bd ? 1.0 : M_PI * 2.0 * kHpl * kC * kC * nd * nd * nd / expm1(kHpl * kC * nd / (kB * m.t_star));
     seed = (float)(w.dm[(size_t)b * m.K + kb] * w.inv_cnt[kb] * m.dilution * w.core[b] / fstar);
   }
-  const float nuv = (float)m.nu[nu];
-  const float c1n3 = (float)(2.0 * kHpl * kC * kC) * nuv * nuv * nuv;
-  const float c2n = (float)(kHpl * kC / kB) * nuv;
-  // Planck intensity at level j and its temperature derivative B y e^y / ((e^y - 1) T)
+  const double nud = m.nu[nu];
+  const float c1n3 = (float)(2.0 * kHpl * kC * kC * nud * nud * nud);
+  const double c2n_log2e = kHpl * kC / kB * 1.4426950408889634074 * nud;
+  // Planck intensity at level j (as the forward kernel forms it) and its temperature
+  // derivative B y e^y / ((e^y - 1) T)
   auto planck_at = [&](int j, float& dbdt) {
     const float t = (float)t_lev[j];
     float y, em1;
-    const float bv = planck_f32(c1n3, c2n, t, y, em1);
+    const float bv = planck_split(c1n3, c2n_log2e, inv_t[j], y, em1);
     dbdt = bv * y * (em1 + 1.0f) * __builtin_amdgcn_rcpf(em1 * t);
     return bv;
   };

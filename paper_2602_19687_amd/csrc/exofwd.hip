@@ -4,6 +4,7 @@
 #include "kernels.h"
 #include "adjoint.h"
 #include "emission.h"
+#include "ck.h"
 
 #include <algorithm>
 #include <array>
@@ -299,6 +300,28 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   // the FP64 emission kernel stages a tile's layers in LDS: at most 128 padded layers
   if (g.mode == EXOFWD_EMISSION && g.precision == EXOFWD_PREC_FP64 && (g.n_layers_max + 31) / 32 * 32 > 128)
     return create_fail(EXOFWD_ERR_UNSUPPORTED, "FP64 emission takes at most 128 padded layers");
+  // correlated-k tables: kCkG g-points per bin, reduced precision, forward model only
+  if (g.ck_g != 0) {
+    if (g.ck_g != kCkG) return create_fail(EXOFWD_ERR_UNSUPPORTED, "correlated-k tables need exactly 8 g-points");
+    if (g.precision != EXOFWD_PREC_MIXED)
+      return create_fail(EXOFWD_ERR_UNSUPPORTED, "correlated-k tables run in reduced precision only");
+    if (g.ck_mix != EXOFWD_CK_RORR && g.ck_mix != EXOFWD_CK_PRODUCT) return create_fail(E, "unknown ck_mix");
+    if (g.ck_mix == EXOFWD_CK_PRODUCT && g.mode != EXOFWD_TRANSMISSION)
+      return create_fail(E, "the product of the absorbers' transmission functions is a transmission mixing");
+    if (g.has_fcld || g.has_bd || (g.has_cloud && g.cloud_model != EXOFWD_CLOUD_GREY_DECK))
+      return create_fail(EXOFWD_ERR_UNSUPPORTED,
+                         "correlated-k tables take no cloudy/clear mixing, isolated object or non-grey cloud");
+    if (!g.ck_weights) return create_fail(E, "ck_weights is NULL");
+    double sw = 0.0;
+    for (int i = 0; i < g.ck_g; ++i) {
+      if (!(g.ck_weights[i] > 0.0)) return create_fail(E, "ck_weights must be > 0");
+      sw += g.ck_weights[i];
+    }
+    if (std::fabs(sw - 1.0) > 1e-9) return create_fail(E, "ck_weights must sum to 1");
+  } else if (g.ck_mix != 0 || g.ck_weights) {
+    return create_fail(E, "ck_mix and ck_weights need ck_g > 0");
+  }
+  const int gk = g.ck_g ? g.ck_g : 1;   // table columns per spectral point
   // The reduced-precision kernels read the encoded tables, and the gradient's stored
   // optical depths of a sample, through buffer resources whose range and offsets are
   // 32-bit: each of these buffers must stay below 2^31 bytes (checked before any
@@ -306,20 +329,20 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   if (g.precision == EXOFWD_PREC_MIXED) {
     const uint64_t lim = 0x7fffffffull;
     const uint64_t npad = ((uint64_t)g.n_nu + kTileNu - 1) / kTileNu * kTileNu;
-    const uint64_t eb = g.mode == EXOFWD_EMISSION ? 4 : 2;
+    const uint64_t eb = (g.mode == EXOFWD_EMISSION || g.ck_g) ? 4 : 2;
     const uint64_t lpad = ((uint64_t)g.n_layers_max + 31) / 32 * 32;
-    const uint64_t tab = (uint64_t)g.n_species * g.n_t * g.n_p * npad * eb;
+    const uint64_t tab = (uint64_t)g.n_species * g.n_t * g.n_p * npad * gk * eb;
     const uint64_t cia = g.has_cia ? 2ull * g.n_tc * npad * eb : 0;
-    if (tab > lim || cia > lim || lpad * npad * 4 > lim)
+    if (tab > lim || cia > lim || lpad * npad * gk * 4 > lim)
       return create_fail(EXOFWD_ERR_UNSUPPORTED,
                          "reduced precision addresses each table, and a sample's stored optical depths, with "
                          "32-bit offsets: line table " + std::to_string(tab) + " B, CIA table " +
-                             std::to_string(cia) + " B, optical depths " + std::to_string(lpad * npad * 4) +
+                             std::to_string(cia) + " B, optical depths " + std::to_string(lpad * npad * gk * 4) +
                              " B; each must be below 2^31 B");
   }
   // log10 tables must be finite: a zero cross-section is given as a finite floor
   // (the reduced-precision encoding keeps each wavenumber's range over the grid)
-  if (!all_finite(g.log10_xsec, (size_t)g.n_species * g.n_t * g.n_p * g.n_nu))
+  if (!all_finite(g.log10_xsec, (size_t)g.n_species * g.n_t * g.n_p * g.n_nu * gk))
     return create_fail(E, "log10_xsec holds a non-finite entry");
   if (g.has_cia && !all_finite(g.log10_cia, (size_t)2 * g.n_tc * g.n_nu))
     return create_fail(E, "log10_cia holds a non-finite entry");
@@ -384,6 +407,8 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   m.idx_bd = m.has_bd ? k : -1;
   k += 2 * m.has_bd;
   m.bd_dist = g.has_bd ? g.bd_distance : 0.0;
+  m.ck = g.ck_g ? 1 : 0;
+  m.ck_mix = g.ck_mix;
   m.idx_scale = m.has_scale ? k++ : -1;
   m.idx_offset = m.has_offset ? k++ : -1;
   m.P = k;
@@ -463,8 +488,9 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   } else {
     std::vector<_Float16> h;
     std::vector<float> off;
-    const bool wide = m.mode == kEmission;
-    encode_tables(g.log10_xsec, m.S, rows, g.n_nu, (int)np, h, off, wide);
+    const bool wide = m.mode == kEmission || m.ck;
+    // correlated-k: one column per (bin, g-point), [bin][g] with the bins padded like wavenumbers
+    encode_tables(g.log10_xsec, m.S, rows, g.n_nu * gk, (int)np * gk, h, off, wide);
     uint16_t* dh = A(dalloc<uint16_t>(c, h.size()));
     float* dc = A(dalloc<float>(c, off.size()));
     float* dn4 = A(dalloc<float>(c, np));
@@ -476,6 +502,20 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
     c->tb.h = dh;
     c->tb.c = dc;
     c->tb.nu4f = dn4;
+    if (m.ck) {
+      float wv[kCkG], ev[kCkG];
+      double run = 0.0;
+      for (int i = 0; i < kCkG; ++i) {
+        wv[i] = (float)g.ck_weights[i];
+        run += g.ck_weights[i];
+        ev[i] = (float)run;
+      }
+      float* dw = A(dalloc<float>(c, kCkG));
+      float* de = A(dalloc<float>(c, kCkG));
+      if (ok) ok = upload(dw, wv, kCkG) && upload(de, ev, kCkG);
+      c->tb.ckw = dw;
+      c->tb.cke = de;
+    }
     if (m.has_cia) {
       encode_tables(g.log10_cia, 2, m.n_tc, g.n_nu, (int)np, h, off, wide);
       uint16_t* dhc = A(dalloc<uint16_t>(c, h.size()));
@@ -506,6 +546,7 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   w.nlay = A(dalloc<int32_t>(c, B));
   w.t_lay = A(dalloc<double>(c, (size_t)B * Lp));
   w.t_lev = A(dalloc<double>(c, (size_t)B * (Lp + 1)));
+  if (m.mode == kEmission && !fp64) w.inv_tlev = A(dalloc<double>(c, (size_t)B * (Lp + 1)));
   w.r_lev = A(dalloc<double>(c, (size_t)B * (Lp + 1)));
   w.core = A(dalloc<double>(c, B));
   w.cloud = A(dalloc<double>(c, (size_t)B * kCloudSpec));
@@ -526,6 +567,7 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
     }
   }
   w.spec = A(dalloc<unsigned char>(c, (size_t)B * m.n_nu * rs));
+  if (m.ck && m.ck_mix == kCkRorr) w.ckmix = A(dalloc<float>(c, (size_t)B * Lp * np * kCkG));
   w.dm = A(dalloc<double>(c, (size_t)B * m.K));
   w.lnl_tmp = A(dalloc<double>(c, B));
   w.mdot = A(dalloc<double>(c, B));
@@ -553,7 +595,8 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
     exofwd_destroy(c);
     return create_fail(EXOFWD_ERR_NOMEM, "device allocation or upload failed");
   }
-  hipError_t e = m.mode == kTransmission ? trans_fwd_configure(m, fp64) : emission_configure(m, fp64);
+  hipError_t e = m.ck ? ck_configure(m) : m.mode == kTransmission ? trans_fwd_configure(m, fp64)
+                                                                   : emission_configure(m, fp64);
   if (e == hipSuccess) e = adjoint_configure(m, fp64);
   if (e != hipSuccess) {
     exofwd_destroy(c);
@@ -656,7 +699,16 @@ static exofwd_status run_forward(exofwd_ctx* c, const Work& w, int32_t B, const 
   launch_profile(c->m, w, Bv, params, n_layers, fp64, st);
   prof_end(c, st);
   if ((s = check_hip(c, hipGetLastError(), "profile launch"))) return s;
-  if (c->m.mode == kTransmission) {
+  if (c->m.ck) {
+    if (c->m.ck_mix == kCkRorr) {
+      prof_begin(c, "ck_mix", st);
+      launch_ck_mix(c->m, w, c->tb, Bv, st);
+      prof_end(c, st);
+      if ((s = check_hip(c, hipGetLastError(), "k-distribution mixing launch"))) return s;
+    }
+    prof_begin(c, "ck_spectrum", st);
+    launch_ck_spectrum(c->m, w, c->tb, Bv, spec, st);
+  } else if (c->m.mode == kTransmission) {
     prof_begin(c, "trans_fwd", st);
     launch_trans_fwd(c->m, w, c->tb, Bv, spec, fp64, st, (float*)dtau_out);
   } else {
@@ -691,6 +743,7 @@ static size_t carve_forward_work(const exofwd_ctx* c, int B, bool internal_spec,
   w.nlay = (int32_t*)take(4 * Bv);
   w.t_lay = (double*)take(8 * Bv * Lp);
   w.t_lev = (double*)take(8 * Bv * (Lp + 1));
+  if (!trans && !fp64) w.inv_tlev = (double*)take(8 * Bv * (Lp + 1));
   w.r_lev = (double*)take(8 * Bv * (Lp + 1));
   w.core = (double*)take(8 * Bv);
   w.cloud = (double*)take(8 * Bv * kCloudSpec);
@@ -703,6 +756,7 @@ static size_t carve_forward_work(const exofwd_ctx* c, int B, bool internal_spec,
   if (trans && fp64) w.pm64 = (double*)take(8 * Bv * Lp * Lp);
   if (trans && !fp64) w.pfrag = (uint16_t*)take(2 * Bv * 2 * (Lp / 32) * (Lp / 16) * 512);
   if (internal_spec) w.spec = take(rs * Bv * (size_t)m.n_nu);
+  if (m.ck && m.ck_mix == kCkRorr) w.ckmix = (float*)take(4 * Bv * Lp * (size_t)m.n_nu_pad * kCkG);
   w.dm = (double*)take(8 * Bv * (size_t)m.K);
   w.lnl_tmp = (double*)take(8 * Bv);
   w.mdot = (double*)take(8 * Bv);
@@ -898,7 +952,7 @@ exofwd_status exofwd_autotune(exofwd_ctx* c, int32_t B, const double* params, co
   if (!c) return EXOFWD_ERR_ARG;
   if (B < 1 || B > c->batch_max) return fail(c, EXOFWD_ERR_SHAPE, "B outside [1, batch_max]");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, EXOFWD_ERR_DEVICE, "hipSetDevice failed");
-  const bool mixed_trans = c->precision == EXOFWD_PREC_MIXED && c->m.mode == kTransmission;
+  const bool mixed_trans = c->precision == EXOFWD_PREC_MIXED && c->m.mode == kTransmission && !c->m.ck;
   if (!mixed_trans) return EXOFWD_OK;   // the FP64 and emission launches have no tunable shape
   const bool grad = adjoint_supported(c->m, false);
   const std::string key = tuning_key(c, B);

@@ -229,6 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
   for (int j = tid; j <= Lp; j += kBlock) {
     r_lev[j] = j <= L ? s_r[j] : 0.0;
     t_lev[j] = (m.mode == kEmission && j <= L) ? s_tl[j] : 0.0;
+    if (w.inv_tlev) w.inv_tlev[(size_t)b * (Lp + 1) + j] = j <= L ? 1.0 / s_tl[j] : 0.0;
   }
   // transmission: opaque-core depth (r_0/R_s)^2; emission: (R_ref/R_s)^2 of Eq. 45
   if (tid == 0)

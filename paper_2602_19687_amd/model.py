@@ -72,6 +72,11 @@ def build_config(wl, precision: int, batch_max: int, device: int = 0, n_layers_m
     cfg.y_obs = _dptr(arr(wl["y_obs"], np.float64), C.c_double)
     cfg.y_err = _dptr(arr(wl["y_err"], np.float64), C.c_double)
     cfg.offset_mask = _dptr(arr(wl["offset_mask"], np.uint8), C.c_uint8)
+    if wl.get("ck", False):
+        cw = arr(wl["ck_w"], np.float64)
+        cfg.ck_g = len(cw)
+        cfg.ck_mix = int(wl.get("ck_mix", 0))
+        cfg.ck_weights = _dptr(cw, C.c_double)
     cfg.device = device
     return cfg, keep
 

@@ -8,8 +8,7 @@ Workloads: the grey-deck transmission setup (every 30th of 30000 wavenumbers,
 30 bins) and the emission setup (every 40th of 20000, 20 bins), 100 layers,
 4 samples drawn from the prior bounds.  Tolerances: spectra and lnL 1e-5
 (FP64) / 1e-3 (mixed); gradients per component relative to
-max(|g*_j|, 1e-3 max|g*|): 1e-5 (FP64), 1e-3 (mixed transmission), 2e-3
-(mixed emission).
+max(|g*_j|, 1e-3 max|g*|): 1e-5 (FP64), 1e-3 (mixed).
 """
 import numpy as np
 import pytest
@@ -73,7 +72,7 @@ def test_tp_profile_forward_and_grad(tp, cid, prec):
     lnl2, g, st2, _ = fm.grad(th)
     lnl2, g, st2 = lnl2.cpu().numpy(), g.cpu().numpy(), st2.cpu().numpy()
     fm.close()
-    gtol = 1e-5 if prec == "fp64" else (2e-3 if cid == 2 else 1e-3)
+    gtol = 1e-5 if prec == "fp64" else 1e-3
     n_ok, worst_s, worst_g = 0, 0.0, 0.0
     for b, ref in enumerate(fwd):
         assert st[b] == ref["status"] and st2[b] == ref["status"]
@@ -132,7 +131,7 @@ def test_isolated_object_forward_and_grad(tp, prec):
     lnl2, g, st2, _ = fm.grad(th)
     g, st2 = g.cpu().numpy(), st2.cpu().numpy()
     fm.close()
-    gtol = 1e-5 if prec == "fp64" else 2e-3
+    gtol = 1e-5 if prec == "fp64" else 1e-3
     n_ok, worst_s, worst_g = 0, 0.0, 0.0
     for b, ref in enumerate(fwd):
         assert st[b] == ref["status"] and st2[b] == ref["status"]
@@ -171,4 +170,4 @@ def test_milne_emission_ragged_layers(bd):
         assert rel_err(sp[b], ref["spectrum"]) < SPEC_TOL["mixed"]
         worst = max(worst, grad_err(g[b], oracle.grad_complex_step(wl, wl["params"][b], n_layers=int(nl[b]))))
     print(f"Milne emission ragged bd={bd}: gradient {worst:.3e}")
-    assert worst < 2e-3
+    assert worst < 1e-3
