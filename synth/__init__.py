@@ -183,9 +183,9 @@ def ck_sub_grid(edges: np.ndarray, n_sub: int) -> np.ndarray:
     return lo[:, None] + (hi - lo)[:, None] * f[None, :]
 
 
-def lorentz_sigma_nonuniform(nu, gamma, centres, strengths, cutoff=25.0, continuum=1.0e-24):
-    """sigma(nu) [cm^2] at arbitrary ascending nu for one Lorentz half width
-    gamma (the line shape of ``lorentz_log10_xsec``, same cutoff and continuum)."""
+def lorentz_pairs(nu, centres, strengths, cutoff=25.0):
+    """(point index, squared distance, strength) of every (line, point) pair within
+    ``cutoff`` cm^-1, at arbitrary ascending nu."""
     lo = np.searchsorted(nu, centres - cutoff, side="left")
     hi = np.searchsorted(nu, centres + cutoff, side="right")
     cnt = hi - lo
@@ -194,8 +194,14 @@ def lorentz_sigma_nonuniform(nu, gamma, centres, strengths, cutoff=25.0, continu
     offs = np.arange(tot) - np.repeat(np.cumsum(cnt) - cnt, cnt)
     idx = start + offs
     line = np.repeat(np.arange(len(centres)), cnt)
-    d2 = (nu[idx] - centres[line]) ** 2
-    prof = strengths[line] * (gamma / np.pi) / (d2 + gamma * gamma)
+    return idx, (nu[idx] - centres[line]) ** 2, strengths[line]
+
+
+def lorentz_sigma_nonuniform(nu, gamma, centres, strengths, cutoff=25.0, continuum=1.0e-24, pairs=None):
+    """sigma(nu) [cm^2] at arbitrary ascending nu for one Lorentz half width
+    gamma (the line shape of ``lorentz_log10_xsec``, same cutoff and continuum)."""
+    idx, d2, s = lorentz_pairs(nu, centres, strengths, cutoff) if pairs is None else pairs
+    prof = s * (gamma / np.pi) / (d2 + gamma * gamma)
     return continuum + np.bincount(idx, weights=prof, minlength=len(nu))
 
 
@@ -207,12 +213,13 @@ def ck_log10_table(sub_nu, g_nodes, t_grid, logp_grid, centres, strengths, gamma
     interpolation (held constant outside the first and last centres)."""
     n_bins, n_sub = sub_nu.shape
     flat = sub_nu.ravel()
-    gc = (np.arange(n_sub) + 0.5) / n_sub
+    pairs = lorentz_pairs(flat, centres, strengths)
     out = np.empty((len(t_grid), len(logp_grid), n_bins, len(g_nodes)))
     for it, t in enumerate(t_grid):
         for ip, lp in enumerate(logp_grid):
             gam = gamma0 * (10.0 ** lp) * (t / 296.0) ** -0.5
-            sig = np.sort(lorentz_sigma_nonuniform(flat, gam, centres, strengths).reshape(n_bins, n_sub), axis=1)
+            sig = np.sort(lorentz_sigma_nonuniform(flat, gam, centres, strengths, pairs=pairs).reshape(n_bins, n_sub),
+                          axis=1)
             k = np.empty((n_bins, len(g_nodes)))
             for n, gn in enumerate(g_nodes):
                 pos = np.clip(gn * n_sub - 0.5, 0.0, n_sub - 1.0)
