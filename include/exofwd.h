@@ -272,9 +272,13 @@ exofwd_status exofwd_grad(exofwd_ctx* ctx, int32_t B, const double* params,
  * Launch choices of a reduced-precision transmission context, four int32:
  *   [0] forward grid order: 0 samples fastest, 1 wavenumber tiles fastest
  *   [1] reverse-kernel shape: 0 = 128-wavenumber tiles x 4 row blocks (padded
- *       layers <= 128), 1 = 64 x 4 (<= 128), 2 = 64 x 5 (<= 160)
- *   [2] reverse work items per call, one of 512, 1024, 2048, 4096 (each sample's
- *       wavenumbers are split into ceil(items / B) chunks)
+ *       layers <= 128), 1 = 64 x 4, 2 = 64 x 5 (<= 160).  With more than 128 padded
+ *       layers, 1 runs the samples of at most 128 layers with 64 x 4 and the rest with
+ *       64 x 5 (and the forward kernel always runs those two classes with LDS tiles
+ *       of 128 and of all padded layers); 2 runs every sample with 64 x 5
+ *   [2] reverse work items per call, one of 512, 1024, 2048, 4096, 8192 (each sample's
+ *       wavenumbers are split into ceil(items / B) chunks, which run on neighbouring
+ *       workgroups)
  *   [3] 128-wavenumber tiles per wave of the layer-sum kernel: 4, 8, 16, 32 or 64
  * Every choice gives the same results up to FP32 summation order.
  * exofwd_set_tuning returns EXOFWD_ERR_ARG, changing nothing, for a choice that

@@ -22,7 +22,7 @@ __host__ __device__ inline int n_lsums(const Model& m) { return n_sums(m.S); }
 enum : int { kAdjT128M4 = 0, kAdjT64M4 = 1, kAdjT64M5 = 2, kAdjVariants = 3 };
 
 // launch choices the autotuner may change (every value is valid for any workload)
-constexpr int kChunkTargets[] = {512, 1024, 2048, 4096};   // (sample, chunk) work items per reverse launch
+constexpr int kChunkTargets[] = {512, 1024, 2048, 4096, 8192};   // (sample, chunk) work items per reverse launch
 constexpr int kLsTileChoices[] = {4, 8, 16, 32, 64};           // 128-wavenumber tiles per layer-sum wave
 
 struct AdjWork {

@@ -81,8 +81,11 @@ struct AdjShape {
   static constexpr int kItems = MB;                               // (layer octet, half) items per wave
 };
 
+// `cls` (may be null): the layer-count classes of the call (layer_classes), whose class
+// `cl` this launch serves (its samples have at most 32 MB layers)
 template <int S, bool CIA, int TILE, int MB>
-__global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, Tables tb, AdjWork aw, int B, int C) {
+__global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, Tables tb, AdjWork aw, int B, int C,
+                                                              const int32_t* __restrict__ cls, int cl) {
   using Sh = AdjShape<TILE, MB>;
   static_assert(Sh::kThreads == 4 * TILE, "launch bound");
   static_assert(Sh::kItems * Sh::kWaves == 4 * Sh::kHalves * MB, "phase A items cover 4 MB octets per half");
@@ -90,18 +93,27 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
   constexpr int kSlots = Sh::kSlots, kPSlotsA = Sh::kPSlots, kItemsA = Sh::kItems, kHalves = Sh::kHalves;
   extern __shared__ __align__(16) unsigned char lds[];
   const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int b = logical % B, chunk = logical / B;
+  // a sample's chunks on neighbouring workgroups of one XCD: its path-matrix fragments,
+  // re-read for every tile, stay in that XCD's L2 while its chunks run
+  const int chunk = logical % C;
+  int b = logical / C;
+  if (cls) {
+    // the class's samples, longest first; the grid covers the whole batch
+    if (b >= cls[cl]) return;
+    b = cls[2 + cl * B + b];
+  }
   if (w.status[b]) return;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int Lp = m.L_pad, L = w.nlay[b];
-  const int ld = Lp + 4;                               // dwords per wavenumber row (b128-conflict-free)
+  const int rows = Lp < 32 * MB ? Lp : 32 * MB;        // LDS rows: the layers this shape can hold
+  const int ld = rows + 4;                             // dwords per wavenumber row (b128-conflict-free)
   uint32_t* s_dt = reinterpret_cast<uint32_t*>(lds);   // dtau    [nu][ld] as packed bf16 hi/lo
   uint32_t* s_tt = s_dt + kTileA * ld;                 // tau_bar [nu][ld] as packed bf16 hi/lo
   float* s_area = reinterpret_cast<float*>(s_tt + kTileA * ld);   // [Lp]
 
   const float* area = reinterpret_cast<const float*>(w.area) + (size_t)b * Lp;
-  for (int i = tid; i < Lp; i += kBlockA) s_area[i] = area[i];
+  for (int i = tid; i < rows; i += kBlockA) s_area[i] = area[i];
 
   const size_t npad = (size_t)m.n_nu_pad;
   const int KBe = (L + 15) >> 4, MBe = (L + 31) >> 5, KB = Lp >> 4;
@@ -620,7 +632,7 @@ template <int S, bool CIA>
 __global__ __launch_bounds__(kBlockT) void k_trans_adj_fp64(Model m, Work w, Tables tb, AdjWork aw, int B, int C) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int b = logical % B, chunk = logical / B;
+  const int chunk = logical % C, b = logical / C;   // a sample's chunks on one XCD, as above
   if (w.status[b]) return;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1342,16 +1354,24 @@ bool adjoint_supported(const Model& m, bool fp64) {
   return m.L_pad <= (fp64 ? 128 : 160);
 }
 
-int adjoint_default_variant(const Model& m) { return m.L_pad <= 128 ? kAdjT128M4 : kAdjT64M5; }
+// A ragged context of more than kShortLayers padded layers with the 64 x 4 shape runs its
+// samples in two layer-count classes: 64 x 4 for those of at most kShortLayers layers,
+// 64 x 5 for the rest (both walk 64-wavenumber tiles, so the chunks agree).
+static bool adj_split(const Model& m, int variant) { return layer_classes_used(m) && variant == kAdjT64M4; }
+
+int adjoint_default_variant(const Model& m) { return m.L_pad <= 128 ? kAdjT128M4 : kAdjT64M4; }
 
 bool adjoint_variant_fits(const Model& m, int variant) {
-  if (m.L_pad > 32 * adj_mb(variant)) return false;
+  const bool split = adj_split(m, variant);
+  if (m.L_pad > 32 * adj_mb(split ? kAdjT64M5 : variant)) return false;
   // the greedy row-block split must never give a wave more blocks than it has slots
   for (int L = 1; L <= m.L_max; ++L) {
     const int KBe = (L + 15) >> 4, MBe = (L + 31) >> 5;
     for (int part = 0; part < 2; ++part)
       for (int rev = 0; rev < 2; ++rev)
-        if (__builtin_popcount(split_blocks(part, MBe, KBe, rev != 0)) > adj_slots(variant)) return false;
+        if (__builtin_popcount(split_blocks(part, MBe, KBe, rev != 0)) >
+            adj_slots(split && L > kShortLayers ? kAdjT64M5 : variant))
+          return false;
   }
   return true;
 }
@@ -1411,8 +1431,8 @@ bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std:
 static size_t adj_lds_bytes(const Model& m, bool fp64, int variant) {
   const size_t Lp = m.L_pad, ns = n_sums(m.S);
   if (fp64) return (size_t)2 * kTile64 * (Lp + 1) * 8 + Lp * ns * 8;
-  const size_t tile = adj_tile(variant);
-  return std::max(2 * tile * (Lp + 4) * 4 + Lp * 4, tile / 32 * Lp * 8);
+  const size_t tile = adj_tile(variant), rows = std::min(Lp, (size_t)32 * adj_mb(variant));
+  return std::max(2 * tile * (rows + 4) * 4 + rows * 4, tile / 32 * Lp * 8);
 }
 
 template <int S, bool CIA>
@@ -1466,13 +1486,17 @@ hipError_t adjoint_configure(const Model& m, bool fp64) {
   }
   bool any = false;
   for (int v = 0; v < kAdjVariants; ++v) {
-    const size_t bytes = adj_lds_bytes(m, false, v);
-    if (!adjoint_variant_fits(m, v) || bytes > 160 * 1024) continue;
-    const void* k = adj_kernel_for<false>(m.S, m.has_cia, v);
-    if (!k) return hipErrorInvalidValue;
-    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    any = true;
+    if (!adjoint_variant_fits(m, v)) continue;
+    // a split shape also launches 64 x 5 for the long class
+    for (int u : {v, adj_split(m, v) ? (int)kAdjT64M5 : v}) {
+      const size_t bytes = adj_lds_bytes(m, false, u);
+      if (bytes > 160 * 1024) continue;
+      const void* k = adj_kernel_for<false>(m.S, m.has_cia, u);
+      if (!k) return hipErrorInvalidValue;
+      const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+      if (e != hipSuccess) return e;
+      any = true;
+    }
   }
   return any ? hipSuccess : hipErrorInvalidValue;
 }
@@ -1495,10 +1519,19 @@ bool adjoint_set_tuning(AdjWork& aw, const Model& m, int variant, int chunk_targ
 void launch_trans_adjoint(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, bool fp64,
                           hipStream_t st) {
   int C = adjoint_chunks(m, aw, B, fp64);
-  void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&aw, (void*)&B, (void*)&C};
-  const void* k = fp64 ? adj_kernel_for<true>(m.S, m.has_cia, 0) : adj_kernel_for<false>(m.S, m.has_cia, aw.variant);
-  hipLaunchKernel(k, dim3((unsigned)(B * C)), dim3(fp64 ? kBlockT : adj_threads(aw.variant)), args,
-                  adj_lds_bytes(m, fp64, aw.variant), st);
+  if (fp64) {
+    void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&aw, (void*)&B, (void*)&C};
+    hipLaunchKernel(adj_kernel_for<true>(m.S, m.has_cia, 0), dim3((unsigned)(B * C)), dim3(kBlockT), args,
+                    adj_lds_bytes(m, true, 0), st);
+    return;
+  }
+  const int32_t* cls = adj_split(m, aw.variant) ? w.cls : nullptr;   // the forward built the classes
+  for (int cl = 0; cl < (cls ? 2 : 1); ++cl) {
+    const int v = cl == 1 ? (int)kAdjT64M5 : aw.variant;
+    void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&aw, (void*)&B, (void*)&C, (void*)&cls, (void*)&cl};
+    hipLaunchKernel(adj_kernel_for<false>(m.S, m.has_cia, v), dim3((unsigned)(B * C)), dim3(adj_threads(v)), args,
+                    adj_lds_bytes(m, false, v), st);
+  }
 }
 
 void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const AdjWork& aw, int B, bool fp64,

@@ -28,6 +28,7 @@ constexpr int kTileNu = 128;      // wavenumbers per tile of the reduced-precisi
 constexpr int kTile64 = 64;       // wavenumbers per tile of the FP64 and emission kernels
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kBlockT = 512;      // threads per workgroup of the reduced-precision transmission kernels
+constexpr int kShortLayers = 128;  // layer capacity of the short class of a ragged reduced-precision batch
 constexpr int kCkG = 8;           // g-points per bin of a correlated-k table
 constexpr int kCkBinsPerWave = 16;  // bins one wave of the k-distribution mixing kernel walks through
 // a chord optical depth beyond which e^-tau is zero in FP32 with a wide margin
@@ -90,6 +91,7 @@ __host__ __device__ inline bool clear_sample(const Model& m, int b) { return m.h
 struct Work {
   int32_t* status;      // [B]
   int32_t* nlay;        // [B] layers used per sample
+  int32_t* cls;         // layer-count classes (L_pad > kShortLayers, reduced-precision transmission): [2 + 2B]
   double* t_lay;        // [B][L_pad]
   double* t_lev;        // [B][L_pad+1]
   double* inv_tlev;     // reduced-precision emission: [B][L_pad+1] 1 / T at the levels (the Planck exponents)

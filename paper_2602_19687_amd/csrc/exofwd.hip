@@ -544,6 +544,7 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   const size_t rs = fp64 ? 8 : 4;
   w.status = A(dalloc<int32_t>(c, B));
   w.nlay = A(dalloc<int32_t>(c, B));
+  if (layer_classes_used(m) && !fp64) w.cls = A(dalloc<int32_t>(c, 2 + 2 * (size_t)B));
   w.t_lay = A(dalloc<double>(c, (size_t)B * Lp));
   w.t_lev = A(dalloc<double>(c, (size_t)B * (Lp + 1)));
   if (m.mode == kEmission && !fp64) w.inv_tlev = A(dalloc<double>(c, (size_t)B * (Lp + 1)));
@@ -741,6 +742,7 @@ static size_t carve_forward_work(const exofwd_ctx* c, int B, bool internal_spec,
   w = Work{};
   w.status = (int32_t*)take(4 * Bv);
   w.nlay = (int32_t*)take(4 * Bv);
+  if (layer_classes_used(m) && !fp64) w.cls = (int32_t*)take(4 * (2 + 2 * Bv));
   w.t_lay = (double*)take(8 * Bv * Lp);
   w.t_lev = (double*)take(8 * Bv * (Lp + 1));
   if (!trans && !fp64) w.inv_tlev = (double*)take(8 * Bv * (Lp + 1));

@@ -27,6 +27,11 @@ void launch_loglike(const Model& m, const Work& w, int B, const double* params, 
 // cloudy/clear mixing: grad[b] = gv[2b] + gv[2b+1], with d lnL / d f_cld from the likelihood kernel
 void launch_mix_grad(const Model& m, const Work& w, int B, double* grad, hipStream_t st);
 size_t trans_fwd_lds_bytes(const Model& m, bool fp64);
+// Layer-count classes of a reduced-precision transmission call whose padded layer count
+// exceeds kShortLayers: w.cls = [count0, count1, samples of class 0 (at most kShortLayers
+// layers, and invalid ones) longest first, then class 1 longest first, each list B long]
+inline bool layer_classes_used(const Model& m) { return m.mode == kTransmission && !m.ck && m.L_pad > kShortLayers; }
+void launch_layer_classes(const Model& m, const Work& w, int B, hipStream_t st);
 hipError_t trans_fwd_configure(const Model& m, bool fp64);
 
 }  // namespace exofwd

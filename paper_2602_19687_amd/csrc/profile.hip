@@ -376,6 +376,36 @@ __global__ __launch_bounds__(kBlock) void k_cloud_q(Model m, Work w) {
   for (int k = 0; k < kCloudSpec; ++k) out[(size_t)(1 + k) * m.n_nu_pad] = dq[k];
 }
 
+// Layer-count classes of the call: class 0 holds the samples of at most kShortLayers
+// layers (and invalid samples, which the kernels skip), class 1 the rest; each list is
+// ordered longest first (ties by sample index), so the most expensive work items start
+// first.  One workgroup; a sample's rank counts the samples ahead of it in its class.
+__global__ __launch_bounds__(kBlock) void k_layer_classes(Work w, int B) {
+  for (int b = threadIdx.x; b < B; b += kBlock) {
+    const int lb = w.status[b] ? 0 : w.nlay[b];
+    const int cb = lb > kShortLayers ? 1 : 0;
+    int rank = 0;
+    for (int q = 0; q < B; ++q) {
+      const int lq = w.status[q] ? 0 : w.nlay[q];
+      if ((lq > kShortLayers ? 1 : 0) == cb && (lq > lb || (lq == lb && q < b))) ++rank;
+    }
+    w.cls[2 + cb * B + rank] = b;
+  }
+  if (threadIdx.x < 2) {
+    int n = 0;
+    for (int q = 0; q < B; ++q) {
+      const int lq = w.status[q] ? 0 : w.nlay[q];
+      n += (lq > kShortLayers ? 1 : 0) == (int)threadIdx.x;
+    }
+    w.cls[threadIdx.x] = n;
+  }
+}
+
+void launch_layer_classes(const Model& m, const Work& w, int B, hipStream_t st) {
+  (void)m;
+  hipLaunchKernelGGL(k_layer_classes, dim3(1), dim3(kBlock), 0, st, w, B);
+}
+
 void launch_profile(const Model& m, const Work& w, int B, const double* params, const int32_t* n_layers,
                     bool fp64, hipStream_t st) {
   if (fp64) {

@@ -34,15 +34,24 @@ __device__ inline unsigned mblocks_for(int part, int MBe, int KBe) {
   return mine;
 }
 
+// `cls` (may be null): the layer-count classes of the call (layer_classes), whose class
+// `cl` this launch serves; `lt` is the LDS tile's layer capacity (>= every served
+// sample's layers, a multiple of 32)
 template <int S, bool CIA, bool NGC>
 __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Tables tb, int B, float* __restrict__ spec,
-                                                              float* __restrict__ dtau_out) {
+                                                              float* __restrict__ dtau_out, const int32_t* __restrict__ cls,
+                                                              int cl, int lt) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
   // samples fastest: neighbouring workgroups (one XCD) share table columns;
   // tiles fastest: they share one sample's profile
-  const int b = m.fwd_tile_major ? logical / m.n_tiles : logical % B;
+  int b = m.fwd_tile_major ? logical / m.n_tiles : logical % B;
   const int tile = m.fwd_tile_major ? logical % m.n_tiles : logical / B;
+  if (cls) {
+    // the class's samples, longest first; the grid covers the whole batch
+    if (b >= cls[cl]) return;
+    b = cls[2 + cl * B + b];
+  }
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int Lp = m.L_pad;
@@ -53,16 +62,16 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
     return;
   }
   const int L = w.nlay[b];
-  const int stride = Lp + 8;   // bf16 per wavenumber row of the B operand (keeps b128 reads conflict-free)
+  const int stride = lt + 8;   // bf16 per wavenumber row of the B operand (keeps b128 reads conflict-free)
   uint16_t* s_bhi = reinterpret_cast<uint16_t*>(lds);
   uint16_t* s_blo = s_bhi + kTileNu * stride;
   float* s_area = reinterpret_cast<float*>(s_blo + kTileNu * stride);
-  float* s_red = s_area + Lp;   // [8][32]
+  float* s_red = s_area + lt;   // [8][32]
   int* s_live = reinterpret_cast<int*>(s_red + 8 * 32);   // [0, MB): row block holds a chord below kOpaqueTau; [7]: frontier
   if (tid < 8) s_live[tid] = 0;
 
   const float* area = reinterpret_cast<const float*>(w.area) + (size_t)b * Lp;
-  for (int i = tid; i < Lp; i += kBlockT) s_area[i] = area[i];
+  for (int i = tid; i < lt; i += kBlockT) s_area[i] = area[i];
 
   // phase A: vertical optical depth of every layer -> bf16 hi/lo B operand in LDS
   const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * rec_len(S);
@@ -282,10 +291,12 @@ const void* fwd_kernel_for(int S, bool cia, bool ng) {
   return nullptr;
 }
 
-size_t trans_fwd_lds_bytes(const Model& m, bool fp64) {
+static size_t fwd_lds_bytes(const Model& m, bool fp64, int lt) {
   if (fp64) return (size_t)m.L_pad * kTile64 * 8 + 4 * kTile64 * 8;
-  return (size_t)2 * kTileNu * (m.L_pad + 8) * 2 + (size_t)m.L_pad * 4 + 8 * 32 * 4 + 8 * 4;
+  return (size_t)2 * kTileNu * (lt + 8) * 2 + (size_t)lt * 4 + 8 * 32 * 4 + 8 * 4;
 }
+
+size_t trans_fwd_lds_bytes(const Model& m, bool fp64) { return fwd_lds_bytes(m, fp64, m.L_pad); }
 
 hipError_t trans_fwd_configure(const Model& m, bool fp64) {
   const void* k = fp64 ? fwd_kernel_for<true>(m.S, m.has_cia, m.cloud_ng) : fwd_kernel_for<false>(m.S, m.has_cia, m.cloud_ng);
@@ -300,8 +311,25 @@ void launch_trans_fwd(const Model& m, const Work& w, const Tables& tb, int B, vo
     void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec};
     hipLaunchKernel(fwd_kernel_for<true>(m.S, m.has_cia, m.cloud_ng), dim3((unsigned)(m.n_tiles64 * B)), dim3(kBlock), args, lds, st);
   } else {
-    void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec, (void*)&dtau_out};
-    hipLaunchKernel(fwd_kernel_for<false>(m.S, m.has_cia, m.cloud_ng), dim3((unsigned)(m.n_tiles * B)), dim3(kBlockT), args, lds, st);
+    const void* k = fwd_kernel_for<false>(m.S, m.has_cia, m.cloud_ng);
+    if (layer_classes_used(m)) {
+      // samples of at most kShortLayers layers run with a kShortLayers-row LDS tile (two
+      // workgroups per CU), the rest with the full one; each launch's grid covers the batch
+      launch_layer_classes(m, w, B, st);
+      for (int cl = 0; cl < 2; ++cl) {
+        const int32_t* cls = w.cls;
+        int lt = cl == 0 ? kShortLayers : m.L_pad;
+        void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec, (void*)&dtau_out, (void*)&cls,
+                        (void*)&cl, (void*)&lt};
+        hipLaunchKernel(k, dim3((unsigned)(m.n_tiles * B)), dim3(kBlockT), args, fwd_lds_bytes(m, false, lt), st);
+      }
+      return;
+    }
+    const int32_t* cls = nullptr;
+    int cl = 0, lt = m.L_pad;
+    void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec, (void*)&dtau_out, (void*)&cls, (void*)&cl,
+                    (void*)&lt};
+    hipLaunchKernel(k, dim3((unsigned)(m.n_tiles * B)), dim3(kBlockT), args, lds, st);
   }
 }
 

@@ -37,7 +37,7 @@ def _model(wl, **kw):
 CHOICES = [
     [0, 0, 1024, 8], [1, 0, 1024, 8], [0, 1, 1024, 8], [0, 2, 1024, 8],
     [0, 0, 512, 4], [0, 0, 4096, 16], [1, 1, 2048, 16], [0, 1, 4096, 4], [1, 0, 4096, 32], [0, 2, 1024, 32],
-    [1, 2, 4096, 64],
+    [1, 2, 4096, 64], [1, 0, 8192, 16],
 ]
 
 
@@ -136,3 +136,35 @@ def test_graph_mode_rejects_null_stream(case):
                                C.c_void_p(lnl.data_ptr()), None, None)
     assert st == 1   # EXOFWD_ERR_ARG
     fm.close()
+
+
+@pytest.fixture(scope="module")
+def ragged_case():
+    # padded to 160 layers, layer counts on both sides of 128 (the two classes), with
+    # invalid-free prior draws of the grey-deck transmission setup
+    wl = reduced(3, n_nu=700, n_bins=20, batch=6, n_layers=150)
+    nl = np.array([150, 64, 129, 128, 97, 140], dtype=np.int32)
+    refs = [oracle.grad_complex_step(wl, wl["params"][b], n_layers=int(nl[b])) for b in range(6)]
+    specs = [oracle.forward(wl, wl["params"][b], n_layers=int(nl[b]))["spectrum"] for b in range(6)]
+    return wl, nl, refs, specs
+
+
+@pytest.mark.parametrize("choice", [[1, 1, 4096, 16], [1, 2, 4096, 16], [0, 1, 1024, 64], [1, 1, 8192, 8]],
+                         ids=["split", "unsplit", "split-samples-fastest", "split-8192"])
+def test_layer_classes_match_oracle(ragged_case, choice):
+    """A ragged batch of more than 128 padded layers: the forward kernel runs the
+    samples of at most 128 layers and the rest as two classes, and reverse shape 1
+    does the same (64 x 4 and 64 x 5); every choice agrees with the oracle."""
+    wl, nl, refs, specs = ragged_case
+    fm = _model(wl)
+    print(f"[gpu] layer classes {choice}", flush=True)
+    fm.set_tuning(choice)
+    th = torch.tensor(wl["params"], device="cuda")
+    lnl, g, st, sp = fm.grad(th, n_layers=nl, want_spectra=True)
+    g, st, sp = g.cpu().numpy(), st.cpu().numpy(), sp.double().cpu().numpy()
+    fm.close()
+    assert np.all(st == 0)
+    serr = max(float(np.max(np.abs(sp[b] - specs[b]) / np.abs(specs[b]))) for b in range(6))
+    gerr = max(grad_err(g[b], refs[b]) for b in range(6))
+    print(f"layer classes {choice}: spectrum {serr:.2e}, gradient {gerr:.2e}")
+    assert serr < TOL and gerr < TOL
