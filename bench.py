@@ -67,10 +67,11 @@ def kernel_model(kernel, Ls, S, n_nu, n_mu=4, ck_mix=0):
         return "mfma", 3 * 3 * int((Ls * (Ls + 1) // 2).sum()) * 2 * n_nu, BF16_MFMA_PEAK_TFLOPS, "TFLOP/s"
     if kernel == "ck_mix":
         # per (sample, layer, bin): S x 8 interpolations (4 FMA + add + exp2 = 10), then S - 1
-        # random-overlap merges of 64 pairs: pair sum (1), the 64-key bitonic network
-        # (672 compare-exchanges, min + max), two 64-long running sums (128) and the rebinning
+        # random-overlap merges of 64 pairs: pair sum (1), the merge of the eight sorted
+        # rows of the pair matrix (three bitonic merge levels, 15 steps of 32
+        # compare-exchanges, min + max), two 64-long running sums (128) and the rebinning
         # (7 edges x FMA + 8 differences x multiply = 22), and the continuum (11)
-        per_merge = 64 + 672 * 2 + 128 + 22
+        per_merge = 64 + 15 * 32 * 2 + 128 + 22
         return "alu", int(Ls.sum()) * n_nu * (S * 8 * 10 + (S - 1) * per_merge + 11), FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
     if kernel == "ck_spectrum":
         # the chord over the (bin, g-point) columns: L(L+1)/2 FMA per column as three bf16 MFMA products

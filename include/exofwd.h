@@ -166,7 +166,8 @@ typedef struct exofwd_config {
   double bd_distance;        /* its distance [cm] (has_bd) */
   /* Correlated-k tables (Section "Gas phase opacities"): with ck_g > 0, nu holds the
    * n_nu spectral bin centres (ascending) and log10_xsec is [n_species][n_t][n_p][n_nu][ck_g]:
-   * log10 k at ck_g g-points of each bin's cross-section distribution (ascending in g),
+   * log10 k at ck_g g-points of each bin's cross-section distribution (non-decreasing in g,
+ * else EXOFWD_ERR_CONFIG),
    * with weights ck_weights[ck_g] (each > 0, summing to 1).  log10_cia is given at the
    * bin centres.  The spectrum has one value per bin and the bins (bin_lo/bin_hi) group
    * spectral bins.  ck_g must be 8; MIXED precision only (FP32 table entries); no

@@ -11,16 +11,21 @@
 // transmission chord (Eq. 44) or the emission sweep (Eq. 45), and the bin's
 // spectrum is the g-weighted sum.
 //
-// k_ck_mix: one wave per (sample, layer) and a run of bins, one bin at a time:
-//   lane s*8 + g interpolates absorber s at g-point g (FP32 table entries relative
-//   to per-(absorber, column) offsets, bilinear in (T, log p), exp2 with the layer
-//   prefactor); a merge puts pair (a, b) on lane 8a + b, sorts the 64 pair sums
-//   across the wave (bitonic, keys = the value's bits above the low six, the pair
-//   index in the low six), forms the running weight and weight x value sums by a
-//   wave prefix scan and reads the rebinned means at the interval edges with a
-//   ballot.  Output: the mixed layer optical depths [B][L_pad][n_bins_pad x 8]
-//   (FP32), read by k_ck_trans (bf16x3 MFMA chord, as the cross-section path) or
-//   k_ck_emis (one lane per (bin, g-point) column sweeping up the layers).
+// k_ck_mix: one wave per (sample, layer) and a run of 16 bins, eight bins at a time,
+//   one per group of eight lanes.  Lane p of a group interpolates every absorber at
+//   g-point p (FP32 table entries relative to per-(absorber, column) offsets,
+//   bilinear in (T, log p), exp2 with the layer prefactor).  A merge gives lane p row
+//   p of the 8 x 8 pair matrix, mixture point p with each absorber point, which
+//   ascends because both distributions do; the 64 pair sums are sorted by the three
+//   merge levels of a bitonic network (DPP lane moves inside the group and
+//   compare-exchanges inside a lane; keys = the value's bits above the low six, the
+//   pair index in the low six), the exact sums and weights are looked up by index, and
+//   the integral of the sorted distribution over each g-interval comes from each
+//   element's overlap with it, in FP64, reduce-scattered over the group so that lane p
+//   receives its own interval.  Output: the mixed layer optical depths
+//   [B][L_pad][n_bins_pad x 8] (FP32), read by k_ck_trans (bf16x3 MFMA chord, as the
+//   cross-section path) or k_ck_emis (one lane per (bin, g-point) column sweeping up
+//   the layers).
 #include "ck.h"
 #include "emission.h"
 #include "kernels.h"
@@ -28,22 +33,112 @@
 
 namespace exofwd {
 
-// ascending bitonic sort of one 32-bit key per lane across the wave
-__device__ inline uint32_t wave_sort_u32(uint32_t key, int lane) {
+// DPP lane moves inside 8-lane groups (gfx9 encodings): quad_perm patterns and the
+// half-row (8-lane) mirror
+constexpr int kDppXor1 = 0xB1;     // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;     // quad_perm [2,3,0,1]
+constexpr int kDppQuadMirror = 0x1B;   // quad_perm [3,2,1,0]
+constexpr int kDppHalfMirror = 0x141;  // row_half_mirror: lane p <-> 7 - p of each 8
+constexpr int kDppShr1 = 0x111, kDppShr2 = 0x112, kDppShr4 = 0x114;   // row_shr:1, 2, 4
+
+template <int CTRL>
+__device__ inline uint32_t dpp_u(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
+}
+
+// One cross-lane step of the sorting network: register r meets the partner lane's
+// register r (or 7 - r with `rev`); the lower lane of the pair keeps the smaller key.
+template <int CTRL, bool REV>
+__device__ inline void net_cross(uint32_t (&k)[8], bool lower) {
+  uint32_t o[8];
 #pragma unroll
-  for (int k = 2; k <= 64; k <<= 1) {
+  for (int r = 0; r < 8; ++r) o[r] = dpp_u<CTRL>(k[REV ? 7 - r : r]);
 #pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      const uint32_t other = (uint32_t)__shfl_xor((int)key, j);
-      const bool up = (lane & k) == 0, low = (lane & j) == 0;
-      key = (low == up) ? min(key, other) : max(key, other);
+  for (int r = 0; r < 8; ++r) k[r] = lower ? min(k[r], o[r]) : max(k[r], o[r]);
+}
+// half-cleaner inside a lane: registers r and r + J (r & J == 0) ordered ascending
+template <int J>
+__device__ inline void net_local(uint32_t (&k)[8]) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+    if (!(r & J)) {
+      const uint32_t lo = min(k[r], k[r + J]), hi = max(k[r], k[r + J]);
+      k[r] = lo;
+      k[r + J] = hi;
     }
+}
+
+// Sort the 64 keys of an 8-lane group, element 8p + r on lane p, register r, when each
+// lane's eight registers already ascend: the three merge levels of a bitonic network
+// whose first step in each level pairs mirror images (so every run is merged ascending).
+__device__ inline void sort_group64(uint32_t (&k)[8], int p) {
+  // runs of 16: lanes p, p ^ 1
+  net_cross<kDppXor1, true>(k, (p & 1) == 0);
+  net_local<4>(k); net_local<2>(k); net_local<1>(k);
+  // runs of 32: lanes of a quad, mirrored, then p ^ 1
+  net_cross<kDppQuadMirror, true>(k, (p & 2) == 0);
+  net_cross<kDppXor1, false>(k, (p & 1) == 0);
+  net_local<4>(k); net_local<2>(k); net_local<1>(k);
+  // runs of 64: the 8 lanes mirrored, then p ^ 2, p ^ 1
+  net_cross<kDppHalfMirror, true>(k, (p & 4) == 0);
+  net_cross<kDppXor2, false>(k, (p & 2) == 0);
+  net_cross<kDppXor1, false>(k, (p & 1) == 0);
+  net_local<4>(k); net_local<2>(k); net_local<1>(k);
+}
+
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint64_t lo = dpp_u<CTRL>((uint32_t)u), hi = dpp_u<CTRL>((uint32_t)(u >> 32));
+  return __longlong_as_double((long long)(lo | (hi << 32)));
+}
+
+// exclusive prefix over the 8 lanes of a group (lane p gets the sum of lanes < p)
+__device__ inline double group_excl8(double x, int p) {
+  double s = x, t;
+  t = dpp_d<kDppShr1>(s);
+  s += p >= 1 ? t : 0.0;
+  t = dpp_d<kDppShr2>(s);
+  s += p >= 2 ? t : 0.0;
+  t = dpp_d<kDppShr4>(s);
+  s += p >= 4 ? t : 0.0;
+  return s - x;
+}
+
+// reduce-scatter over the 8 lanes of a group: lane p gets the sum over the lanes of
+// their d[p].  Three halving steps, each with a partner whose lane differs in the bit
+// that decides which half of the remaining entries a lane keeps.
+__device__ inline double group_reduce_scatter8(const double (&d)[8], int p) {
+  double h[4], q[2];
+  const bool k4 = p & 4, k2 = p & 2, k1 = p & 1;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {   // partner 7 - p: the other bit 2
+    const double keep = k4 ? d[i + 4] : d[i], send = k4 ? d[i] : d[i + 4];
+    h[i] = keep + dpp_d<kDppHalfMirror>(send);
   }
-  return key;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {   // partner p ^ 3: the same bit 2, the other bit 1
+    const double keep = k2 ? h[i + 2] : h[i], send = k2 ? h[i] : h[i + 2];
+    q[i] = keep + dpp_d<kDppQuadMirror>(send);
+  }
+  const double keep = k1 ? q[1] : q[0], send = k1 ? q[0] : q[1];
+  return keep + dpp_d<kDppXor1>(send);
+}
+
+// lane r of this lane's group of eight (ds_swizzle bit mode: and 0x18, or r)
+template <int R>
+__device__ inline float group_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x18 | (R << 5)));
 }
 
 template <int S, bool CIA>
 __global__ __launch_bounds__(kBlock) void k_ck_mix(Model m, Work w, Tables tb, int B) {
+  // per wave: the 64 pair sums of each of its 8 bins, looked up after the sort; per
+  // block: the 64 pair weights w_a w_b (FP64)
+  __shared__ float s_val[kBlock / 64][512];
+  __shared__ double s_wpair[64];
+  if (threadIdx.x < 64) s_wpair[threadIdx.x] = tb.ckwd[threadIdx.x >> 3] * tb.ckwd[threadIdx.x & 7];
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int b = blockIdx.z, l = blockIdx.y;
@@ -61,91 +156,125 @@ __global__ __launch_bounds__(kBlock) void k_ck_mix(Model m, Work w, Tables tb, i
   const __amdgpu_buffer_rsrc_t rh = make_rsrc(tb.h, (size_t)S * m.n_t * m.n_p * ncol * 4);
   const __amdgpu_buffer_rsrc_t rhc = make_rsrc(CIA ? (const void*)tb.hc : (const void*)tb.h,
                                                CIA ? (size_t)2 * m.n_tc * npad * 4 : 0);
-  // this lane's absorber and g-point, and its table row
-  const int sl = lane >> 3, gl = lane & 7;
-  const bool live = sl < S;
-  const float lam = live ? rl[kRecFixed + sl] : 0.0f;
-  const uint32_t row = live ? (uint32_t)((sl * m.n_t + it) * m.n_p + ip) * row_bytes : 0u;
-  const float* coff = tb.c + (size_t)(live ? sl : 0) * ncol;
-  // weight of g-point (lane & 7), its reciprocal, and the interval edges E_0..E_6
-  const float wg = tb.ckw[gl], inv_wg = 1.0f / wg;
-  float edge[kCkG - 1];
-#pragma unroll
-  for (int n = 0; n < kCkG - 1; ++n) edge[n] = tb.cke[n];
+  // eight bins per pass, one per group of eight lanes; lane p of a group is g-point p
+  // of its bin and row p of each merge's pair matrix
+  const int grp = lane >> 3, p = lane & 7;
+  const double inv_wg = 1.0 / tb.ckwd[p];
+  float* vals = s_val[wv] + grp * 64;
   float* out = w.ckmix + ((size_t)b * Lp + l) * ncol;
 
-  for (int t = 0; t < kCkBinsPerWave; ++t) {
-    const int j = j0 + t;
-    if (j >= m.n_nu) break;
-    const uint32_t col = (uint32_t)(j * kCkG + gl);
-    float sp = 0.0f;
-    if (live) {
-      const uint32_t voff = col * 4u;
-      float v = coff[col] + lam;
+  for (int t = 0; t < kCkBinsPerWave; t += 8) {
+    const int jr = j0 + t + grp;
+    const bool real = jr < m.n_nu;
+    const int j = real ? jr : m.n_nu - 1;   // a group past the last bin repeats it and stores nothing
+    const uint32_t col = (uint32_t)(j * kCkG + p);
+    // this lane's g-point of every absorber
+    float sp[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t row = (uint32_t)((s * m.n_t + it) * m.n_p + ip) * row_bytes, voff = col * 4u;
+      float v = tb.c[(size_t)s * ncol + col] + rl[kRecFixed + s];
       v = fmaf(w00, load_f32(rh, voff, row), v);
       v = fmaf(w10, load_f32(rh, voff, row + tstep), v);
       v = fmaf(w01, load_f32(rh, voff, row + row_bytes), v);
       v = fmaf(w11, load_f32(rh, voff, row + tstep + row_bytes), v);
-      sp = exp2_fast(v);
+      sp[s] = exp2_fast(v);
     }
-    // the running mixture, g-point (lane & 7) on every lane: absorber 0 to start
-    float mix = __shfl(sp, gl);
+    float mix = sp[0];   // the running mixture at g-point p: absorber 0 to start
 #pragma unroll
     for (int s = 1; s < S; ++s) {
-      // pair (a, c) = (lane >> 3, lane & 7): mixture point a with absorber s point c
-      const float v = __shfl(mix, sl) + __shfl(sp, 8 * s + gl);
-      // optical depths are >= 0, so the bit patterns order like the values; the low
-      // six bits carry the pair index (pairs within 64 ulp may swap: <4e-6 relative)
-      const uint32_t key = wave_sort_u32((__float_as_uint(v) & ~63u) | (uint32_t)lane, lane);
-      const int idx = (int)(key & 63u);
-      const float vv = __shfl(mix, idx >> 3) + __shfl(sp, 8 * s + (idx & 7));
-      const float ww = __shfl(wg, idx >> 3) * __shfl(wg, idx & 7);
-      // running sums along the sorted order: weight (g at the element's upper end) and weight x value
-      float c = ww, p = ww * vv;
+      // row p of the pair matrix: mixture point p with each point r of absorber s, which
+      // ascends in r (a k-table row ascends in g)
+      float v[8];
+      v[0] = mix + group_bcast<0>(sp[s]);
+      v[1] = mix + group_bcast<1>(sp[s]);
+      v[2] = mix + group_bcast<2>(sp[s]);
+      v[3] = mix + group_bcast<3>(sp[s]);
+      v[4] = mix + group_bcast<4>(sp[s]);
+      v[5] = mix + group_bcast<5>(sp[s]);
+      v[6] = mix + group_bcast<6>(sp[s]);
+      v[7] = mix + group_bcast<7>(sp[s]);
+      // the previous merge's lookups are done before the table is rewritten
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      uint32_t key[8];
 #pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const float c2 = __shfl_up(c, off), p2 = __shfl_up(p, off);
-        if (lane >= off) {
-          c += c2;
-          p += p2;
-        }
+      for (int r = 0; r < 8; ++r) {
+        vals[8 * p + r] = v[r];
+        // optical depths are >= 0, so the bit patterns order like the values; the low
+        // six bits carry the pair index (pairs within 64 ulp may swap: < 4e-6 relative)
+        key[r] = (__float_as_uint(v[r]) & ~63u) | (uint32_t)(8 * p + r);
       }
-      const float c_up = __shfl_up(c, 1), p_up = __shfl_up(p, 1);
-      const float c_lo = lane ? c_up : 0.0f;
-      const float p_lo = lane ? p_up : 0.0f;
-      // integral of the sorted distribution up to each interior edge, from the one
-      // element whose g-interval [c_lo, c) holds it
-      float I[kCkG];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      sort_group64(key, p);
+      // The group's 64 pairs in sorted order, element 8p + r on lane p, and where each
+      // ends on the g axis, U_r.  The g bookkeeping runs in FP64: an interval edge often
+      // falls exactly on an element boundary (a negligible absorber leaves the pairs in
+      // blocks of one mixture point, whose weights sum to the edge), and there an FP32
+      // rounding of the running weight would move a sliver of the next, possibly far
+      // larger, value into the interval.
+      double vd[8], U[8];
+      double cs = 0.0;
 #pragma unroll
-      for (int n = 0; n < kCkG - 1; ++n) {
-        const uint64_t own = __builtin_amdgcn_ballot_w64(c_lo <= edge[n] && edge[n] < c);
-        const int owner = own ? (int)__builtin_ctzll(own) : 63;
-        I[n] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fmaf(edge[n] - c_lo, vv, p_lo)), owner));
+      for (int r = 0; r < 8; ++r) {
+        const uint32_t idx = key[r] & 63u;
+        vd[r] = (double)vals[idx];
+        U[r] = s_wpair[idx];
+        cs += U[r];
       }
-      I[kCkG - 1] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p), 63));
-      float hi = I[0], lo = 0.0f;
+      const double c_lane = group_excl8(cs, p);
+      double run = c_lane;
 #pragma unroll
-      for (int n = 1; n < kCkG; ++n)
-        if (gl == n) {
-          hi = I[n];
-          lo = I[n - 1];
+      for (int r = 0; r < 8; ++r) {
+        run += U[r];
+        U[r] = run;
+      }
+      // D[n]: this lane's share of the integral of the sorted distribution over the
+      // g-interval [E_{n-1}, E_n], from the overlap of each element [U_{r-1}, U_r) with it
+      double D[8], prev = 0.0;
+#pragma unroll
+      for (int n = 0; n < kCkG; ++n) {
+        double part = 0.0;
+        if (n < kCkG - 1) {
+          const double E = tb.cke[n];
+          double lo = fmin(E, c_lane);
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            const double hi = fmin(E, U[r]);
+            part = fma(vd[r], hi - lo, part);
+            lo = hi;
+          }
+        } else {
+          double lo = c_lane;
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            part = fma(vd[r], U[r] - lo, part);
+            lo = U[r];
+          }
         }
-      mix = (hi - lo) * inv_wg;
+        D[n] = part - prev;
+        prev = part;
+      }
+      // lane p: the integral over its own interval, summed over the group, / w_p
+      mix = (float)(group_reduce_scatter8(D, p) * inv_wg);
     }
     // grey continuum at the bin centre: deck, Rayleigh and the two CIA pairs
     float dc = fmaf(ray, tb.nu4f[j], deck);
     if (CIA) {
 #pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        const uint32_t rowc = (uint32_t)(p * m.n_tc + itc) * (uint32_t)npad * 4u;
+      for (int q = 0; q < 2; ++q) {
+        const uint32_t rowc = (uint32_t)(q * m.n_tc + itc) * (uint32_t)npad * 4u;
         const uint32_t vo = (uint32_t)j * 4u;
-        float v = tb.cc[(size_t)p * npad + j] + rl[5 + p];
+        float v = tb.cc[(size_t)q * npad + j] + rl[5 + q];
         v = fmaf(1.0f - wtc, load_f32(rhc, vo, rowc), v);
         v = fmaf(wtc, load_f32(rhc, vo, rowc + (uint32_t)npad * 4u), v);
         dc += exp2_fast(v);
       }
     }
-    if (lane < kCkG) out[col] = mix + dc;
+    if (real) out[col] = mix + dc;
   }
 }
 

@@ -133,7 +133,8 @@ struct Tables {
   const double* tc64;    // fp64: [2][n_tc][n_nu_pad] log10 k
   const double* nu4d;    // fp64: [n_nu_pad]
   const float* ckw;      // correlated-k: [kCkG] g-point weights
-  const float* cke;      // correlated-k: [kCkG] upper edges of the g-intervals (running sums of the weights)
+  const double* ckwd;    // correlated-k: [kCkG] g-point weights in FP64 (the mixing's bookkeeping)
+  const double* cke;     // correlated-k: [kCkG] upper edges of the g-intervals (running sums of the weights)
 };
 
 }  // namespace exofwd

@@ -346,6 +346,15 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
     return create_fail(E, "log10_xsec holds a non-finite entry");
   if (g.has_cia && !all_finite(g.log10_cia, (size_t)2 * g.n_tc * g.n_nu))
     return create_fail(E, "log10_cia holds a non-finite entry");
+  // a k-table row is a cumulative distribution's inverse: non-decreasing in g (the
+  // mixing kernel merges the rows as sorted runs)
+  if (g.ck_g) {
+    const size_t rows = (size_t)g.n_species * g.n_t * g.n_p * g.n_nu;
+    for (size_t r = 0; r < rows; ++r)
+      for (int q = 1; q < g.ck_g; ++q)
+        if (g.log10_xsec[r * g.ck_g + q] < g.log10_xsec[r * g.ck_g + q - 1])
+          return create_fail(E, "log10_xsec: a k-table row decreases in g");
+  }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || g.device < 0 || g.device >= ndev)
     return create_fail(EXOFWD_ERR_DEVICE, "no HIP device with ordinal " + std::to_string(g.device));
@@ -503,17 +512,21 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
     c->tb.c = dc;
     c->tb.nu4f = dn4;
     if (m.ck) {
-      float wv[kCkG], ev[kCkG];
+      float wv[kCkG];
+      double wd[kCkG], ev[kCkG];
       double run = 0.0;
       for (int i = 0; i < kCkG; ++i) {
         wv[i] = (float)g.ck_weights[i];
+        wd[i] = g.ck_weights[i];
         run += g.ck_weights[i];
-        ev[i] = (float)run;
+        ev[i] = run;
       }
       float* dw = A(dalloc<float>(c, kCkG));
-      float* de = A(dalloc<float>(c, kCkG));
-      if (ok) ok = upload(dw, wv, kCkG) && upload(de, ev, kCkG);
+      double* dwd = A(dalloc<double>(c, kCkG));
+      double* de = A(dalloc<double>(c, kCkG));
+      if (ok) ok = upload(dw, wv, kCkG) && upload(dwd, wd, kCkG) && upload(de, ev, kCkG);
       c->tb.ckw = dw;
+      c->tb.ckwd = dwd;
       c->tb.cke = de;
     }
     if (m.has_cia) {

@@ -202,3 +202,22 @@ def test_create_refuses_non_finite_tables(what, value):
         assert lib.exofwd_create(C.byref(cfg), C.byref(ctx)) == L.ERR_CONFIG
         assert ctx.value is None
         assert "non-finite" in lib.exofwd_last_error(None).decode()
+
+
+def test_create_refuses_k_table_decreasing_in_g():
+    """A k-table row is the inverse of a cumulative distribution, so it never
+    decreases in g; the mixing kernel merges the rows as sorted runs, and creation
+    refuses a row that breaks the order."""
+    import synth
+    from paper_2602_19687_amd.model import build_config
+    lib = pkg.load()
+    wl = dict(synth.workload(7, batch=2))
+    tab = np.array(wl["log10_xsec"], copy=True)
+    row = tab[2, 5, 7, 100]
+    row[3], row[4] = row[4] + 0.5, row[3]
+    wl["log10_xsec"] = tab
+    cfg, keep = build_config(wl, L.PREC_MIXED, 2)
+    ctx = C.c_void_p()
+    assert lib.exofwd_create(C.byref(cfg), C.byref(ctx)) == L.ERR_CONFIG
+    assert ctx.value is None
+    assert "decreases in g" in lib.exofwd_last_error(None).decode()

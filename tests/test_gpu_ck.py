@@ -70,6 +70,40 @@ def test_ck_ragged_layers(cid, mix):
     _compare(wl, wl["params"], n_layers=nl, label=f"ragged mix {mix}")
 
 
+# RORR with one absorber dominating: the pairs of a merge then sort in blocks of
+# one g-point of the larger distribution, and the g-interval edges fall exactly on
+# block boundaries; the mixing keeps its g bookkeeping in FP64 so that rounding does
+# not move part of the next block's (far larger) value across an edge.  Tolerance:
+# 2e-5 (the path's other roundings give below 3e-6 on these spectra; running
+# weights rounded to FP32 give errors up to 4e-3 in single mixed g-points).
+TOL_DOMINANT = 2e-5
+
+
+@pytest.mark.parametrize("cid", [7, 8], ids=["trans", "emis"])
+def test_ck_rorr_dominant_absorber(cid):
+    wl = reduced_ck(cid, n_ck=130, n_bins=10, batch=4, step=15)
+    wl["ck_mix"] = synth.CK_MIX_RORR
+    first = 3 if cid == 7 else 5
+    S = wl["log10_xsec"].shape[0]
+    th = np.repeat(wl["params"][:1], 4, axis=0)
+    th[:, first:first + S] = -12.0
+    for b, dom in enumerate((0, S - 1, S // 2)):
+        th[b, first + dom] = -2.5
+    th[3, first] = th[3, first + 1] = -3.0          # two comparable absorbers, the rest negligible
+    print(f"[gpu] ck dominant absorber cid={cid}", flush=True)
+    fm = _model(wl, 4)
+    spec, lnl, st = fm.forward(torch.tensor(th, device="cuda"))
+    spec = spec.double().cpu().numpy()
+    fm.close()
+    errs = []
+    for b in range(4):
+        ref = oracle.forward(wl, th[b])
+        assert st[b].item() == ref["status"] == 0
+        errs.append(rel_err(spec[b], ref["spectrum"]))
+    print(f"ck dominant absorber c{cid}: spectrum max rel err {max(errs):.3e}")
+    assert max(errs) < TOL_DOMINANT, errs
+
+
 def test_ck_invalid_samples():
     wl = reduced_ck(8, n_ck=64, n_bins=4, batch=3, step=30)
     th = wl["params"].copy()
