@@ -84,37 +84,43 @@ def kernel_model(kernel, Ls, S, n_nu, n_mu=4, ck_mix=0):
     raise ValueError(kernel)
 
 
-def sources_digest():
-    """SHA-256 over the kernel sources; a counter summary holds the digest of the
-    sources it was taken with."""
+def source_digest(hip_name):
+    """SHA-256 over one kernel source file and the csrc headers it includes
+    (transitively); a counter summary records it per kernel, so a change to one
+    kernel's sources voids only that kernel's figures."""
     import hashlib
-    d = hashlib.sha256()
+    import re
     csrc = os.path.join(ROOT, "paper_2602_19687_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                d.update(name.encode() + b"\0" + f.read())
+    seen, todo = set(), [hip_name]
+    while todo:
+        name = todo.pop()
+        if name in seen or not os.path.exists(os.path.join(csrc, name)):
+            continue
+        seen.add(name)
+        with open(os.path.join(csrc, name)) as f:
+            todo += re.findall(r'^#include "([^"]+)"', f.read(), flags=re.M)
+    d = hashlib.sha256()
+    for name in sorted(seen):
+        with open(os.path.join(csrc, name), "rb") as f:
+            d.update(name.encode() + b"\0" + f.read())
     return d.hexdigest()
 
 
 def measured_traffic(kernel, workload_tag="transmission_ns_b1024"):
     """HBM bytes per launch of `kernel` from the committed PMC summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by a copy-kernel calibration), or
-    None when the summary is missing or the kernel sources have changed since."""
+    None when the summary is missing or the kernel's sources have changed since
+    (each line names the source file and its digest)."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload_tag}.md")
     if not os.path.exists(path):
         return None
-    digest, traffic = None, {}
     with open(path) as f:
         for line in f:
-            if line.startswith("sources_sha256:"):
-                digest = line.split(":", 1)[1].strip()
-            elif line.startswith("traffic_bytes_per_launch:"):
-                k, v = line.split(":", 1)[1].split()
-                traffic[k] = float(v)
-    if digest != sources_digest():
-        return None
-    return traffic.get(kernel)
+            if line.startswith("traffic_bytes_per_launch:"):
+                parts = line.split(":", 1)[1].split()
+                if len(parts) == 4 and parts[0] == kernel:
+                    return float(parts[1]) if source_digest(parts[2]) == parts[3] else None
+    return None
 
 
 _WL = {}

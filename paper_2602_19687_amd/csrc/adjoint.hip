@@ -24,6 +24,12 @@ namespace exofwd {
 
 typedef __attribute__((ext_vector_type(4))) double f64x4;
 
+// a float pair read once (stored dtau_bar): a non-temporal load
+__device__ inline float2 ld_stream2(const float* p) {
+  const float2v v = __builtin_nontemporal_load(reinterpret_cast<const float2v*>(p));
+  return make_float2(v.x, v.y);
+}
+
 __device__ inline float wave_sum(float v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -199,7 +205,7 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
       const uint32_t soff = (uint32_t)((8 * o * npad + (size_t)tile * kTileA) * 4);
 #pragma unroll
       for (int j = 0; j < 8; ++j)
-        pf[q][j] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs_dt, voff, soff + j * rowb, 0);
+        pf[q][j] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs_dt, voff, soff + j * rowb, kCpolStream);
     }
   };
   auto stage = [&](int tile) {
@@ -369,7 +375,7 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
           // rows [L, 32 MBe) land in this sample's padding rows, which nothing reads
           // element copied to a scalar first: a bit_cast of a vector element lowers to element 0
           __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((float)acc[j]), rs_db,
-                                                (uint32_t)((row * npad + col) * 4), 0, 0);
+                                                (uint32_t)((row * npad + col) * 4), 0, kCpolStream);
         }
       }
     }
@@ -488,7 +494,7 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
 #pragma unroll
     for (int q = 0; q < kLs; ++q) {
       dbq[q] = (l0 + q < L && l0 + q >= lo_row)
-                   ? *reinterpret_cast<const float2*>(dtb + (size_t)(l0 + q) * npad + nu0 + 2 * lane)
+                   ? ld_stream2(dtb + (size_t)(l0 + q) * npad + nu0 + 2 * lane)
                    : make_float2(0.0f, 0.0f);
       live |= dbq[q].x != 0.0f || dbq[q].y != 0.0f;
     }

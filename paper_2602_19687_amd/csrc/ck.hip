@@ -274,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_ck_mix(Model m, Work w, Tables tb, i
         dc += exp2_fast(v);
       }
     }
-    if (real) out[col] = mix + dc;
+    if (real) __builtin_nontemporal_store(mix + dc, &out[col]);   // read once, by the spectrum kernel
   }
 }
 
@@ -316,7 +316,10 @@ __global__ __launch_bounds__(kBlockT) void k_ck_trans(Model m, Work w, Tables tb
     for (int q = 0; q < 8; ++q) {
       const int l = 8 * o + q;
       float2 d = make_float2(0.0f, 0.0f);
-      if (l < L && real) d = *reinterpret_cast<const float2*>(src + (size_t)l * ncol);
+      if (l < L && real) {
+        const float2v v = __builtin_nontemporal_load(reinterpret_cast<const float2v*>(src + (size_t)l * ncol));
+        d = make_float2(v.x, v.y);
+      }
       e0[q] = fminf(d.x, 16384.0f);
       e1[q] = fminf(d.y, 16384.0f);
     }
@@ -594,7 +597,7 @@ __global__ __launch_bounds__(kBlock) void k_ck_emis(Model m, Work w, Tables tb, 
   }
   const bool real = j < m.n_nu;   // columns of padding bins hold nothing
   for (int l = 0; l < L; ++l) {
-    const float d = real ? dt[(size_t)l * ncol] : 0.0f;
+    const float d = real ? __builtin_nontemporal_load(&dt[(size_t)l * ncol]) : 0.0f;
     const float b_top = planck_at(l + 1);
     const float db = b_bot - b_top;
 #pragma unroll

@@ -26,6 +26,10 @@ constexpr int kMaxKnots = 8;
 constexpr int kMaxMu = 8;
 constexpr int kTileNu = 128;      // wavenumbers per tile of the reduced-precision transmission kernels
 constexpr int kTile64 = 64;       // wavenumbers per tile of the FP64 and emission kernels
+// cache policy of a buffer access that streams data read or written once (the
+// non-temporal bit of gfx950's buffer instructions): it keeps the table lines and
+// path-matrix fragments that other accesses reuse in L2
+constexpr int kCpolStream = 2;
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kBlockT = 512;      // threads per workgroup of the reduced-precision transmission kernels
 constexpr int kShortLayers = 128;  // layer capacity of the short class of a ragged reduced-precision batch

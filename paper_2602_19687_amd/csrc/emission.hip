@@ -227,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_emission_mixed(Model m, Work w, Tabl
       }
     }
     // the reverse pass reads the layer optical depths back
-    if (dtau_out) dtau_out[((size_t)b * Lp + l) * npad + nu] = d;
+    if (dtau_out) __builtin_nontemporal_store(d, &dtau_out[((size_t)b * Lp + l) * npad + nu]);
     // ---- the sweep through layer l for every angle
     const float b_top = planck_at(l + 1);
     const float db = b_bot - b_top;

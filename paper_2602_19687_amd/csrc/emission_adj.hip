@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_emis_adj_mixed(Model m, Work w, AdjW
       bb_lev = fmaf(ib, src, bb_lev);
       inten[k] = fmaf(om, b_top - inten[k], fmaf(db, src, inten[k]));
     }
-    dtb[(size_t)l * npad] = dsum;
+    __builtin_nontemporal_store(dsum, &dtb[(size_t)l * npad]);   // read once, by the layer sums
     const float lev = wave_sum_f(bb_lev * dbdt_bot);
     if (lane == 0) ps[l] = lev;
     bb_lev = bt_bar;
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_emis(Model m, Work w, Tab
     bool live = false;
 #pragma unroll
     for (int q = 0; q < kLayers; ++q) {
-      dbv[q] = q < cnt ? dtb[(size_t)(l0 + q) * npad + nu] : 0.0f;
+      dbv[q] = q < cnt ? __builtin_nontemporal_load(&dtb[(size_t)(l0 + q) * npad + nu]) : 0.0f;
       live |= dbv[q] != 0.0f;
     }
     if (__builtin_amdgcn_ballot_w64(live) == 0) continue;

@@ -194,8 +194,9 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
       const int nu = e & (kTileNu - 1), k = k0 + e / kTileNu;
       const int a = nu * (stride >> 1) + k;
       const uint32_t hp = ph[a], lp = pl[a];
-      dt[(size_t)(2 * k) * npad + nu] = __builtin_amdgcn_perm(lp, hp, 0x05040100u);
-      if (2 * k + 1 < L) dt[(size_t)(2 * k + 1) * npad + nu] = __builtin_amdgcn_perm(lp, hp, 0x07060302u);
+      __builtin_nontemporal_store(__builtin_amdgcn_perm(lp, hp, 0x05040100u), &dt[(size_t)(2 * k) * npad + nu]);
+      if (2 * k + 1 < L)
+        __builtin_nontemporal_store(__builtin_amdgcn_perm(lp, hp, 0x07060302u), &dt[(size_t)(2 * k + 1) * npad + nu]);
     }
   }
 }
