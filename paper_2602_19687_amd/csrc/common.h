@@ -67,6 +67,7 @@ struct Model {
   int mode, tp_kind, n_knots, S, L_max, L_pad, P;
   int has_cia, has_ray, has_cloud, has_scale, has_offset, n_mu;
   int n_nu, n_nu_pad, n_tiles, n_tiles64, n_t, n_p, n_tc, K;
+  int ll_lanes;         // lanes that sum one bin in the likelihood kernel (8, 16, 32 or 64)
   int idx_cloud, idx_scale, idx_offset, n_tp;
   int fwd_tile_major;       // reduced-precision forward grid order: 0 samples fastest, 1 tiles fastest
   int cloud_ng;             // 1: non-grey cloud (q_c profile x Q_ext(nu)); 0: grey deck or none

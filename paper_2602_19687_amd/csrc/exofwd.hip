@@ -399,6 +399,11 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   m.n_p = g.n_p;
   m.n_tc = g.has_cia ? g.n_tc : 2;
   m.K = g.n_bins;
+  {
+    // lanes per bin in the likelihood sums: about one wavenumber per lane or more
+    const double mean = (double)(g.bin_hi[g.n_bins - 1] - g.bin_lo[0]) / g.n_bins;
+    m.ll_lanes = mean >= 64 ? 64 : mean >= 32 ? 32 : mean >= 16 ? 16 : 8;
+  }
   switch (g.tp_kind) {
     case EXOFWD_TP_ISOTHERMAL: m.n_tp = 1; break;
     case EXOFWD_TP_GUILLOT3: m.n_tp = 3; break;
