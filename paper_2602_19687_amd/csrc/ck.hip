@@ -383,27 +383,30 @@ __global__ __launch_bounds__(kBlockT) void k_ck_trans(Model m, Work w, Tables tb
 }
 
 // Transmission with random overlap along each chord (the product of the absorbers'
-// transmission functions): columns (bin, absorber slot s < 8, g-point), 64 per bin
-// and two bins per 128-column tile; absorber 0's columns also carry the grey
-// continuum (exact: the chord is linear, so its factor e^-tau_c multiplies absorber
-// 0's g-sum).  Per chord row the absorption of absorber s is
-// A_s = sum_g w_g (1 - e^-tau_s,g), and the absorbers combine as
-// A (+) B = A + B - A B (= 1 - (1 - A)(1 - B), without the cancellation of a thin
-// chord's 1 - product of transmissions); slots s >= S have zero depth (A = 0).
+// transmission functions): a tile of 16 bins x 8 g-points (128 columns) runs one
+// pass per absorber; absorber 0's columns also carry the grey continuum (exact: the
+// chord is linear, so its factor e^-tau_c multiplies absorber 0's g-sum).  Per chord
+// row the absorption of absorber s is A_s = sum_g w_g (1 - e^-tau_s,g), and the
+// passes combine it as A (+) A_s = A + A_s - A A_s (= 1 - (1 - A)(1 - A_s), without
+// the cancellation of a thin chord's 1 - product of transmissions), kept in LDS per
+// (bin, row).  One absorber per pass keeps a wave's table loads on 16 contiguous
+// bins of one table row.
+constexpr int kProdBins = kTileNu / kCkG;   // bins per tile
+
 template <int S, bool CIA>
 __global__ __launch_bounds__(kBlockT) void k_ck_trans_prod(Model m, Work w, Tables tb, int B,
                                                            float* __restrict__ spec) {
   extern __shared__ __align__(16) unsigned char lds[];
-  const int n_ct = (m.n_nu + 1) / 2;   // two bins per tile
+  const int n_bt = (m.n_nu + kProdBins - 1) / kProdBins;   // bin tiles per sample
   const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int b = logical / n_ct, tile = logical % n_ct;
+  const int b = logical / n_bt, tile = logical % n_bt;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int Lp = m.L_pad;
-  const int j0 = 2 * tile;
+  const int j0 = kProdBins * tile;
   float* out = spec + (size_t)b * m.n_nu;
   if (w.status[b]) {
-    if (tid < 2 && j0 + tid < m.n_nu) out[j0 + tid] = __builtin_nanf("");
+    if (tid < kProdBins && j0 + tid < m.n_nu) out[j0 + tid] = __builtin_nanf("");
     return;
   }
   const int L = w.nlay[b];
@@ -411,24 +414,20 @@ __global__ __launch_bounds__(kBlockT) void k_ck_trans_prod(Model m, Work w, Tabl
   uint16_t* s_bhi = reinterpret_cast<uint16_t*>(lds);
   uint16_t* s_blo = s_bhi + kTileNu * stride;
   float* s_area = reinterpret_cast<float*>(s_blo + kTileNu * stride);
-  float* s_abs = s_area + Lp;          // [4 column blocks][Lp] absorption of four absorbers per row
-  float* s_red = s_abs + 4 * Lp;       // [8] wave partial sums
+  float* s_abs = s_area + Lp;   // [kProdBins][Lp]: combined absorption per bin and chord row
   const float* area = reinterpret_cast<const float*>(w.area) + (size_t)b * Lp;
   for (int i = tid; i < Lp; i += kBlockT) s_area[i] = area[i];
-  for (int i = tid; i < 4 * Lp; i += kBlockT) s_abs[i] = 0.0f;
 
-  // this lane's two columns: bin jj, absorber slot sl, g-points gl and gl + 1
-  const int c2 = 2 * lane, jj = c2 >> 6, sl = (c2 >> 3) & 7, gl = c2 & 7;
-  const int j = min(j0 + jj, m.n_nu - 1);
-  const bool live = sl < S && j0 + jj < m.n_nu;
+  // this lane's two columns: bin jj of the tile, g-points g and g + 1
+  const int c2 = 2 * lane, jj = c2 >> 3, g = c2 & 7;
+  const bool real = j0 + jj < m.n_nu;   // columns of bins past the last hold nothing
+  const int j = real ? j0 + jj : m.n_nu - 1;
   const size_t npad = (size_t)m.n_nu_pad, ncol = npad * kCkG;
   const uint32_t row_bytes = (uint32_t)ncol * 4u, tstep = (uint32_t)m.n_p * row_bytes;
   const __amdgpu_buffer_rsrc_t rh = make_rsrc(tb.h, (size_t)S * m.n_t * m.n_p * ncol * 4);
   const __amdgpu_buffer_rsrc_t rhc = make_rsrc(CIA ? (const void*)tb.hc : (const void*)tb.h,
                                                CIA ? (size_t)2 * m.n_tc * npad * 4 : 0);
-  const uint32_t col = (uint32_t)(j * kCkG + gl);
-  const float* coff = tb.c + (size_t)(live ? sl : 0) * ncol + col;
-  const float cof0 = live ? coff[0] : 0.0f, cof1 = live ? coff[1] : 0.0f;
+  const uint32_t col = (uint32_t)(j * kCkG + g), vo = col * 4u;
   const float nu4 = tb.nu4f[j];
   float cc[2] = {0.0f, 0.0f};
   if (CIA) {
@@ -438,74 +437,7 @@ __global__ __launch_bounds__(kBlockT) void k_ck_trans_prod(Model m, Work w, Tabl
   constexpr int RL = rec_len(S);
   const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * RL;
   const int32_t* cells = w.cells + (size_t)b * Lp;
-
-  // phase A: every layer's optical depth of the tile's columns -> bf16 hi/lo B operand in LDS
-  const int KBe = (L + 15) >> 4;
-  for (int o = wv; o < 2 * KBe; o += kBlockT / 64) {
-    float e0[8], e1[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int l = 8 * o + q;
-      float d0 = 0.0f, d1 = 0.0f;
-      if (l < L && live) {
-        const float* rl = rec + (size_t)l * RL;
-        const int cl = cells[l];
-        const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
-        const float wt = rl[0], wp = rl[1];
-        const float w11 = wt * wp, w10 = wt - w11, w01 = wp - w11, w00 = 1.0f - wt - wp + w11;
-        const uint32_t row = (uint32_t)((sl * m.n_t + it) * m.n_p + ip) * row_bytes;
-        const uint32_t vo = col * 4u;
-        const float lam = rl[kRecFixed + sl];
-        float v0 = cof0 + lam, v1 = cof1 + lam;
-        v0 = fmaf(w00, load_f32(rh, vo, row), v0);
-        v1 = fmaf(w00, load_f32(rh, vo + 4u, row), v1);
-        v0 = fmaf(w10, load_f32(rh, vo, row + tstep), v0);
-        v1 = fmaf(w10, load_f32(rh, vo + 4u, row + tstep), v1);
-        v0 = fmaf(w01, load_f32(rh, vo, row + row_bytes), v0);
-        v1 = fmaf(w01, load_f32(rh, vo + 4u, row + row_bytes), v1);
-        v0 = fmaf(w11, load_f32(rh, vo, row + tstep + row_bytes), v0);
-        v1 = fmaf(w11, load_f32(rh, vo + 4u, row + tstep + row_bytes), v1);
-        d0 = exp2_fast(v0);
-        d1 = exp2_fast(v1);
-        if (sl == 0) {
-          // the grey continuum at the bin centre rides on absorber 0
-          float dc = fmaf(rl[3], nu4, rl[4]);
-          if (CIA) {
-            const float wtc = rl[2];
-#pragma unroll
-            for (int p = 0; p < 2; ++p) {
-              const uint32_t rowc = (uint32_t)(p * m.n_tc + itc) * (uint32_t)npad * 4u;
-              const uint32_t vj = (uint32_t)j * 4u;
-              float v = cc[p] + rl[5 + p];
-              v = fmaf(1.0f - wtc, load_f32(rhc, vj, rowc), v);
-              v = fmaf(wtc, load_f32(rhc, vj, rowc + (uint32_t)npad * 4u), v);
-              dc += exp2_fast(v);
-            }
-          }
-          d0 += dc;
-          d1 += dc;
-        }
-      }
-      e0[q] = fminf(d0, 16384.0f);
-      e1[q] = fminf(d1, 16384.0f);
-    }
-    uint32_t h0[4], l0[4], h1[4], l1[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      split_pair(e0[2 * q], e0[2 * q + 1], h0[q], l0[q]);
-      split_pair(e1[2 * q], e1[2 * q + 1], h1[q], l1[q]);
-    }
-    const int r0 = c2 * stride + 8 * o, r1 = r0 + stride;
-    *reinterpret_cast<uint4*>(s_bhi + r0) = make_uint4(h0[0], h0[1], h0[2], h0[3]);
-    *reinterpret_cast<uint4*>(s_blo + r0) = make_uint4(l0[0], l0[1], l0[2], l0[3]);
-    *reinterpret_cast<uint4*>(s_bhi + r1) = make_uint4(h1[0], h1[1], h1[2], h1[3]);
-    *reinterpret_cast<uint4*>(s_blo + r1) = make_uint4(l1[0], l1[1], l1[2], l1[3]);
-  }
-  __syncthreads();
-
-  // phase B: tau = P dtau; wave wv owns 32-column block (wv & 3) and half (wv >> 2) of the row blocks
-  const int MBe = (L + 31) >> 5;
-  const int KB = Lp >> 4;
+  const int KBe = (L + 15) >> 4, MBe = (L + 31) >> 5, KB = Lp >> 4;
   const int nb = wv & 3;
   const size_t plane = (size_t)(Lp >> 5) * KB * 512;
   const uint16_t* fh = w.pfrag + (size_t)b * 2 * plane;
@@ -513,48 +445,116 @@ __global__ __launch_bounds__(kBlockT) void k_ck_trans_prod(Model m, Work w, Tabl
   const int ccol = 32 * nb + (lane & 31);
   const int khalf = 8 * (lane >> 5);
   const float wg = tb.ckw[lane & 7];
-  for (int mi = (wv >> 2); mi < MBe; mi += 2) {
-    f32x16 acc = {};
-    for (int kb = 2 * mi; kb < KBe; ++kb) {
-      const size_t fo = ((size_t)(mi * KB + kb) * 64 + lane) * 8;
-      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(fh + fo);
-      const bf16x8 al = *reinterpret_cast<const bf16x8*>(fl + fo);
-      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(s_bhi + ccol * stride + 16 * kb + khalf);
-      const bf16x8 bl = *reinterpret_cast<const bf16x8*>(s_blo + ccol * stride + 16 * kb + khalf);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
-    }
-    // phase C: per row, the g-weighted absorption of each absorber (8 lanes), then the
-    // four absorbers of this column block combined
+  const int bin_c = 4 * nb + ((lane & 31) >> 3);   // the tile bin of this lane's MFMA column
+
+#pragma unroll 1
+  for (int s = 0; s < S; ++s) {
+    // phase A: absorber s's optical depth of every layer at the tile's columns -> bf16
+    // hi/lo B operand in LDS
+    const float2 cof = *reinterpret_cast<const float2*>(tb.c + (size_t)s * ncol + col);
+    for (int o = wv; o < 2 * KBe; o += kBlockT / 64) {
+      float e0[8], e1[8];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      float a = wg * one_minus_exp(acc[q], exp2_fast(-1.4426950408889634f * acc[q]));
-      a += __shfl_xor(a, 1);
-      a += __shfl_xor(a, 2);
-      a += __shfl_xor(a, 4);
-      float o2 = __shfl_xor(a, 8);
-      a = a + o2 - a * o2;
-      o2 = __shfl_xor(a, 16);
-      a = a + o2 - a * o2;
-      const int r = 32 * mi + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-      if ((lane & 31) == 0) s_abs[nb * Lp + r] = a;
+      for (int q = 0; q < 8; ++q) {
+        const int l = 8 * o + q;
+        float d0 = 0.0f, d1 = 0.0f;
+        if (l < L) {
+          const float* rl = rec + (size_t)l * RL;
+          const int cl = cells[l];
+          const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
+          const float wt = rl[0], wp = rl[1];
+          const float w11 = wt * wp, w10 = wt - w11, w01 = wp - w11, w00 = 1.0f - wt - wp + w11;
+          const uint32_t row = (uint32_t)((s * m.n_t + it) * m.n_p + ip) * row_bytes;
+          const float lam = rl[kRecFixed + s];
+          float v0 = cof.x + lam, v1 = cof.y + lam;
+          const float2 t00 = load_f32x2(rh, vo, row), t10 = load_f32x2(rh, vo, row + tstep);
+          const float2 t01 = load_f32x2(rh, vo, row + row_bytes), t11 = load_f32x2(rh, vo, row + tstep + row_bytes);
+          v0 = fmaf(w00, t00.x, v0);
+          v1 = fmaf(w00, t00.y, v1);
+          v0 = fmaf(w10, t10.x, v0);
+          v1 = fmaf(w10, t10.y, v1);
+          v0 = fmaf(w01, t01.x, v0);
+          v1 = fmaf(w01, t01.y, v1);
+          v0 = fmaf(w11, t11.x, v0);
+          v1 = fmaf(w11, t11.y, v1);
+          d0 = exp2_fast(v0);
+          d1 = exp2_fast(v1);
+          if (s == 0) {
+            // the grey continuum at the bin centre rides on absorber 0
+            float dc = fmaf(rl[3], nu4, rl[4]);
+            if (CIA) {
+              const float wtc = rl[2];
+#pragma unroll
+              for (int p = 0; p < 2; ++p) {
+                const uint32_t rowc = (uint32_t)(p * m.n_tc + itc) * (uint32_t)npad * 4u;
+                const uint32_t vj = (uint32_t)j * 4u;
+                float v = cc[p] + rl[5 + p];
+                v = fmaf(1.0f - wtc, load_f32(rhc, vj, rowc), v);
+                v = fmaf(wtc, load_f32(rhc, vj, rowc + (uint32_t)npad * 4u), v);
+                dc += exp2_fast(v);
+              }
+            }
+            d0 += dc;
+            d1 += dc;
+          }
+          if (!real) d0 = d1 = 0.0f;
+        }
+        e0[q] = fminf(d0, 16384.0f);
+        e1[q] = fminf(d1, 16384.0f);
+      }
+      uint32_t h0[4], l0[4], h1[4], l1[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        split_pair(e0[2 * q], e0[2 * q + 1], h0[q], l0[q]);
+        split_pair(e1[2 * q], e1[2 * q + 1], h1[q], l1[q]);
+      }
+      const int r0 = c2 * stride + 8 * o, r1 = r0 + stride;
+      *reinterpret_cast<uint4*>(s_bhi + r0) = make_uint4(h0[0], h0[1], h0[2], h0[3]);
+      *reinterpret_cast<uint4*>(s_blo + r0) = make_uint4(l0[0], l0[1], l0[2], l0[3]);
+      *reinterpret_cast<uint4*>(s_bhi + r1) = make_uint4(h1[0], h1[1], h1[2], h1[3]);
+      *reinterpret_cast<uint4*>(s_blo + r1) = make_uint4(l1[0], l1[1], l1[2], l1[3]);
     }
+    __syncthreads();
+
+    // phase B: tau = P dtau; wave wv owns 32-column block nb and half (wv >> 2) of the row blocks
+    for (int mi = (wv >> 2); mi < MBe; mi += 2) {
+      f32x16 acc = {};
+      for (int kb = 2 * mi; kb < KBe; ++kb) {
+        const size_t fo = ((size_t)(mi * KB + kb) * 64 + lane) * 8;
+        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(fh + fo);
+        const bf16x8 al = *reinterpret_cast<const bf16x8*>(fl + fo);
+        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(s_bhi + ccol * stride + 16 * kb + khalf);
+        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(s_blo + ccol * stride + 16 * kb + khalf);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+      }
+      // phase C: per row, absorber s's g-weighted absorption in its bin (8 lanes),
+      // combined into the bin's running absorption
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        float a = wg * one_minus_exp(acc[q], exp2_fast(-1.4426950408889634f * acc[q]));
+        a += __shfl_xor(a, 1);
+        a += __shfl_xor(a, 2);
+        a += __shfl_xor(a, 4);
+        const int r = 32 * mi + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+        if ((lane & 7) == 0) {
+          float* pa = s_abs + bin_c * Lp + r;
+          const float prev = s == 0 ? 0.0f : *pa;
+          *pa = prev + a - prev * a;
+        }
+      }
+    }
+    __syncthreads();   // the next pass overwrites the B operand
   }
-  __syncthreads();
-  // the two column blocks of each bin, annulus-weighted and summed over the rows
-  const int bj = tid >> 8, i = tid & 255;
+  // the bins' combined absorption, annulus-weighted and summed over the rows: 32
+  // threads per bin
+  const int bj = tid >> 5;
   float v = 0.0f;
-  if (i < Lp) {
-    const float a = s_abs[(2 * bj) * Lp + i], c = s_abs[(2 * bj + 1) * Lp + i];
-    v = s_area[i] * (a + c - a * c);
-  }
+  for (int i = tid & 31; i < 32 * MBe; i += 32) v = fmaf(s_area[i], s_abs[bj * Lp + i], v);
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  if (lane == 0) s_red[wv] = v;
-  __syncthreads();
-  if (tid < 2 && j0 + tid < m.n_nu)
-    out[j0 + tid] = (float)w.core[b] + s_red[4 * tid] + s_red[4 * tid + 1] + s_red[4 * tid + 2] + s_red[4 * tid + 3];
+  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((tid & 31) == 0 && j0 + bj < m.n_nu) out[j0 + bj] = (float)w.core[b] + v;
 }
 
 // Emission: one lane per (bin, g-point) column, sweeping up the layers with the
@@ -658,7 +658,7 @@ static size_t ck_trans_lds_bytes(const Model& m) {
   return (size_t)2 * kTileNu * (m.L_pad + 8) * 2 + (size_t)m.L_pad * 4 + 8 * 32 * 4;
 }
 static size_t ck_prod_lds_bytes(const Model& m) {
-  return (size_t)2 * kTileNu * (m.L_pad + 8) * 2 + (size_t)m.L_pad * 4 * 5 + 8 * 4;
+  return (size_t)2 * kTileNu * (m.L_pad + 8) * 2 + (size_t)m.L_pad * 4 * (1 + kProdBins);
 }
 
 hipError_t ck_configure(const Model& m) {
@@ -684,7 +684,8 @@ void launch_ck_mix(const Model& m, const Work& w, const Tables& tb, int B, hipSt
 void launch_ck_spectrum(const Model& m, const Work& w, const Tables& tb, int B, void* spec, hipStream_t st) {
   if (m.ck_mix == kCkProduct) {
     void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec};
-    hipLaunchKernel(ck_prod_kernel_for(m.S, m.has_cia), dim3((unsigned)(B * ((m.n_nu + 1) / 2))), dim3(kBlockT), args,
+    hipLaunchKernel(ck_prod_kernel_for(m.S, m.has_cia),
+                    dim3((unsigned)(B * ((m.n_nu + kProdBins - 1) / kProdBins))), dim3(kBlockT), args,
                     ck_prod_lds_bytes(m), st);
     return;
   }
