@@ -393,6 +393,12 @@ __global__ __launch_bounds__(kBlockT) void k_ck_trans(Model m, Work w, Tables tb
 // bins of one table row.
 constexpr int kProdBins = kTileNu / kCkG;   // bins per tile
 
+// two adjacent FP32 table entries (8 bytes) through a buffer resource
+__device__ inline float2 load_f32x2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+  return make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
+}
+
 template <int S, bool CIA>
 __global__ __launch_bounds__(kBlockT) void k_ck_trans_prod(Model m, Work w, Tables tb, int B,
                                                            float* __restrict__ spec) {

@@ -108,10 +108,6 @@ __device__ inline LaneConst<S> load_lane(const Model& m, const Tables& tb, int n
 __device__ inline float load_f32(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   return __builtin_bit_cast(float, (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
-__device__ inline float2 load_f32x2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
-  return make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
-}
 __device__ inline half2_t load_h2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   return __builtin_bit_cast(half2_t, (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
