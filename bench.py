@@ -123,6 +123,22 @@ def measured_traffic(kernel, workload_tag="transmission_ns_b1024"):
     return None
 
 
+def measured_sq(kernel, workload_tag="transmission_ns_b1024"):
+    """(VALU instructions per SIMD and cycle, MFMA busy fraction) of `kernel` from the
+    committed SQ counter summary, or None when it is missing or the kernel's sources
+    have changed since."""
+    path = os.path.join(ROOT, "profiles", f"sq_counters_{workload_tag}.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("sq_per_launch:"):
+                parts = line.split(":", 1)[1].split()
+                if len(parts) == 5 and parts[0] == kernel:
+                    return (float(parts[1]), float(parts[2])) if source_digest(parts[3]) == parts[4] else None
+    return None
+
+
 _WL = {}
 
 
@@ -430,9 +446,12 @@ def main():
             bk, ak, pk, _ = model_of(k)
             a = ak / (per[k] / 1e3) / 1e12
             tr = measured_traffic(k, tag)
+            sq = measured_sq(k, tag)
             roofline.setdefault("kernels", {})[k] = {"bound": bk, "ms": round(per[k], 4), "achieved": round(a, 2),
                                                      "peak": pk, "frac": round(a / pk, 4), "traffic": tr,
-                                                     "traffic_gbs": round(tr / (per[k] / 1e3) / 1e9, 1) if tr else None}
+                                                     "traffic_gbs": round(tr / (per[k] / 1e3) / 1e9, 1) if tr else None,
+                                                     "valu_ipc": sq[0] if sq else None,
+                                                     "mfma_busy": sq[1] if sq else None}
     # table-gather bytes the method needs (the forward pass) per launch time: an algorithmic
     # rate, not HBM traffic (the tables stay in the 256 MB MALL across samples; rocprof's
     # counters give the HBM bytes, `traffic` above)
