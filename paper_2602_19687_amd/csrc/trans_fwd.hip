@@ -35,9 +35,11 @@ __device__ inline unsigned mblocks_for(int part, int MBe, int KBe) {
 }
 
 // `cls` (may be null): the layer-count classes of the call (layer_classes), whose class
-// `cl` this launch serves; `lt` is the LDS tile's layer capacity (>= every served
-// sample's layers, a multiple of 32)
-template <int S, bool CIA, bool NGC>
+// `cl` this launch serves; `lt` is the LDS tile's layer capacity, a multiple of 32: at
+// least every served sample's layers, or with KS (K split) fewer: the layers then pass
+// through LDS in chunks of lt, each chunk's products accumulating into the chords, and
+// the packed optical depths for the reverse pass are written as they are formed
+template <int S, bool CIA, bool NGC, bool KS>
 __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Tables tb, int B, float* __restrict__ spec,
                                                               float* __restrict__ dtau_out, const int32_t* __restrict__ cls,
                                                               int cl, int lt) {
@@ -65,13 +67,14 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
   const int stride = lt + 8;   // bf16 per wavenumber row of the B operand (keeps b128 reads conflict-free)
   uint16_t* s_bhi = reinterpret_cast<uint16_t*>(lds);
   uint16_t* s_blo = s_bhi + kTileNu * stride;
+  const int n_area = KS ? Lp : lt;   // chord rows
   float* s_area = reinterpret_cast<float*>(s_blo + kTileNu * stride);
-  float* s_red = s_area + lt;   // [8][32]
+  float* s_red = s_area + n_area;   // [8][32]
   int* s_live = reinterpret_cast<int*>(s_red + 8 * 32);   // [0, MB): row block holds a chord below kOpaqueTau; [7]: frontier
   if (tid < 8) s_live[tid] = 0;
 
   const float* area = reinterpret_cast<const float*>(w.area) + (size_t)b * Lp;
-  for (int i = tid; i < lt; i += kBlockT) s_area[i] = area[i];
+  for (int i = tid; i < n_area; i += kBlockT) s_area[i] = area[i];
 
   // phase A: vertical optical depth of every layer -> bf16 hi/lo B operand in LDS
   const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * rec_len(S);
@@ -96,39 +99,58 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
   // a layer in the same table cell as the wave's previous one reuses its pairs
   LayerRaw<S, CIA> raw;
   int cell_prev = -1;
-  for (int o = wv; o < 2 * KBe; o += kBlockT / 64) {
-    float e0[8], e1[8];
+  // layer octets [o_lo, o_hi) -> LDS rows from 8 (o - o_lo)
+  auto phase_a = [&](int o_lo, int o_hi) {
+    for (int o = o_lo + wv; o < o_hi; o += kBlockT / 64) {
+      float e0[8], e1[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int l = 8 * o + j;
-      float d0 = 0.0f, d1 = 0.0f;
-      if (l < L) {
-        const LayerCoef<S> c = load_layer<S>(m, cells, rec, l, (uint32_t)nu0 * 2u, g);
-        if (c.cell != cell_prev) {
-          fetch_terms<S, CIA>(c, g, rh, rhc, voff, raw);
-          cell_prev = c.cell;
+      for (int j = 0; j < 8; ++j) {
+        const int l = 8 * o + j;
+        float d0 = 0.0f, d1 = 0.0f;
+        if (l < L) {
+          const LayerCoef<S> c = load_layer<S>(m, cells, rec, l, (uint32_t)nu0 * 2u, g);
+          if (c.cell != cell_prev) {
+            fetch_terms<S, CIA>(c, g, rh, rhc, voff, raw);
+            cell_prev = c.cell;
+          }
+          eval_terms<S, CIA, NGC>(c, kc, raw, d0, d1, q0, q1);
+          d0 = fminf(d0, 16384.0f);
+          d1 = fminf(d1, 16384.0f);
         }
-        eval_terms<S, CIA, NGC>(c, kc, raw, d0, d1, q0, q1);
-        d0 = fminf(d0, 16384.0f);
-        d1 = fminf(d1, 16384.0f);
+        e0[j] = d0;
+        e1[j] = d1;
       }
-      e0[j] = d0;
-      e1[j] = d1;
-    }
-    // bf16 hi/lo planes, pairs of consecutive layers per dword
-    uint32_t h0[4], l0[4], h1[4], l1[4];
+      // bf16 hi/lo planes, pairs of consecutive layers per dword
+      uint32_t h0[4], l0[4], h1[4], l1[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      split_pair(e0[2 * j], e0[2 * j + 1], h0[j], l0[j]);
-      split_pair(e1[2 * j], e1[2 * j + 1], h1[j], l1[j]);
+      for (int j = 0; j < 4; ++j) {
+        split_pair(e0[2 * j], e0[2 * j + 1], h0[j], l0[j]);
+        split_pair(e1[2 * j], e1[2 * j + 1], h1[j], l1[j]);
+      }
+      const int r0 = (2 * lane) * stride + 8 * (o - o_lo), r1 = r0 + stride;
+      *reinterpret_cast<uint4*>(s_bhi + r0) = make_uint4(h0[0], h0[1], h0[2], h0[3]);
+      *reinterpret_cast<uint4*>(s_blo + r0) = make_uint4(l0[0], l0[1], l0[2], l0[3]);
+      *reinterpret_cast<uint4*>(s_bhi + r1) = make_uint4(h1[0], h1[1], h1[2], h1[3]);
+      *reinterpret_cast<uint4*>(s_blo + r1) = make_uint4(l1[0], l1[1], l1[2], l1[3]);
+      if (KS && dtau_out) {
+        // the packed optical depths (bf16 hi | bf16 lo << 16) of the octet's layers
+        // for the reverse pass: a later chunk overwrites these LDS rows
+        uint32_t* dt = reinterpret_cast<uint32_t*>(dtau_out) + (size_t)b * Lp * npad + nu0 + 2 * lane;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int l = 8 * o + 2 * j;
+          if (l < L) {
+            __builtin_nontemporal_store(__builtin_amdgcn_perm(l0[j], h0[j], 0x05040100u), dt + (size_t)l * npad);
+            __builtin_nontemporal_store(__builtin_amdgcn_perm(l1[j], h1[j], 0x05040100u), dt + (size_t)l * npad + 1);
+          }
+          if (l + 1 < L) {
+            __builtin_nontemporal_store(__builtin_amdgcn_perm(l0[j], h0[j], 0x07060302u), dt + (size_t)(l + 1) * npad);
+            __builtin_nontemporal_store(__builtin_amdgcn_perm(l1[j], h1[j], 0x07060302u), dt + (size_t)(l + 1) * npad + 1);
+          }
+        }
+      }
     }
-    const int r0 = (2 * lane) * stride + 8 * o, r1 = r0 + stride;
-    *reinterpret_cast<uint4*>(s_bhi + r0) = make_uint4(h0[0], h0[1], h0[2], h0[3]);
-    *reinterpret_cast<uint4*>(s_blo + r0) = make_uint4(l0[0], l0[1], l0[2], l0[3]);
-    *reinterpret_cast<uint4*>(s_bhi + r1) = make_uint4(h1[0], h1[1], h1[2], h1[3]);
-    *reinterpret_cast<uint4*>(s_blo + r1) = make_uint4(l1[0], l1[1], l1[2], l1[3]);
-  }
-  __syncthreads();
+  };
 
   // phase B: tau = P dtau on MFMA; wave wv owns 32-column block (wv & 3) and a
   // cost-balanced half (wv >> 2) of the 32-row blocks
@@ -142,20 +164,23 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
   const int col = 32 * nb + (lane & 31);
   const int khalf = 8 * (lane >> 5);
   float dsum = 0.0f;
-  for (int mi = 0; mi < MBe; ++mi) {
-    if (!(mine & (1u << mi))) continue;
-    f32x16 acc = {};
-    for (int kb = 2 * mi; kb < KBe; ++kb) {
+  // row block mi's products over the K blocks [k_lo, k_hi), B rows from LDS row 16 (kb - k_base)
+  auto chord = [&](f32x16 acc, int mi, int k_lo, int k_hi, int k_base) {
+    for (int kb = k_lo; kb < k_hi; ++kb) {
       const size_t fo = ((size_t)(mi * KB + kb) * 64 + lane) * 8;
       const bf16x8 ah = *reinterpret_cast<const bf16x8*>(fh + fo);
       const bf16x8 al = *reinterpret_cast<const bf16x8*>(fl + fo);
-      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(s_bhi + col * stride + 16 * kb + khalf);
-      const bf16x8 bl = *reinterpret_cast<const bf16x8*>(s_blo + col * stride + 16 * kb + khalf);
+      const int kr = 16 * (kb - k_base) + khalf;
+      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(s_bhi + col * stride + kr);
+      const bf16x8 bl = *reinterpret_cast<const bf16x8*>(s_blo + col * stride + kr);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
     }
-    // phase C: annulus-weighted absorption 1 - e^-tau, summed over rows
+    return acc;
+  };
+  // phase C: annulus-weighted absorption 1 - e^-tau of row block mi, summed over rows
+  auto absorb = [&](const f32x16& acc, int mi) {
     bool live = false;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
@@ -165,6 +190,40 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
     }
     // the reverse pass skips row blocks whose chords are all opaque across the tile
     if (dtau_out && __builtin_amdgcn_ballot_w64(live) != 0 && lane == 0) s_live[mi] = 1;
+  };
+  if constexpr (!KS) {
+    phase_a(0, 2 * KBe);
+    __syncthreads();
+    for (int mi = 0; mi < MBe; ++mi) {
+      if (!(mine & (1u << mi))) continue;
+      absorb(chord(f32x16{}, mi, 2 * mi, KBe, 0), mi);
+    }
+  } else {
+    // up to three row blocks per wave (five row blocks in two cost-balanced halves)
+    int slot_mi[3];
+    {
+      int q = 0;
+      for (int mi = 0; mi < MBe; ++mi)
+        if ((mine & (1u << mi)) && q < 3) slot_mi[q++] = mi;
+      for (; q < 3; ++q) slot_mi[q] = -1;
+    }
+    f32x16 acc[3] = {f32x16{}, f32x16{}, f32x16{}};
+    const int kc = lt >> 4;   // K blocks per chunk
+    for (int k0 = 0; k0 < KBe; k0 += kc) {
+      const int k1 = k0 + kc < KBe ? k0 + kc : KBe;
+      phase_a(2 * k0, 2 * k1);
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int mi = slot_mi[q];
+        if (mi < 0) continue;
+        acc[q] = chord(acc[q], mi, 2 * mi > k0 ? 2 * mi : k0, k1, k0);
+      }
+      __syncthreads();   // the next chunk overwrites the LDS rows
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      if (slot_mi[q] >= 0) absorb(acc[q], slot_mi[q]);
   }
   dsum += __shfl_xor(dsum, 32);
   if (lane < 32) s_red[wv * 32 + lane] = dsum;
@@ -181,6 +240,7 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
       w.front[(size_t)b * m.n_tiles + tile] = f;
       s_live[7] = f;
     }
+    if constexpr (KS) return;   // the optical depths were written as they were formed
     __syncthreads();
     // the reverse pass reads the layer optical depths back instead of recomputing
     // them, already split: one dword (bf16 hi | bf16 lo << 16) per layer and
@@ -275,15 +335,16 @@ __global__ __launch_bounds__(kBlock) void k_trans_fwd_fp64(Model m, Work w, Tabl
 // ---------------------------------------------------------------------------
 // host side: one instance per (species count, CIA present)
 template <bool F64, int S, bool CIA>
-const void* fwd_kernel(bool ng) {
+const void* fwd_kernel(bool ng, bool ks) {
   if constexpr (F64) return (const void*)k_trans_fwd_fp64<S, CIA>;
-  else return ng ? (const void*)k_trans_fwd_mixed<S, CIA, true> : (const void*)k_trans_fwd_mixed<S, CIA, false>;
+  else if (ks) return ng ? (const void*)k_trans_fwd_mixed<S, CIA, true, true> : (const void*)k_trans_fwd_mixed<S, CIA, false, true>;
+  else return ng ? (const void*)k_trans_fwd_mixed<S, CIA, true, false> : (const void*)k_trans_fwd_mixed<S, CIA, false, false>;
 }
 
 template <bool F64>
-const void* fwd_kernel_for(int S, bool cia, bool ng) {
+const void* fwd_kernel_for(int S, bool cia, bool ng, bool ks = false) {
 #define EXOFWD_CASE(n) \
-  case n: return cia ? fwd_kernel<F64, n, true>(ng) : fwd_kernel<F64, n, false>(ng);
+  case n: return cia ? fwd_kernel<F64, n, true>(ng, ks) : fwd_kernel<F64, n, false>(ng, ks);
   switch (S) {
     EXOFWD_CASE(1) EXOFWD_CASE(2) EXOFWD_CASE(3) EXOFWD_CASE(4)
     EXOFWD_CASE(5) EXOFWD_CASE(6) EXOFWD_CASE(7) EXOFWD_CASE(8)
@@ -292,9 +353,9 @@ const void* fwd_kernel_for(int S, bool cia, bool ng) {
   return nullptr;
 }
 
-static size_t fwd_lds_bytes(const Model& m, bool fp64, int lt) {
+static size_t fwd_lds_bytes(const Model& m, bool fp64, int lt, bool ks = false) {
   if (fp64) return (size_t)m.L_pad * kTile64 * 8 + 4 * kTile64 * 8;
-  return (size_t)2 * kTileNu * (lt + 8) * 2 + (size_t)lt * 4 + 8 * 32 * 4 + 8 * 4;
+  return (size_t)2 * kTileNu * (lt + 8) * 2 + (size_t)(ks ? m.L_pad : lt) * 4 + 8 * 32 * 4 + 8 * 4;
 }
 
 size_t trans_fwd_lds_bytes(const Model& m, bool fp64) { return fwd_lds_bytes(m, fp64, m.L_pad); }
@@ -302,7 +363,12 @@ size_t trans_fwd_lds_bytes(const Model& m, bool fp64) { return fwd_lds_bytes(m, 
 hipError_t trans_fwd_configure(const Model& m, bool fp64) {
   const void* k = fp64 ? fwd_kernel_for<true>(m.S, m.has_cia, m.cloud_ng) : fwd_kernel_for<false>(m.S, m.has_cia, m.cloud_ng);
   if (!k) return hipErrorInvalidValue;
-  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)trans_fwd_lds_bytes(m, fp64));
+  hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)trans_fwd_lds_bytes(m, fp64));
+  if (e != hipSuccess || fp64 || !layer_classes_used(m)) return e;
+  const void* ks = fwd_kernel_for<false>(m.S, m.has_cia, m.cloud_ng, true);
+  if (!ks) return hipErrorInvalidValue;
+  return hipFuncSetAttribute(ks, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fwd_lds_bytes(m, false, kShortLayers, true));
 }
 
 void launch_trans_fwd(const Model& m, const Work& w, const Tables& tb, int B, void* spec, bool fp64, hipStream_t st,
@@ -314,15 +380,18 @@ void launch_trans_fwd(const Model& m, const Work& w, const Tables& tb, int B, vo
   } else {
     const void* k = fwd_kernel_for<false>(m.S, m.has_cia, m.cloud_ng);
     if (layer_classes_used(m)) {
-      // samples of at most kShortLayers layers run with a kShortLayers-row LDS tile (two
-      // workgroups per CU), the rest with the full one; each launch's grid covers the batch
+      // samples of at most kShortLayers layers run with a kShortLayers-row LDS tile, the
+      // rest with the same tile in two K chunks (two workgroups per CU either way); each
+      // launch's grid covers the batch
       launch_layer_classes(m, w, B, st);
+      const void* ks = fwd_kernel_for<false>(m.S, m.has_cia, m.cloud_ng, true);
       for (int cl = 0; cl < 2; ++cl) {
         const int32_t* cls = w.cls;
-        int lt = cl == 0 ? kShortLayers : m.L_pad;
+        int lt = kShortLayers;
         void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec, (void*)&dtau_out, (void*)&cls,
                         (void*)&cl, (void*)&lt};
-        hipLaunchKernel(k, dim3((unsigned)(m.n_tiles * B)), dim3(kBlockT), args, fwd_lds_bytes(m, false, lt), st);
+        hipLaunchKernel(cl == 0 ? k : ks, dim3((unsigned)(m.n_tiles * B)), dim3(kBlockT), args,
+                        fwd_lds_bytes(m, false, lt, cl == 1), st);
       }
       return;
     }
