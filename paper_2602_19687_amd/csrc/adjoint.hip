@@ -104,7 +104,8 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
   const int chunk = logical % C;
   int b = logical / C;
   if (cls) {
-    // the class's samples, longest first; the grid covers the whole batch
+    // the class's samples, longest first, dealt round the XCDs; the grid covers the whole batch
+    b = class_position(b, B, C);
     if (b >= cls[cl]) return;
     b = cls[2 + cl * B + b];
   }

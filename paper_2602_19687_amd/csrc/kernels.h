@@ -14,6 +14,17 @@ __device__ inline int xcd_logical_block(int bid, int nblk) {
   return (bid & 7) * (nblk >> 3) + (bid >> 3);
 }
 
+// Position in a layer-count class's sample list of sample slot s of a launch whose
+// logical blocks (xcd_logical_block over n_slots * per_slot blocks) give each XCD a
+// contiguous run of n_slots / 8 slots: the positions are dealt round the XCDs
+// (slot s of XCD k holds position 8 (s - k n_slots / 8) + k), so a class that fills
+// only part of the grid still spreads over every XCD, longest samples first on each.
+__device__ inline int class_position(int s, int n_slots, int per_slot) {
+  if ((n_slots & 7) != 0 || (((long)n_slots * per_slot) & 7) != 0) return s;
+  const int spx = n_slots >> 3;
+  return (s % spx) * 8 + s / spx;
+}
+
 void launch_profile(const Model& m, const Work& w, int B, const double* params, const int32_t* n_layers,
                     bool fp64, hipStream_t st);
 // dtau_out (reduced precision only, may be null): layer optical depths [B][L_pad][n_nu_pad] for the reverse pass

@@ -50,7 +50,9 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
   int b = m.fwd_tile_major ? logical / m.n_tiles : logical % B;
   const int tile = m.fwd_tile_major ? logical % m.n_tiles : logical / B;
   if (cls) {
-    // the class's samples, longest first; the grid covers the whole batch
+    // the class's samples, longest first; the grid covers the whole batch (tiles
+    // fastest: sample slots dealt round the XCDs)
+    if (m.fwd_tile_major) b = class_position(b, B, m.n_tiles);
     if (b >= cls[cl]) return;
     b = cls[2 + cl * B + b];
   }
