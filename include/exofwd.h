@@ -272,11 +272,12 @@ exofwd_status exofwd_grad(exofwd_ctx* ctx, int32_t B, const double* params,
 /*
  * Launch choices of a reduced-precision transmission context, four int32:
  *   [0] forward grid order: 0 samples fastest, 1 wavenumber tiles fastest
- *   [1] reverse-kernel shape: 0 = 128-wavenumber tiles x 4 row blocks (padded
- *       layers <= 128), 1 = 64 x 4, 2 = 64 x 5 (<= 160).  With more than 128 padded
- *       layers, 1 runs the samples of at most 128 layers with 64 x 4 and the rest with
- *       64 x 5 (and the forward kernel always runs those two classes with LDS tiles
- *       of 128 and of all padded layers); 2 runs every sample with 64 x 5
+ *   [1] reverse-kernel shape: 0 = 128-wavenumber tiles x 4 row blocks, 1 = 64 x 4,
+ *       2 = 64 x 5 (padded layers <= 160; 0 and 1 alone serve <= 128).  With more than
+ *       128 padded layers, 0 and 1 run the samples of at most 128 layers with their
+ *       shape and the rest with 64 x 5 (and the forward kernel always runs those two
+ *       classes, the longer one in two 128-layer chunks); 2 runs every sample with
+ *       64 x 5
  *   [2] reverse work items per call, one of 512, 1024, 2048, 4096, 8192 (each sample's
  *       wavenumbers are split into ceil(items / B) chunks, which run on neighbouring
  *       workgroups)

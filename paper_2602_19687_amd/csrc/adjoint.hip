@@ -1361,10 +1361,14 @@ bool adjoint_supported(const Model& m, bool fp64) {
   return m.L_pad <= (fp64 ? 128 : 160);
 }
 
-// A ragged context of more than kShortLayers padded layers with the 64 x 4 shape runs its
-// samples in two layer-count classes: 64 x 4 for those of at most kShortLayers layers,
-// 64 x 5 for the rest (both walk 64-wavenumber tiles, so the chunks agree).
-static bool adj_split(const Model& m, int variant) { return layer_classes_used(m) && variant == kAdjT64M4; }
+// A ragged context of more than kShortLayers padded layers with a 4-row-block shape (128 x 4
+// or 64 x 4) runs its samples in two layer-count classes: that shape for those of at most
+// kShortLayers layers, 64 x 5 for the rest.  Both launches split every sample into the
+// same number of wavenumber chunks (bounded by the wider shape's tile count), so the
+// per-chunk partials and their reduction are those of a single launch.
+static bool adj_split(const Model& m, int variant) {
+  return layer_classes_used(m) && (variant == kAdjT64M4 || variant == kAdjT128M4);
+}
 
 int adjoint_default_variant(const Model& m) { return m.L_pad <= 128 ? kAdjT128M4 : kAdjT64M4; }
 

@@ -149,12 +149,15 @@ def ragged_case():
     return wl, nl, refs, specs
 
 
-@pytest.mark.parametrize("choice", [[1, 1, 4096, 16], [1, 2, 4096, 16], [0, 1, 1024, 64], [1, 1, 8192, 8]],
-                         ids=["split", "unsplit", "split-samples-fastest", "split-8192"])
+@pytest.mark.parametrize("choice", [[1, 1, 4096, 16], [1, 2, 4096, 16], [0, 1, 1024, 64], [1, 1, 8192, 8],
+                                    [1, 0, 4096, 16], [0, 0, 512, 64], [0, 0, 2048, 64]],
+                         ids=["split", "unsplit", "split-samples-fastest", "split-8192", "split-128",
+                              "split-128-512", "split-128-2048"])
 def test_layer_classes_match_oracle(ragged_case, choice):
     """A ragged batch of more than 128 padded layers: the forward kernel runs the
-    samples of at most 128 layers and the rest as two classes, and reverse shape 1
-    does the same (64 x 4 and 64 x 5); every choice agrees with the oracle."""
+    samples of at most 128 layers and the rest as two classes, and reverse shapes 0
+    and 1 do the same (128 x 4 or 64 x 4, then 64 x 5, with equal chunk counts);
+    every choice agrees with the oracle."""
     wl, nl, refs, specs = ragged_case
     fm = _model(wl)
     print(f"[gpu] layer classes {choice}", flush=True)
