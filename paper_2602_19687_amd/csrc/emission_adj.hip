@@ -177,13 +177,11 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_emis(Model m, Work w, Tab
     // a layer seen through no transmission at any wavenumber of the tile adds
     // nothing (the skip is per layer: the opaque depth varies across a tile)
     float dbv[kLayers];
-    bool live = false;
 #pragma unroll
-    for (int q = 0; q < kLayers; ++q) {
+    for (int q = 0; q < kLayers; ++q)
       dbv[q] = q < cnt ? __builtin_nontemporal_load(&dtb[(size_t)(l0 + q) * npad + nu]) : 0.0f;
-      live |= dbv[q] != 0.0f;
-    }
-    if (__builtin_amdgcn_ballot_w64(live) == 0) continue;
+    // the table entries are fetched together with dtau_bar (one memory round trip per
+    // tile), before the test that skips a tile whose dtau_bar is zero
     float cs[S], ccs[2];
 #pragma unroll
     for (int s = 0; s < S; ++s) cs[s] = tb.c[(size_t)s * npad + nu];
@@ -206,6 +204,10 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_emis(Model m, Work w, Tab
         tp[4 * S + 2 * p + 1] = load_f32(rhc, voff, row + row_bytes);
       }
     }
+    bool live = false;
+#pragma unroll
+    for (int q = 0; q < kLayers; ++q) live |= dbv[q] != 0.0f;
+    if (__builtin_amdgcn_ballot_w64(live) == 0) continue;
 #pragma unroll
     for (int q = 0; q < kLayers; ++q) {
       if (q >= cnt) continue;
