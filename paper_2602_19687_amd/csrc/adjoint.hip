@@ -433,12 +433,12 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
 }
 
 // ============================================================================
-// reduced-precision per-layer sums: one wave per (sample, ls_layers layers, ls_tiles tiles);
-// lanes hold two wavenumbers, partial sums stay in registers across the tiles
-// and are reduced over the wave once
-// layers per wave: three layers' accumulators keep the kernel under 128 VGPRs (four waves per
-// SIMD); the non-grey cloud's extra sum needs two
-__host__ __device__ constexpr int ls_layers(bool ngc) { return ngc ? 2 : 3; }
+// reduced-precision per-layer sums: one wave per (sample, layer group, ls_tiles tiles),
+// a layer group being a run of up to kLsGroup consecutive layers in one table cell
+// (listed by the profile kernel), whose table pairs are fetched once per tile,
+// together with the tile's dtau_bar; lanes hold two wavenumbers, partial sums stay
+// in registers across the tiles and are reduced over the wave once
+__host__ __device__ constexpr int ls_layers(bool ngc) { return kLsGroup; }
 
 template <int S, bool CIA, bool NGC>
 __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Tables tb, AdjWork aw, int B) {
@@ -448,17 +448,17 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
   // consecutive waves (one wavenumber chunk) on one XCD: its L2 holds that chunk's table columns
   const int gw = xcd_logical_block(blockIdx.x, gridDim.x) * (kBlock / 64) +
                  __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int NG = (m.L_max + kLs - 1) / kLs;
+  const int NG = m.L_max;   // groups per sample: at most one per layer
   const int per_chunk = B * NG;
   const int chunk = gw / per_chunk;
   if (chunk >= aw.lsum_chunks) return;
   const int rem = gw - chunk * per_chunk;
   const int b = rem / NG, lg = rem - b * NG;
   if (w.status[b]) return;
-  const int L = w.nlay[b];
-  const int l0 = lg * kLs;
-  if (l0 >= L) return;
   const int Lp = m.L_pad;
+  const int32_t* grp = w.lsg + (size_t)b * (Lp + 1);
+  if (lg >= grp[0]) return;
+  const int l0 = grp[1 + lg] & 0xffff, cnt = grp[1 + lg] >> 16;
   const size_t npad = (size_t)m.n_nu_pad;
   TableGeom g;
   g.row_bytes = (uint32_t)npad * 2u;
@@ -489,18 +489,22 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
     // exactly zero there and the tile adds nothing (the deep layers of most
     // atmospheres).  Rows below the reverse pass's opaque frontier are not stored.
     const int lo_row = 32 * w.front[(size_t)b * m.n_tiles + tile];
-    if (l0 + kLs <= lo_row) continue;
+    if (l0 + cnt <= lo_row) continue;
     float2 dbq[kLs];
+#pragma unroll
+    for (int q = 0; q < kLs; ++q)
+      dbq[q] = (q < cnt && l0 + q >= lo_row) ? ld_stream2(dtb + (size_t)(l0 + q) * npad + nu0 + 2 * lane)
+                                             : make_float2(0.0f, 0.0f);
+    // the group's table pairs, fetched with dtau_bar (one memory round trip per tile)
+    // before the test that skips a tile whose dtau_bar is zero
+    const LayerCoef<S> c0 = load_layer<S>(m, cells, rec, l0, (uint32_t)nu0 * 2u, g);
+    LayerRaw<S, CIA> raw;
+    fetch_terms<S, CIA>(c0, g, rh, rhc, voff, raw);
+    const LaneConst<S> kc = load_lane<S, CIA>(m, tb, nu0 + 2 * lane);
     bool live = false;
 #pragma unroll
-    for (int q = 0; q < kLs; ++q) {
-      dbq[q] = (l0 + q < L && l0 + q >= lo_row)
-                   ? ld_stream2(dtb + (size_t)(l0 + q) * npad + nu0 + 2 * lane)
-                   : make_float2(0.0f, 0.0f);
-      live |= dbq[q].x != 0.0f || dbq[q].y != 0.0f;
-    }
+    for (int q = 0; q < kLs; ++q) live |= dbq[q].x != 0.0f || dbq[q].y != 0.0f;
     if (__builtin_amdgcn_ballot_w64(live) == 0) continue;
-    const LaneConst<S> kc = load_lane<S, CIA>(m, tb, nu0 + 2 * lane);
     float q0 = 1.0f, q1 = 1.0f;
     if constexpr (NGC) {
       const float2 q = *reinterpret_cast<const float2*>(cq + nu0 + 2 * lane);
@@ -509,12 +513,11 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
     }
 #pragma unroll
     for (int q = 0; q < kLs; ++q) {
-      const int l = l0 + q;
-      if (l >= L) continue;
+      if (q >= cnt) continue;
       const float2 db = dbq[q];
-      const LayerCoef<S> c = load_layer<S>(m, cells, rec, l, (uint32_t)nu0 * 2u, g);
+      const LayerCoef<S> c = q == 0 ? c0 : load_layer<S>(m, cells, rec, l0 + q, (uint32_t)nu0 * 2u, g);
       float t0_[S + 2], t1_[S + 2], dw0[S + 2], dw1[S + 2];
-      layer_terms_deriv<S, CIA>(c, kc, g, rh, rhc, voff, t0_, t1_, dw0, dw1);
+      eval_terms_deriv<S, CIA>(c, kc, raw, t0_, t1_, dw0, dw1);
       // G_s += db t_s per wavenumber; the T-weight sums take db once per wavenumber
       // times z = sum_s t_s dw_s
       float z0 = 0.0f, z1 = 0.0f;
@@ -547,7 +550,7 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
 #pragma unroll
   for (int q = 0; q < kLs; ++q) {
     const int l = l0 + q;
-    if (l >= L) continue;
+    if (q >= cnt) continue;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const float tot = wave_sum(acc[q][k]);
@@ -1551,7 +1554,7 @@ void launch_layer_sums(const Model& m, const Work& w, const Tables& tb, const Ad
     launch_layer_sums_emis(m, w, tb, aw, B, fp64, st);
     return;
   }
-  const int nl = ls_layers(m.cloud_ng), NG = (m.L_max + nl - 1) / nl;
+  const int NG = m.L_max;   // layer groups per sample: at most one per layer
   const long waves = (long)aw.lsum_chunks * B * NG;
   void* args2[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&aw, (void*)&B};
   // a whole number of blocks per XCD; the waves past the last chunk return at once

@@ -21,7 +21,7 @@ constexpr double kInvalidLnL = -1.0e300;
 
 constexpr int kMaxSpecies = 8;
 constexpr int kMaxLayers = 160;   // L_max; padded layer count is a multiple of 32
-constexpr int kLsGroup = 3;       // most layers in one reduced-precision emission layer-sum group
+constexpr int kLsGroup = 3;       // most layers in one reduced-precision layer-sum group
 constexpr int kMaxKnots = 8;
 constexpr int kMaxMu = 8;
 constexpr int kTileNu = 128;      // wavenumbers per tile of the reduced-precision transmission kernels
@@ -105,7 +105,7 @@ struct Work {
   double* cloud;        // [B][kCloudSpec] non-grey cloud: r_eff [cm], a, Q0, A, lambda0 [um], omega [um], xi
   float* cloud_q;       // reduced precision, non-grey: [B][1 + kCloudSpec][n_nu_pad] Q_ext(nu), dQ_ext/dp_k
   int32_t* cells;       // [B][L_pad] packed cells
-  int32_t* lsg;         // reduced-precision emission: [B][L_pad + 1] layer-sum groups, their number
+  int32_t* lsg;         // reduced precision: [B][L_pad + 1] layer-sum groups, their number
                         //   and then (first layer | layers << 16) of each: runs of at most
                         //   kLsGroup consecutive layers in one table cell, in layer order
   int32_t* front;       // reduced precision: [B][n_tiles] opaque 32-row chord blocks at the bottom of

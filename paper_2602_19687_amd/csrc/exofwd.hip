@@ -572,7 +572,7 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
   if (m.cloud_ng && g.precision == EXOFWD_PREC_MIXED)
     w.cloud_q = A(dalloc<float>(c, (size_t)B * (1 + kCloudSpec) * m.n_nu_pad));
   w.cells = A(dalloc<int32_t>(c, (size_t)B * Lp));
-  if (!fp64 && m.mode == kEmission) w.lsg = A(dalloc<int32_t>(c, (size_t)B * (Lp + 1)));
+  if (!fp64) w.lsg = A(dalloc<int32_t>(c, (size_t)B * (Lp + 1)));
   if (m.mode == kTransmission && !fp64) w.front = A(dalloc<int32_t>(c, (size_t)B * m.n_tiles));
   w.rec = A(dalloc<unsigned char>(c, (size_t)B * Lp * RL * rs));
   w.area = A(dalloc<unsigned char>(c, (size_t)B * Lp * rs));
@@ -769,7 +769,7 @@ static size_t carve_forward_work(const exofwd_ctx* c, int B, bool internal_spec,
   w.cloud = (double*)take(8 * Bv * kCloudSpec);
   if (m.cloud_ng && !fp64) w.cloud_q = (float*)take(4 * Bv * (1 + kCloudSpec) * (size_t)m.n_nu_pad);
   w.cells = (int32_t*)take(4 * Bv * Lp);
-  if (!fp64 && !trans) w.lsg = (int32_t*)take(4 * Bv * (Lp + 1));
+  if (!fp64) w.lsg = (int32_t*)take(4 * Bv * (Lp + 1));
   if (trans && !fp64) w.front = (int32_t*)take(4 * Bv * (size_t)m.n_tiles);
   w.rec = take(rs * Bv * Lp * (size_t)rec_len(m.S));
   w.area = take(rs * Bv * Lp);
