@@ -4,17 +4,18 @@ Its kernels are exofwd_forward's with the per-call workspace in a static device
 array, so its spectra, lnL and status must equal exofwd_forward's bit for bit on
 the same inputs.  Each case makes two calls in a row, the second with a smaller
 batch (the array keeps the first call's contents), for the reduced-precision and
-FP64 transmission models (ragged layer counts), reduced-precision emission, the
-non-grey cloud and the partly cloudy limb (whose spectra always pass through the
-array); a batch whose workspace exceeds the array is refused with
-EXOFWD_ERR_SHAPE and leaves the context usable.
+FP64 transmission models (ragged layer counts, also past 128 layers, where the
+samples run in two layer-count classes), reduced-precision emission, the non-grey
+cloud, the partly cloudy limb (whose spectra always pass through the array) and
+the correlated-k models (both mixings); a batch whose workspace exceeds the array
+is refused with EXOFWD_ERR_SHAPE and leaves the context usable.
 """
 import ctypes as C
 
 import numpy as np
 import pytest
 
-from parity_util import reduced
+from parity_util import reduced, reduced_ck
 
 pytestmark = pytest.mark.gpu
 
@@ -41,8 +42,11 @@ CASES = [
     (1, "mixed", True),
     (1, "fp64", True),
     (2, "mixed", False),
+    (4, "mixed", True),
     (5, "mixed", False),
     (6, "mixed", False),
+    (7, "mixed", False),
+    (8, "mixed", False),
 ]
 
 
@@ -50,7 +54,10 @@ CASES = [
 def test_noalloc_forward_equals_forward(cid, prec, ragged):
     from paper_2602_19687_amd import ForwardModel
     from paper_2602_19687_amd import _lib as L
-    wl = reduced(cid, n_nu=1000, n_bins=37, batch=12)
+    if cid in (7, 8):
+        wl = reduced_ck(cid, n_ck=150, n_bins=15, batch=12, step=13)
+    else:
+        wl = reduced(cid, n_nu=1000, n_bins=37, batch=12)
     fm = ForwardModel(wl, precision=prec, batch_max=12)
     lib = fm.lib
     rng = np.random.default_rng(100 + cid)
