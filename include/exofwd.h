@@ -211,8 +211,8 @@ int32_t exofwd_num_nu(const exofwd_ctx* ctx);       /* n_nu, or -1 */
 int32_t exofwd_num_bins(const exofwd_ctx* ctx);     /* K, or -1 */
 int32_t exofwd_precision(const exofwd_ctx* ctx);    /* EXOFWD_PREC_*, or -1 */
 /* 1 if exofwd_grad supports this context's workload, 0 if not, -1 for a NULL
- * context.  Supported: transmission with n_layers_max <= 160 in MIXED precision or
- * <= 128 in FP64; emission with n_layers_max <= 160 in MIXED or <= 128 in FP64;
+ * context.  Supported: transmission with n_layers_max <= 160 (both precisions);
+ * emission with n_layers_max <= 160 in MIXED or <= 128 in FP64;
  * every T-p profile and cloud model. */
 int32_t exofwd_grad_supported(const exofwd_ctx* ctx);
 

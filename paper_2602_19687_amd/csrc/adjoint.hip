@@ -635,10 +635,11 @@ __device__ inline void opacity_fp64_terms(const Model& m, const Tables& tb, int 
   dtau = acc;
 }
 
-constexpr int kRows64 = 16;    // rows per wave (L_pad <= 128, 8 waves)
-constexpr int kPSlots64 = 5;   // 16x16 Pbar tiles per wave
-
-template <int S, bool CIA>
+// Two instances: TILE = 64 wavenumbers with ROWS = 16 rows per wave (L_pad <= 128),
+// and TILE = 32 with ROWS = 20 (L_pad <= 160: the tile's dtau and tau_bar, 2 TILE
+// (L_pad + 1) doubles, then fit in LDS; lanes 32-63 hold no wavenumber and add zeros).
+// PSLOTS: 16x16 Pbar tiles per wave.
+template <int S, bool CIA, int TILE, int ROWS, int PSLOTS>
 __global__ __launch_bounds__(kBlockT) void k_trans_adj_fp64(Model m, Work w, Tables tb, AdjWork aw, int B, int C) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int logical = xcd_logical_block(blockIdx.x, gridDim.x);
@@ -650,8 +651,9 @@ __global__ __launch_bounds__(kBlockT) void k_trans_adj_fp64(Model m, Work w, Tab
   constexpr int NS = n_sums(S);
   const int ld = Lp + 1;                              // padded row length (doubles)
   double* s_dt = reinterpret_cast<double*>(lds);      // dtau [nu][ld]
-  double* s_tb = s_dt + kTile64 * ld;                 // tau_bar [nu][ld], later dtau_bar
-  double* s_sums = s_tb + kTile64 * ld;               // [Lp][NS]
+  double* s_tb = s_dt + TILE * ld;                    // tau_bar [nu][ld], later dtau_bar
+  double* s_sums = s_tb + TILE * ld;                  // [Lp][NS]
+  const bool act = lane < TILE;                       // this lane holds a wavenumber of the tile
   for (int i = tid; i < Lp * NS; i += kBlockT) s_sums[i] = 0.0;
 
   const double* rec = reinterpret_cast<const double*>(w.rec) + (size_t)b * Lp * rec_len(S);
@@ -660,94 +662,96 @@ __global__ __launch_bounds__(kBlockT) void k_trans_adj_fp64(Model m, Work w, Tab
   const double* area = reinterpret_cast<const double*>(w.area) + (size_t)b * Lp;
   const double* dm = w.dm + (size_t)b * m.K;
 
-  double abar_r[kRows64];
+  double abar_r[ROWS];
 #pragma unroll
-  for (int k = 0; k < kRows64; ++k) abar_r[k] = 0.0;
+  for (int k = 0; k < ROWS; ++k) abar_r[k] = 0.0;
   // 16x16 Pbar tiles with column block >= row block, round-robin over waves
   const int MB16 = (L + 15) >> 4;
-  int pt_mi[kPSlots64], pt_nl[kPSlots64];
+  int pt_mi[PSLOTS], pt_nl[PSLOTS];
   {
     int t = 0;
-    for (int q = 0; q < kPSlots64; ++q) pt_mi[q] = pt_nl[q] = -1;
+    for (int q = 0; q < PSLOTS; ++q) pt_mi[q] = pt_nl[q] = -1;
     for (int mi = 0; mi < MB16; ++mi)
       for (int nl = mi; nl < MB16; ++nl, ++t)
-        if (t % 8 == wv && t / 8 < kPSlots64) {
+        if (t % 8 == wv && t / 8 < PSLOTS) {
           pt_mi[t / 8] = mi;
           pt_nl[t / 8] = nl;
         }
   }
-  f64x4 pacc[kPSlots64];
+  f64x4 pacc[PSLOTS];
 #pragma unroll
-  for (int q = 0; q < kPSlots64; ++q) pacc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < PSLOTS; ++q) pacc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
 
   // non-grey cloud: Q_ext(nu) and its spectral derivatives, and (wave 0) the sums over
   // nu of G(nu) dQ/dp_k with G = sum_l D_l dtau_bar_l
   double hq[kCloudSpec] = {};
   CloudCoef<double> cc{};
   if (m.cloud_ng) cc = load_cloud<double>(w.cloud + (size_t)b * kCloudSpec);
-  const int t0 = chunk * m.n_tiles64 / C, t1 = (chunk + 1) * m.n_tiles64 / C;
+  const int ntiles = m.n_nu_pad / TILE;
+  const int t0 = chunk * ntiles / C, t1 = (chunk + 1) * ntiles / C;
   for (int tile = t0; tile < t1; ++tile) {
-    const int nu = tile * kTile64 + lane;
+    const int nu = tile * TILE + (act ? lane : 0);
     const double nu4 = tb.nu4d[nu];
     double dqx[kCloudSpec];
     const double qx = m.cloud_ng ? cloud_q<double>(m.cloud_qext, cc, m.nu[nu], dqx) : 1.0;
     for (int l = wv; l < Lp; l += 8) {
       double d = 0.0;
-      if (l < L) opacity_fp64_terms<S, CIA>(m, tb, cells[l], rec + (size_t)l * rec_len(S), nu, nu4, d, nullptr, nullptr, qx);
-      s_dt[lane * ld + l] = d;
+      if (l < L && act) opacity_fp64_terms<S, CIA>(m, tb, cells[l], rec + (size_t)l * rec_len(S), nu, nu4, d, nullptr, nullptr, qx);
+      if (act) s_dt[lane * ld + l] = d;
     }
     const int bin = w.bin_of[nu];
-    const double dbar = bin >= 0 ? dm[bin] * w.inv_cnt[bin] : 0.0;
+    const double dbar = bin >= 0 && act ? dm[bin] * w.inv_cnt[bin] : 0.0;
     __syncthreads();
     // tau_i, seeds, tau_bar
 #pragma unroll
-    for (int k = 0; k < kRows64; ++k) {
+    for (int k = 0; k < ROWS; ++k) {
       const int i = wv + 8 * k;
       if (i < Lp) {
         double tbv = 0.0;
-        if (i < L) {
+        if (i < L && act) {
           double tau = 0.0;
           for (int l = i; l < L; ++l) tau = fma(pm[(size_t)i * Lp + l], s_dt[lane * ld + l], tau);
           const double one_m_e = -expm1(-tau);
           abar_r[k] += dbar * one_m_e;
           tbv = dbar * area[i] * (1.0 - one_m_e);
         }
-        s_tb[lane * ld + i] = tbv;
+        if (act) s_tb[lane * ld + i] = tbv;
       }
     }
     __syncthreads();
     // Pbar += tau_bar dtau^T (FP64 MFMA, k = wavenumber)
 #pragma unroll
-    for (int q = 0; q < kPSlots64; ++q) {
+    for (int q = 0; q < PSLOTS; ++q) {
       const int mi = pt_mi[q], nl = pt_nl[q];
       if (mi < 0) continue;
       const int ri = 16 * mi + (lane & 15), cl = 16 * nl + (lane & 15);
 #pragma unroll 1
-      for (int ks = 0; ks < kTile64 / 4; ++ks) {
+      for (int ks = 0; ks < TILE / 4; ++ks) {
         const int nr = 4 * ks + (lane >> 4);
         pacc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_tb[nr * ld + ri], s_dt[nr * ld + cl], pacc[q], 0, 0, 0);
       }
     }
     // dtau_bar_l = sum_{i <= l} P_il tau_bar_i
-    double dtb[kRows64];
+    double dtb[ROWS];
 #pragma unroll
-    for (int k = 0; k < kRows64; ++k) {
+    for (int k = 0; k < ROWS; ++k) {
       const int l = wv + 8 * k;
       double acc = 0.0;
-      if (l < L)
+      if (l < L && act)
         for (int i = 0; i <= l; ++i) acc = fma(pm[(size_t)i * Lp + l], s_tb[lane * ld + i], acc);
       dtb[k] = acc;
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kRows64; ++k) {
+    for (int k = 0; k < ROWS; ++k) {
       const int l = wv + 8 * k;
-      if (l < Lp) s_tb[lane * ld + l] = dtb[k];
+      if (l < Lp && act) s_tb[lane * ld + l] = dtb[k];
     }
     __syncthreads();
     if (m.cloud_ng && wv == 0) {
       double g = 0.0;
-      for (int l = 0; l < L; ++l) g = fma(rec[(size_t)l * rec_len(S) + 4], s_tb[lane * ld + l], g);
+      if (act)
+        for (int l = 0; l < L; ++l) g = fma(rec[(size_t)l * rec_len(S) + 4], s_tb[lane * ld + l], g);
 #pragma unroll
       for (int k = 0; k < kCloudSpec; ++k) hq[k] = fma(g, dqx[k], hq[k]);
     }
@@ -755,7 +759,7 @@ __global__ __launch_bounds__(kBlockT) void k_trans_adj_fp64(Model m, Work w, Tab
     for (int l = wv; l < L; l += 8) {
       double d, t[S + 2], dw[S + 2];
       opacity_fp64_terms<S, CIA>(m, tb, cells[l], rec + (size_t)l * rec_len(S), nu, nu4, d, t, dw, qx);
-      const double db = s_tb[lane * ld + l];
+      const double db = act ? s_tb[lane * ld + l] : 0.0;
       double sums[NS];
       double ht = 0.0, htc = 0.0;
 #pragma unroll
@@ -797,7 +801,7 @@ __global__ __launch_bounds__(kBlockT) void k_trans_adj_fp64(Model m, Work w, Tab
   }
   double* pb = reinterpret_cast<double*>(aw.pbar) + pair * Lp * Lp;
 #pragma unroll
-  for (int q = 0; q < kPSlots64; ++q) {
+  for (int q = 0; q < PSLOTS; ++q) {
     const int mi = pt_mi[q], nl = pt_nl[q];
     if (mi < 0) continue;
 #pragma unroll
@@ -806,7 +810,7 @@ __global__ __launch_bounds__(kBlockT) void k_trans_adj_fp64(Model m, Work w, Tab
   }
   double* ab = aw.abar + pair * Lp;
 #pragma unroll
-  for (int k = 0; k < kRows64; ++k) {
+  for (int k = 0; k < ROWS; ++k) {
     const int i = wv + 8 * k;
     const double v = wave_sum(abar_r[k]);
     if (lane == 0 && i < Lp) ab[i] = v;
@@ -1345,6 +1349,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce_chunks(Model m, Work w, AdjWo
 // host side
 // reduced-precision reverse kernel shapes: (tile, row blocks)
 static int adj_tile(int variant) { return variant == kAdjT128M4 ? 128 : 64; }
+// FP64 reverse kernel: instance 0 (64-wavenumber tiles) up to 128 padded layers, 1 (32) up to 160
+static int adj_fp64_instance(const Model& m) { return m.L_pad <= 128 ? 0 : 1; }
+static int adj_tile64(const Model& m) { return adj_fp64_instance(m) == 0 ? 64 : 32; }
 static int adj_mb(int variant) { return variant == kAdjT64M5 ? 5 : 4; }
 static int adj_threads(int variant) { return 4 * adj_tile(variant); }
 static int adj_slots(int variant) { return (adj_mb(variant) + 1) / 2; }
@@ -1352,7 +1359,7 @@ static int adj_slots(int variant) { return (adj_mb(variant) + 1) / 2; }
 int adjoint_chunks(const Model& m, const AdjWork& aw, int B, bool fp64) {
   if (m.mode == kEmission) return 1;   // the emission reverse pass keeps no per-chunk partials
   // the FP64 reverse kernel walks 64-wavenumber tiles
-  const int tiles = m.n_nu_pad / (fp64 ? kTile64 : adj_tile(aw.variant));
+  const int tiles = m.n_nu_pad / (fp64 ? adj_tile64(m) : adj_tile(aw.variant));
   const int target = fp64 ? 1024 : aw.chunk_target;
   int c = (target + B - 1) / B;
   return c < 1 ? 1 : (c > tiles ? tiles : c);
@@ -1361,7 +1368,7 @@ int adjoint_chunks(const Model& m, const AdjWork& aw, int B, bool fp64) {
 bool adjoint_supported(const Model& m, bool fp64) {
   if (m.ck) return false;   // the correlated-k path is a forward model only
   if (m.mode == kEmission) return m.L_pad <= (fp64 ? 128 : 160);
-  return m.L_pad <= (fp64 ? 128 : 160);
+  return m.L_pad <= 160;
 }
 
 // A ragged context of more than kShortLayers padded layers with a 4-row-block shape (128 x 4
@@ -1444,7 +1451,7 @@ bool adjoint_alloc(AdjWork& aw, const Model& m, int B_max, bool fp64, const std:
 
 static size_t adj_lds_bytes(const Model& m, bool fp64, int variant) {
   const size_t Lp = m.L_pad, ns = n_sums(m.S);
-  if (fp64) return (size_t)2 * kTile64 * (Lp + 1) * 8 + Lp * ns * 8;
+  if (fp64) return (size_t)2 * adj_tile64(m) * (Lp + 1) * 8 + Lp * ns * 8;
   const size_t tile = adj_tile(variant), rows = std::min(Lp, (size_t)32 * adj_mb(variant));
   return std::max(2 * tile * (rows + 4) * 4 + rows * 4, tile / 32 * Lp * 8);
 }
@@ -1461,7 +1468,8 @@ const void* adj_mixed_kernel(int variant) {
 
 template <bool F64, int S, bool CIA>
 const void* adj_kernel(int variant) {
-  if constexpr (F64) return (void)variant, (const void*)k_trans_adj_fp64<S, CIA>;
+  if constexpr (F64)
+    return variant == 0 ? (const void*)k_trans_adj_fp64<S, CIA, 64, 16, 5> : (const void*)k_trans_adj_fp64<S, CIA, 32, 20, 7>;
   else return adj_mixed_kernel<S, CIA>(variant);
 }
 
@@ -1493,7 +1501,7 @@ const void* ls_kernel_for(int S, bool cia, bool ng) {
 hipError_t adjoint_configure(const Model& m, bool fp64) {
   if (!adjoint_supported(m, fp64) || m.mode == kEmission) return hipSuccess;
   if (fp64) {
-    const void* k = adj_kernel_for<true>(m.S, m.has_cia, 0);
+    const void* k = adj_kernel_for<true>(m.S, m.has_cia, adj_fp64_instance(m));
     const size_t bytes = adj_lds_bytes(m, true, 0);
     if (!k || bytes > 160 * 1024) return hipErrorInvalidValue;
     return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -1535,8 +1543,8 @@ void launch_trans_adjoint(const Model& m, const Work& w, const Tables& tb, const
   int C = adjoint_chunks(m, aw, B, fp64);
   if (fp64) {
     void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&aw, (void*)&B, (void*)&C};
-    hipLaunchKernel(adj_kernel_for<true>(m.S, m.has_cia, 0), dim3((unsigned)(B * C)), dim3(kBlockT), args,
-                    adj_lds_bytes(m, true, 0), st);
+    hipLaunchKernel(adj_kernel_for<true>(m.S, m.has_cia, adj_fp64_instance(m)), dim3((unsigned)(B * C)), dim3(kBlockT),
+                    args, adj_lds_bytes(m, true, 0), st);
     return;
   }
   const int32_t* cls = adj_split(m, aw.variant) ? w.cls : nullptr;   // the forward built the classes

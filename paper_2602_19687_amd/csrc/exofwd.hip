@@ -816,7 +816,7 @@ exofwd_status exofwd_grad(exofwd_ctx* c, int32_t B, const double* params, const 
   if (!lnL || !grad) return fail(c, EXOFWD_ERR_ARG, "lnL and grad are required");
   if (!adjoint_supported(c->m, c->precision == EXOFWD_PREC_FP64))
     return fail(c, EXOFWD_ERR_UNSUPPORTED,
-                "the adjoint needs at most 160 padded layers (reduced precision) or 128 (FP64)");
+                "the adjoint needs at most 160 padded layers (128 for FP64 emission)");
   auto enqueue = [&]() { return run_grad(c, B, params, n_layers, spectra, lnL, grad, status, hip_stream); };
   if (!c->use_graphs) return enqueue();
   return graph_call(c, 1, B, {params, n_layers, spectra, lnL, grad, status, nullptr}, (hipStream_t)hip_stream,

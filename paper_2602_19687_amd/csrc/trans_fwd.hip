@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
   uint16_t* s_blo = s_bhi + kTileNu * stride;
   const int n_area = KS ? Lp : lt;   // chord rows
   float* s_area = reinterpret_cast<float*>(s_blo + kTileNu * stride);
-  float* s_red = s_area + n_area;   // [8][32]
+  double* s_red = reinterpret_cast<double*>(s_area + n_area);   // [8][32]
   int* s_live = reinterpret_cast<int*>(s_red + 8 * 32);   // [0, MB): row block holds a chord below kOpaqueTau; [7]: frontier
   if (tid < 8) s_live[tid] = 0;
 
@@ -165,7 +165,10 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
   const uint16_t* fl = fh + plane;
   const int col = 32 * nb + (lane & 31);
   const int khalf = 8 * (lane >> 5);
-  float dsum = 0.0f;
+  // the annulus sum in FP64: near the best fit the likelihood seeds carry the spectrum's
+  // rounding relative to the noise level, and a gradient that cancels to a fraction of
+  // its terms carries it too
+  double dsum = 0.0;
   // row block mi's products over the K blocks [k_lo, k_hi), B rows from LDS row 16 (kb - k_base)
   auto chord = [&](f32x16 acc, int mi, int k_lo, int k_hi, int k_base) {
     for (int kb = k_lo; kb < k_hi; ++kb) {
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int row = 32 * mi + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
-      dsum = fmaf(s_area[row], one_minus_exp(acc[j], exp2_fast(-1.4426950408889634f * acc[j])), dsum);
+      dsum = fma((double)s_area[row], (double)one_minus_exp(acc[j], exp2_fast(-1.4426950408889634f * acc[j])), dsum);
       live |= !(acc[j] > kOpaqueTau);
     }
     // the reverse pass skips row blocks whose chords are all opaque across the tile
@@ -232,8 +235,8 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
   __syncthreads();
   if (tid < kTileNu) {
     const int h = tid >> 5, c = tid & 31;
-    const float tot = s_red[h * 32 + c] + s_red[(h + 4) * 32 + c];
-    if (nu0 + tid < m.n_nu) out[nu0 + tid] = (float)w.core[b] + tot;
+    const double tot = s_red[h * 32 + c] + s_red[(h + 4) * 32 + c];
+    if (nu0 + tid < m.n_nu) out[nu0 + tid] = (float)(w.core[b] + tot);
   }
   if (dtau_out) {
     if (tid == 0) {
@@ -357,7 +360,7 @@ const void* fwd_kernel_for(int S, bool cia, bool ng, bool ks = false) {
 
 static size_t fwd_lds_bytes(const Model& m, bool fp64, int lt, bool ks = false) {
   if (fp64) return (size_t)m.L_pad * kTile64 * 8 + 4 * kTile64 * 8;
-  return (size_t)2 * kTileNu * (lt + 8) * 2 + (size_t)(ks ? m.L_pad : lt) * 4 + 8 * 32 * 4 + 8 * 4;
+  return (size_t)2 * kTileNu * (lt + 8) * 2 + (size_t)(ks ? m.L_pad : lt) * 4 + 8 * 32 * 8 + 8 * 4;
 }
 
 size_t trans_fwd_lds_bytes(const Model& m, bool fp64) { return fwd_lds_bytes(m, fp64, m.L_pad); }
