@@ -438,12 +438,11 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
 // (listed by the profile kernel), whose table pairs are fetched once per tile,
 // together with the tile's dtau_bar; lanes hold two wavenumbers, partial sums stay
 // in registers across the tiles and are reduced over the wave once
-__host__ __device__ constexpr int ls_layers(bool ngc) { return kLsGroup; }
 
 template <int S, bool CIA, bool NGC>
 __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Tables tb, AdjWork aw, int B) {
   constexpr int NS = n_sums(S);
-  constexpr int kLs = ls_layers(NGC);
+  constexpr int kLs = kLsGroup;
   const int lane = threadIdx.x & 63;
   // consecutive waves (one wavenumber chunk) on one XCD: its L2 holds that chunk's table columns
   const int gw = xcd_logical_block(blockIdx.x, gridDim.x) * (kBlock / 64) +
