@@ -193,8 +193,7 @@ enum { EXOFWD_CK_RORR = 0, EXOFWD_CK_PRODUCT = 1 };
  *   EXOFWD_ERR_CONFIG       an invalid description, including a non-finite entry in
  *                           log10_xsec or log10_cia (give a zero cross-section as a
  *                           finite floor);
- *   EXOFWD_ERR_UNSUPPORTED  FP64 emission with more than 128 padded layers; in MIXED
- *                           precision, a line or CIA table of 2^31 bytes or more once
+ *   EXOFWD_ERR_UNSUPPORTED  in MIXED precision, a line or CIA table of 2^31 bytes or more once
  *                           encoded (2 bytes per entry in transmission, 4 in emission,
  *                           n_nu padded to a multiple of 128), or padded layers x padded
  *                           n_nu x 4 bytes of 2^31 or more (the reduced-precision
@@ -211,9 +210,9 @@ int32_t exofwd_num_nu(const exofwd_ctx* ctx);       /* n_nu, or -1 */
 int32_t exofwd_num_bins(const exofwd_ctx* ctx);     /* K, or -1 */
 int32_t exofwd_precision(const exofwd_ctx* ctx);    /* EXOFWD_PREC_*, or -1 */
 /* 1 if exofwd_grad supports this context's workload, 0 if not, -1 for a NULL
- * context.  Supported: transmission with n_layers_max <= 160 (both precisions);
- * emission with n_layers_max <= 160 in MIXED or <= 128 in FP64;
- * every T-p profile and cloud model. */
+ * context.  Supported: transmission and emission with cross-section tables
+ * (n_layers_max <= 160, both precisions), every T-p profile and cloud model; not
+ * the correlated-k tables, whose path is a forward model only. */
 int32_t exofwd_grad_supported(const exofwd_ctx* ctx);
 
 /*

@@ -1366,7 +1366,6 @@ int adjoint_chunks(const Model& m, const AdjWork& aw, int B, bool fp64) {
 
 bool adjoint_supported(const Model& m, bool fp64) {
   if (m.ck) return false;   // the correlated-k path is a forward model only
-  if (m.mode == kEmission) return m.L_pad <= (fp64 ? 128 : 160);
   return m.L_pad <= 160;
 }
 

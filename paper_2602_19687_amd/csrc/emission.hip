@@ -57,8 +57,11 @@ __device__ inline Real lin_source(Real x, Real e) {
   }
 }
 
-// plain FP64 path
-template <typename Real>
+// plain FP64 path.  STAGED: the Planck intensities at the levels are staged in LDS
+// with the layer optical depths (up to 128 padded layers); beyond, the LDS holds the
+// optical depths alone and each angle's sweep forms the level intensities itself
+// (the same values)
+template <typename Real, bool STAGED>
 __global__ __launch_bounds__(kBlock) void k_emission(Model m, Work w, Tables tb, int B, Real* __restrict__ spec,
                                                      Real* __restrict__ dtau_out) {
   static_assert(sizeof(Real) == 8, "the reduced-precision path is k_emission_mixed");
@@ -74,9 +77,9 @@ __global__ __launch_bounds__(kBlock) void k_emission(Model m, Work w, Tables tb,
     return;
   }
   const int L = w.nlay[b];
-  Real* s_dt = reinterpret_cast<Real*>(lds);          // [Lp][64]
-  Real* s_b = s_dt + (size_t)Lp * kTile64;            // [Lp+1][64] Planck at levels
-  Real* s_f = s_b + (size_t)(Lp + 1) * kTile64;       // [4][64] flux partials
+  Real* s_dt = reinterpret_cast<Real*>(lds);                        // [Lp][64]
+  Real* s_b = s_dt + (size_t)Lp * kTile64;                          // [Lp+1][64] Planck at levels (STAGED)
+  Real* s_f = s_b + (STAGED ? (size_t)(Lp + 1) * kTile64 : 0);      // [4][64] flux partials
   const int RL = rec_len(m.S);
   const Real* rec = reinterpret_cast<const Real*>(w.rec) + (size_t)b * Lp * RL;
   const int32_t* cells = w.cells + (size_t)b * Lp;
@@ -88,22 +91,28 @@ __global__ __launch_bounds__(kBlock) void k_emission(Model m, Work w, Tables tb,
     // the reverse pass reads the layer optical depths back
     if (dtau_out) dtau_out[((size_t)b * Lp + l) * m.n_nu_pad + nu] = s_dt[l * kTile64 + lane];
   }
-  for (int j = wv; j <= L; j += 4) s_b[j * kTile64 + lane] = planck<Real>(Real(t_lev[j]), nuv);
+  if constexpr (STAGED)
+    for (int j = wv; j <= L; j += 4) s_b[j * kTile64 + lane] = planck<Real>(Real(t_lev[j]), nuv);
   __syncthreads();
+  auto level_b = [&](int j) {
+    if constexpr (STAGED) return s_b[j * kTile64 + lane];
+    else return planck<Real>(Real(t_lev[j]), nuv);
+  };
 
   // upward sweep, one (wavenumber, angle) per thread
   Real flux = Real(0);
   for (int k = wv; k < m.n_mu; k += 4) {
     const Real mu = Real(m.mu_nodes[k]);
     const Real inv_mu = Real(1) / mu;
-    Real inten = s_b[lane];
+    Real inten = level_b(0), bb = inten;
     for (int l = 0; l < L; ++l) {
       const Real x = s_dt[l * kTile64 + lane] * inv_mu;
       Real e;
       if constexpr (sizeof(Real) == 8) e = exp(-x); else e = __expf(-x);
-      const Real bb = s_b[l * kTile64 + lane], bt = s_b[(l + 1) * kTile64 + lane];
+      const Real bt = level_b(l + 1);
       // I e^-x + B_top (1 - e^-x) + (B_bot - B_top) src, as an increment of I
       inten += -expm1(-x) * (bt - inten) + (bb - bt) * lin_source<Real>(x, e);
+      bb = bt;
     }
     flux += Real(2.0 * M_PI * m.mu_weights[k]) * mu * inten;
   }
@@ -268,16 +277,23 @@ const void* emis_kernel_for(int S, bool cia) {
   return nullptr;
 }
 
+// FP64: level intensities staged with the optical depths up to 128 padded layers
+static bool emis_staged(const Model& m) { return m.L_pad <= 128; }
+
+static const void* emis_fp64_kernel(const Model& m) {
+  return emis_staged(m) ? (const void*)k_emission<double, true> : (const void*)k_emission<double, false>;
+}
+
 size_t emission_lds_bytes(const Model& m, bool fp64) {
   if (!fp64) return 0;   // the reduced-precision kernel streams without LDS
   const size_t rs = 8;
-  return rs * ((size_t)m.L_pad * kTile64 + (size_t)(m.L_pad + 1) * kTile64 + 4 * kTile64);
+  return rs * ((size_t)m.L_pad * kTile64 + (emis_staged(m) ? (size_t)(m.L_pad + 1) * kTile64 : 0) + 4 * kTile64);
 }
 
 hipError_t emission_configure(const Model& m, bool fp64) {
   const size_t bytes = emission_lds_bytes(m, fp64);
   if (bytes > 160 * 1024) return hipErrorInvalidValue;
-  if (fp64) return hipFuncSetAttribute((const void*)k_emission<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (fp64) return hipFuncSetAttribute(emis_fp64_kernel(m), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   const void* k = emis_kernel_for(m.S, m.has_cia);
   if (!k) return hipErrorInvalidValue;
   return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -287,8 +303,10 @@ void launch_emission(const Model& m, const Work& w, const Tables& tb, int B, voi
                      void* dtau_out) {
   const size_t lds = emission_lds_bytes(m, fp64);
   if (fp64) {
-    hipLaunchKernelGGL(k_emission<double>, dim3((unsigned)(m.n_tiles64 * B)), dim3(kBlock), lds, st, m, w, tb, B,
-                       (double*)spec, (double*)dtau_out);
+    double* spec_d = (double*)spec;
+    double* dtau_d = (double*)dtau_out;
+    void* args[] = {(void*)&m, (void*)&w, (void*)&tb, (void*)&B, (void*)&spec_d, (void*)&dtau_d};
+    hipLaunchKernel(emis_fp64_kernel(m), dim3((unsigned)(m.n_tiles64 * B)), dim3(kBlock), args, lds, st);
   } else {
     // four 64-wavenumber tiles (one per wave) of one sample per workgroup
     const dim3 grid((unsigned)((m.n_tiles64 + 3) / 4 * B));

@@ -297,9 +297,6 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
     return create_fail(E, "cloudy/clear mixing needs a transmission model with a cloud");
   if (g.has_bd && (g.mode != EXOFWD_EMISSION || g.has_scale || !(g.bd_distance > 0.0)))
     return create_fail(E, "an isolated object is an emission model without R_p scaling and with a distance > 0");
-  // the FP64 emission kernel stages a tile's layers in LDS: at most 128 padded layers
-  if (g.mode == EXOFWD_EMISSION && g.precision == EXOFWD_PREC_FP64 && (g.n_layers_max + 31) / 32 * 32 > 128)
-    return create_fail(EXOFWD_ERR_UNSUPPORTED, "FP64 emission takes at most 128 padded layers");
   // correlated-k tables: kCkG g-points per bin, reduced precision, forward model only
   if (g.ck_g != 0) {
     if (g.ck_g != kCkG) return create_fail(EXOFWD_ERR_UNSUPPORTED, "correlated-k tables need exactly 8 g-points");
@@ -816,7 +813,7 @@ exofwd_status exofwd_grad(exofwd_ctx* c, int32_t B, const double* params, const 
   if (!lnL || !grad) return fail(c, EXOFWD_ERR_ARG, "lnL and grad are required");
   if (!adjoint_supported(c->m, c->precision == EXOFWD_PREC_FP64))
     return fail(c, EXOFWD_ERR_UNSUPPORTED,
-                "the adjoint needs at most 160 padded layers (128 for FP64 emission)");
+                "the adjoint needs at most 160 padded layers");
   auto enqueue = [&]() { return run_grad(c, B, params, n_layers, spectra, lnL, grad, status, hip_stream); };
   if (!c->use_graphs) return enqueue();
   return graph_call(c, 1, B, {params, n_layers, spectra, lnL, grad, status, nullptr}, (hipStream_t)hip_stream,

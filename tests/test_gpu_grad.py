@@ -229,13 +229,31 @@ def test_emission_fp64_grad_vs_complex_step():
     assert max(errs) < TOL["fp64"]
 
 
-def test_emission_fp64_beyond_128_layers_unsupported():
-    # the FP64 emission kernels stage a tile's layers in LDS: the context is refused
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_emission_grad_up_to_150_layers(prec):
+    """Emission at 160 padded layers: the FP64 forward then keeps only the optical
+    depths in LDS (each angle's sweep forms the level intensities), and the FP64 and
+    reduced-precision adjoints run past 128 layers; per-sample layer counts on both
+    sides of 128."""
     from paper_2602_19687_amd import ForwardModel
-    from paper_2602_19687_amd import _lib as L
-    wl = reduced(2, n_nu=200, n_bins=8, batch=2, step=90, n_layers=130)
-    with pytest.raises(L.ExoError, match="unsupported"):
-        ForwardModel(wl, precision="fp64", batch_max=2)
+    wl = reduced(2, n_nu=300, n_bins=10, batch=4, step=60, n_layers=150)
+    nl = np.array([150, 129, 97, 33], dtype=np.int32)
+    nl_t = torch.tensor(nl, device="cuda")
+    lnl, g, st, lnl_f = _grad(wl, prec, wl["params"], n_layers=nl_t)
+    assert np.array_equal(lnl, lnl_f)
+    fm = ForwardModel(wl, precision=prec, batch_max=4)
+    spec, _, _ = fm.forward(torch.tensor(wl["params"], dtype=torch.float64, device="cuda"), n_layers=nl_t)
+    spec = spec.cpu().numpy()
+    fm.close()
+    stol = {"fp64": 1e-5, "mixed": 1e-4}[prec]
+    for b in range(4):
+        ref = oracle.forward(wl, wl["params"][b], n_layers=int(nl[b]))
+        gref = oracle.grad_complex_step(wl, wl["params"][b], n_layers=int(nl[b]))
+        assert st[b] == 0 and ref["status"] == 0
+        es = np.max(np.abs(spec[b] - ref["spectrum"]) / np.abs(ref["spectrum"]))
+        e = grad_err(g[b], gref)
+        print(f"emission {prec} L={nl[b]} (L_pad 160): spectrum err {es:.3e}, grad err {e:.3e}")
+        assert es < stol and e < TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
