@@ -41,21 +41,21 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// cost-balanced split of 32-row blocks between two waves; `rev` costs rows by
-// their K extent in the transposed product (grows with the block index)
-__host__ __device__ inline unsigned split_blocks(int part, int MBe, int KBe, bool rev) {
+// cost-balanced split of 32-row blocks between `parts` (2 or 4) waves: each block in
+// turn goes to the part with the least cost so far (the lowest such part on a tie);
+// `rev` costs rows by their K extent in the transposed product (grows with the
+// block index)
+__host__ __device__ inline unsigned split_blocks(int part, int parts, int MBe, int KBe, bool rev) {
   unsigned mine = 0;
-  int c0 = 0, c1 = 0;
+  int c[4] = {0, 0, 0, 0};
   for (int q = 0; q < MBe; ++q) {
     const int mi = rev ? MBe - 1 - q : q;
     const int cost = rev ? (2 * mi + 2 < KBe ? 2 * mi + 2 : KBe) : KBe - 2 * mi;
-    if (c0 <= c1) {
-      if (part == 0) mine |= 1u << mi;
-      c0 += cost;
-    } else {
-      if (part == 1) mine |= 1u << mi;
-      c1 += cost;
-    }
+    int best = 0;
+    for (int p = 1; p < parts; ++p)
+      if (c[p] < c[best]) best = p;
+    if (best == part) mine |= 1u << mi;
+    c[best] += cost;
   }
   return mine;
 }
@@ -73,28 +73,28 @@ __device__ inline int nth_bit(unsigned mask, int q) {
 // ============================================================================
 // reduced-precision reverse kernel over TILE-wavenumber tiles for up to MB
 // 32-row blocks (L_pad <= 32 MB); each wave owns one 32-wavenumber column block
-// and one of two cost-balanced halves of the row blocks, so every path-matrix
+// and one of PARTS cost-balanced parts of the row blocks, so every path-matrix
 // fragment it loads feeds the products of its whole column block
-template <int TILE, int MB>
+template <int TILE, int MB, int PARTS>
 struct AdjShape {
   static constexpr int kTile = TILE;
   static constexpr int kNb = TILE / 32;                           // column blocks per tile
-  static constexpr int kWaves = 2 * kNb;                          // two row-block halves per column block
+  static constexpr int kWaves = PARTS * kNb;                      // PARTS row-block parts per column block
   static constexpr int kThreads = 64 * kWaves;
   static constexpr int kHalves = TILE / 64;                       // 64-wavenumber halves (phase A items)
-  static constexpr int kSlots = (MB + 1) / 2;                     // row blocks per wave (checked on the host)
+  static constexpr int kSlots = PARTS == 2 ? (MB + 1) / 2 : (MB <= 4 ? 1 : 2);   // row blocks per wave (checked on the host)
   static constexpr int kPSlots = (MB * (MB + 1) / 2 + kWaves - 1) / kWaves;   // 32x32 Pbar tiles per wave
-  static constexpr int kItems = MB;                               // (layer octet, half) items per wave
+  static constexpr int kItems = (4 * kHalves * MB + kWaves - 1) / kWaves;     // (layer octet, half) items per wave
 };
 
 // `cls` (may be null): the layer-count classes of the call (layer_classes), whose class
 // `cl` this launch serves (its samples have at most 32 MB layers)
-template <int S, bool CIA, int TILE, int MB>
-__global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, Tables tb, AdjWork aw, int B, int C,
-                                                              const int32_t* __restrict__ cls, int cl) {
-  using Sh = AdjShape<TILE, MB>;
-  static_assert(Sh::kThreads == 4 * TILE, "launch bound");
-  static_assert(Sh::kItems * Sh::kWaves == 4 * Sh::kHalves * MB, "phase A items cover 4 MB octets per half");
+template <int S, bool CIA, int TILE, int MB, int PARTS>
+__global__ __launch_bounds__(2 * PARTS * TILE) void k_trans_adj_mixed(Model m, Work w, Tables tb, AdjWork aw, int B,
+                                                                      int C, const int32_t* __restrict__ cls, int cl) {
+  using Sh = AdjShape<TILE, MB, PARTS>;
+  static_assert(Sh::kThreads == 2 * PARTS * TILE, "launch bound");
+  static_assert(Sh::kItems * Sh::kWaves >= 4 * Sh::kHalves * MB, "phase A items cover 4 MB octets per half");
   constexpr int kTileA = Sh::kTile, kBlockA = Sh::kThreads, kNbA = Sh::kNb, kWavesA = Sh::kWaves;
   constexpr int kSlots = Sh::kSlots, kPSlotsA = Sh::kPSlots, kItemsA = Sh::kItems, kHalves = Sh::kHalves;
   extern __shared__ __align__(16) unsigned char lds[];
@@ -129,8 +129,8 @@ __global__ __launch_bounds__(4 * TILE) void k_trans_adj_mixed(Model m, Work w, T
   // readfirstlane keeps them in scalar registers
   int t_mi[kSlots], d_ml[kSlots];
   {
-    const unsigned mine_t = split_blocks(part, MBe, KBe, false);   // rows i of tau
-    const unsigned mine_d = split_blocks(part, MBe, KBe, true);    // rows l of dtau_bar
+    const unsigned mine_t = split_blocks(part, PARTS, MBe, KBe, false);   // rows i of tau
+    const unsigned mine_d = split_blocks(part, PARTS, MBe, KBe, true);    // rows l of dtau_bar
 #pragma unroll
     for (int q = 0; q < kSlots; ++q) {
       t_mi[q] = __builtin_amdgcn_readfirstlane(nth_bit(mine_t, q));
@@ -1352,8 +1352,13 @@ static int adj_tile(int variant) { return variant == kAdjT128M4 ? 128 : 64; }
 static int adj_fp64_instance(const Model& m) { return m.L_pad <= 128 ? 0 : 1; }
 static int adj_tile64(const Model& m) { return adj_fp64_instance(m) == 0 ? 64 : 32; }
 static int adj_mb(int variant) { return variant == kAdjT64M5 ? 5 : 4; }
-static int adj_threads(int variant) { return 4 * adj_tile(variant); }
-static int adj_slots(int variant) { return (adj_mb(variant) + 1) / 2; }
+// row-block parts per column block: the 64-wavenumber shapes run eight waves, two per
+// SIMD, each with a quarter of the row blocks
+static int adj_parts(int variant) { return variant == kAdjT128M4 ? 2 : 4; }
+static int adj_threads(int variant) { return 64 * adj_parts(variant) * (adj_tile(variant) / 32); }
+static int adj_slots(int variant) {
+  return adj_parts(variant) == 2 ? (adj_mb(variant) + 1) / 2 : (adj_mb(variant) <= 4 ? 1 : 2);
+}
 
 int adjoint_chunks(const Model& m, const AdjWork& aw, int B, bool fp64) {
   if (m.mode == kEmission) return 1;   // the emission reverse pass keeps no per-chunk partials
@@ -1386,11 +1391,10 @@ bool adjoint_variant_fits(const Model& m, int variant) {
   // the greedy row-block split must never give a wave more blocks than it has slots
   for (int L = 1; L <= m.L_max; ++L) {
     const int KBe = (L + 15) >> 4, MBe = (L + 31) >> 5;
-    for (int part = 0; part < 2; ++part)
+    const int v = split && L > kShortLayers ? (int)kAdjT64M5 : variant;
+    for (int part = 0; part < adj_parts(v); ++part)
       for (int rev = 0; rev < 2; ++rev)
-        if (__builtin_popcount(split_blocks(part, MBe, KBe, rev != 0)) >
-            adj_slots(split && L > kShortLayers ? kAdjT64M5 : variant))
-          return false;
+        if (__builtin_popcount(split_blocks(part, adj_parts(v), MBe, KBe, rev != 0)) > adj_slots(v)) return false;
   }
   return true;
 }
@@ -1457,9 +1461,9 @@ static size_t adj_lds_bytes(const Model& m, bool fp64, int variant) {
 template <int S, bool CIA>
 const void* adj_mixed_kernel(int variant) {
   switch (variant) {
-    case kAdjT128M4: return (const void*)k_trans_adj_mixed<S, CIA, 128, 4>;
-    case kAdjT64M4: return (const void*)k_trans_adj_mixed<S, CIA, 64, 4>;
-    case kAdjT64M5: return (const void*)k_trans_adj_mixed<S, CIA, 64, 5>;
+    case kAdjT128M4: return (const void*)k_trans_adj_mixed<S, CIA, 128, 4, 2>;
+    case kAdjT64M4: return (const void*)k_trans_adj_mixed<S, CIA, 64, 4, 4>;
+    case kAdjT64M5: return (const void*)k_trans_adj_mixed<S, CIA, 64, 5, 4>;
   }
   return nullptr;
 }
