@@ -114,7 +114,10 @@ __global__ __launch_bounds__(2 * PARTS * TILE) void k_trans_adj_mixed(Model m, W
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int Lp = m.L_pad, L = w.nlay[b];
   const int rows = Lp < 32 * MB ? Lp : 32 * MB;        // LDS rows: the layers this shape can hold
-  const int ld = rows + 4;                             // dwords per wavenumber row (b128-conflict-free)
+  // dwords per wavenumber row (b128-conflict-free), fixed by the shape rather than by
+  // L_pad: the gathers of phase E then address eight rows from one register with
+  // immediate offsets
+  constexpr int ld = 32 * MB + 4;
   uint32_t* s_dt = reinterpret_cast<uint32_t*>(lds);   // dtau    [nu][ld] as packed bf16 hi/lo
   uint32_t* s_tt = s_dt + kTileA * ld;                 // tau_bar [nu][ld] as packed bf16 hi/lo
   float* s_area = reinterpret_cast<float*>(s_tt + kTileA * ld);   // [Lp]
@@ -317,11 +320,15 @@ __global__ __launch_bounds__(2 * PARTS * TILE) void k_trans_adj_mixed(Model m, W
       const uint32_t* pbp = s_dt + 8 * h * ld + 32 * nl + (lane & 31);
 #pragma unroll 1
       for (int ks = 0; ks < kTileA / 16; ++ks) {
+        // the step's row offset kept opaque in a scalar register: each operand's eight
+        // rows are then one address plus immediate offsets (the arrays lie past 64 KB)
+        int off = 16 * ks * ld;
+        asm volatile("" : "+s"(off));
         uint32_t va[8], vb[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          va[e] = pa[(16 * ks + e) * ld];
-          vb[e] = pbp[(16 * ks + e) * ld];
+          va[e] = pa[off + e * ld];
+          vb[e] = pbp[off + e * ld];
         }
         bf16x8 ah, al, bh, bl;
         frag_hl(va, ah, al);
@@ -1455,7 +1462,7 @@ static size_t adj_lds_bytes(const Model& m, bool fp64, int variant) {
   const size_t Lp = m.L_pad, ns = n_sums(m.S);
   if (fp64) return (size_t)2 * adj_tile64(m) * (Lp + 1) * 8 + Lp * ns * 8;
   const size_t tile = adj_tile(variant), rows = std::min(Lp, (size_t)32 * adj_mb(variant));
-  return std::max(2 * tile * (rows + 4) * 4 + rows * 4, tile / 32 * Lp * 8);
+  return std::max(2 * tile * (32 * adj_mb(variant) + 4) * 4 + rows * 4, tile / 32 * Lp * 8);
 }
 
 template <int S, bool CIA>
