@@ -152,6 +152,50 @@ __global__ __launch_bounds__(2 * PARTS * TILE) void k_trans_adj_mixed(Model m, W
   const int col = 32 * nb + (lane & 31);
   const int h = lane >> 5;
   const double* dm = w.dm + (size_t)b * m.K;
+  // 32x32 product over k-steps [k_lo, k_hi): A = path-matrix fragments (rs) of blocks
+  // row0 + k, B = the packed hi/lo rows 16k.. of the LDS array src at this wave's
+  // column.  The fragments go in two groups of two steps: one group's loads are in
+  // flight while the other group's products run.  Every iteration issues the same
+  // loads (steps past k_hi read the next row block's fragments, or zeros past the
+  // buffer's range, and are never used), so the waits count only the older group.
+  auto kloop = [&](__amdgpu_buffer_rsrc_t rs, int row0, int k_lo, int k_hi, const uint32_t* src) {
+    f32x16 acc = {};
+    bf16x8 ga[2][2], gb[2][2];   // [step][hi, lo]
+    auto load = [&](bf16x8 (&g)[2][2], int k) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        g[u][0] = frag(rs, row0 + k + u, 0);
+        g[u][1] = frag(rs, row0 + k + u, lo_plane);
+      }
+    };
+    auto product = [&](const bf16x8 (&g)[2][2], int k0) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int k = k0 + u;
+        if (k >= k_hi) break;
+        bf16x8 bh, bl;
+        {
+          const uint4 x0 = *reinterpret_cast<const uint4*>(src + col * ld + 16 * k + 8 * h);
+          const uint4 x1 = *reinterpret_cast<const uint4*>(src + col * ld + 16 * k + 8 * h + 4);
+          const uint32_t x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+          frag_hl(x, bh, bl);
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(g[u][1], bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(g[u][0], bl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(g[u][0], bh, acc, 0, 0, 0);
+      }
+    };
+    load(ga, k_lo);
+#pragma unroll 1
+    for (int kb = k_lo; kb < k_hi; kb += 4) {
+      load(gb, kb + 2);
+      product(ga, kb);
+      if (kb + 2 >= k_hi) break;
+      load(ga, kb + 4);
+      product(gb, kb + 2);
+    }
+    return acc;
+  };
 
   // Pbar tiles (32x32, column block >= row block), round-robin over the waves
   int pt_mi[kPSlotsA], pt_nl[kPSlotsA];
@@ -263,31 +307,7 @@ __global__ __launch_bounds__(2 * PARTS * TILE) void k_trans_adj_mixed(Model m, W
             *reinterpret_cast<uint4*>(s_tt + col * ld + 32 * mi + 8 * qd + 4 * h) = make_uint4(0u, 0u, 0u, 0u);
           continue;
         }
-        f32x16 acc = {};
-        // path-matrix fragments are loaded two k-steps ahead (a fragment past the
-        // sample's blocks reads the next row block's or zeros and is never used)
-        bf16x8 nh = frag(rs_p, mi * KB + 2 * mi, 0), nl_ = frag(rs_p, mi * KB + 2 * mi, lo_plane);
-        bf16x8 mh = frag(rs_p, mi * KB + 2 * mi + 1, 0), ml_ = frag(rs_p, mi * KB + 2 * mi + 1, lo_plane);
-#pragma unroll 1
-        for (int kb = 2 * mi; kb < KBe; ++kb) {
-          const bf16x8 ah = nh, al = nl_;
-          nh = mh;
-          nl_ = ml_;
-          if (kb + 2 < KBe) {
-            mh = frag(rs_p, mi * KB + kb + 2, 0);
-            ml_ = frag(rs_p, mi * KB + kb + 2, lo_plane);
-          }
-          bf16x8 bh, bl;
-          {
-            const uint4 x0 = *reinterpret_cast<const uint4*>(s_dt + col * ld + 16 * kb + 8 * h);
-            const uint4 x1 = *reinterpret_cast<const uint4*>(s_dt + col * ld + 16 * kb + 8 * h + 4);
-            const uint32_t x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-            frag_hl(x, bh, bl);
-          }
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
-        }
+        const f32x16 acc = kloop(rs_p, mi * KB, 2 * mi, KBe, s_dt);
 #pragma unroll
         for (int qd = 0; qd < 4; ++qd) {
           float tv[4];
@@ -351,32 +371,10 @@ __global__ __launch_bounds__(2 * PARTS * TILE) void k_trans_adj_mixed(Model m, W
         // rows below the opaque frontier would be exact zeros: the readers of
         // dtau_bar consult the frontier instead, so they are not stored
         if (ml < mi0) continue;
-        f32x16 acc = {};
         const int kend = min(2 * ml + 2, KBe);
         // the seed rows of blocks below mi0 are zero: the sum starts at row 32 mi0
         const int kbeg = min(2 * mi0, kend);
-        bf16x8 nh = frag(rs_pt, ml * KB + kbeg, 0), nl_ = frag(rs_pt, ml * KB + kbeg, lo_plane);
-        bf16x8 mh = frag(rs_pt, ml * KB + kbeg + 1, 0), ml_ = frag(rs_pt, ml * KB + kbeg + 1, lo_plane);
-#pragma unroll 1
-        for (int ki = kbeg; ki < kend; ++ki) {
-          const bf16x8 ah = nh, al = nl_;
-          nh = mh;
-          nl_ = ml_;
-          if (ki + 2 < kend) {
-            mh = frag(rs_pt, ml * KB + ki + 2, 0);
-            ml_ = frag(rs_pt, ml * KB + ki + 2, lo_plane);
-          }
-          bf16x8 bh, bl;
-          {
-            const uint4 x0 = *reinterpret_cast<const uint4*>(s_tt + col * ld + 16 * ki + 8 * h);
-            const uint4 x1 = *reinterpret_cast<const uint4*>(s_tt + col * ld + 16 * ki + 8 * h + 4);
-            const uint32_t x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-            frag_hl(x, bh, bl);
-          }
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
-        }
+        const f32x16 acc = kloop(rs_pt, ml * KB, kbeg, kend, s_tt);
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           const int row = 32 * ml + 8 * (j >> 2) + 4 * h + (j & 3);
