@@ -161,26 +161,54 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
   const int nb = wv & 3;
   const unsigned mine = mblocks_for(wv >> 2, MBe, KBe);
   const size_t plane = (size_t)(Lp >> 5) * KB * 512;
-  const uint16_t* fh = w.pfrag + (size_t)b * 2 * plane;
-  const uint16_t* fl = fh + plane;
+  // this sample's P fragments (hi plane, then lo plane): lanes address their 16 bytes
+  // with the vector offset, blocks with the scalar offset
+  const __amdgpu_buffer_rsrc_t rs_f = make_rsrc(w.pfrag + (size_t)b * 2 * plane, 2 * plane * 2);
+  const uint32_t lo_plane = (uint32_t)plane * 2u, voff_f = (uint32_t)lane * 16u;
+  auto frag = [&](int blk, uint32_t pl) {
+    return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs_f, voff_f, (uint32_t)blk * 1024u + pl, 0));
+  };
   const int col = 32 * nb + (lane & 31);
   const int khalf = 8 * (lane >> 5);
   // the annulus sum in FP64: near the best fit the likelihood seeds carry the spectrum's
   // rounding relative to the noise level, and a gradient that cancels to a fraction of
   // its terms carries it too
   double dsum = 0.0;
-  // row block mi's products over the K blocks [k_lo, k_hi), B rows from LDS row 16 (kb - k_base)
+  // row block mi's products over the K blocks [k_lo, k_hi), B rows from LDS row 16 (kb - k_base).
+  // The fragments go in two groups of two K blocks, one group's loads in flight while the
+  // other's products run; every iteration issues the same loads (blocks past k_hi read
+  // the next row block's fragments, or zeros past the buffer's range, and are never used)
   auto chord = [&](f32x16 acc, int mi, int k_lo, int k_hi, int k_base) {
-    for (int kb = k_lo; kb < k_hi; ++kb) {
-      const size_t fo = ((size_t)(mi * KB + kb) * 64 + lane) * 8;
-      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(fh + fo);
-      const bf16x8 al = *reinterpret_cast<const bf16x8*>(fl + fo);
-      const int kr = 16 * (kb - k_base) + khalf;
-      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(s_bhi + col * stride + kr);
-      const bf16x8 bl = *reinterpret_cast<const bf16x8*>(s_blo + col * stride + kr);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+    if (k_lo >= k_hi) return acc;
+    bf16x8 ga[2][2], gb[2][2];   // [K block][hi, lo]
+    auto load = [&](bf16x8 (&gr)[2][2], int k) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        gr[u][0] = frag(mi * KB + k + u, 0);
+        gr[u][1] = frag(mi * KB + k + u, lo_plane);
+      }
+    };
+    auto product = [&](const bf16x8 (&gr)[2][2], int k0) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int kb = k0 + u;
+        if (kb >= k_hi) break;
+        const int kr = 16 * (kb - k_base) + khalf;
+        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(s_bhi + col * stride + kr);
+        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(s_blo + col * stride + kr);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gr[u][1], bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gr[u][0], bl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gr[u][0], bh, acc, 0, 0, 0);
+      }
+    };
+    load(ga, k_lo);
+#pragma unroll 1
+    for (int kb = k_lo; kb < k_hi; kb += 4) {
+      load(gb, kb + 2);
+      product(ga, kb);
+      if (kb + 2 >= k_hi) break;
+      load(ga, kb + 4);
+      product(gb, kb + 2);
     }
     return acc;
   };
