@@ -437,6 +437,53 @@ __global__ __launch_bounds__(2 * PARTS * TILE) void k_trans_adj_mixed(Model m, W
   }
 }
 
+// a * h.x + c and a * h.y + c with the FP16 half taken as an operand of the FMA
+// (v_fma_mix_f32): the same single rounding as converting it first, without a
+// converted copy of the table pairs held in registers across a group's layers
+__device__ inline float fma_f16lo(float a, half2_t h, float c) {
+  float d;
+  asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[0,1,0]" : "=v"(d) : "v"(a), "v"(h), "v"(c));
+  return d;
+}
+__device__ inline float fma_f16hi(float a, half2_t h, float c) {
+  float d;
+  asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[0,1,0] op_sel_hi:[0,1,0]" : "=v"(d) : "v"(a), "v"(h), "v"(c));
+  return d;
+}
+
+// Line terms of one layer (and its CIA terms) for two wavenumbers with the
+// derivative of each exponent with respect to the T weight: the arithmetic of
+// eval_terms_deriv, with the line pairs entering their FMAs as FP16 operands
+template <int S, bool CIA>
+__device__ inline void eval_terms_deriv_f16(const LayerCoef<S>& c, const LaneConst<S>& k, const LayerRaw<S, CIA>& r,
+                                            float* t0, float* t1, float* dw0, float* dw1) {
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const half2_t h00 = r.h[4 * s], h10 = r.h[4 * s + 1], h01 = r.h[4 * s + 2], h11 = r.h[4 * s + 3];
+    const float cl0 = k.c0[s] + c.lam[s], cl1 = k.c1[s] + c.lam[s];
+    const float u00 = fma_f16lo(c.omp, h00, fma_f16lo(c.wp, h01, cl0));
+    const float u10 = fma_f16lo(c.omp, h10, fma_f16lo(c.wp, h11, cl0));
+    const float u01 = fma_f16hi(c.omp, h00, fma_f16hi(c.wp, h01, cl1));
+    const float u11 = fma_f16hi(c.omp, h10, fma_f16hi(c.wp, h11, cl1));
+    dw0[s] = u10 - u00;
+    dw1[s] = u11 - u01;
+    t0[s] = exp2_fast(fmaf(c.wt, dw0[s], u00));
+    t1[s] = exp2_fast(fmaf(c.wt, dw1[s], u01));
+  }
+  if constexpr (CIA) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const half2_t a = r.h[4 * S + 2 * p], b = r.h[4 * S + 2 * p + 1];
+      const float u0 = (float)a.x + (k.cc0[p] + c.lamc[p]);
+      const float u1 = (float)a.y + (k.cc1[p] + c.lamc[p]);
+      dw0[S + p] = (float)b.x - (float)a.x;
+      dw1[S + p] = (float)b.y - (float)a.y;
+      t0[S + p] = exp2_fast(fmaf(c.wtc, dw0[S + p], u0));
+      t1[S + p] = exp2_fast(fmaf(c.wtc, dw1[S + p], u1));
+    }
+  }
+}
+
 // ============================================================================
 // reduced-precision per-layer sums: one wave per (sample, layer group, ls_tiles tiles),
 // a layer group being a run of up to kLsGroup consecutive layers in one table cell
@@ -521,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
       const float2 db = dbq[q];
       const LayerCoef<S> c = q == 0 ? c0 : load_layer<S>(m, cells, rec, l0 + q, (uint32_t)nu0 * 2u, g);
       float t0_[S + 2], t1_[S + 2], dw0[S + 2], dw1[S + 2];
-      eval_terms_deriv<S, CIA>(c, kc, raw, t0_, t1_, dw0, dw1);
+      eval_terms_deriv_f16<S, CIA>(c, kc, raw, t0_, t1_, dw0, dw1);
       // G_s += db t_s per wavenumber; the T-weight sums take db once per wavenumber
       // times z = sum_s t_s dw_s
       float z0 = 0.0f, z1 = 0.0f;
