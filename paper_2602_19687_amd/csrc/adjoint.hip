@@ -1126,48 +1126,73 @@ __global__ __launch_bounds__(kBlock) void k_chain(Model m, Work w, AdjWork aw, i
   }
 
   // path-matrix adjoint: column pass (r_l, r_{l+1}) and row pass (b_i); four entries'
-  // loads are issued together, each entry summed over the chunks in chunk order
+  // loads are issued together, each entry summed over the chunks in chunk order.  Each
+  // column's (row's) entries are split into nseg contiguous segments on different
+  // threads (the longest column set the pace of the whole block); the segments'
+  // partial sums, kept in s_red (free here), are added in segment order
   const PbarT* pbar = reinterpret_cast<const PbarT*>(aw.pbar) + (size_t)b * C * Lp * Lp;
   const size_t pst = (size_t)Lp * Lp;
   const bool trans = m.mode == kTransmission;
-  for (int l = tid; l < (trans ? L : 0); l += kBlock) {
+  constexpr int kMaxSeg = 4;
+  const int nseg = trans ? max(1, min(kMaxSeg, kBlock / max(L, 1))) : 1;
+  double* s_plo = s_red;                              // [kMaxSeg][kMaxLayers]
+  double* s_pup = s_red + kMaxSeg * kMaxLayers;
+  double* s_pb = s_red + 2 * kMaxSeg * kMaxLayers;
+  for (int t = tid; t < (trans ? nseg * L : 0); t += kBlock) {
+    const int l = t % L, sg = t / L;
+    const int ia = sg * (l + 1) / nseg, ib = (sg + 1) * (l + 1) / nseg;   // rows i <= l
     double clo = 0.0, cup = 0.0;
-    for (int i0 = 0; i0 <= l; i0 += 4) {
+    for (int i0 = ia; i0 < ib; i0 += 4) {
       double p[4] = {0.0, 0.0, 0.0, 0.0};
       for (int c = 0; c < Cn; ++c)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (i0 + u <= l) p[u] += (double)pbar[c * pst + (size_t)(i0 + u) * Lp + l];
+          if (i0 + u < ib) p[u] += (double)pbar[c * pst + (size_t)(i0 + u) * Lp + l];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        if (i0 + u > l) break;
+        if (i0 + u >= ib) break;
         double dlo, dup, db;
         path_derivs(s_r, i0 + u, l, dlo, dup, db);
         clo += p[u] * dlo;
         cup += p[u] * dup;
       }
     }
-    s_clo[l] = clo;
-    s_cup[l] = cup;
+    s_plo[sg * kMaxLayers + l] = clo;
+    s_pup[sg * kMaxLayers + l] = cup;
   }
-  for (int i = tid; i < (trans ? L : 0); i += kBlock) {
+  for (int t = tid; t < (trans ? nseg * L : 0); t += kBlock) {
+    const int i = t % L, sg = t / L, n = L - 1 - i;   // columns l = i + 1 .. L - 1
+    const int la = i + 1 + sg * n / nseg, lb = i + 1 + (sg + 1) * n / nseg;
     double acc = 0.0;
-    for (int l0 = i + 1; l0 < L; l0 += 4) {
+    for (int l0 = la; l0 < lb; l0 += 4) {
       double p[4] = {0.0, 0.0, 0.0, 0.0};
       for (int c = 0; c < Cn; ++c)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (l0 + u < L) p[u] += (double)pbar[c * pst + (size_t)i * Lp + l0 + u];
+          if (l0 + u < lb) p[u] += (double)pbar[c * pst + (size_t)i * Lp + l0 + u];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        if (l0 + u >= L) break;
+        if (l0 + u >= lb) break;
         double dlo, dup, db;
         path_derivs(s_r, i, l0 + u, dlo, dup, db);
         acc += p[u] * db;
       }
     }
-    s_bb[i] = acc;
+    s_pb[sg * kMaxLayers + i] = acc;
   }
+  __syncthreads();
+  for (int l = tid; l < (trans ? L : 0); l += kBlock) {
+    double clo = 0.0, cup = 0.0, bb = 0.0;
+    for (int sg = 0; sg < nseg; ++sg) {
+      clo += s_plo[sg * kMaxLayers + l];
+      cup += s_pup[sg * kMaxLayers + l];
+      bb += s_pb[sg * kMaxLayers + l];
+    }
+    s_clo[l] = clo;
+    s_cup[l] = cup;
+    s_bb[l] = bb;
+  }
+  __syncthreads();   // s_red is reused below
   // emission: no chord; the levels move the optical depths only through dr
   for (int l = tid; l < (trans ? 0 : L); l += kBlock) s_clo[l] = s_cup[l] = s_bb[l] = 0.0;
   // seed of the core term: the bins' d lnL / d depth summed over the block
