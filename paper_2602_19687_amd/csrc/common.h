@@ -41,12 +41,13 @@ constexpr float kOpaqueTau = 110.0f;
 
 // per-layer record of the opacity kernels (one per sample and layer)
 //   [0] wT, [1] wP, [2] wTc, [3] Rayleigh coefficient R_l (x (nu/1e4)^4),
-//   [4] cloud term D_l, [5] lam_c1, [6] lam_c2, [7..7+S) lam_s
-// with lam = log2 of the per-layer prefactor (n X dr, n^2 X X dr).  D_l is the
-// grey deck's optical depth, or for the non-grey cloud the layer's column
+//   [4] cloud term D_l, [5] lam_c1, [6] lam_c2, [7..7+S) lam_s, [7+S..7+2S) col_s
+// with lam = log2 of the per-layer prefactor (n X dr, n^2 X X dr) and col_s = n X_s dr
+// itself (the line prefactor fits FP32; the CIA one, quadratic in n, need not).
+// D_l is the grey deck's optical depth, or for the non-grey cloud the layer's column
 // q_l rho_l dr_l 3 / (4 r_eff) that multiplies Q_ext(nu).
 constexpr int kRecFixed = 7;
-__host__ __device__ constexpr int rec_len(int s) { return kRecFixed + s; }
+__host__ __device__ constexpr int rec_len(int s) { return kRecFixed + 2 * s; }
 
 // packed interpolation cells of one layer: iT | iP << 8 | iTc << 16
 __host__ __device__ inline int pack_cells(int it, int ip, int itc) { return it | (ip << 8) | (itc << 16); }

@@ -31,6 +31,7 @@ struct LayerCoef {
   uint32_t rowc[2];     // byte offset of the (pair, iTc) CIA row at the tile start
   float w00, w10, w01, w11, wtc, R, D;
   float lam[S], lamc[2];
+  float col[S];        // line prefactors n X_s dr (2^lam)
   float wt, wp, omp;   // T and log p weights, 1 - wP (derivative form of the bilinear)
   int cell;            // packed (iT, iP, iTc): equal cells read equal table pairs
 };
@@ -66,6 +67,7 @@ __device__ inline LayerCoef<S> load_layer(const Model& m, const int32_t* __restr
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     c.lam[s] = rl[kRecFixed + s];
+    c.col[s] = rl[kRecFixed + S + s];
     c.row[s] = (uint32_t)(((s * m.n_t + it) * m.n_p + ip)) * g.row_bytes + nu0_bytes;
   }
 #pragma unroll
@@ -153,21 +155,21 @@ __device__ inline void eval_terms(const LayerCoef<S>& c, const LaneConst<S>& k, 
     d0 = fmaf(c.R, k.nu4_0, c.D);
     d1 = fmaf(c.R, k.nu4_1, c.D);
   }
+  // line terms: the cross-section (log2 sigma = c + the interpolated entry) times the
+  // layer's prefactor, which then costs no add to the exponent
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const half2_t h00 = r.h[4 * s], h10 = r.h[4 * s + 1], h01 = r.h[4 * s + 2], h11 = r.h[4 * s + 3];
-    float v0 = k.c0[s] + c.lam[s];
-    float v1 = k.c1[s] + c.lam[s];
-    v0 = fmaf(c.w00, (float)h00.x, v0);
-    v1 = fmaf(c.w00, (float)h00.y, v1);
+    float v0 = fmaf(c.w00, (float)h00.x, k.c0[s]);
+    float v1 = fmaf(c.w00, (float)h00.y, k.c1[s]);
     v0 = fmaf(c.w10, (float)h10.x, v0);
     v1 = fmaf(c.w10, (float)h10.y, v1);
     v0 = fmaf(c.w01, (float)h01.x, v0);
     v1 = fmaf(c.w01, (float)h01.y, v1);
     v0 = fmaf(c.w11, (float)h11.x, v0);
     v1 = fmaf(c.w11, (float)h11.y, v1);
-    d0 += exp2_fast(v0);
-    d1 += exp2_fast(v1);
+    d0 = fmaf(c.col[s], exp2_fast(v0), d0);
+    d1 = fmaf(c.col[s], exp2_fast(v1), d1);
   }
   if constexpr (CIA) {
 #pragma unroll
