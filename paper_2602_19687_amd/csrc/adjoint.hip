@@ -519,7 +519,7 @@ __global__ __launch_bounds__(kBlock) void k_layer_sums_mixed(Model m, Work w, Ta
   const __amdgpu_buffer_rsrc_t rhc = make_rsrc(CIA ? (const void*)tb.hc : (const void*)tb.h,
                                                CIA ? (size_t)2 * m.n_tc * npad * 2 : 0);
   const uint32_t voff = (uint32_t)lane * 4u;
-  const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * rec_len(S);
+  const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * rec_len_wide(S);
   const int32_t* cells = w.cells + (size_t)b * Lp;
   const float* dtb = aw.dtb + (size_t)b * Lp * npad;
 
@@ -620,7 +620,7 @@ __global__ __launch_bounds__(kBlock) void k_cloud_spectral(Model m, Work w, AdjW
   if (b >= B || w.status[b]) return;
   const int L = w.nlay[b], Lp = m.L_pad;
   const size_t npad = (size_t)m.n_nu_pad;
-  const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * rec_len(m.S);
+  const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * rec_len_wide(m.S);
   const float* dtb = aw.dtb + (size_t)b * Lp * npad;
   const float* cq = w.cloud_q + (size_t)b * (1 + kCloudSpec) * npad;
   float hq[kCloudSpec] = {};
@@ -630,7 +630,7 @@ __global__ __launch_bounds__(kBlock) void k_cloud_spectral(Model m, Work w, AdjW
     float g0 = 0.0f, g1 = 0.0f;
     // rows below the opaque frontier are zero (and not stored)
     for (int l = 32 * w.front[(size_t)b * m.n_tiles + tile]; l < L; ++l) {
-      const float dl = rec[(size_t)l * rec_len(m.S) + 4];
+      const float dl = rec[(size_t)l * rec_len_wide(m.S) + 4];
       const float2 d = *reinterpret_cast<const float2*>(dtb + (size_t)l * npad + nu);
       g0 = fmaf(dl, d.x, g0);
       g1 = fmaf(dl, d.y, g1);

@@ -41,13 +41,12 @@ constexpr float kOpaqueTau = 110.0f;
 
 // per-layer record of the opacity kernels (one per sample and layer)
 //   [0] wT, [1] wP, [2] wTc, [3] Rayleigh coefficient R_l (x (nu/1e4)^4),
-//   [4] cloud term D_l, [5] lam_c1, [6] lam_c2, [7..7+S) lam_s, [7+S..7+2S) col_s
-// with lam = log2 of the per-layer prefactor (n X dr, n^2 X X dr) and col_s = n X_s dr
-// itself (the line prefactor fits FP32; the CIA one, quadratic in n, need not).
-// D_l is the grey deck's optical depth, or for the non-grey cloud the layer's column
+//   [4] cloud term D_l, [5] lam_c1, [6] lam_c2, [7..7+S) lam_s
+// with lam = log2 of the per-layer prefactor (n X dr, n^2 X X dr).  D_l is the
+// grey deck's optical depth, or for the non-grey cloud the layer's column
 // q_l rho_l dr_l 3 / (4 r_eff) that multiplies Q_ext(nu).
 constexpr int kRecFixed = 7;
-__host__ __device__ constexpr int rec_len(int s) { return kRecFixed + 2 * s; }
+__host__ __device__ constexpr int rec_len(int s) { return kRecFixed + s; }
 
 // packed interpolation cells of one layer: iT | iP << 8 | iTc << 16
 __host__ __device__ inline int pack_cells(int it, int ip, int itc) { return it | (ip << 8) | (itc << 16); }
@@ -88,6 +87,15 @@ struct Model {
   const double* nu;         // [n_nu_pad] (padded with the last value)
 };
 
+// The reduced-precision transmission records (not correlated-k) also carry, after
+// the logs, the S line prefactors col_s = n X_s dr themselves (they fit FP32; the CIA
+// prefactor, quadratic in n, need not): [7+S..7+2S) col_s
+__host__ __device__ constexpr int rec_len_wide(int s) { return kRecFixed + 2 * s; }
+__host__ __device__ inline bool rec_wide(const Model& m, bool fp64) { return m.mode == kTransmission && !fp64 && !m.ck; }
+__host__ __device__ inline int rec_stride(const Model& m, bool fp64) {
+  return rec_wide(m, fp64) ? rec_len_wide(m.S) : rec_len(m.S);
+}
+
 // real sample and cloud-free flag of a virtual sample
 __host__ __device__ inline int real_sample(const Model& m, int b) { return m.has_fcld ? b >> 1 : b; }
 __host__ __device__ inline bool clear_sample(const Model& m, int b) { return m.has_fcld && (b & 1); }
@@ -112,7 +120,7 @@ struct Work {
   int32_t* front;       // reduced precision: [B][n_tiles] opaque 32-row chord blocks at the bottom of
                         //   each 128-wavenumber tile (every tau > kOpaqueTau), set by a forward pass
                         //   that stores the layer optical depths
-  void* rec;            // [B][L_pad][rec_len] float (mixed) or double (fp64)
+  void* rec;            // [B][L_pad][rec_stride] float (mixed) or double (fp64)
   void* area;           // [B][L_pad] (r_{i+1}^2 - r_i^2)/R_s^2, float or double
   double* pm64;         // fp64: [B][L_pad][L_pad] path matrix
   uint16_t* pfrag;      // mixed: [B][MB][KB][64][8] bf16, hi then lo planes

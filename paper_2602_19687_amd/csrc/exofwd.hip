@@ -450,7 +450,7 @@ exofwd_status exofwd_create(const exofwd_config* cfg, exofwd_ctx** out) {
 
   const bool fp64 = g.precision == EXOFWD_PREC_FP64;
   // per-sample buffers hold the virtual samples (two per sample with the cloudy/clear mixing)
-  const int Lp = m.L_pad, B = g.batch_max * (m.has_fcld ? 2 : 1), RL = rec_len(m.S);
+  const int Lp = m.L_pad, B = g.batch_max * (m.has_fcld ? 2 : 1), RL = rec_stride(m, fp64);
   const size_t np = (size_t)m.n_nu_pad;
   bool ok = true;
   auto A = [&](auto* p) { ok = ok && p != nullptr; return p; };
@@ -768,7 +768,7 @@ static size_t carve_forward_work(const exofwd_ctx* c, int B, bool internal_spec,
   w.cells = (int32_t*)take(4 * Bv * Lp);
   if (!fp64) w.lsg = (int32_t*)take(4 * Bv * (Lp + 1));
   if (trans && !fp64) w.front = (int32_t*)take(4 * Bv * (size_t)m.n_tiles);
-  w.rec = take(rs * Bv * Lp * (size_t)rec_len(m.S));
+  w.rec = take(rs * Bv * Lp * (size_t)rec_stride(m, fp64));
   w.area = take(rs * Bv * Lp);
   if (trans && fp64) w.pm64 = (double*)take(8 * Bv * Lp * Lp);
   if (trans && !fp64) w.pfrag = (uint16_t*)take(2 * Bv * 2 * (Lp / 32) * (Lp / 16) * 512);

@@ -50,7 +50,7 @@ __device__ inline LayerCoef<S> load_layer(const Model& m, const int32_t* __restr
   const int cl = cells[l];
   const int it = cl & 255, ip = (cl >> 8) & 255, itc = cl >> 16;
   c.cell = cl;
-  const float* rl = rec + (size_t)l * rec_len(S);
+  const float* rl = rec + (size_t)l * rec_len_wide(S);
   const float wt = rl[0], wp = rl[1];
   c.wt = wt;
   c.wp = wp;

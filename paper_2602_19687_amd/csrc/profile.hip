@@ -237,7 +237,8 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
                                         : r_ref * r_ref / (m.has_bd ? m.bd_dist * m.bd_dist : m.r_s * m.r_s);
 
   // per-layer opacity records
-  const int RL = rec_len(m.S);
+  const bool wide = rec_wide(m, sizeof(Real) == 8);
+  const int RL = rec_stride(m, sizeof(Real) == 8);
   Real* rec = reinterpret_cast<Real*>(w.rec) + (size_t)b * Lp * RL;
   Real* area = reinterpret_cast<Real*>(w.area) + (size_t)b * Lp;
   const double log10_pc = m.has_cloud ? th[m.idx_cloud] : 0.0;
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
       w.cells[(size_t)b * Lp + l] = 0;
       for (int k = 0; k < RL; ++k) rl[k] = Real(0);
       rl[5] = rl[6] = Real(-1000);
-      for (int s = 0; s < m.S; ++s) rl[kRecFixed + s] = Real(-1000);   // the columns stay 0
+      for (int s = 0; s < m.S; ++s) rl[kRecFixed + s] = Real(-1000);   // the prefactors stay 0
       area[l] = Real(0);
       continue;
     }
@@ -295,10 +296,9 @@ __global__ __launch_bounds__(kBlock) void k_profile(Model m, Work w, const doubl
     rl[4] = Real(dcl);
     rl[5] = Real(m.has_cia ? log2(n * n * xh2 * xh2 * dr) : -1000.0);
     rl[6] = Real(m.has_cia ? log2(n * n * xh2 * xhe * dr) : -1000.0);
-    for (int s = 0; s < m.S; ++s) {
-      rl[kRecFixed + s] = Real(log2(n * x[s] * dr));
-      rl[kRecFixed + m.S + s] = Real(n * x[s] * dr);
-    }
+    for (int s = 0; s < m.S; ++s) rl[kRecFixed + s] = Real(log2(n * x[s] * dr));
+    if (wide)
+      for (int s = 0; s < m.S; ++s) rl[kRecFixed + m.S + s] = Real(n * x[s] * dr);
     area[l] = Real(dr * (s_r[l] + s_r[l + 1]) / (m.r_s * m.r_s));
   }
   if (w.lsg) {

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kBlockT) void k_trans_fwd_mixed(Model m, Work w, Ta
   for (int i = tid; i < n_area; i += kBlockT) s_area[i] = area[i];
 
   // phase A: vertical optical depth of every layer -> bf16 hi/lo B operand in LDS
-  const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * rec_len(S);
+  const float* rec = reinterpret_cast<const float*>(w.rec) + (size_t)b * Lp * rec_len_wide(S);
   const int32_t* cells = w.cells + (size_t)b * Lp;
   TableGeom g;
   g.row_bytes = (uint32_t)m.n_nu_pad * 2u;
