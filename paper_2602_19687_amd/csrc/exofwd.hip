@@ -1022,7 +1022,7 @@ exofwd_status exofwd_autotune(exofwd_ctx* c, int32_t B, const double* params, co
     if (exofwd_set_tuning(c, t) != EXOFWD_OK) return 1e30;
     if (step() != EXOFWD_OK) return 1e30;
     float best = 1e30f;
-    for (int rep = 0; rep < 3; ++rep) {
+    for (int rep = 0; rep < 5; ++rep) {
       hipEventRecord(e0, st);
       if (step() != EXOFWD_OK) return 1e30;
       hipEventRecord(e1, st);
@@ -1058,6 +1058,12 @@ exofwd_status exofwd_autotune(exofwd_ctx* c, int32_t B, const double* params, co
         }
       for (int lt : kLsTileChoices) {
         int32_t t[4] = {best_t[0], best_t[1], best_t[2], lt};
+        consider(t);
+      }
+      // the forward grid order once more, now beside the tuned reverse pass (the two
+      // orders are within a few per cent of each other)
+      for (int o = 0; o < 2; ++o) {
+        int32_t t[4] = {o, best_t[1], best_t[2], best_t[3]};
         consider(t);
       }
     }
